@@ -1,0 +1,174 @@
+/*
+ * rsfgp — recursive skeletonization factorization (RSF) of a spatial
+ * Gaussian-process covariance matrix on one AMD Instinct MI355X (gfx950), and
+ * the log-likelihood and score equations built on it.
+ *
+ * The method is that of Minden, Damle, Ho and Ying, "Fast spatial Gaussian
+ * process maximum likelihood estimation via skeletonization factorizations":
+ *   - Section 2 (eq. rskelf): Sigma(theta) ~= F, a product of block
+ *     unit-triangular skeletonization operators and a block-diagonal Cholesky
+ *     factor, built level by level over a quadtree of the observation sites;
+ *   - Section 2.4: F^-1 b, F^(1/2) w and log|F| from sweeps over the factors;
+ *   - eq. loglikelihood and Algorithm 1: l(theta) = -1/2 z^T F^-1 z
+ *     - 1/2 log|F| - (n/2) log 2 pi;
+ *   - eq. gradient and Section 3: g_i = 1/2 z^T F^-1 Sigma_i F^-1 z
+ *     - 1/2 Tr(F^-1 Sigma_i), the trace taken by matrix peeling (Section 3.2).
+ *
+ * Conventions for every entry point:
+ *   - Return value: RSF_OK (0) or a negative rsf_status.  No C++ exception
+ *     crosses this interface.  On error, outputs are left untouched and a
+ *     message is available from rsf_last_error() (thread-local).
+ *   - Pointers named d_* are device (HIP) pointers; all others are host.
+ *     The caller owns every input and output buffer.  A factor handle owns
+ *     all device memory it allocates until rsf_factor_destroy().
+ *   - Vectors are in the caller's point order; the library keeps its tree
+ *     permutation internal.  Blocks of vectors are column-major n x nrhs with
+ *     leading dimension ld >= n.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  A handle is used
+ *     by one stream at a time.  Calls that return a host scalar synchronise
+ *     that stream.
+ *   - theta = (rho, sigma2, nugget): length scale, variance, nugget.  The
+ *     covariance is Sigma_ij = sigma2 k(|x_i - x_j| / rho) + nugget [i == j]
+ *     with k from the Matern closed forms (eq. diffkernels) or the rational
+ *     quadratic kernel (eq. rationalquadratic with the length scale).
+ */
+#ifndef RSFGP_H
+#define RSFGP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int rsf_status;
+typedef struct rsf_factor_s* rsf_factor;
+
+enum {
+  RSF_OK = 0,
+  RSF_E_INVALID = -1,   /* bad argument: n < 1, leaf < 1, eps <= 0, rho <= 0, ... */
+  RSF_E_NOT_SPD = -2,   /* a diagonal block (or the root) lost positive definiteness
+                           (the remark after eq. rskelf: a crude eps can do this) */
+  RSF_E_OOM = -3,       /* device allocation failed or opts.mem_cap_bytes exceeded */
+  RSF_E_HIP = -4,       /* a HIP runtime call failed */
+  RSF_E_DUPLICATE = -5, /* two observation sites coincide (the nugget is a delta on
+                           observation indices, so sites must be unique) */
+  RSF_E_NONFINITE = -6  /* a coordinate or parameter is NaN or infinite */
+};
+
+/* Covariance families.  Matern nu = 1/2, 3/2, 5/2 closed forms (eq. diffkernels)
+ * and the rational quadratic kernel with fixed shape alpha (opts.rq_alpha). */
+enum { RSF_MATERN12 = 0, RSF_MATERN32 = 1, RSF_MATERN52 = 2, RSF_RQ = 3 };
+
+typedef struct {
+  int n_prox;           /* proxy points per box (Section 2.3.1; Section 5 uses 256) */
+  int prox_rings;       /* rings the proxy points are spread over (Fig. 3 draws an annulus) */
+  double r_near;        /* near-field radius in box half-widths (Fig. 3: 1.8) */
+  double prox_r_in;     /* inner / outer radius of the proxy annulus in half-widths */
+  double prox_r_out;    /*   (Fig. 3: 1.75 and 2.45) */
+  double rq_alpha;      /* shape alpha of the rational quadratic kernel */
+  size_t mem_cap_bytes; /* 0 = unlimited; otherwise RSF_E_OOM beyond this many bytes */
+} rsf_opts;
+
+/* Fills *opts with the defaults above (n_prox 256, 4 rings, 1.8, 1.75, 2.45,
+ * alpha 1, no cap).  Errors: RSF_E_INVALID if opts is NULL. */
+rsf_status rsf_opts_default(rsf_opts* opts);
+
+/* Builds F ~= Sigma(theta) (Section 2, eq. rskelf; Algorithm 1, step "factor").
+ *   d_points  device, n x 2 row-major FP64 (x_i, y_i), caller's order; copied.
+ *   n         number of observations (>= 1).
+ *   theta     host, p = 3 values (rho, sigma2, nugget).
+ *   kernel    RSF_MATERN12 .. RSF_RQ.
+ *   eps       relative tolerance of every interpolative decomposition
+ *             (Definition "interpolative decomposition"), > 0.
+ *   leaf      maximum points per quadtree leaf (n_occ of Section 5), >= 1.
+ *   opts      NULL for defaults.
+ *   out       receives the new handle (unchanged on error).
+ * Errors: RSF_E_INVALID, RSF_E_NONFINITE, RSF_E_DUPLICATE, RSF_E_NOT_SPD,
+ *         RSF_E_OOM, RSF_E_HIP. */
+rsf_status rsf_factor_create(const double* d_points, int64_t n, const double* theta, int p,
+                             int kernel, double eps, int leaf, const rsf_opts* opts,
+                             void* stream, rsf_factor* out);
+
+/* Releases every device buffer of f.  NULL is a no-op. */
+void rsf_factor_destroy(rsf_factor f);
+
+/* log|F| = 2 log|C| (Section 2.4), summed in a fixed order.  out: host scalar. */
+rsf_status rsf_logdet(rsf_factor f, double* out);
+
+/* d_x = F^-1 d_b for nrhs columns (Section 2.4, the F^-1 product formula).
+ * d_b, d_x: device, n x nrhs column-major, leading dimension ld >= n; d_x may
+ * alias d_b.  Errors: RSF_E_INVALID, RSF_E_OOM, RSF_E_HIP. */
+rsf_status rsf_solve(rsf_factor f, const double* d_b, double* d_x, int64_t nrhs, int64_t ld,
+                     void* stream);
+
+/* d_y = F d_x (Section 2.4).  Same layout rules as rsf_solve. */
+rsf_status rsf_apply(rsf_factor f, const double* d_x, double* d_y, int64_t nrhs, int64_t ld,
+                     void* stream);
+
+/* d_z = F^(1/2) d_w with F = F^(1/2) (F^(1/2))^T (Section 2.4, the generalized
+ * square root): a draw from N(0, F) when d_w ~ N(0, I).  Same layout rules. */
+rsf_status rsf_apply_sqrt(rsf_factor f, const double* d_w, double* d_z, int64_t nrhs,
+                          int64_t ld, void* stream);
+
+/* Log-likelihood of observations d_z (device, n values, caller's order):
+ * l = -1/2 z^T F^-1 z - 1/2 log|F| - (n/2) log 2 pi (eq. loglikelihood; the
+ * reading of Algorithm 1 keeps the (n/2) factor of the equation).
+ *   out            host scalar.
+ *   d_alpha_or_null  if not NULL, receives F^-1 z (device, n values). */
+rsf_status rsf_loglik(rsf_factor f, const double* d_z, double* out, double* d_alpha_or_null,
+                      void* stream);
+
+typedef struct {
+  double q[3];          /* 1/2 alpha^T Sigma_i alpha, alpha = F^-1 z */
+  double t[3];          /* Tr(F^-1 Sigma_i) */
+  double trace_inv;     /* Tr F^-1 (peeled) */
+  int peel_levels;      /* quadtree levels peeled */
+  int peel_cols[32];    /* probe columns per quadrant block at each level */
+  int peel_rank[32];    /* largest sibling-block rank found at each level */
+  int leaf_cols;        /* n_L of the extraction step */
+  double seconds[4];    /* factor Sigma_rho, quadratic terms, peeling, total */
+} rsf_grad_info;
+
+/* Score equations g (eq. gradient; Algorithm 1): for theta = (rho, sigma2,
+ * nugget),
+ *   g_i = q_i - t_i / 2,  q_i = 1/2 alpha^T Sigma_i alpha,  t_i = Tr(F^-1 Sigma_i),
+ * with Sigma_rho represented by its own skeletonization (multiply-only form),
+ * Sigma_sigma2 = (Sigma - nugget I) / sigma2 and Sigma_nugget = I, and the
+ * traces taken by matrix peeling (Section 3.2) of F^-1 and of
+ * 1/2 (F^-1 F_rho + F_rho F^-1) (Algorithm 1, the symmetrized operator) to
+ * relative tolerance eps_peel, with Gaussian probes from Philox4x32-10 keyed by
+ * seed.
+ *   d_z       device, n observations (caller's order).
+ *   g         host, 3 values.
+ *   info_or_null  host; receives the split terms and peeling statistics. */
+rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
+                    rsf_grad_info* info_or_null, void* stream);
+
+typedef struct {
+  int64_t n;
+  int depth;            /* deepest level L */
+  int nbox;             /* quadtree boxes */
+  int root_size;        /* DOFs left for the dense root factor */
+  int64_t factor_bytes; /* device bytes held by the factors */
+} rsf_tree_info;
+
+/* Tree introspection.  perm (host, n values or NULL) receives the tree order:
+ * perm[t] = caller index of the t-th point. */
+rsf_status rsf_tree_export(rsf_factor f, int32_t* perm, rsf_tree_info* info);
+
+/* Skeletons of the boxes at depth `level` (1 .. depth) in breadth-first box
+ * order: counts (host, boxes-at-level + 1 values or NULL) receives prefix
+ * offsets, idx (host or NULL) the skeleton DOFs as caller indices in pivot
+ * order.  *nbox_out (host) receives the number of boxes at that level. */
+rsf_status rsf_skeleton_export(rsf_factor f, int level, int32_t* offsets, int32_t* idx,
+                               int32_t* nbox_out);
+
+/* Message describing the last error on this thread ("" if none). */
+const char* rsf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSFGP_H */

@@ -1,0 +1,205 @@
+"""ctypes binding of include/rsfgp.h (argument marshalling only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MATERN12, MATERN32, MATERN52, RQ = 0, 1, 2, 3
+
+_ERRORS = {-1: "RSF_E_INVALID", -2: "RSF_E_NOT_SPD", -3: "RSF_E_OOM", -4: "RSF_E_HIP",
+           -5: "RSF_E_DUPLICATE", -6: "RSF_E_NONFINITE"}
+
+
+class RsfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (_ERRORS.get(code, str(code)), msg))
+        self.code = code
+        self.name = _ERRORS.get(code, str(code))
+
+
+class Options(C.Structure):
+    _fields_ = [("n_prox", C.c_int), ("prox_rings", C.c_int), ("r_near", C.c_double),
+                ("prox_r_in", C.c_double), ("prox_r_out", C.c_double), ("rq_alpha", C.c_double),
+                ("mem_cap_bytes", C.c_size_t)]
+
+
+class GradInfo(C.Structure):
+    _fields_ = [("q", C.c_double * 3), ("t", C.c_double * 3), ("trace_inv", C.c_double),
+                ("peel_levels", C.c_int), ("peel_cols", C.c_int * 32), ("peel_rank", C.c_int * 32),
+                ("leaf_cols", C.c_int), ("seconds", C.c_double * 4)]
+
+
+class TreeInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("depth", C.c_int), ("nbox", C.c_int), ("root_size", C.c_int),
+                ("factor_bytes", C.c_int64)]
+
+
+_lib = None
+
+
+def library_path():
+    return os.environ.get("RSFGP_LIB", os.path.join(HERE, "librsfgp.so"))
+
+
+def load():
+    """Loads librsfgp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = library_path()
+    if not os.path.exists(path):
+        raise RuntimeError("librsfgp.so not built at %s (run paper_1603_08057_amd/build.py)" % path)
+    lib = C.CDLL(path)
+    vp, dp, i64 = C.c_void_p, C.POINTER(C.c_double), C.c_int64
+    sigs = {
+        "rsf_opts_default": ([C.POINTER(Options)], C.c_int),
+        "rsf_factor_create": ([vp, i64, dp, C.c_int, C.c_int, C.c_double, C.c_int, C.POINTER(Options), vp,
+                               C.POINTER(vp)], C.c_int),
+        "rsf_factor_destroy": ([vp], None),
+        "rsf_logdet": ([vp, dp], C.c_int),
+        "rsf_solve": ([vp, vp, vp, i64, i64, vp], C.c_int),
+        "rsf_apply": ([vp, vp, vp, i64, i64, vp], C.c_int),
+        "rsf_apply_sqrt": ([vp, vp, vp, i64, i64, vp], C.c_int),
+        "rsf_loglik": ([vp, vp, dp, vp, vp], C.c_int),
+        "rsf_grad": ([vp, vp, C.c_double, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
+        "rsf_tree_export": ([vp, C.POINTER(C.c_int32), C.POINTER(TreeInfo)], C.c_int),
+        "rsf_skeleton_export": ([vp, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                 C.POINTER(C.c_int32)], C.c_int),
+        "rsf_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise RsfError(rc, load().rsf_last_error().decode(errors="replace"))
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f64(x, shape=None):
+    torch = _torch()
+    if not isinstance(x, torch.Tensor):
+        x = torch.as_tensor(x, dtype=torch.float64)
+    x = x.to(device="cuda", dtype=torch.float64)
+    if shape is not None:
+        x = x.reshape(shape)
+    return x.contiguous()
+
+
+def _colmajor(b, n):
+    """(n,) or (n, nrhs) tensor -> (device column-major buffer as (nrhs, n) tensor, nrhs, squeeze)."""
+    b = _dev_f64(b)
+    if b.dim() == 1:
+        return b.reshape(1, n).contiguous(), 1, True
+    return b.t().contiguous(), b.shape[1], False
+
+
+class Factor:
+    """F ~= Sigma(theta) for observation sites `points` (n x 2)."""
+
+    def __init__(self, points, theta, kernel=MATERN32, eps=1e-6, leaf=64, n_prox=256, prox_rings=4,
+                 r_near=1.8, prox_r_in=1.75, prox_r_out=2.45, rq_alpha=1.0, mem_cap_bytes=0):
+        lib = load()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("rsfgp needs a HIP device")
+        pts = _dev_f64(points)
+        if pts.dim() != 2 or pts.shape[1] != 2:
+            raise ValueError("points must be n x 2")
+        self.n = pts.shape[0]
+        self.points = pts
+        opts = Options()
+        lib.rsf_opts_default(C.byref(opts))
+        opts.n_prox, opts.prox_rings, opts.r_near = n_prox, prox_rings, r_near
+        opts.prox_r_in, opts.prox_r_out, opts.rq_alpha = prox_r_in, prox_r_out, rq_alpha
+        opts.mem_cap_bytes = mem_cap_bytes
+        th = (C.c_double * 3)(*[float(v) for v in theta])
+        h = C.c_void_p()
+        _check(lib.rsf_factor_create(C.c_void_p(pts.data_ptr()), self.n, th, 3, int(kernel), float(eps),
+                                     int(leaf), C.byref(opts), _stream(), C.byref(h)))
+        self._h = h
+        self.theta = tuple(float(v) for v in theta)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rsf_factor_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def logdet(self):
+        out = C.c_double()
+        _check(load().rsf_logdet(self._h, C.byref(out)))
+        return out.value
+
+    def _block(self, fn, b):
+        torch = _torch()
+        cm, nrhs, sq = _colmajor(b, self.n)
+        out = torch.empty_like(cm)
+        _check(fn(self._h, C.c_void_p(cm.data_ptr()), C.c_void_p(out.data_ptr()), nrhs, self.n, _stream()))
+        return out.reshape(-1) if sq else out.t()
+
+    def solve(self, b):
+        return self._block(load().rsf_solve, b)
+
+    def apply(self, x):
+        return self._block(load().rsf_apply, x)
+
+    def apply_sqrt(self, w):
+        return self._block(load().rsf_apply_sqrt, w)
+
+    def loglik(self, z, want_alpha=False):
+        torch = _torch()
+        z = _dev_f64(z, (self.n,))
+        out = C.c_double()
+        alpha = torch.empty_like(z) if want_alpha else None
+        _check(load().rsf_loglik(self._h, C.c_void_p(z.data_ptr()), C.byref(out),
+                                 C.c_void_p(alpha.data_ptr()) if want_alpha else None, _stream()))
+        return (out.value, alpha) if want_alpha else out.value
+
+    def grad(self, z, eps_peel=None, seed=0):
+        z = _dev_f64(z, (self.n,))
+        g = (C.c_double * 3)()
+        info = GradInfo()
+        eps_peel = float(eps_peel) if eps_peel is not None else -1.0
+        _check(load().rsf_grad(self._h, C.c_void_p(z.data_ptr()), eps_peel, int(seed), g, C.byref(info),
+                               _stream()))
+        return [g[0], g[1], g[2]], info
+
+    def tree_info(self, want_perm=False):
+        info = TreeInfo()
+        perm = (C.c_int32 * self.n)() if want_perm else None
+        _check(load().rsf_tree_export(self._h, perm, C.byref(info)))
+        d = {"n": info.n, "depth": info.depth, "nbox": info.nbox, "root_size": info.root_size,
+             "factor_bytes": info.factor_bytes}
+        if want_perm:
+            d["perm"] = list(perm)
+        return d
+
+    def skeletons(self, level):
+        """(offsets, caller indices) of the skeletons of the boxes at `level`."""
+        nb = C.c_int32()
+        _check(load().rsf_skeleton_export(self._h, level, None, None, C.byref(nb)))
+        offs = (C.c_int32 * (nb.value + 1))()
+        _check(load().rsf_skeleton_export(self._h, level, offs, None, C.byref(nb)))
+        idx = (C.c_int32 * max(1, offs[nb.value]))()
+        _check(load().rsf_skeleton_export(self._h, level, offs, idx, C.byref(nb)))
+        return list(offs), list(idx)[:offs[nb.value]]

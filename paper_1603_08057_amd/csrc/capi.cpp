@@ -1,0 +1,261 @@
+// The C ABI of rsfgp (declared in include/rsfgp.h).
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "rsf.h"
+
+using namespace rsf;
+
+namespace {
+thread_local std::string g_last_error;
+
+int fail_with(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+template <class F>
+int guarded(F&& f) {
+  try {
+    g_last_error.clear();
+    f();
+    return RSF_OK;
+  } catch (const Error& e) {
+    return fail_with(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail_with(RSF_E_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail_with(RSF_E_HIP, e.what());
+  }
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+void check_handle(rsf_factor f) { RSF_CHECK(f != nullptr, RSF_E_INVALID, "null factor handle"); }
+
+void make_proxy_table(rsf_factor_s* h) {
+  const Options& o = h->opt;
+  const int per = o.n_prox / o.prox_rings;
+  std::vector<double> u(2 * (size_t)o.n_prox);
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int q = 0; q < o.prox_rings; ++q) {
+    const double rad = o.r_in + (o.r_out - o.r_in) * (q + 0.5) / o.prox_rings;
+    for (int j = 0; j < per; ++j) {
+      const double ang = two_pi * (j + (double)q / o.prox_rings) / per;
+      u[q * per + j] = rad * std::cos(ang);
+      u[o.n_prox + q * per + j] = rad * std::sin(ang);
+    }
+  }
+  h->prox_u = h->arena.make<double>(u.size());
+  RSF_HIP(hipMemcpy(h->prox_u, u.data(), u.size() * sizeof(double), hipMemcpyHostToDevice));
+}
+}  // namespace
+
+extern "C" {
+
+const char* rsf_last_error(void) { return g_last_error.c_str(); }
+
+rsf_status rsf_opts_default(rsf_opts* o) {
+  if (!o) return fail_with(RSF_E_INVALID, "opts is NULL");
+  o->n_prox = 256;
+  o->prox_rings = 4;
+  o->r_near = 1.8;
+  o->prox_r_in = 1.75;
+  o->prox_r_out = 2.45;
+  o->rq_alpha = 1.0;
+  o->mem_cap_bytes = 0;
+  return RSF_OK;
+}
+
+rsf_status rsf_factor_create(const double* d_points, int64_t n, const double* theta, int p, int kernel,
+                             double eps, int leaf, const rsf_opts* opts, void* stream, rsf_factor* out) {
+  rsf_factor_s* h = nullptr;
+  int rc = guarded([&] {
+    RSF_CHECK(out != nullptr && d_points != nullptr && theta != nullptr, RSF_E_INVALID, "null argument");
+    RSF_CHECK(p == 3, RSF_E_INVALID, "theta must hold 3 values (rho, sigma2, nugget)");
+    RSF_CHECK(n >= 1, RSF_E_INVALID, "n must be >= 1");
+    RSF_CHECK(leaf >= 1, RSF_E_INVALID, "leaf must be >= 1");
+    RSF_CHECK(kernel >= RSF_MATERN12 && kernel <= RSF_RQ, RSF_E_INVALID, "unknown kernel");
+    for (int i = 0; i < 3; ++i) RSF_CHECK(std::isfinite(theta[i]), RSF_E_NONFINITE, "non-finite theta");
+    RSF_CHECK(std::isfinite(eps), RSF_E_NONFINITE, "non-finite eps");
+    RSF_CHECK(eps > 0.0, RSF_E_INVALID, "eps must be > 0");
+    RSF_CHECK(theta[0] > 0.0, RSF_E_INVALID, "rho must be > 0");
+    RSF_CHECK(theta[1] > 0.0, RSF_E_INVALID, "sigma2 must be > 0");
+    rsf_opts o;
+    if (opts)
+      o = *opts;
+    else
+      rsf_opts_default(&o);
+    RSF_CHECK(o.n_prox >= 1 && o.prox_rings >= 1 && o.n_prox % o.prox_rings == 0, RSF_E_INVALID,
+              "n_prox must be a positive multiple of prox_rings");
+    RSF_CHECK(o.r_near > 0 && o.prox_r_in > 0 && o.prox_r_out >= o.prox_r_in && o.rq_alpha > 0, RSF_E_INVALID,
+              "bad proxy geometry or rq_alpha");
+    hipStream_t s = as_stream(stream);
+    std::vector<double> xy(2 * (size_t)n);
+    RSF_HIP(hipMemcpyAsync(xy.data(), d_points, xy.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    RSF_HIP(hipStreamSynchronize(s));
+    h = new rsf_factor_s();
+    h->opt.n_prox = o.n_prox;
+    h->opt.prox_rings = o.prox_rings;
+    h->opt.r_near = o.r_near;
+    h->opt.r_in = o.prox_r_in;
+    h->opt.r_out = o.prox_r_out;
+    h->opt.rq_alpha = o.rq_alpha;
+    h->opt.mem_cap = o.mem_cap_bytes;
+    h->arena.cap = o.mem_cap_bytes;
+    h->kernel = kernel;
+    h->eps = eps;
+    h->leaf = leaf;
+    for (int i = 0; i < 3; ++i) h->theta[i] = theta[i];
+    h->tree = build_tree(xy.data(), n, leaf);
+    std::vector<double> px(n), py(n);
+    for (int64_t t = 0; t < n; ++t) {
+      px[t] = xy[2 * (size_t)h->tree.perm[t]];
+      py[t] = xy[2 * (size_t)h->tree.perm[t] + 1];
+    }
+    h->px = h->arena.make<double>(n);
+    h->py = h->arena.make<double>(n);
+    h->perm = h->arena.make<int>(n);
+    RSF_HIP(hipMemcpy(h->px, px.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    RSF_HIP(hipMemcpy(h->py, py.data(), n * sizeof(double), hipMemcpyHostToDevice));
+    RSF_HIP(hipMemcpy(h->perm, h->tree.perm.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    make_proxy_table(h);
+    build_factor(h, h->F, 0, s);
+    RSF_HIP(hipStreamSynchronize(s));
+  });
+  if (rc != RSF_OK) {
+    delete h;
+    return rc;
+  }
+  *out = h;
+  return RSF_OK;
+}
+
+void rsf_factor_destroy(rsf_factor f) {
+  if (!f) return;
+  (void)hipDeviceSynchronize();
+  delete f;
+}
+
+rsf_status rsf_logdet(rsf_factor f, double* out) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(out != nullptr, RSF_E_INVALID, "null output");
+    *out = f->F.logdet;
+  });
+}
+
+static void check_block(rsf_factor f, const void* a, const void* b, int64_t nrhs, int64_t ld) {
+  check_handle(f);
+  RSF_CHECK(a != nullptr && b != nullptr, RSF_E_INVALID, "null vector");
+  RSF_CHECK(nrhs >= 0, RSF_E_INVALID, "nrhs must be >= 0");
+  RSF_CHECK(ld >= f->tree.n, RSF_E_INVALID, "ld must be >= n");
+  RSF_CHECK(nrhs < (int64_t(1) << 24), RSF_E_INVALID, "nrhs too large");
+}
+
+rsf_status rsf_solve(rsf_factor f, const double* d_b, double* d_x, int64_t nrhs, int64_t ld, void* stream) {
+  return guarded([&] {
+    check_block(f, d_b, d_x, nrhs, ld);
+    if (nrhs == 0) return;
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const int nc = (int)nrhs;
+    double* P = scr.make<double>((size_t)f->tree.n * nc);
+    to_panel(f, d_b, ld, P, nc, nc, s);
+    sweep_solve(f, f->F, P, nc, nc, scr, s);
+    from_panel(f, P, nc, nc, d_x, ld, s);
+  });
+}
+
+rsf_status rsf_apply(rsf_factor f, const double* d_x, double* d_y, int64_t nrhs, int64_t ld, void* stream) {
+  return guarded([&] {
+    check_block(f, d_x, d_y, nrhs, ld);
+    if (nrhs == 0) return;
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const int nc = (int)nrhs;
+    const size_t sz = (size_t)f->tree.n * nc;
+    double* P = scr.make<double>(sz);
+    double* Q = scr.make<double>(sz);
+    to_panel(f, d_x, ld, P, nc, nc, s);
+    sweep_sqrt_t(f, f->F, P, Q, nc, nc, scr, s);
+    sweep_sqrt(f, f->F, Q, P, nc, nc, scr, s);
+    from_panel(f, P, nc, nc, d_y, ld, s);
+  });
+}
+
+rsf_status rsf_apply_sqrt(rsf_factor f, const double* d_w, double* d_z, int64_t nrhs, int64_t ld,
+                          void* stream) {
+  return guarded([&] {
+    check_block(f, d_w, d_z, nrhs, ld);
+    if (nrhs == 0) return;
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const int nc = (int)nrhs;
+    const size_t sz = (size_t)f->tree.n * nc;
+    double* P = scr.make<double>(sz);
+    double* Q = scr.make<double>(sz);
+    to_panel(f, d_w, ld, P, nc, nc, s);
+    sweep_sqrt(f, f->F, P, Q, nc, nc, scr, s);
+    from_panel(f, Q, nc, nc, d_z, ld, s);
+  });
+}
+
+rsf_status rsf_loglik(rsf_factor f, const double* d_z, double* out, double* d_alpha_or_null, void* stream) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(d_z != nullptr && out != nullptr, RSF_E_INVALID, "null argument");
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const long long n = f->tree.n;
+    double* Z = scr.make<double>(n);
+    double* A = scr.make<double>(n);
+    double* dot = scr.make<double>(1);
+    to_panel(f, d_z, n, Z, 1, 1, s);
+    copy_dev(A, Z, n, s);
+    sweep_solve(f, f->F, A, 1, 1, scr, s);
+    device_dot(Z, A, n, dot, scr, s);
+    double zt = 0.0;
+    RSF_HIP(hipMemcpyAsync(&zt, dot, sizeof(double), hipMemcpyDeviceToHost, s));
+    RSF_HIP(hipStreamSynchronize(s));
+    if (d_alpha_or_null) from_panel(f, A, 1, 1, d_alpha_or_null, n, s);
+    const double log2pi = 1.8378770664093454835606594728112;
+    *out = -0.5 * zt - 0.5 * f->F.logdet - 0.5 * (double)n * log2pi;
+  });
+}
+
+rsf_status rsf_tree_export(rsf_factor f, int32_t* perm, rsf_tree_info* info) {
+  return guarded([&] {
+    check_handle(f);
+    if (perm) std::memcpy(perm, f->tree.perm.data(), f->tree.n * sizeof(int32_t));
+    if (info) {
+      info->n = f->tree.n;
+      info->depth = f->tree.maxdepth;
+      info->nbox = f->tree.nbox();
+      info->root_size = f->F.nroot;
+      info->factor_bytes = (int64_t)f->F.arena.bytes;
+    }
+  });
+}
+
+rsf_status rsf_skeleton_export(rsf_factor f, int level, int32_t* offsets, int32_t* idx, int32_t* nbox_out) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(level >= 1 && level <= f->tree.maxdepth, RSF_E_INVALID, "level out of range");
+    const LevelFactor& L = f->F.levels[level];
+    if (nbox_out) *nbox_out = L.nb;
+    if (offsets)
+      for (int i = 0; i <= L.nb; ++i) offsets[i] = (int32_t)L.s_off[i];
+    if (idx && L.total_s > 0) {
+      std::vector<int> tmp(L.total_s);
+      RSF_HIP(hipMemcpy(tmp.data(), L.S, L.total_s * sizeof(int), hipMemcpyDeviceToHost));
+      for (long long q = 0; q < L.total_s; ++q) idx[q] = f->tree.perm[tmp[q]];
+    }
+  });
+}
+
+rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
+                    rsf_grad_info* info, void* stream);
+
+}  // extern "C"

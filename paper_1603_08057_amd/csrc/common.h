@@ -1,0 +1,191 @@
+// Shared declarations of the rsfgp HIP library (internal).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rsfgp.h"
+
+namespace rsf {
+
+// ---------------------------------------------------------------- errors
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define RSF_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      throw ::rsf::Error(e_ == hipErrorOutOfMemory ? RSF_E_OOM : RSF_E_HIP,             \
+                         std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+#define RSF_CHECK(cond, code, msg)                     \
+  do {                                                 \
+    if (!(cond)) throw ::rsf::Error((code), (msg));    \
+  } while (0)
+
+// ---------------------------------------------------------------- device memory
+// A device allocation owned by a factor (freed in the destructor).  Every
+// allocation is accounted against the handle's memory cap.
+struct Arena {
+  std::vector<void*> blocks;
+  size_t bytes = 0;
+  size_t cap = 0;  // 0 = unlimited
+  void* alloc(size_t nbytes);
+  template <class T>
+  T* make(size_t count) {
+    return static_cast<T*>(alloc(count * sizeof(T)));
+  }
+  void release();
+  ~Arena() { release(); }
+};
+
+// Scratch allocations for one call; freed (after a stream sync) when the
+// object goes out of scope.
+struct Scratch {
+  std::vector<void*> blocks;
+  hipStream_t stream = nullptr;
+  size_t cap_left = 0;  // 0 = unlimited
+  explicit Scratch(hipStream_t s) : stream(s) {}
+  void* alloc(size_t nbytes);
+  template <class T>
+  T* make(size_t count) {
+    return static_cast<T*>(alloc(count * sizeof(T)));
+  }
+  ~Scratch();
+};
+
+template <class T>
+inline void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
+  if (!src.empty())
+    RSF_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
+// ---------------------------------------------------------------- batched GEMM
+// C(i, j) = alpha * sum_p A(i, p) B(p, j) + beta * C(i, j) for one problem.
+// Element (i, j) of an operand X lives at X.ptr[row(i) * rs + j * cs] where
+// row(i) = idx ? idx[i] : i.  Transposition is a swap of rs and cs (with the
+// index map moving along); gathers and scatters of vector-panel rows use idx.
+struct GemmDesc {
+  const double* A;
+  const double* B;
+  double* C;
+  const int* aidx;
+  const int* bidx;
+  const int* cidx;
+  long long ars, acs, brs, bcs, crs, ccs;
+  int M, N, K;
+  double alpha, beta;
+};
+
+struct Mat {
+  const double* p = nullptr;
+  long long rs = 0, cs = 0;
+  const int* idx = nullptr;
+};
+// column-major m x n with leading dimension ld
+inline Mat colmaj(const double* p, long long ld) { return Mat{p, 1, ld, nullptr}; }
+// transpose of a column-major matrix
+inline Mat colmajT(const double* p, long long ld) { return Mat{p, ld, 1, nullptr}; }
+// rows of a row-major panel (row = DOF, ld = panel width), optional row map
+inline Mat panel(const double* p, long long ld, const int* idx = nullptr) {
+  return Mat{p, ld, 1, idx};
+}
+
+inline GemmDesc gemm_desc(int M, int N, int K, double alpha, Mat A, Mat B, double beta, Mat C) {
+  GemmDesc d;
+  d.A = A.p;
+  d.B = B.p;
+  d.C = const_cast<double*>(C.p);
+  d.aidx = A.idx;
+  d.bidx = B.idx;
+  d.cidx = C.idx;
+  d.ars = A.rs;
+  d.acs = A.cs;
+  d.brs = B.rs;
+  d.bcs = B.cs;
+  d.crs = C.rs;
+  d.ccs = C.cs;
+  d.M = M;
+  d.N = N;
+  d.K = K;
+  d.alpha = alpha;
+  d.beta = beta;
+  return d;
+}
+
+// Launches one batched GEMM over all problems in `descs` (problems with an
+// empty output are skipped).  The descriptors are copied to the device.
+void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s);
+
+// Reproducible sum of n doubles (fixed reduction tree) into *out (device).
+void device_sum(const double* x, long long n, double* out, Scratch& scr, hipStream_t s);
+// out[0] = sum_i x[i] * y[i] (fixed reduction tree).
+void device_dot(const double* x, const double* y, long long n, double* out, Scratch& scr,
+                hipStream_t s);
+
+// ---------------------------------------------------------------- kernel functions
+enum { K_MATERN12 = 0, K_MATERN32 = 1, K_MATERN52 = 2, K_RQ = 3 };
+
+struct KernelParams {
+  int kernel;
+  double rho, sigma2, nugget, alpha;
+  int deriv;  // 0: Sigma entries, 1: d/drho entries
+};
+
+__device__ __forceinline__ double corr_dev(double s, int kernel, double alpha) {
+  if (kernel == K_MATERN12) return exp(-s);
+  if (kernel == K_MATERN32) {
+    double t = 1.7320508075688772 * s;
+    return (1.0 + t) * exp(-t);
+  }
+  if (kernel == K_MATERN52) {
+    double t = 2.23606797749979 * s;
+    return (1.0 + t + (5.0 / 3.0) * s * s) * exp(-t);
+  }
+  if (alpha == 1.0) return 1.0 / (1.0 + 0.5 * s * s);
+  return pow(1.0 + s * s / (2.0 * alpha), -alpha);
+}
+
+__device__ __forceinline__ double dcorr_drho_dev(double r, double rho, int kernel, double alpha) {
+  double s = r / rho;
+  if (kernel == K_MATERN12) return (r / (rho * rho)) * exp(-s);
+  if (kernel == K_MATERN32) return 3.0 * r * r / (rho * rho * rho) * exp(-1.7320508075688772 * s);
+  if (kernel == K_MATERN52)
+    return (5.0 * r * r / (3.0 * rho * rho * rho)) * (1.0 + 2.23606797749979 * s) *
+           exp(-2.23606797749979 * s);
+  if (alpha == 1.0) {
+    double b = 1.0 / (1.0 + 0.5 * s * s);
+    return (r * r / (rho * rho * rho)) * b * b;
+  }
+  return (r * r / (rho * rho * rho)) * pow(1.0 + s * s / (2.0 * alpha), -alpha - 1.0);
+}
+
+// Kernel entry between two distinct sites at distance components (dx, dy).
+__device__ __forceinline__ double kentry(double dx, double dy, const KernelParams& kp) {
+  double r = sqrt(dx * dx + dy * dy);
+  if (kp.deriv) return kp.sigma2 * dcorr_drho_dev(r, kp.rho, kp.kernel, kp.alpha);
+  return kp.sigma2 * corr_dev(r / kp.rho, kp.kernel, kp.alpha);
+}
+
+// Diagonal entry (same observation).
+__device__ __forceinline__ double kdiag(const KernelParams& kp) {
+  return kp.deriv ? 0.0 : kp.sigma2 + kp.nugget;
+}
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+constexpr int WG = 256;
+
+}  // namespace rsf

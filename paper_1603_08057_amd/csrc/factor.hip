@@ -1,0 +1,1049 @@
+// Recursive skeletonization factorization on the GPU (Sections 2.1 - 2.3):
+// per quadtree level, one launch set covers every box of that depth:
+//   near field (modified proxy trick, Section 2.3.1)  -> near_kernel
+//   compression matrix [Sigma(N, I); M(Gamma, I)]     -> kaux_kernel
+//   interpolative decomposition by pivoted QR         -> cpqr_* kernels
+//   block elimination (X_sr, X_rr = L L^T, W, X_ss)   -> assemble_kernel, schur_kernel
+// and the remaining DOFs of the root get a blocked dense Cholesky.
+#include <algorithm>
+#include <cmath>
+
+#include "rsf.h"
+
+namespace rsf {
+
+// ------------------------------------------------------------------ small helpers
+__global__ void fill_kernel(double* p, long long n, double v) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void fill_zero(double* p, long long n, hipStream_t s) {
+  if (n <= 0) return;
+  long long blocks = std::min<long long>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, n, 0.0);
+  RSF_HIP(hipGetLastError());
+}
+
+void copy_dev(double* dst, const double* src, long long n, hipStream_t s) {
+  if (n > 0) RSF_HIP(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+}
+
+// dst[t] = src ? src[t] : base + t
+struct CopySeg {
+  int* dst;
+  const int* src;
+  int base;
+  int count;
+};
+
+__global__ void copy_segs_kernel(const CopySeg* __restrict__ segs) {
+  const CopySeg g = segs[blockIdx.x];
+  for (int t = threadIdx.x; t < g.count; t += blockDim.x) g.dst[t] = g.src ? g.src[t] : g.base + t;
+}
+
+static void run_copy_segs(const std::vector<CopySeg>& segs, Scratch& scr, hipStream_t s) {
+  if (segs.empty()) return;
+  CopySeg* d = scr.make<CopySeg>(segs.size());
+  upload(d, segs, s);
+  hipLaunchKernelGGL(copy_segs_kernel, dim3((unsigned)segs.size()), dim3(256), 0, s, d);
+  RSF_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ near field
+// For box B: every active DOF outside B whose distance to B's centre is below
+// r_near * h.  Candidate groups (boxes of the same depth and shallower leaves
+// whose square meets the disc) come from the host; the kernel filters their
+// DOFs and compacts the survivors in order (wave ballots).
+struct NearJob {
+  double cx, cy, r2;
+  int owner;        // this box's group id (its own DOFs are excluded)
+  int cand0, cand1; // range into the candidate list
+  int* out;
+  int* cnt;
+};
+
+__global__ __launch_bounds__(256) void near_kernel(const NearJob* __restrict__ jobs,
+                                                    const int* __restrict__ cand,
+                                                    const long long* __restrict__ seg_off,
+                                                    const int* __restrict__ seg_len,
+                                                    const int* __restrict__ seg_owner,
+                                                    const int* __restrict__ dofs,
+                                                    const double* __restrict__ px,
+                                                    const double* __restrict__ py) {
+  __shared__ int wave_tot[4];
+  const NearJob J = jobs[blockIdx.x];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int base = 0;
+  for (int c = J.cand0; c < J.cand1; ++c) {
+    const int sg = cand[c];
+    if (seg_owner[sg] == J.owner) continue;
+    const long long off = seg_off[sg];
+    const int len = seg_len[sg];
+    for (int t0 = 0; t0 < len; t0 += 256) {
+      const int t = t0 + tid;
+      int dof = -1;
+      bool keep = false;
+      if (t < len) {
+        dof = dofs[off + t];
+        const double dx = px[dof] - J.cx, dy = py[dof] - J.cy;
+        keep = dx * dx + dy * dy < J.r2;
+      }
+      const unsigned long long m = __ballot(keep);
+      const int before = __popcll(m & ((1ull << lane) - 1ull));
+      if (lane == 0) wave_tot[wave] = __popcll(m);
+      __syncthreads();
+      int wofs = 0;
+      for (int w = 0; w < wave; ++w) wofs += wave_tot[w];
+      const int tot = wave_tot[0] + wave_tot[1] + wave_tot[2] + wave_tot[3];
+      if (keep) J.out[base + wofs + before] = dof;
+      base += tot;
+      __syncthreads();
+    }
+  }
+  if (tid == 0) *J.cnt = base;
+}
+
+// ------------------------------------------------------------------ compression matrix
+struct KauxJob {
+  double* A;
+  long long ld;
+  int a;
+  const int* act;
+  const int* near;
+  const int* ncnt;
+  double cx, cy, h;
+};
+
+__global__ __launch_bounds__(256) void kaux_kernel(const KauxJob* __restrict__ jobs, KernelParams kp,
+                                                    const double* __restrict__ px,
+                                                    const double* __restrict__ py,
+                                                    const double* __restrict__ pu, int nprox) {
+  const KauxJob J = jobs[blockIdx.x];
+  const int nc = *J.ncnt;
+  const long long m = nc + nprox;
+  const long long tot = m * J.a;
+  for (long long e = blockIdx.y * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.y) {
+    const int j = (int)(e / m), i = (int)(e - (long long)j * m);
+    const int q = J.act[j];
+    double xr, yr;
+    if (i < nc) {
+      const int p = J.near[i];
+      xr = px[p];
+      yr = py[p];
+    } else {
+      xr = J.cx + J.h * pu[i - nc];
+      yr = J.cy + J.h * pu[nprox + i - nc];
+    }
+    J.A[(long long)j * J.ld + i] = kentry(xr - px[q], yr - py[q], kp);
+  }
+}
+
+// ------------------------------------------------------------------ pivoted QR (ID)
+// Householder QR with column pivoting; the pivot is the column with the
+// largest residual norm (recomputed from the residual rows at every step,
+// ties to the lowest index); stop when that norm is <= eps * |R_11|.  After
+// the loop T = R_11^-1 R_12 overwrites R_12 in place.
+struct CpqrJob {
+  double* A;
+  long long ld;
+  int a;
+  const int* ncnt;
+  int* piv;
+  int* kout;
+  // multi-workgroup path only
+  double* norms;
+  double* v;
+  double* scal;  // [0] = v^T v, [1] = |R_11|
+  int* done;
+};
+
+struct ArgMax {
+  double v;
+  int i;
+};
+
+__device__ __forceinline__ bool better(double v1, int i1, double v2, int i2) {
+  return v1 > v2 || (v1 == v2 && i1 < i2);
+}
+
+// workgroup-wide argmax of norms[s .. a), lowest index among ties
+__device__ ArgMax wg_argmax(const double* norms, int s, int a, ArgMax* red) {
+  const int tid = threadIdx.x;
+  double bv = -1.0;
+  int bi = 0x7fffffff;
+  for (int j = s + tid; j < a; j += blockDim.x) {
+    const double v = norms[j];
+    if (better(v, j, bv, bi)) {
+      bv = v;
+      bi = j;
+    }
+  }
+  red[tid].v = bv;
+  red[tid].i = bi;
+  __syncthreads();
+  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
+    if (tid < w && better(red[tid + w].v, red[tid + w].i, red[tid].v, red[tid].i)) red[tid] = red[tid + w];
+    __syncthreads();
+  }
+  ArgMax r = red[0];
+  __syncthreads();
+  return r;
+}
+
+__device__ double wg_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  v = wave_sum(v);
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Swap columns s and p, build the Householder vector of column s into vbuf,
+// write alpha on the diagonal and zeros below.  Returns v^T v.
+__device__ double householder_step(double* A, long long ld, long long m, int s, int p, int* piv,
+                                   double* vbuf, double* red) {
+  const int tid = threadIdx.x;
+  if (p != s) {
+    for (long long i = tid; i < m; i += blockDim.x) {
+      const double t = A[(long long)s * ld + i];
+      A[(long long)s * ld + i] = A[(long long)p * ld + i];
+      A[(long long)p * ld + i] = t;
+    }
+    if (tid == 0) {
+      const int t = piv[s];
+      piv[s] = piv[p];
+      piv[p] = t;
+    }
+  }
+  __syncthreads();
+  double* col = A + (long long)s * ld;
+  double ss = 0.0;
+  for (long long i = s + tid; i < m; i += blockDim.x) {
+    const double x = col[i];
+    vbuf[i - s] = x;
+    ss += x * x;
+  }
+  const double sigma2 = wg_sum(ss, red);
+  const double sigma = sqrt(sigma2);
+  const double x0 = col[s];
+  const double alpha = x0 >= 0.0 ? -sigma : sigma;
+  const double v0 = x0 - alpha;
+  // v^T v = sigma^2 - x0^2 + v0^2 summed as in a direct dot product
+  double vv = 0.0;
+  for (long long i = s + 1 + tid; i < m; i += blockDim.x) vv += vbuf[i - s] * vbuf[i - s];
+  const double vtv = wg_sum(vv, red) + v0 * v0;
+  __syncthreads();
+  if (tid == 0) vbuf[0] = v0;
+  for (long long i = s + 1 + tid; i < m; i += blockDim.x) col[i] = 0.0;
+  if (tid == 0) col[s] = alpha;
+  __syncthreads();
+  return vtv;
+}
+
+// Apply the reflector to columns [j0, j1) (j > s), one wave per column, and
+// recompute each column's residual norm over rows s+1 .. m-1.
+__device__ void reflect_columns(double* A, long long ld, long long m, int s, int j0, int j1,
+                                const double* v, double vtv, double* norms) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = j0 + wave; j < j1; j += nw) {
+    double* col = A + (long long)j * ld;
+    double w = 0.0;
+    for (long long i = s + lane; i < m; i += 64) w += v[i - s] * col[i];
+    w = wave_sum(w);
+    const double f = vtv > 0.0 ? 2.0 * w / vtv : 0.0;
+    double sq = 0.0;
+    for (long long i = s + lane; i < m; i += 64) {
+      const double x = col[i] - f * v[i - s];
+      col[i] = x;
+      if (i > s) sq += x * x;
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) norms[j] = sqrt(sq);
+  }
+}
+
+// T = R_11^-1 R_12 in place (columns k .. a-1), one thread per column.
+__device__ void backsub_columns(double* A, long long ld, int k, int j0, int j1, int stride) {
+  for (int j = j0; j < j1; j += stride) {
+    double* col = A + (long long)j * ld;
+    for (int i = k - 1; i >= 0; --i) {
+      double x = col[i];
+      for (int l = i + 1; l < k; ++l) x -= A[(long long)l * ld + i] * col[l];
+      col[i] = x / A[(long long)i * ld + i];
+    }
+  }
+}
+
+constexpr int CPQR_MAXA = 512;
+constexpr int CPQR_MAXM = 4096;
+
+__global__ __launch_bounds__(256) void cpqr_box_kernel(const CpqrJob* __restrict__ jobs,
+                                                        double eps, int nprox) {
+  __shared__ double norms[CPQR_MAXA];
+  __shared__ double v[CPQR_MAXM];
+  __shared__ ArgMax red[256];
+  __shared__ double redd[8];
+  const CpqrJob J = jobs[blockIdx.x];
+  const int a = J.a;
+  const long long m = (long long)*J.ncnt + nprox;
+  const int mn = (int)std::min<long long>(m, a);
+  double* A = J.A;
+  for (int j = threadIdx.x; j < a; j += blockDim.x) J.piv[j] = j;
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int j = wave; j < a; j += 4) {
+      double sq = 0.0;
+      for (long long i = lane; i < m; i += 64) {
+        const double x = A[(long long)j * J.ld + i];
+        sq += x * x;
+      }
+      sq = wave_sum(sq);
+      if (lane == 0) norms[j] = sqrt(sq);
+    }
+  }
+  __syncthreads();
+  double r11 = 0.0;
+  int k = 0;
+  for (int s = 0; s < mn; ++s) {
+    const ArgMax am = wg_argmax(norms, s, a, red);
+    if (s == 0) r11 = am.v;
+    if (!(am.v > eps * r11) || am.v == 0.0) break;
+    if (threadIdx.x == 0 && am.i != s) norms[am.i] = norms[s];
+    const double vtv = householder_step(A, J.ld, m, s, am.i, J.piv, v, redd);
+    reflect_columns(A, J.ld, m, s, s + 1, a, v, vtv, norms);
+    __syncthreads();
+    k = s + 1;
+  }
+  __syncthreads();
+  backsub_columns(A, J.ld, k, k + (int)threadIdx.x, a, blockDim.x);
+  if (threadIdx.x == 0) *J.kout = k;
+}
+
+// Multi-workgroup path for large boxes: one launch per pivoting step.
+__global__ __launch_bounds__(256) void cpqr_big_init_kernel(const CpqrJob* __restrict__ jobs,
+                                                             int nprox) {
+  const CpqrJob J = jobs[blockIdx.x];
+  const long long m = (long long)*J.ncnt + nprox;
+  const int j0 = blockIdx.y * 16, j1 = std::min(J.a, j0 + 16);
+  if (blockIdx.y == 0 && threadIdx.x == 0) {
+    *J.done = 0;
+    *J.kout = 0;
+  }
+  for (int j = j0 + (int)threadIdx.x; j < j1; j += blockDim.x) J.piv[j] = j;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = j0 + wave; j < j1; j += 4) {
+    double sq = 0.0;
+    for (long long i = lane; i < m; i += 64) {
+      const double x = J.A[(long long)j * J.ld + i];
+      sq += x * x;
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) J.norms[j] = sqrt(sq);
+  }
+}
+
+__global__ __launch_bounds__(256) void cpqr_big_pivot_kernel(const CpqrJob* __restrict__ jobs,
+                                                              int s, double eps, int nprox,
+                                                              int* ndone) {
+  __shared__ ArgMax red[256];
+  __shared__ double redd[8];
+  const CpqrJob J = jobs[blockIdx.x];
+  if (*J.done) return;
+  const long long m = (long long)*J.ncnt + nprox;
+  const int mn = (int)std::min<long long>(m, J.a);
+  bool finish = s >= mn;
+  ArgMax am{0.0, 0};
+  if (!finish) {
+    am = wg_argmax(J.norms, s, J.a, red);
+    if (s == 0 && threadIdx.x == 0) J.scal[1] = am.v;
+    __syncthreads();
+    const double r11 = (s == 0) ? am.v : J.scal[1];
+    finish = !(am.v > eps * r11) || am.v == 0.0;
+  }
+  if (finish) {
+    if (threadIdx.x == 0) {
+      *J.kout = s;
+      *J.done = 1;
+      atomicAdd(ndone, 1);
+    }
+    return;
+  }
+  if (threadIdx.x == 0 && am.i != s) J.norms[am.i] = J.norms[s];
+  const double vtv = householder_step(J.A, J.ld, m, s, am.i, J.piv, J.v, redd);
+  if (threadIdx.x == 0) J.scal[0] = vtv;
+}
+
+constexpr int BIG_MAXM = 12288;
+
+__global__ __launch_bounds__(256) void cpqr_big_update_kernel(const CpqrJob* __restrict__ jobs,
+                                                               int s, int nprox) {
+  __shared__ double v[BIG_MAXM];
+  const CpqrJob J = jobs[blockIdx.x];
+  if (*J.done) return;
+  const int j0 = std::max(s + 1, (int)blockIdx.y * 16), j1 = std::min(J.a, (int)blockIdx.y * 16 + 16);
+  if (j0 >= j1) return;
+  const long long m = (long long)*J.ncnt + nprox;
+  for (long long i = s + threadIdx.x; i < m; i += blockDim.x) v[i - s] = J.v[i - s];
+  __syncthreads();
+  reflect_columns(J.A, J.ld, m, s, j0, j1, v, J.scal[0], J.norms);
+}
+
+__global__ __launch_bounds__(256) void cpqr_backsub_kernel(const CpqrJob* __restrict__ jobs) {
+  const CpqrJob J = jobs[blockIdx.x];
+  const int k = *J.kout;
+  const int j0 = k + blockIdx.y * 256 + threadIdx.x;
+  backsub_columns(J.A, J.ld, k, j0, J.a, 256 * gridDim.y);
+}
+
+// ------------------------------------------------------------------ elimination
+// Diagonal block of a box in pivot order.  Chol form at a parent: the
+// children's X_ss blocks on the diagonal, kernel entries between different
+// children; elsewhere kernel entries (the nugget on the diagonal).
+struct AsmJob {
+  double* A;  // a x a, ld a
+  int a;
+  const int* act;
+  const int* piv;       // nullptr = identity
+  int nchild;
+  int coff[5];          // child segments of the active list
+  const double* xss[4]; // child X_ss (k_c x k_c, ld k_c); nullptr = use kernel entries
+};
+
+__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, KernelParams kp,
+                                                        const double* __restrict__ px,
+                                                        const double* __restrict__ py) {
+  const AsmJob J = jobs[blockIdx.x];
+  const long long tot = (long long)J.a * J.a;
+  for (long long e = blockIdx.y * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.y) {
+    const int j = (int)(e / J.a), i = (int)(e - (long long)j * J.a);
+    const int u = J.piv ? J.piv[i] : i, w = J.piv ? J.piv[j] : j;
+    double val;
+    int cu = -1, cw = -1;
+    if (J.nchild > 0) {
+      for (int c = 0; c < J.nchild; ++c) {
+        if (u >= J.coff[c] && u < J.coff[c + 1]) cu = c;
+        if (w >= J.coff[c] && w < J.coff[c + 1]) cw = c;
+      }
+    }
+    if (cu >= 0 && cu == cw && J.xss[cu]) {
+      const int kc = J.coff[cu + 1] - J.coff[cu];
+      val = J.xss[cu][(long long)(w - J.coff[cu]) * kc + (u - J.coff[cu])];
+    } else {
+      const int p = J.act[u], q = J.act[w];
+      val = (p == q) ? kdiag(kp) : kentry(px[p] - px[q], py[p] - py[q], kp);
+    }
+    J.A[(long long)j * J.a + i] = val;
+  }
+}
+
+// Block elimination of one box (one workgroup), partition [S, R] of I:
+//   X_sr = A_sr - A_ss T,  X_rr = A_rr - T^T X_sr - A_rs T,
+//   chol form:  X_rr = L L^T, Linv = L^-1, W = X_sr L^-T, X_ss = A_ss - W W^T,
+//               logdet_b = 2 sum log L_jj;
+//   mult form:  keep X_sr and X_rr.
+struct SchurJob {
+  const double* A;    // a x a, ld a
+  const double* Tsrc; // T inside the compression matrix (rows 0..k-1, columns k..a-1)
+  long long ldts;
+  double* T;          // k x r
+  double* Xsr;        // k x r
+  double* L;          // r x r work (chol) / X_rr output (mult)
+  double* Linv;       // r x r (chol)
+  double* W;          // k x r (chol)
+  double* Xss;        // k x k (chol)
+  double* logdet;     // one value
+  int* fail;
+  int a, k;
+};
+
+__global__ __launch_bounds__(256) void schur_kernel(const SchurJob* __restrict__ jobs, int mult) {
+  __shared__ double redd[8];
+  const SchurJob J = jobs[blockIdx.x];
+  const int a = J.a, k = J.k, r = a - k, tid = threadIdx.x, nt = blockDim.x;
+  const double* A = J.A;
+#define AA(i, j) A[(long long)(j) * a + (i)]
+  for (long long e = tid; e < (long long)k * r; e += nt) {
+    const int p = (int)(e % k), j = (int)(e / k);
+    J.T[e] = J.Tsrc[(long long)(k + j) * J.ldts + p];
+  }
+  __syncthreads();
+  const double* T = J.T;
+  for (long long e = tid; e < (long long)k * r; e += nt) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    double x = AA(i, k + j);
+    for (int p = 0; p < k; ++p) x -= AA(i, p) * T[(long long)j * k + p];
+    J.Xsr[e] = x;
+  }
+  __syncthreads();
+  for (long long e = tid; e < (long long)r * r; e += nt) {
+    const int i = (int)(e % r), j = (int)(e / r);
+    if (!mult && i < j) {
+      J.L[e] = 0.0;
+      continue;
+    }
+    double x = AA(k + i, k + j);
+    for (int p = 0; p < k; ++p)
+      x -= T[(long long)i * k + p] * J.Xsr[(long long)j * k + p] + AA(k + i, p) * T[(long long)j * k + p];
+    J.L[e] = x;
+  }
+  __syncthreads();
+  if (mult) return;
+  double* L = J.L;
+  // right-looking Cholesky of the lower triangle
+  for (int j = 0; j < r; ++j) {
+    const double d = L[(long long)j * r + j];
+    if (!(d > 0.0)) {
+      if (tid == 0) *J.fail = 1;
+      return;
+    }
+    const double ljj = sqrt(d);
+    __syncthreads();
+    if (tid == 0) L[(long long)j * r + j] = ljj;
+    for (int i = j + 1 + tid; i < r; i += nt) L[(long long)j * r + i] /= ljj;
+    __syncthreads();
+    const long long rem = r - j - 1;
+    for (long long e = tid; e < rem * rem; e += nt) {
+      const int ii = j + 1 + (int)(e % rem), ll = j + 1 + (int)(e / rem);
+      if (ii >= ll) L[(long long)ll * r + ii] -= L[(long long)j * r + ii] * L[(long long)j * r + ll];
+    }
+    __syncthreads();
+  }
+  {
+    double ld = 0.0;
+    if (tid == 0)
+      for (int j = 0; j < r; ++j) ld += log(L[(long long)j * r + j]);
+    if (tid == 0) *J.logdet = 2.0 * ld;
+  }
+  // Linv = L^-1, one column per thread (forward substitution)
+  for (int c = tid; c < r; c += nt) {
+    double* col = J.Linv + (long long)c * r;
+    for (int i = 0; i < c; ++i) col[i] = 0.0;
+    col[c] = 1.0 / L[(long long)c * r + c];
+    for (int i = c + 1; i < r; ++i) {
+      double x = 0.0;
+      for (int l = c; l < i; ++l) x -= L[(long long)l * r + i] * col[l];
+      col[i] = x / L[(long long)i * r + i];
+    }
+  }
+  __syncthreads();
+  // W = X_sr L^-T:  W(i, j) = sum_{l <= j} X_sr(i, l) Linv(j, l)
+  for (long long e = tid; e < (long long)k * r; e += nt) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    double x = 0.0;
+    for (int l = 0; l <= j; ++l) x += J.Xsr[(long long)l * k + i] * J.Linv[(long long)l * r + j];
+    J.W[e] = x;
+  }
+  __syncthreads();
+  for (long long e = tid; e < (long long)k * k; e += nt) {
+    const int i = (int)(e % k), j = (int)(e / k);
+    double x = AA(i, j);
+    for (int l = 0; l < r; ++l) x -= J.W[(long long)l * k + i] * J.W[(long long)l * k + j];
+    J.Xss[e] = x;
+  }
+#undef AA
+}
+
+// S and R lists of each box from its active list and pivots.
+struct SplitJob {
+  const int* act;
+  const int* piv;
+  int* S;
+  int* R;
+  int a, k;
+};
+
+__global__ void split_kernel(const SplitJob* __restrict__ jobs) {
+  const SplitJob J = jobs[blockIdx.x];
+  for (int t = threadIdx.x; t < J.a; t += blockDim.x) {
+    const int d = J.act[J.piv[t]];
+    if (t < J.k)
+      J.S[t] = d;
+    else
+      J.R[t - J.k] = d;
+  }
+}
+
+// ------------------------------------------------------------------ root: blocked Cholesky
+// Diagonal block (nb <= 64) of L in place: Cholesky, log-diagonal, inverse.
+__global__ __launch_bounds__(256) void diag_chol_kernel(double* L, long long ld, int kb, int nb,
+                                                         double* Dinv, double* logd, int* fail) {
+  __shared__ double B[64][65];
+  __shared__ double I[64][65];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int i = e % nb, j = e / nb;
+    B[i][j] = L[(long long)(kb + j) * ld + kb + i];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = B[j][j];
+    if (!(d > 0.0)) {
+      if (tid == 0) *fail = 1;
+      return;
+    }
+    const double s = sqrt(d);
+    __syncthreads();
+    if (tid == 0) B[j][j] = s;
+    for (int i = j + 1 + tid; i < nb; i += 256) B[i][j] /= s;
+    __syncthreads();
+    for (int e = tid; e < nb * nb; e += 256) {
+      const int i = e % nb, l = e / nb;
+      if (l > j && i >= l) B[i][l] -= B[i][j] * B[l][j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    double s = 0.0;
+    for (int j = 0; j < nb; ++j) s += log(B[j][j]);
+    *logd = 2.0 * s;
+  }
+  for (int c = tid; c < nb; c += 256) {
+    for (int i = 0; i < nb; ++i) I[i][c] = 0.0;
+    I[c][c] = 1.0 / B[c][c];
+    for (int i = c + 1; i < nb; ++i) {
+      double x = 0.0;
+      for (int l = c; l < i; ++l) x -= B[i][l] * I[l][c];
+      I[i][c] = x / B[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int i = e % nb, j = e / nb;
+    L[(long long)(kb + j) * ld + kb + i] = (i >= j) ? B[i][j] : 0.0;
+    Dinv[(long long)j * 64 + i] = I[i][j];
+  }
+}
+
+__global__ void triu_zero_kernel(double* A, int N) {
+  for (int j = blockIdx.x; j < N; j += gridDim.x)
+    for (int i = threadIdx.x; i < j; i += blockDim.x) A[(long long)j * N + i] = 0.0;
+}
+
+// Cholesky (lower) of the N x N matrix L (ld N) in place and Linv = L^-1;
+// log-determinant partials per diagonal block into logd[N/64 + 1].
+static void blocked_chol_inv(double* L, int N, double* Linv, double* logd, int* fail, Scratch& scr,
+                             hipStream_t s) {
+  const int nbk = (N + 63) / 64;
+  double* Dinv = scr.make<double>((size_t)nbk * 64 * 64);
+  double* P = scr.make<double>((size_t)N * 64);
+  for (int b = 0; b < nbk; ++b) {
+    const int kb = b * 64, nb = std::min(64, N - kb), rest = N - kb - nb;
+    hipLaunchKernelGGL(diag_chol_kernel, dim3(1), dim3(256), 0, s, L, (long long)N, kb, nb,
+                       Dinv + (size_t)b * 4096, logd + b, fail);
+    RSF_HIP(hipGetLastError());
+    if (rest > 0) {
+      // panel P = L(kb+nb:, kb:kb+nb) Dinv^T, copied back into L
+      std::vector<GemmDesc> g{gemm_desc(rest, nb, nb, 1.0, colmaj(L + (long long)kb * N + kb + nb, N),
+                                        colmajT(Dinv + (size_t)b * 4096, 64), 0.0, colmaj(P, rest))};
+      gemm_batched(g, scr, s);
+      RSF_HIP(hipMemcpy2DAsync(L + (long long)kb * N + kb + nb, N * sizeof(double), P,
+                               rest * sizeof(double), rest * sizeof(double), nb,
+                               hipMemcpyDeviceToDevice, s));
+      // trailing update L(rest, rest) -= P P^T
+      std::vector<GemmDesc> t{gemm_desc(rest, rest, nb, -1.0, colmaj(P, rest), colmajT(P, rest), 1.0,
+                                        colmaj(L + (long long)(kb + nb) * N + kb + nb, N))};
+      gemm_batched(t, scr, s);
+    }
+  }
+  // zero the strict upper triangle of L is not needed; build Linv block row by block row:
+  // Linv(i, 0:i) = -Dinv_i L(i, 0:i) Linv(0:i, 0:i),  Linv(i, i) = Dinv_i
+  fill_zero(Linv, (long long)N * N, s);
+  double* Q = scr.make<double>((size_t)N * 64);
+  for (int b = 0; b < nbk; ++b) {
+    const int kb = b * 64, nb = std::min(64, N - kb);
+    RSF_HIP(hipMemcpy2DAsync(Linv + (long long)kb * N + kb, N * sizeof(double), Dinv + (size_t)b * 4096,
+                             64 * sizeof(double), nb * sizeof(double), nb, hipMemcpyDeviceToDevice, s));
+    if (kb == 0) continue;
+    // Q (nb x kb) = L(kb:kb+nb, 0:kb) Linv(0:kb, 0:kb)
+    std::vector<GemmDesc> g1{gemm_desc(nb, kb, kb, 1.0, colmaj(L + kb, N), colmaj(Linv, N), 0.0,
+                                       colmaj(Q, nb))};
+    gemm_batched(g1, scr, s);
+    std::vector<GemmDesc> g2{gemm_desc(nb, kb, nb, -1.0, colmaj(Dinv + (size_t)b * 4096, 64), colmaj(Q, nb),
+                                       0.0, colmaj(Linv + kb, N))};
+    gemm_batched(g2, scr, s);
+  }
+}
+
+// ------------------------------------------------------------------ host driver
+static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
+  const Tree& t = h->tree;
+  const Options& o = h->opt;
+  F.mult = mult;
+  F.kp.kernel = h->kernel;
+  F.kp.rho = h->theta[0];
+  F.kp.sigma2 = h->theta[1];
+  F.kp.nugget = h->theta[2];
+  F.kp.alpha = o.rq_alpha;
+  F.kp.deriv = mult;
+  F.arena.release();
+  F.arena.cap = o.mem_cap == 0 ? 0 : std::max<long long>(1, (long long)o.mem_cap - (long long)h->arena.bytes);
+  F.levels.assign(t.maxdepth + 1, LevelFactor());
+  F.logdet = 0.0;
+  const int D = t.maxdepth, nprox = o.n_prox;
+  Scratch keep(s);  // lives through the whole build: X_ss of the previous level
+  std::vector<double*> xss(t.nbox(), nullptr);
+  std::vector<int> kbox(t.nbox(), 0);
+  std::vector<const int*> sbox(t.nbox(), nullptr);
+  std::vector<double> ld_parts;
+  int* fail = keep.make<int>(1);
+  RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
+
+  for (int d = D; d >= 1; --d) {
+    Scratch scr(s);
+    LevelFactor& L = F.levels[d];
+    const int b0 = t.lev[d], b1 = t.lev[d + 1], nb = b1 - b0;
+    L.depth = d;
+    L.box0 = b0;
+    L.nb = nb;
+    L.a.assign(nb, 0);
+    L.k.assign(nb, 0);
+    std::vector<long long> aoff(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      const int b = b0 + i;
+      int a = 0;
+      if (t.leaf[b])
+        a = t.count[b];
+      else
+        for (int c : t.child[b])
+          if (c >= 0) a += kbox[c];
+      L.a[i] = a;
+      aoff[i + 1] = aoff[i] + a;
+    }
+    // DOF lists of the groups active at this level: the depth-d boxes, then
+    // the points of shallower leaves
+    std::vector<long long> seg_off;
+    std::vector<int> seg_len, seg_owner, seg_box;
+    long long tot = aoff[nb];
+    for (int i = 0; i < nb; ++i) {
+      seg_off.push_back(aoff[i]);
+      seg_len.push_back(L.a[i]);
+      seg_owner.push_back(b0 + i);
+      seg_box.push_back(b0 + i);
+    }
+    for (int b = 0; b < b0; ++b)
+      if (t.leaf[b]) {
+        seg_off.push_back(tot);
+        seg_len.push_back(t.count[b]);
+        seg_owner.push_back(b);
+        seg_box.push_back(b);
+        tot += t.count[b];
+      }
+    int* dofs = scr.make<int>(std::max<long long>(tot, 1));
+    std::vector<CopySeg> cs;
+    for (int i = 0; i < nb; ++i) {
+      const int b = b0 + i;
+      if (t.leaf[b]) {
+        cs.push_back({dofs + aoff[i], nullptr, t.begin[b], t.count[b]});
+      } else {
+        long long o2 = aoff[i];
+        for (int c : t.child[b])
+          if (c >= 0 && kbox[c] > 0) {
+            cs.push_back({dofs + o2, sbox[c], 0, kbox[c]});
+            o2 += kbox[c];
+          }
+      }
+    }
+    for (size_t g = nb; g < seg_off.size(); ++g)
+      cs.push_back({dofs + seg_off[g], nullptr, t.begin[seg_box[g]], seg_len[g]});
+    run_copy_segs(cs, scr, s);
+    const int* act = dofs;  // the first aoff[nb] entries
+
+    // candidate groups per box (geometry only)
+    std::vector<int> cand;
+    std::vector<NearJob> nj(nb);
+    std::vector<long long> mub(nb), kaoff(nb + 1, 0), noff(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      const int b = b0 + i;
+      const double R = o.r_near * t.half[b];
+      nj[i].cx = t.cx[b];
+      nj[i].cy = t.cy[b];
+      nj[i].r2 = R * R;
+      nj[i].owner = b;
+      nj[i].cand0 = (int)cand.size();
+      long long ub = 0;
+      for (size_t g = 0; g < seg_off.size(); ++g) {
+        const int gb = seg_box[g];
+        if (gb == b || seg_len[g] == 0) continue;
+        const double dx = std::max(std::fabs(t.cx[gb] - t.cx[b]) - t.half[gb], 0.0);
+        const double dy = std::max(std::fabs(t.cy[gb] - t.cy[b]) - t.half[gb], 0.0);
+        if (dx * dx + dy * dy < R * R * (1.0 + 1e-12) + 1e-300) {
+          cand.push_back((int)g);
+          ub += seg_len[g];
+        }
+      }
+      nj[i].cand1 = (int)cand.size();
+      noff[i + 1] = noff[i] + ub;
+      mub[i] = ub + nprox;
+      kaoff[i + 1] = kaoff[i] + mub[i] * L.a[i];
+    }
+    int* near = scr.make<int>(std::max<long long>(noff[nb], 1));
+    int* ncnt = scr.make<int>(nb);
+    for (int i = 0; i < nb; ++i) {
+      nj[i].out = near + noff[i];
+      nj[i].cnt = ncnt + i;
+    }
+    {
+      NearJob* dj = scr.make<NearJob>(nb);
+      int* dc = scr.make<int>(std::max<size_t>(cand.size(), 1));
+      long long* dso = scr.make<long long>(seg_off.size());
+      int* dsl = scr.make<int>(seg_len.size());
+      int* dsw = scr.make<int>(seg_owner.size());
+      upload(dj, nj, s);
+      upload(dc, cand, s);
+      upload(dso, seg_off, s);
+      upload(dsl, seg_len, s);
+      upload(dsw, seg_owner, s);
+      hipLaunchKernelGGL(near_kernel, dim3(nb), dim3(256), 0, s, dj, dc, dso, dsl, dsw, dofs, h->px, h->py);
+      RSF_HIP(hipGetLastError());
+    }
+    // compression matrices
+    double* Kaux = scr.make<double>(std::max<long long>(kaoff[nb], 1));
+    {
+      std::vector<KauxJob> kj(nb);
+      for (int i = 0; i < nb; ++i) {
+        const int b = b0 + i;
+        kj[i] = KauxJob{Kaux + kaoff[i], mub[i], L.a[i], act + aoff[i], near + noff[i], ncnt + i,
+                        t.cx[b], t.cy[b], t.half[b]};
+      }
+      KauxJob* dk = scr.make<KauxJob>(nb);
+      upload(dk, kj, s);
+      long long maxe = 0;
+      for (int i = 0; i < nb; ++i) maxe = std::max(maxe, mub[i] * L.a[i]);
+      const int gy = std::max(1, std::min(64, ceil_div(maxe, 256 * 8)));
+      hipLaunchKernelGGL(kaux_kernel, dim3(nb, gy), dim3(256), 0, s, dk, F.kp, h->px, h->py, h->prox_u, nprox);
+      RSF_HIP(hipGetLastError());
+    }
+    // interpolative decompositions
+    int* piv = scr.make<int>(std::max<long long>(aoff[nb], 1));
+    int* kout = scr.make<int>(nb);
+    {
+      int maxa = 0;
+      long long maxm = 0;
+      for (int i = 0; i < nb; ++i) {
+        maxa = std::max(maxa, L.a[i]);
+        maxm = std::max(maxm, mub[i]);
+      }
+      std::vector<CpqrJob> cj(nb);
+      const bool big = (maxa > CPQR_MAXA || maxm > CPQR_MAXM || nb < 128);
+      double* norms = big ? scr.make<double>(std::max<long long>(aoff[nb], 1)) : nullptr;
+      double* vb = big ? scr.make<double>(std::max<long long>(noff[nb] + (long long)nb * nprox, 1)) : nullptr;
+      double* scal = big ? scr.make<double>(2 * nb) : nullptr;
+      int* done = big ? scr.make<int>(nb + 1) : nullptr;
+      for (int i = 0; i < nb; ++i) {
+        cj[i] = CpqrJob{Kaux + kaoff[i], mub[i], L.a[i], ncnt + i, piv + aoff[i], kout + i,
+                        big ? norms + aoff[i] : nullptr, big ? vb + noff[i] + (long long)i * nprox : nullptr,
+                        big ? scal + 2 * i : nullptr, big ? done + i : nullptr};
+      }
+      CpqrJob* dj = scr.make<CpqrJob>(nb);
+      upload(dj, cj, s);
+      if (!big) {
+        hipLaunchKernelGGL(cpqr_box_kernel, dim3(nb), dim3(256), 0, s, dj, h->eps, nprox);
+        RSF_HIP(hipGetLastError());
+      } else {
+        RSF_CHECK(maxm <= BIG_MAXM, RSF_E_INVALID,
+                  "compression matrix too tall (" + std::to_string(maxm) + " rows)");
+        int* ndone = done + nb;
+        RSF_HIP(hipMemsetAsync(ndone, 0, sizeof(int), s));
+        const int chunks = std::max(1, ceil_div(maxa, 16));
+        hipLaunchKernelGGL(cpqr_big_init_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, nprox);
+        RSF_HIP(hipGetLastError());
+        long long steps = 0;
+        for (int i = 0; i < nb; ++i) steps = std::max<long long>(steps, std::min<long long>(mub[i], L.a[i]));
+        for (int st = 0; st <= steps; ++st) {
+          hipLaunchKernelGGL(cpqr_big_pivot_kernel, dim3(nb), dim3(256), 0, s, dj, st, h->eps, nprox, ndone);
+          RSF_HIP(hipGetLastError());
+          if (st == steps) break;
+          hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, st, nprox);
+          RSF_HIP(hipGetLastError());
+          if ((st & 15) == 15) {
+            int nd = 0;
+            RSF_HIP(hipMemcpyAsync(&nd, ndone, sizeof(int), hipMemcpyDeviceToHost, s));
+            RSF_HIP(hipStreamSynchronize(s));
+            if (nd >= nb) break;
+          }
+        }
+        const int bchunks = std::max(1, std::min(16, ceil_div(maxa, 256)));
+        hipLaunchKernelGGL(cpqr_backsub_kernel, dim3(nb, bchunks), dim3(256), 0, s, dj);
+        RSF_HIP(hipGetLastError());
+      }
+    }
+    std::vector<int> kh(nb);
+    RSF_HIP(hipMemcpyAsync(kh.data(), kout, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+    int fh = 0;
+    RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    RSF_HIP(hipStreamSynchronize(s));
+    RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "redundant block not positive definite at depth " + std::to_string(d + 1));
+    // factor storage
+    L.k = kh;
+    L.s_off.assign(nb + 1, 0);
+    L.r_off.assign(nb + 1, 0);
+    L.t_off.assign(nb + 1, 0);
+    L.l_off.assign(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      const long long k = kh[i], r = L.a[i] - kh[i];
+      RSF_CHECK(k >= 0 && r >= 0, RSF_E_HIP, "bad rank from the ID kernel");
+      L.s_off[i + 1] = L.s_off[i] + k;
+      L.r_off[i + 1] = L.r_off[i] + r;
+      L.t_off[i + 1] = L.t_off[i] + k * r;
+      L.l_off[i + 1] = L.l_off[i] + r * r;
+      L.max_k = std::max<int>(L.max_k, (int)k);
+      L.max_r = std::max<int>(L.max_r, (int)r);
+    }
+    L.total_s = L.s_off[nb];
+    L.total_r = L.r_off[nb];
+    L.total_t = L.t_off[nb];
+    L.total_l = L.l_off[nb];
+    L.S = F.arena.make<int>(std::max<long long>(L.total_s, 1));
+    L.R = F.arena.make<int>(std::max<long long>(L.total_r, 1));
+    L.T = F.arena.make<double>(std::max<long long>(L.total_t, 1));
+    L.W = F.arena.make<double>(std::max<long long>(L.total_t, 1));
+    L.Lm = F.arena.make<double>(std::max<long long>(L.total_l, 1));
+    {
+      std::vector<SplitJob> sj(nb);
+      for (int i = 0; i < nb; ++i)
+        sj[i] = SplitJob{act + aoff[i], piv + aoff[i], L.S + L.s_off[i], L.R + L.r_off[i], L.a[i], kh[i]};
+      SplitJob* dj = scr.make<SplitJob>(nb);
+      upload(dj, sj, s);
+      hipLaunchKernelGGL(split_kernel, dim3(nb), dim3(256), 0, s, dj);
+      RSF_HIP(hipGetLastError());
+    }
+    // diagonal blocks and elimination
+    std::vector<long long> a2off(nb + 1, 0), k2off(nb + 1, 0);
+    for (int i = 0; i < nb; ++i) {
+      a2off[i + 1] = a2off[i] + (long long)L.a[i] * L.a[i];
+      k2off[i + 1] = k2off[i] + (long long)kh[i] * kh[i];
+    }
+    double* Ablk = scr.make<double>(std::max<long long>(a2off[nb], 1));
+    {
+      std::vector<AsmJob> aj(nb);
+      long long maxe = 1;
+      for (int i = 0; i < nb; ++i) {
+        const int b = b0 + i;
+        AsmJob& J = aj[i];
+        J.A = Ablk + a2off[i];
+        J.a = L.a[i];
+        J.act = act + aoff[i];
+        J.piv = piv + aoff[i];
+        J.nchild = 0;
+        J.coff[0] = 0;
+        if (!t.leaf[b]) {
+          for (int c : t.child[b])
+            if (c >= 0) {
+              J.xss[J.nchild] = mult ? nullptr : xss[c];
+              J.coff[J.nchild + 1] = J.coff[J.nchild] + kbox[c];
+              J.nchild++;
+            }
+        }
+        maxe = std::max(maxe, (long long)J.a * J.a);
+      }
+      AsmJob* dj = scr.make<AsmJob>(nb);
+      upload(dj, aj, s);
+      const int gy = std::max(1, std::min(64, ceil_div(maxe, 256 * 8)));
+      hipLaunchKernelGGL(assemble_kernel, dim3(nb, gy), dim3(256), 0, s, dj, F.kp, h->px, h->py);
+      RSF_HIP(hipGetLastError());
+    }
+    double* Xsr = mult ? L.W : scr.make<double>(std::max<long long>(L.total_t, 1));
+    if (!mult) L.Lf = F.arena.make<double>(std::max<long long>(L.total_l, 1));
+    double* Lw = mult ? L.Lm : L.Lf;
+    double* Xss = mult ? nullptr : keep.make<double>(std::max<long long>(k2off[nb], 1));
+    double* ldp = scr.make<double>(nb);
+    fill_zero(ldp, nb, s);
+    {
+      std::vector<SchurJob> sj(nb);
+      for (int i = 0; i < nb; ++i) {
+        sj[i] = SchurJob{Ablk + a2off[i], Kaux + kaoff[i], mub[i], L.T + L.t_off[i], Xsr + L.t_off[i],
+                         Lw + L.l_off[i], mult ? nullptr : L.Lm + L.l_off[i], mult ? nullptr : L.W + L.t_off[i],
+                         mult ? nullptr : Xss + k2off[i], ldp + i, fail, L.a[i], kh[i]};
+      }
+      SchurJob* dj = scr.make<SchurJob>(nb);
+      upload(dj, sj, s);
+      hipLaunchKernelGGL(schur_kernel, dim3(nb), dim3(256), 0, s, dj, mult);
+      RSF_HIP(hipGetLastError());
+    }
+    if (!mult) {
+      std::vector<double> lh(nb);
+      RSF_HIP(hipMemcpyAsync(lh.data(), ldp, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+      RSF_HIP(hipStreamSynchronize(s));
+      for (double v : lh) ld_parts.push_back(v);
+    }
+    for (int i = 0; i < nb; ++i) {
+      const int b = b0 + i;
+      kbox[b] = kh[i];
+      sbox[b] = L.S + L.s_off[i];
+      xss[b] = mult ? nullptr : Xss + k2off[i];
+    }
+  }
+  // root: the remaining DOFs of the top box
+  {
+    Scratch scr(s);
+    std::vector<CopySeg> cs;
+    int N = 0;
+    AsmJob J{};
+    J.nchild = 0;
+    J.coff[0] = 0;
+    std::vector<int> segk;
+    if (D == 0) N = t.count[0];
+    else
+      for (int c : t.child[0])
+        if (c >= 0) N += kbox[c];
+    F.nroot = N;
+    F.root_idx = F.arena.make<int>(std::max(N, 1));
+    if (D == 0) {
+      cs.push_back({F.root_idx, nullptr, 0, N});
+    } else {
+      int o2 = 0;
+      for (int c : t.child[0])
+        if (c >= 0) {
+          if (kbox[c] > 0) cs.push_back({F.root_idx + o2, sbox[c], 0, kbox[c]});
+          J.xss[J.nchild] = mult ? nullptr : xss[c];
+          J.coff[J.nchild + 1] = J.coff[J.nchild] + kbox[c];
+          J.nchild++;
+          o2 += kbox[c];
+        }
+    }
+    run_copy_segs(cs, scr, s);
+    if (N > 0) {
+      double* A = F.arena.make<double>((size_t)N * N);
+      if (mult) F.Aroot = A;
+      else F.Lroot = A;
+      J.A = A;
+      J.a = N;
+      J.act = F.root_idx;
+      J.piv = nullptr;
+      AsmJob* dj = scr.make<AsmJob>(1);
+      upload(dj, std::vector<AsmJob>{J}, s);
+      const int gy = std::max(1, std::min(1024, ceil_div((long long)N * N, 256 * 8)));
+      hipLaunchKernelGGL(assemble_kernel, dim3(1, gy), dim3(256), 0, s, dj, F.kp, h->px, h->py);
+      RSF_HIP(hipGetLastError());
+      if (!mult) {
+        F.Lroot_inv = F.arena.make<double>((size_t)N * N);
+        const int nbk = (N + 63) / 64;
+        double* logd = scr.make<double>(nbk);
+        blocked_chol_inv(A, N, F.Lroot_inv, logd, fail, scr, s);
+        std::vector<double> lh(nbk);
+        int fh = 0;
+        RSF_HIP(hipMemcpyAsync(lh.data(), logd, nbk * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipStreamSynchronize(s));
+        RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "covariance factor lost positive definiteness (root or a redundant block)");
+        hipLaunchKernelGGL(triu_zero_kernel, dim3(std::min(N, 4096)), dim3(256), 0, s, A, N);
+        RSF_HIP(hipGetLastError());
+        for (double v : lh) ld_parts.push_back(v);
+      }
+    }
+  }
+  if (!mult) {
+    double sum = 0.0;
+    for (double v : ld_parts) sum += v;
+    F.logdet = sum;
+  }
+}
+
+}  // namespace rsf

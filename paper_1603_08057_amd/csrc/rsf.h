@@ -1,0 +1,124 @@
+// Internal state of a factor handle: the quadtree (host), the per-level
+// skeletonization factors (device) and the operations on them.
+#pragma once
+#include <array>
+#include <memory>
+
+#include "common.h"
+
+namespace rsf {
+
+// Quadtree over the observation sites (Section 2.1).  Box ids are breadth
+// first, so the boxes of one depth form the id range [lev[d], lev[d + 1]).
+// Every box covers the contiguous tree-order range [begin, begin + count).
+struct Tree {
+  int64_t n = 0;
+  std::vector<double> cx, cy, half;
+  std::vector<int> depth, parent, quad, begin, count;
+  std::vector<std::array<int, 4>> child;
+  std::vector<char> leaf;
+  std::vector<int> lev;   // size maxdepth + 2
+  std::vector<int> perm;  // perm[t] = caller index of tree position t
+  int maxdepth = 0;
+  int nbox() const { return (int)cx.size(); }
+};
+
+// Builds the tree (root = square on the bounding-box midpoint, split while a
+// box holds more than `leaf` points, x >= cx east, y >= cy north, children
+// NW, NE, SW, SE, stable partition).  Throws on duplicate sites.
+Tree build_tree(const double* xy_host, int64_t n, int leaf);
+
+// Factors of the boxes of one depth.  Per box b (local index within the level):
+// k skeleton DOFs S, r = a - k redundant DOFs R (tree-order DOF ids, pivot
+// order), and dense blocks, all column-major:
+//   T (k x r)       interpolation matrix of the ID,
+//   chol mode:  Linv (r x r) = L^-1 with X_rr = L L^T,  W (k x r) = X_sr L^-T,
+//   mult mode:  Xsr (k x r), Xrr (r x r).
+struct LevelFactor {
+  int depth = 0, box0 = 0, nb = 0;
+  std::vector<int> a, k;
+  std::vector<long long> s_off, r_off;     // offsets into S / R (ints)
+  std::vector<long long> t_off, l_off;     // offsets into T/W/Xsr and Linv/Xrr (doubles)
+  int* S = nullptr;
+  int* R = nullptr;
+  double* T = nullptr;
+  double* W = nullptr;     // chol: W; mult: Xsr
+  double* Lm = nullptr;    // chol: Linv; mult: Xrr
+  double* Lf = nullptr;    // chol: L (Cholesky factor of X_rr, lower)
+  long long total_s = 0, total_r = 0, total_t = 0, total_l = 0;
+  int max_k = 0, max_r = 0;
+};
+
+struct FactorData {
+  int mult = 0;             // 0: Schur/Cholesky form of Sigma; 1: multiply-only form
+  KernelParams kp{};
+  std::vector<LevelFactor> levels;  // index = depth (0 unused)
+  int nroot = 0;
+  int* root_idx = nullptr;
+  double* Lroot_inv = nullptr;  // chol: inverse Cholesky factor of the root block (lower)
+  double* Lroot = nullptr;      // chol: Cholesky factor of the root block (lower)
+  double* Aroot = nullptr;      // mult: the root block
+  double logdet = 0.0;
+  Arena arena;
+};
+
+struct Options {
+  int n_prox = 256, prox_rings = 4;
+  double r_near = 1.8, r_in = 1.75, r_out = 2.45, rq_alpha = 1.0;
+  size_t mem_cap = 0;
+};
+
+}  // namespace rsf
+
+struct rsf_factor_s {
+  rsf::Tree tree;
+  rsf::Options opt;
+  int kernel = 0;
+  double eps = 0.0;
+  int leaf = 0;
+  double theta[3] = {0, 0, 0};
+  double* px = nullptr;  // device, tree order
+  double* py = nullptr;
+  int* perm = nullptr;   // device copy of tree.perm
+  rsf::Arena arena;      // points, permutation, proxy table
+  double* prox_u = nullptr;  // device unit offsets of the proxy points (x then y)
+  rsf::FactorData F;
+  std::unique_ptr<rsf::FactorData> Frho;
+};
+
+namespace rsf {
+
+// Builds one factorization over h's tree (Sections 2.1-2.3).
+void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s);
+
+// Sweeps over vector panels in tree order, row-major n x nc with leading
+// dimension ld (row = DOF).  X is overwritten.
+void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld,
+                 Scratch& scr, hipStream_t s);
+void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, double* V, int nc,
+                long long ld, Scratch& scr, hipStream_t s);
+void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double* Out, int nc,
+                  long long ld, Scratch& scr, hipStream_t s);
+void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, double* Y, int nc,
+                      long long ld, Scratch& scr, hipStream_t s);
+
+// user order column-major (ld) <-> tree order row-major panel (ldp)
+void to_panel(const rsf_factor_s* h, const double* src, long long ld, double* P, int nc,
+              long long ldp, hipStream_t s);
+void from_panel(const rsf_factor_s* h, const double* P, int nc, long long ldp, double* dst,
+                long long ld, hipStream_t s);
+
+// Peeled traces of F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1) (Section 3.2).
+struct PeelStats {
+  int levels = 0;
+  int cols[32] = {0};
+  int rank[32] = {0};
+  int leaf_cols = 0;
+};
+void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv,
+                 double* tr_rho, PeelStats* st, hipStream_t s);
+
+void fill_zero(double* p, long long n, hipStream_t s);
+void copy_dev(double* dst, const double* src, long long n, hipStream_t s);
+
+}  // namespace rsf

@@ -1,0 +1,106 @@
+// Quadtree over the observation sites (Section 2.1 of the paper; adaptive as
+// in the remark on the tree).  Host code: the tree is pure geometry, built once
+// per point set and shared by every factorization and sweep on it.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "rsf.h"
+
+namespace rsf {
+
+Tree build_tree(const double* xy, int64_t n, int leaf) {
+  RSF_CHECK(n >= 1, RSF_E_INVALID, "n must be >= 1");
+  RSF_CHECK(leaf >= 1, RSF_E_INVALID, "leaf must be >= 1");
+  RSF_CHECK(n < (int64_t(1) << 31), RSF_E_INVALID, "n must fit in 31 bits");
+  double xmin = xy[0], xmax = xy[0], ymin = xy[1], ymax = xy[1];
+  for (int64_t i = 0; i < n; ++i) {
+    const double x = xy[2 * i], y = xy[2 * i + 1];
+    RSF_CHECK(std::isfinite(x) && std::isfinite(y), RSF_E_NONFINITE,
+              "non-finite coordinate at point " + std::to_string(i));
+    xmin = std::min(xmin, x);
+    xmax = std::max(xmax, x);
+    ymin = std::min(ymin, y);
+    ymax = std::max(ymax, y);
+  }
+  {  // the nugget is a delta on observation indices: sites must be unique
+    std::vector<int64_t> o(n);
+    std::iota(o.begin(), o.end(), 0);
+    std::sort(o.begin(), o.end(), [&](int64_t a, int64_t b) {
+      return xy[2 * a] < xy[2 * b] || (xy[2 * a] == xy[2 * b] && xy[2 * a + 1] < xy[2 * b + 1]);
+    });
+    for (int64_t i = 1; i < n; ++i)
+      RSF_CHECK(!(xy[2 * o[i]] == xy[2 * o[i - 1]] && xy[2 * o[i] + 1] == xy[2 * o[i - 1] + 1]),
+                RSF_E_DUPLICATE,
+                "duplicate observation site (points " + std::to_string(o[i - 1]) + " and " +
+                    std::to_string(o[i]) + ")");
+  }
+  Tree t;
+  t.n = n;
+  double h = std::max(xmax - xmin, ymax - ymin) / 2.0;
+  if (!(h > 0.0)) h = 0.5;
+  t.cx.push_back((xmin + xmax) / 2.0);
+  t.cy.push_back((ymin + ymax) / 2.0);
+  t.half.push_back(h);
+  t.depth.push_back(0);
+  t.parent.push_back(-1);
+  t.quad.push_back(-1);
+  t.begin.push_back(0);
+  t.count.push_back((int)n);
+  t.child.push_back({-1, -1, -1, -1});
+  t.perm.assign(n, 0);
+  const int max_depth = 40;
+  std::vector<std::pair<int, std::vector<int>>> frontier;
+  {
+    std::vector<int> all(n);
+    std::iota(all.begin(), all.end(), 0);
+    frontier.emplace_back(0, std::move(all));
+  }
+  while (!frontier.empty()) {
+    std::vector<std::pair<int, std::vector<int>>> next;
+    for (auto& fb : frontier) {
+      const int b = fb.first;
+      std::vector<int>& idx = fb.second;
+      if ((int)idx.size() > leaf && t.depth[b] < max_depth) {
+        std::vector<int> q[4];
+        const double cx = t.cx[b], cy = t.cy[b];
+        for (int i : idx) {
+          const bool east = xy[2 * (int64_t)i] >= cx, north = xy[2 * (int64_t)i + 1] >= cy;
+          q[north ? (east ? 1 : 0) : (east ? 3 : 2)].push_back(i);
+        }
+        int off = t.begin[b];
+        const double hh = t.half[b] / 2.0;
+        for (int c = 0; c < 4; ++c) {
+          if (q[c].empty()) continue;
+          const int id = (int)t.cx.size();
+          t.cx.push_back((c == 1 || c == 3) ? cx + hh : cx - hh);
+          t.cy.push_back((c == 0 || c == 1) ? cy + hh : cy - hh);
+          t.half.push_back(hh);
+          t.depth.push_back(t.depth[b] + 1);
+          t.parent.push_back(b);
+          t.quad.push_back(c);
+          t.begin.push_back(off);
+          t.count.push_back((int)q[c].size());
+          t.child.push_back({-1, -1, -1, -1});
+          t.child[b][c] = id;
+          off += (int)q[c].size();
+          next.emplace_back(id, std::move(q[c]));
+        }
+      } else {
+        std::copy(idx.begin(), idx.end(), t.perm.begin() + t.begin[b]);
+      }
+    }
+    frontier.swap(next);
+  }
+  const int nb = t.nbox();
+  t.leaf.assign(nb, 0);
+  for (int b = 0; b < nb; ++b)
+    t.leaf[b] = (t.child[b][0] < 0 && t.child[b][1] < 0 && t.child[b][2] < 0 && t.child[b][3] < 0);
+  t.maxdepth = *std::max_element(t.depth.begin(), t.depth.end());
+  t.lev.assign(t.maxdepth + 2, 0);
+  for (int b = 0; b < nb; ++b) t.lev[t.depth[b] + 1] = b + 1;  // ids are sorted by depth
+  for (int d = 1; d <= t.maxdepth + 1; ++d) t.lev[d] = std::max(t.lev[d], t.lev[d - 1]);
+  return t;
+}
+
+}  // namespace rsf
