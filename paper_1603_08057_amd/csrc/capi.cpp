@@ -256,6 +256,8 @@ rsf_status rsf_skeleton_export(rsf_factor f, int level, int32_t* offsets, int32_
 }
 
 rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
-                    rsf_grad_info* info, void* stream);
+                    rsf_grad_info* info, void* stream) {
+  return guarded([&] { grad_eval(f, d_z, eps_peel, seed, g, info, stream); });
+}
 
 }  // extern "C"

@@ -1,8 +1,735 @@
-// Score equations (eq. gradient; Algorithm 1) on top of the factorizations.
+// Score equations (eq. gradient; Algorithm 1) on top of the factorizations,
+// with the traces taken by matrix peeling for weakly admissible operators
+// (Section 3.2):
+//   per quadtree level, Gaussian probes restricted to the boxes of one
+//   quadrant, one multi-column product with the operator (the sweeps), the
+//   coarser levels' low-rank blocks subtracted, and a randomized low-rank
+//   approximation (eq. lowrankapprox) of every sibling block; at the leaves the
+//   diagonal blocks are extracted and their traces summed (Section 3.2.4).
+// The operators F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1) are peeled together from
+// the same probes and share their products with F^-1.
+#include <chrono>
+#include <cmath>
+
 #include "rsf.h"
 
-extern "C" rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
-                               rsf_grad_info* info, void* stream) {
-  (void)f; (void)d_z; (void)eps_peel; (void)seed; (void)g; (void)info; (void)stream;
-  return RSF_E_INVALID;
+namespace rsf {
+
+// ------------------------------------------------------------------ Philox4x32-10
+// Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2, 3"
+// (SC'11): ten rounds of two 32-bit multiply-hi/lo mixes with a Weyl key
+// schedule.  Counter (dof, column, level, stream), key = the 64-bit seed.
+__device__ __forceinline__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
 }
+
+// Standard normal by Box-Muller from two 53-bit uniforms in (0, 1).
+__device__ __forceinline__ double probe_normal(uint32_t d, uint32_t j, uint32_t level, uint32_t stream,
+                                               uint64_t seed) {
+  uint32_t c[4] = {d, j, level, stream};
+  philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+  const uint64_t a = (((uint64_t)c[0] << 32) | c[1]) >> 11;
+  const uint64_t b = (((uint64_t)c[2] << 32) | c[3]) >> 11;
+  const double u1 = ((double)a + 0.5) * 0x1.0p-53;
+  const double u2 = ((double)b + 0.5) * 0x1.0p-53;
+  return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+// W[d, q(d) * nc + t] = Om[d, j0 + t] = N(d, j0 + t, level) for the DOFs of the
+// depth-`level` boxes (qd[d] = quadrant, -1 elsewhere).  W is zero elsewhere.
+__global__ void probe_kernel(const int* __restrict__ qd, long long n, int nc, int j0, int level, uint64_t seed,
+                             double* __restrict__ W, double* __restrict__ Om, long long ldo) {
+  const long long tot = n * nc;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const long long d = e / nc;
+    const int t = (int)(e - d * nc);
+    const int q = qd[d];
+    if (q < 0) continue;
+    const double v = probe_normal((uint32_t)d, (uint32_t)(j0 + t), (uint32_t)level, 0u, seed);
+    W[d * 4LL * nc + (long long)q * nc + t] = v;
+    Om[d * ldo + j0 + t] = v;
+  }
+}
+
+// Y[d, q * C + j0 + t] = B[d, q * nc + t] for the rows of the depth-`level` boxes.
+__global__ void store_samples_kernel(const int* __restrict__ qd, long long n, int nc, int j0, int C,
+                                     const double* __restrict__ B, double* __restrict__ Y) {
+  const long long tot = n * 4LL * nc;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const long long d = e / (4LL * nc);
+    const int c = (int)(e - d * 4LL * nc);
+    if (qd[d] < 0) continue;
+    const int q = c / nc, t = c - q * nc;
+    Y[d * 4LL * C + (long long)q * C + j0 + t] = B[e];
+  }
+}
+
+// dst[d, q * Cd + t] = src[d, q * Cs + t] for t < cols, q < nq
+__global__ void regrid_kernel(long long n, int nq, int cols, const double* __restrict__ src, int Cs,
+                              double* __restrict__ dst, int Cd) {
+  const long long tot = n * nq * (long long)cols;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const long long d = e / ((long long)nq * cols);
+    const int c = (int)(e - d * nq * (long long)cols);
+    const int q = c / cols, t = c - q * cols;
+    dst[d * (long long)nq * Cd + (long long)q * Cd + t] = src[d * (long long)nq * Cs + (long long)q * Cs + t];
+  }
+}
+
+__global__ void axpby_kernel(long long n, double a, const double* __restrict__ x, double b,
+                             const double* __restrict__ y, double* __restrict__ out) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) out[i] = a * x[i] + b * y[i];
+}
+
+__global__ void eye_blocks_kernel(const int* __restrict__ lbeg, const int* __restrict__ lcnt, int nleaf,
+                                  double* __restrict__ E, int nL) {
+  const int b = blockIdx.x;
+  if (b >= nleaf) return;
+  for (int t = threadIdx.x; t < lcnt[b]; t += blockDim.x) E[(long long)(lbeg[b] + t) * nL + t] = 1.0;
+}
+
+// sum over leaves b and t < count_b of H[begin_b + t, t], in a fixed order
+__global__ __launch_bounds__(256) void leaf_trace_kernel(const int* __restrict__ lbeg, const int* __restrict__ lcnt,
+                                                          int nleaf, const double* __restrict__ H, int nL,
+                                                          double* out) {
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int b = threadIdx.x; b < nleaf; b += 256) {
+    double s = 0.0;
+    for (int t = 0; t < lcnt[b]; ++t) s += H[(long long)(lbeg[b] + t) * nL + t];
+    acc += s;
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = part[0];
+}
+
+// ------------------------------------------------------------------ small dense factorizations
+// All run one workgroup per matrix on column-major blocks in global memory.
+__device__ bool wg_chol_lower(double* A, long long lda, int n) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  for (int j = 0; j < n; ++j) {
+    const double d = A[(long long)j * lda + j];
+    if (!(d > 0.0)) return false;
+    const double ljj = sqrt(d);
+    __syncthreads();
+    if (tid == 0) A[(long long)j * lda + j] = ljj;
+    for (int i = j + 1 + tid; i < n; i += nt) A[(long long)j * lda + i] /= ljj;
+    __syncthreads();
+    const long long rem = n - j - 1;
+    for (long long e = tid; e < rem * rem; e += nt) {
+      const int ii = j + 1 + (int)(e % rem), ll = j + 1 + (int)(e / rem);
+      if (ii >= ll) A[(long long)ll * lda + ii] -= A[(long long)j * lda + ii] * A[(long long)j * lda + ll];
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
+__device__ void wg_tri_inv_lower(const double* L, long long ldl, double* Li, long long ldi, int n) {
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    double* col = Li + (long long)c * ldi;
+    for (int i = 0; i < c; ++i) col[i] = 0.0;
+    col[c] = 1.0 / L[(long long)c * ldl + c];
+    for (int i = c + 1; i < n; ++i) {
+      double x = 0.0;
+      for (int l = c; l < i; ++l) x -= L[(long long)l * ldl + i] * col[l];
+      col[i] = x / L[(long long)i * ldl + i];
+    }
+  }
+  __syncthreads();
+}
+
+// Pivoted Cholesky of the Gram matrix G = Y^T Y: the same pivots and rank as
+// column-pivoted QR of Y in exact arithmetic (residual diagonal = squared
+// residual column norm); stops when the largest residual diagonal is
+// <= tol^2 times the first pivot's.  Writes the rank, the pivots, and
+// Linv = (leading k x k lower factor)^-1.
+struct PcholJob {
+  double* G;
+  int n;
+  int* piv;
+  int* kout;
+  double* Linv;  // ldi = n
+};
+
+__global__ __launch_bounds__(256) void pchol_kernel(const PcholJob* __restrict__ jobs, double tol2) {
+  __shared__ double red_v[256];
+  __shared__ int red_i[256];
+  const PcholJob J = jobs[blockIdx.x];
+  const int n = J.n, tid = threadIdx.x, nt = blockDim.x;
+  double* G = J.G;
+  for (int j = tid; j < n; j += nt) J.piv[j] = j;
+  __syncthreads();
+  double d1 = 0.0;
+  int k = 0;
+  for (int s = 0; s < n; ++s) {
+    double bv = -1.0;
+    int bi = 0x7fffffff;
+    for (int j = s + tid; j < n; j += nt) {
+      const double v = G[(long long)j * n + j];
+      if (v > bv || (v == bv && j < bi)) {
+        bv = v;
+        bi = j;
+      }
+    }
+    red_v[tid] = bv;
+    red_i[tid] = bi;
+    __syncthreads();
+    for (int w = nt / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        const double v2 = red_v[tid + w];
+        const int i2 = red_i[tid + w];
+        if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) {
+          red_v[tid] = v2;
+          red_i[tid] = i2;
+        }
+      }
+      __syncthreads();
+    }
+    const double dp = red_v[0];
+    const int p = red_i[0];
+    __syncthreads();
+    if (s == 0) d1 = dp;
+    if (!(dp > tol2 * d1) || !(dp > 0.0)) break;
+    if (p != s) {
+      // symmetric swap of rows / columns s and p in the lower triangle, kept as a full matrix
+      for (int i = tid; i < n; i += nt) {
+        const double t = G[(long long)s * n + i];
+        G[(long long)s * n + i] = G[(long long)p * n + i];
+        G[(long long)p * n + i] = t;
+      }
+      __syncthreads();
+      for (int j = tid; j < n; j += nt) {
+        const double t = G[(long long)j * n + s];
+        G[(long long)j * n + s] = G[(long long)j * n + p];
+        G[(long long)j * n + p] = t;
+      }
+      if (tid == 0) {
+        const int t = J.piv[s];
+        J.piv[s] = J.piv[p];
+        J.piv[p] = t;
+      }
+      __syncthreads();
+    }
+    const double lss = sqrt(G[(long long)s * n + s]);
+    __syncthreads();
+    for (int i = s + 1 + tid; i < n; i += nt) G[(long long)s * n + i] /= lss;
+    if (tid == 0) G[(long long)s * n + s] = lss;
+    __syncthreads();
+    // trailing update of the full symmetric remainder
+    const long long rem = n - s - 1;
+    for (long long e = tid; e < rem * rem; e += nt) {
+      const int ii = s + 1 + (int)(e % rem), jj = s + 1 + (int)(e / rem);
+      G[(long long)jj * n + ii] -= G[(long long)s * n + ii] * G[(long long)s * n + jj];
+    }
+    __syncthreads();
+    k = s + 1;
+  }
+  __syncthreads();
+  wg_tri_inv_lower(G, n, J.Linv, n, k);
+  if (tid == 0) *J.kout = k;
+}
+
+// Cholesky + inverse of SPD matrices (normal equations of the core matrix).
+struct CholJob {
+  double* A;
+  int n;
+  double* Linv;
+  int* fail;
+};
+
+__global__ __launch_bounds__(256) void chol_inv_kernel(const CholJob* __restrict__ jobs) {
+  const CholJob J = jobs[blockIdx.x];
+  if (J.n == 0) return;
+  if (!wg_chol_lower(J.A, J.n, J.n)) {
+    if (threadIdx.x == 0) *J.fail = 1;
+    return;
+  }
+  wg_tri_inv_lower(J.A, J.n, J.Linv, J.n, J.n);
+}
+
+// ------------------------------------------------------------------ host side
+static unsigned grid_of(long long tot) {
+  return (unsigned)std::max<long long>(1, std::min<long long>((tot + 255) / 256, 8192));
+}
+
+namespace {
+
+constexpr int OVERSAMPLE = 10;
+constexpr int FIRST_COLS = 64;
+constexpr int MIN_COLS = 24;
+
+int next_cols(int prev_rank) {
+  int c = (3 * prev_rank + 3) / 4 + OVERSAMPLE;
+  c = std::max(MIN_COLS, c);
+  return (c + 7) / 8 * 8;
+}
+
+struct PairLR {
+  int i, j;     // box ids (i before j in sibling order)
+  int k1 = 0, k2 = 0;
+  double* M = nullptr;  // k1 x k2, column-major
+};
+
+// Low-rank blocks of one level for one operator.
+struct LevelLR {
+  bool any = false;
+  std::vector<int> boxes;                // boxes of this level that are in some pair
+  std::vector<int> K;                    // per box: total basis columns
+  std::vector<double*> U;                // per box: count_b x K_b, column-major
+  std::vector<std::vector<int>> koff;    // per box: offset of the basis for each pair entry
+  std::vector<PairLR> pairs;
+  // per pair: position of the pair's bases inside U_i and U_j
+  std::vector<int> off_i, off_j, pos_i, pos_j;
+};
+
+struct Peeler {
+  const rsf_factor_s* h;
+  const Tree& t;
+  hipStream_t s;
+  Arena store;  // low-rank blocks of every level
+  std::vector<LevelLR> lr[2];
+  Peeler(const rsf_factor_s* hh, hipStream_t ss) : h(hh), t(hh->tree), s(ss) {}
+
+  // out_op = G_op X for both operators (X row-major n x nc); X is preserved.
+  void apply_ops(const double* X, int nc, double* out0, double* out1, Scratch& scr) {
+    const long long n = t.n, sz = n * nc;
+    double* A = scr.make<double>(sz);
+    double* V = scr.make<double>(sz);
+    double* Z = scr.make<double>(sz);
+    copy_dev(out0, X, sz, s);
+    sweep_solve(h, h->F, out0, nc, nc, scr, s);  // F^-1 X
+    copy_dev(A, X, sz, s);
+    sweep_apply_mult(h, *h->Frho, A, V, nc, nc, scr, s);  // F_rho X
+    sweep_solve(h, h->F, V, nc, nc, scr, s);               // F^-1 F_rho X
+    copy_dev(A, out0, sz, s);
+    sweep_apply_mult(h, *h->Frho, A, Z, nc, nc, scr, s);  // F_rho F^-1 X
+    hipLaunchKernelGGL(axpby_kernel, dim3(grid_of(sz)), dim3(256), 0, s, sz, 0.5, V, 0.5, Z, out1);
+    RSF_HIP(hipGetLastError());
+  }
+
+  // out -= sum_{m < upto} G^(m) X  for operator op
+  void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr) {
+    for (int m = 1; m < upto && m < (int)lr[op].size(); ++m) {
+      const LevelLR& L = lr[op][m];
+      if (!L.any) continue;
+      const int nbx = (int)L.boxes.size();
+      std::vector<long long> poff(nbx + 1, 0);
+      for (int b = 0; b < nbx; ++b) poff[b + 1] = poff[b] + (long long)L.K[b] * nc;
+      double* P = scr.make<double>(std::max<long long>(poff[nbx], 1));
+      double* Q = scr.make<double>(std::max<long long>(poff[nbx], 1));
+      // a pair with one empty basis contributes nothing: its Q segment stays zero
+      fill_zero(Q, poff[nbx], s);
+      std::vector<GemmDesc> g1;
+      for (int b = 0; b < nbx; ++b) {
+        const int box = L.boxes[b];
+        g1.push_back(gemm_desc(L.K[b], nc, t.count[box], 1.0, colmajT(L.U[b], t.count[box]),
+                               panel(X + (long long)t.begin[box] * nc, nc), 0.0, panel(P + poff[b], nc)));
+      }
+      gemm_batched(g1, scr, s);
+      std::vector<GemmDesc> g2;
+      for (size_t p = 0; p < L.pairs.size(); ++p) {
+        const PairLR& pr = L.pairs[p];
+        if (pr.k1 == 0 || pr.k2 == 0) continue;
+        // Q_i[seg(i, j)] = M P_j[seg(j, i)],  Q_j[seg(j, i)] = M^T P_i[seg(i, j)]
+        g2.push_back(gemm_desc(pr.k1, nc, pr.k2, 1.0, colmaj(pr.M, pr.k1),
+                               panel(P + poff[L.pos_j[p]] + (long long)L.off_j[p] * nc, nc), 0.0,
+                               panel(Q + poff[L.pos_i[p]] + (long long)L.off_i[p] * nc, nc)));
+        g2.push_back(gemm_desc(pr.k2, nc, pr.k1, 1.0, colmajT(pr.M, pr.k1),
+                               panel(P + poff[L.pos_i[p]] + (long long)L.off_i[p] * nc, nc), 0.0,
+                               panel(Q + poff[L.pos_j[p]] + (long long)L.off_j[p] * nc, nc)));
+      }
+      gemm_batched(g2, scr, s);
+      std::vector<GemmDesc> g3;
+      for (int b = 0; b < nbx; ++b) {
+        const int box = L.boxes[b];
+        g3.push_back(gemm_desc(t.count[box], nc, L.K[b], -1.0, colmaj(L.U[b], t.count[box]), panel(Q + poff[b], nc),
+                               1.0, panel(out + (long long)t.begin[box] * nc, nc)));
+      }
+      gemm_batched(g3, scr, s);
+    }
+  }
+
+  void run(double eps_peel, uint64_t seed, double* tr_inv, double* tr_rho, PeelStats* st) {
+    const long long n = t.n;
+    const int D = t.maxdepth;
+    for (int op = 0; op < 2; ++op) lr[op].assign(D + 1, LevelLR());
+    int prev = -1;
+    std::vector<int> qd(n);
+    for (int lev = 1; lev <= D; ++lev) {
+      Scratch scr(s);
+      const int b0 = t.lev[lev], b1 = t.lev[lev + 1];
+      std::vector<std::pair<int, int>> pairs;
+      for (int p = t.lev[lev - 1]; p < t.lev[lev]; ++p) {
+        std::vector<int> ks;
+        for (int c : t.child[p])
+          if (c >= 0) ks.push_back(c);
+        for (size_t a = 0; a < ks.size(); ++a)
+          for (size_t b = a + 1; b < ks.size(); ++b) pairs.emplace_back(ks[a], ks[b]);
+      }
+      if (pairs.empty()) continue;
+      std::fill(qd.begin(), qd.end(), -1);
+      for (int b = b0; b < b1; ++b)
+        for (int u = 0; u < t.count[b]; ++u) qd[t.begin[b] + u] = t.quad[b];
+      int* dqd = scr.make<int>(n);
+      upload(dqd, qd, s);
+      int c = prev < 0 ? FIRST_COLS : next_cols(prev);
+      int total = 0, Ccap = 0;
+      double* Om = nullptr;
+      double* Y[2] = {nullptr, nullptr};
+      // per ordered sample block: (row box, column quadrant box)
+      std::vector<std::pair<int, int>> blocks;
+      for (auto& pr : pairs) {
+        blocks.emplace_back(pr.first, pr.second);
+        blocks.emplace_back(pr.second, pr.first);
+      }
+      const int nblk = (int)blocks.size();
+      std::vector<int> rk(2 * nblk);
+      int* dk = nullptr;
+      int* dpiv = nullptr;
+      double* Gram = nullptr;
+      double* Ginv = nullptr;
+      std::vector<long long> goff;
+      int maxrank = 0;
+      while (true) {
+        const int newc = c - total;
+        // grow the probe and sample stores to c columns per quadrant block
+        {
+          double* Om2 = scr.make<double>((size_t)n * c);
+          double* Y2[2] = {scr.make<double>((size_t)n * 4 * c), scr.make<double>((size_t)n * 4 * c)};
+          if (total > 0) {
+            hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * total)), dim3(256), 0, s, n, 1, total, Om, Ccap, Om2, c);
+            for (int op = 0; op < 2; ++op)
+              hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * 4 * total)), dim3(256), 0, s, n, 4, total, Y[op], Ccap,
+                                 Y2[op], c);
+            RSF_HIP(hipGetLastError());
+          }
+          Om = Om2;
+          Y[0] = Y2[0];
+          Y[1] = Y2[1];
+          Ccap = c;
+        }
+        {
+          Scratch rs(s);
+          const long long sz = n * 4LL * newc;
+          double* Wm = rs.make<double>(sz);
+          fill_zero(Wm, sz, s);
+          hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * newc)), dim3(256), 0, s, dqd, n, newc, total, lev, seed,
+                             Wm, Om, (long long)c);
+          RSF_HIP(hipGetLastError());
+          double* B0 = rs.make<double>(sz);
+          double* B1 = rs.make<double>(sz);
+          apply_ops(Wm, 4 * newc, B0, B1, rs);
+          subtract_lowrank(0, lev, Wm, 4 * newc, B0, rs);
+          subtract_lowrank(1, lev, Wm, 4 * newc, B1, rs);
+          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, newc, total, c, B0, Y[0]);
+          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, newc, total, c, B1, Y[1]);
+          RSF_HIP(hipGetLastError());
+        }
+        total = c;
+        // ranks of every sample block by pivoted Cholesky of its Gram matrix
+        goff.assign(2 * nblk + 1, 0);
+        for (int e = 0; e < 2 * nblk; ++e) goff[e + 1] = goff[e] + (long long)total * total;
+        Gram = scr.make<double>(goff[2 * nblk]);
+        Ginv = scr.make<double>(goff[2 * nblk]);
+        dk = scr.make<int>(2 * nblk);
+        dpiv = scr.make<int>((size_t)2 * nblk * total);
+        std::vector<GemmDesc> g;
+        std::vector<PcholJob> pj;
+        for (int op = 0; op < 2; ++op)
+          for (int e = 0; e < nblk; ++e) {
+            const int rb = blocks[e].first, cbx = blocks[e].second;
+            const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * total + (long long)t.quad[cbx] * total;
+            const int idx = op * nblk + e;
+            g.push_back(gemm_desc(total, total, t.count[rb], 1.0, Mat{Yb, 1, 4LL * total, nullptr},
+                                  panel(Yb, 4LL * total), 0.0, colmaj(Gram + goff[idx], total)));
+            pj.push_back(PcholJob{Gram + goff[idx], total, dpiv + (long long)idx * total, dk + idx, Ginv + goff[idx]});
+          }
+        gemm_batched(g, scr, s);
+        PcholJob* dj = scr.make<PcholJob>(pj.size());
+        upload(dj, pj, s);
+        hipLaunchKernelGGL(pchol_kernel, dim3((unsigned)pj.size()), dim3(256), 0, s, dj, eps_peel * eps_peel);
+        RSF_HIP(hipGetLastError());
+        RSF_HIP(hipMemcpyAsync(rk.data(), dk, rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipStreamSynchronize(s));
+        bool need = false;
+        maxrank = 0;
+        for (int op = 0; op < 2; ++op)
+          for (int e = 0; e < nblk; ++e) {
+            const int k = rk[op * nblk + e];
+            maxrank = std::max(maxrank, k);
+            if (k + OVERSAMPLE > total && total < t.count[blocks[e].second]) need = true;
+          }
+        if (!need) break;
+        c = 2 * total;
+      }
+      prev = maxrank;
+      if (st && lev < 32) {
+        st->cols[lev] = total;
+        st->rank[lev] = maxrank;
+      }
+      // bases U = Y(:, piv[:k]) Linv^T, stored per box as [U_(b, sibling) ...]
+      for (int op = 0; op < 2; ++op) {
+        LevelLR& L = lr[op][lev];
+        L.any = true;
+        std::vector<int> pos(t.nbox(), -1);
+        for (auto& pr : pairs)
+          for (int bx : {pr.first, pr.second})
+            if (pos[bx] < 0) {
+              pos[bx] = (int)L.boxes.size();
+              L.boxes.push_back(bx);
+            }
+        const int nbx = (int)L.boxes.size();
+        L.K.assign(nbx, 0);
+        std::vector<int> blk_off(nblk);
+        for (int e = 0; e < nblk; ++e) {
+          const int b = pos[blocks[e].first];
+          blk_off[e] = L.K[b];
+          L.K[b] += rk[op * nblk + e];
+        }
+        L.U.assign(nbx, nullptr);
+        for (int b = 0; b < nbx; ++b)
+          L.U[b] = store.make<double>(std::max<long long>((long long)t.count[L.boxes[b]] * L.K[b], 1));
+        std::vector<GemmDesc> g;
+        for (int e = 0; e < nblk; ++e) {
+          const int k = rk[op * nblk + e];
+          if (k == 0) continue;
+          const int rb = blocks[e].first, cbx = blocks[e].second;
+          const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * total + (long long)t.quad[cbx] * total;
+          const int idx = op * nblk + e;
+          const int cnt = t.count[rb];
+          // U^T (k x cnt) = Linv (k x k) * Y(:, piv)^T
+          g.push_back(gemm_desc(k, cnt, k, 1.0, colmaj(Ginv + goff[idx], total),
+                                Mat{Yb, 1, 4LL * total, dpiv + (long long)idx * total}, 0.0,
+                                Mat{L.U[pos[rb]] + (long long)blk_off[e] * cnt, cnt, 1, nullptr}));
+        }
+        gemm_batched(g, scr, s);
+        // core matrices M = (Om_i^T U1)^+ (Om_i^T Y_ij) (U2^T Om_j)^+ per unordered pair
+        const int np = (int)pairs.size();
+        std::vector<long long> a1o(np + 1, 0), a2o(np + 1, 0), co(np + 1, 0), n1o(np + 1, 0), n2o(np + 1, 0),
+            po(np + 1, 0);
+        for (int p = 0; p < np; ++p) {
+          const int k1 = rk[op * nblk + 2 * p], k2 = rk[op * nblk + 2 * p + 1];
+          a1o[p + 1] = a1o[p] + (long long)total * k1;
+          a2o[p + 1] = a2o[p] + (long long)k2 * total;
+          co[p + 1] = co[p] + (long long)total * total;
+          n1o[p + 1] = n1o[p] + (long long)k1 * k1;
+          n2o[p + 1] = n2o[p] + (long long)k2 * k2;
+          po[p + 1] = po[p] + (long long)k1 * std::max(k2, total);
+        }
+        Scratch ms(s);
+        double* A1 = ms.make<double>(std::max<long long>(a1o[np], 1));
+        double* A2 = ms.make<double>(std::max<long long>(a2o[np], 1));
+        double* Cm = ms.make<double>(std::max<long long>(co[np], 1));
+        double* N1 = ms.make<double>(std::max<long long>(n1o[np], 1));
+        double* N2 = ms.make<double>(std::max<long long>(n2o[np], 1));
+        double* N1i = ms.make<double>(std::max<long long>(n1o[np], 1));
+        double* N2i = ms.make<double>(std::max<long long>(n2o[np], 1));
+        double* T1 = ms.make<double>(std::max<long long>(po[np], 1));
+        double* T2 = ms.make<double>(std::max<long long>(po[np], 1));
+        int* fail = ms.make<int>(1);
+        RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
+        L.pairs.resize(np);
+        L.off_i.resize(np);
+        L.off_j.resize(np);
+        L.pos_i.resize(np);
+        L.pos_j.resize(np);
+        std::vector<GemmDesc> ga, gb, gc, gd, ge, gf;
+        std::vector<CholJob> cj;
+        for (int p = 0; p < np; ++p) {
+          const int bi = pairs[p].first, bj = pairs[p].second;
+          const int k1 = rk[op * nblk + 2 * p], k2 = rk[op * nblk + 2 * p + 1];
+          PairLR& pr = L.pairs[p];
+          pr.i = bi;
+          pr.j = bj;
+          pr.k1 = k1;
+          pr.k2 = k2;
+          L.off_i[p] = blk_off[2 * p];
+          L.off_j[p] = blk_off[2 * p + 1];
+          L.pos_i[p] = pos[bi];
+          L.pos_j[p] = pos[bj];
+          if (k1 == 0 || k2 == 0) continue;
+          pr.M = store.make<double>((size_t)k1 * k2);
+          const int ci = t.count[bi], cjn = t.count[bj];
+          const double* U1 = L.U[pos[bi]] + (long long)blk_off[2 * p] * ci;
+          const double* U2 = L.U[pos[bj]] + (long long)blk_off[2 * p + 1] * cjn;
+          const Mat OmiT{Om + (long long)t.begin[bi] * total, 1, (long long)total, nullptr};
+          const Mat Omj = panel(Om + (long long)t.begin[bj] * total, total);
+          const double* Yij = Y[op] + (long long)t.begin[bi] * 4 * total + (long long)t.quad[bj] * total;
+          ga.push_back(gemm_desc(total, k1, ci, 1.0, OmiT, colmaj(U1, ci), 0.0, colmaj(A1 + a1o[p], total)));
+          ga.push_back(gemm_desc(total, total, ci, 1.0, OmiT, panel(Yij, 4LL * total), 0.0, colmaj(Cm + co[p], total)));
+          ga.push_back(gemm_desc(k2, total, cjn, 1.0, colmajT(U2, cjn), Omj, 0.0, colmaj(A2 + a2o[p], k2)));
+          gb.push_back(gemm_desc(k1, k1, total, 1.0, colmajT(A1 + a1o[p], total), colmaj(A1 + a1o[p], total), 0.0,
+                                 colmaj(N1 + n1o[p], k1)));
+          gb.push_back(gemm_desc(k2, k2, total, 1.0, colmaj(A2 + a2o[p], k2), colmajT(A2 + a2o[p], k2), 0.0,
+                                 colmaj(N2 + n2o[p], k2)));
+          // T1 = A1^T C (k1 x total); T2 = T1 A2^T (k1 x k2)
+          gb.push_back(gemm_desc(k1, total, total, 1.0, colmajT(A1 + a1o[p], total), colmaj(Cm + co[p], total), 0.0,
+                                 colmaj(T1 + po[p], k1)));
+          cj.push_back(CholJob{N1 + n1o[p], k1, N1i + n1o[p], fail});
+          cj.push_back(CholJob{N2 + n2o[p], k2, N2i + n2o[p], fail});
+          gc.push_back(gemm_desc(k1, k2, total, 1.0, colmaj(T1 + po[p], k1), colmajT(A2 + a2o[p], k2), 0.0,
+                                 colmaj(T2 + po[p], k1)));
+          // M = N1^-1 T2 N2^-1 with N^-1 = Linv^T Linv
+          gd.push_back(gemm_desc(k1, k2, k1, 1.0, colmaj(N1i + n1o[p], k1), colmaj(T2 + po[p], k1), 0.0,
+                                 colmaj(T1 + po[p], k1)));
+          ge.push_back(gemm_desc(k1, k2, k1, 1.0, colmajT(N1i + n1o[p], k1), colmaj(T1 + po[p], k1), 0.0,
+                                 colmaj(T2 + po[p], k1)));
+          gf.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(T2 + po[p], k1), colmajT(N2i + n2o[p], k2), 0.0,
+                                 colmaj(T1 + po[p], k1)));
+          gf.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(T1 + po[p], k1), colmaj(N2i + n2o[p], k2), 0.0,
+                                 colmaj(pr.M, k1)));
+        }
+        gemm_batched(ga, ms, s);
+        gemm_batched(gb, ms, s);
+        if (!cj.empty()) {
+          CholJob* dcj = ms.make<CholJob>(cj.size());
+          upload(dcj, cj, s);
+          hipLaunchKernelGGL(chol_inv_kernel, dim3((unsigned)cj.size()), dim3(256), 0, s, dcj);
+          RSF_HIP(hipGetLastError());
+        }
+        gemm_batched(gc, ms, s);
+        gemm_batched(gd, ms, s);
+        gemm_batched(ge, ms, s);
+        // the two products of gf depend on each other: run them in order
+        std::vector<GemmDesc> gf1, gf2;
+        for (size_t q = 0; q < gf.size(); ++q) (q % 2 == 0 ? gf1 : gf2).push_back(gf[q]);
+        gemm_batched(gf1, ms, s);
+        gemm_batched(gf2, ms, s);
+        int fh = 0;
+        RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipStreamSynchronize(s));
+        RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: singular normal equations of a core matrix");
+      }
+    }
+    // extraction at the leaves
+    Scratch scr(s);
+    std::vector<int> lbeg, lcnt;
+    int nL = 1;
+    for (int b = 0; b < t.nbox(); ++b)
+      if (t.leaf[b]) {
+        lbeg.push_back(t.begin[b]);
+        lcnt.push_back(t.count[b]);
+        nL = std::max(nL, t.count[b]);
+      }
+    const int nleaf = (int)lbeg.size();
+    int* dlb = scr.make<int>(nleaf);
+    int* dlc = scr.make<int>(nleaf);
+    upload(dlb, lbeg, s);
+    upload(dlc, lcnt, s);
+    const long long sz = n * nL;
+    double* E = scr.make<double>(sz);
+    fill_zero(E, sz, s);
+    hipLaunchKernelGGL(eye_blocks_kernel, dim3(nleaf), dim3(256), 0, s, dlb, dlc, nleaf, E, nL);
+    RSF_HIP(hipGetLastError());
+    double* H0 = scr.make<double>(sz);
+    double* H1 = scr.make<double>(sz);
+    apply_ops(E, nL, H0, H1, scr);
+    subtract_lowrank(0, D + 1, E, nL, H0, scr);
+    subtract_lowrank(1, D + 1, E, nL, H1, scr);
+    double* tr = scr.make<double>(2);
+    hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb, dlc, nleaf, H0, nL, tr);
+    hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb, dlc, nleaf, H1, nL, tr + 1);
+    RSF_HIP(hipGetLastError());
+    double th[2];
+    RSF_HIP(hipMemcpyAsync(th, tr, sizeof(th), hipMemcpyDeviceToHost, s));
+    RSF_HIP(hipStreamSynchronize(s));
+    *tr_inv = th[0];
+    *tr_rho = th[1];
+    if (st) {
+      st->levels = D;
+      st->leaf_cols = nL;
+    }
+  }
+};
+
+}  // namespace
+
+void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv, double* tr_rho,
+                 PeelStats* st, hipStream_t s) {
+  Peeler p(h, s);
+  p.run(eps_peel, seed, tr_inv, tr_rho, st);
+}
+
+}  // namespace rsf
+
+namespace rsf {
+
+void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g, rsf_grad_info* info,
+               void* stream) {
+  using clk = std::chrono::steady_clock;
+  RSF_CHECK(f != nullptr, RSF_E_INVALID, "null factor handle");
+  RSF_CHECK(d_z != nullptr && g != nullptr, RSF_E_INVALID, "null argument");
+  if (!(eps_peel > 0.0)) eps_peel = f->eps;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const auto t0 = clk::now();
+  if (!f->Frho) {
+    f->Frho.reset(new FactorData());
+    build_factor(f, *f->Frho, 1, s);
+  }
+  RSF_HIP(hipStreamSynchronize(s));
+  const auto t1 = clk::now();
+  Scratch scr(s);
+  const long long n = f->tree.n;
+  double* Z = scr.make<double>(n);
+  double* A = scr.make<double>(n);
+  double* X = scr.make<double>(n);
+  double* Y = scr.make<double>(n);
+  double* dots = scr.make<double>(3);
+  to_panel(f, d_z, n, Z, 1, 1, s);
+  copy_dev(A, Z, n, s);
+  sweep_solve(f, f->F, A, 1, 1, scr, s);
+  copy_dev(X, A, n, s);
+  sweep_apply_mult(f, *f->Frho, X, Y, 1, 1, scr, s);
+  device_dot(A, Y, n, dots, scr, s);
+  device_dot(Z, A, n, dots + 1, scr, s);
+  device_dot(A, A, n, dots + 2, scr, s);
+  double hd[3];
+  RSF_HIP(hipMemcpyAsync(hd, dots, sizeof(hd), hipMemcpyDeviceToHost, s));
+  RSF_HIP(hipStreamSynchronize(s));
+  const auto t2 = clk::now();
+  const double s2 = f->theta[1], nug = f->theta[2];
+  double q[3] = {0.5 * hd[0], 0.5 * (hd[1] - nug * hd[2]) / s2, 0.5 * hd[2]};
+  double trinv = 0.0, trrho = 0.0;
+  PeelStats ps;
+  peel_traces(f, eps_peel, seed, &trinv, &trrho, &ps, s);
+  const auto t3 = clk::now();
+  double tt[3] = {trrho, ((double)n - nug * trinv) / s2, trinv};
+  for (int i = 0; i < 3; ++i) g[i] = q[i] - 0.5 * tt[i];
+  if (info) {
+    for (int i = 0; i < 3; ++i) {
+      info->q[i] = q[i];
+      info->t[i] = tt[i];
+    }
+    info->trace_inv = trinv;
+    info->peel_levels = ps.levels;
+    for (int i = 0; i < 32; ++i) {
+      info->peel_cols[i] = ps.cols[i];
+      info->peel_rank[i] = ps.rank[i];
+    }
+    info->leaf_cols = ps.leaf_cols;
+    info->seconds[0] = std::chrono::duration<double>(t1 - t0).count();
+    info->seconds[1] = std::chrono::duration<double>(t2 - t1).count();
+    info->seconds[2] = std::chrono::duration<double>(t3 - t2).count();
+    info->seconds[3] = std::chrono::duration<double>(t3 - t0).count();
+  }
+}
+
+}  // namespace rsf

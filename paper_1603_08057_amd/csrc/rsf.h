@@ -118,6 +118,10 @@ struct PeelStats {
 void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv,
                  double* tr_rho, PeelStats* st, hipStream_t s);
 
+// Score equations: g (3 values) and the split terms in info (may be null).
+void grad_eval(rsf_factor_s* f, const double* d_z, double eps_peel, uint64_t seed, double* g,
+               rsf_grad_info* info, void* stream);
+
 void fill_zero(double* p, long long n, hipStream_t s);
 void copy_dev(double* dst, const double* src, long long n, hipStream_t s);
 
