@@ -1,0 +1,152 @@
+"""Benchmark: log-likelihood + score evaluations per second on one MI355X.
+
+One step = one evaluation of Algorithm 1 for a parameter vector theta on fixed
+observation sites: build F ~= Sigma(theta) (quadtree, near fields, IDs,
+elimination, root), l(theta) from one solve and log|F|, then the score:
+F_rho (multiply-only skeletonization of dSigma/drho), the quadratic terms and
+the peeled traces of F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1).  Inputs are
+resident on the device before the timed region.
+
+Workload (default): n = 65536 sites uniform in [0,1]^2 (seed 31), Matern 3/2,
+theta = (0.05, 1.0, 1e-4), eps = 1e-6, leaf 64, 256 proxies on 4 rings,
+eps_peel = eps; z = F^(1/2) w with w ~ N(0, I) (seed 32), drawn once before timing.
+
+Prints one JSON line (see the repository's design notes for the fields).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, HERE)
+
+FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+
+
+def cpu_baseline(spec, name, budget_s=20.0):
+    """The dense oracle (l and g by FP64 Cholesky) timed on the host on a
+    sample n chosen to take roughly budget_s, scaled to the workload's n by
+    the O(n^3) cost of the dense route."""
+    import numpy as np
+    from oracle import dense
+    import workloads as W
+    cores = os.cpu_count() or 1
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except Exception:
+        pass
+    m = 2048
+    t = 0.0
+    while True:
+        P = W.workload_points(name, m)
+        z = W.gaussian(m, spec["w_seed"])
+        t0 = time.time()
+        dense.loglik_and_grad(P, z, spec["theta"], spec["kernel"], spec["alpha"], block=2048)
+        t = time.time() - t0
+        if t * 8 > budget_s or m * 2 > spec["n"]:
+            break
+        m *= 2
+    scale = (spec["n"] / m) ** 3
+    return {"value": 1.0 / (t * scale), "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": "dense FP64 oracle l+grad at n=%d (same recipe), %.2f s, scaled by (%d/%d)^3"
+                      % (m, t, spec["n"], m)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c3_matern32_n65536")
+    ap.add_argument("--n", type=int, default=None, help="override n (same recipe)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1603_08057_amd as R
+    import workloads as W
+
+    spec = dict(W.WORKLOADS[args.workload])
+    name = args.workload
+    if args.n:
+        spec["n"] = args.n
+    n = spec["n"]
+    dev = torch.device("cuda:0")
+    P = torch.tensor(W.workload_points(name, n), dtype=torch.float64, device=dev)
+    w = torch.tensor(W.gaussian(n, spec["w_seed"]), dtype=torch.float64, device=dev)
+    theta = spec["theta"]
+    kw = dict(kernel=spec["kernel"], eps=spec["eps"], leaf=spec["leaf"], n_prox=spec["n_prox"],
+              prox_rings=spec["prox_rings"], rq_alpha=spec["alpha"])
+    F0 = R.Factor(P, theta, **kw)
+    z = F0.apply_sqrt(w)
+    F0.close()
+    torch.cuda.synchronize()
+    print("setup done: n=%d" % n, file=sys.stderr, flush=True)
+
+    def step():
+        F = R.Factor(P, theta, **kw)
+        ell = F.loglik(z)
+        g, info = F.grad(z, spec["eps"], spec.get("peel_seed", 0))
+        F.close()
+        return ell, g, info
+
+    for i in range(args.warmup):
+        t0 = time.time()
+        ell, g, info = step()
+        print("warmup %d: %.3f s  l=%.6e g=%s  phases=%s" % (i, time.time() - t0, ell, g, list(info.seconds)),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    R.trace_read(reset=True)
+    R.trace_enable(True)
+    t0 = time.time()
+    for i in range(args.steps):
+        ell, g, info = step()
+        print("step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.time() - t0
+    R.trace_enable(False)
+    ms, flops, nbytes, launches = R.trace_read(reset=True)
+    ms_per_step = 1000.0 * elapsed / args.steps
+    achieved = (flops / (ms * 1e-3)) / 1e12 if ms > 0 else 0.0
+    out = {
+        "metric": "loglik+grad evals/sec at n=%d (eps=%g)" % (n, spec["eps"]),
+        "value": args.steps / elapsed,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name if not args.n else "%s_recipe_n%d" % (name, n), "n": n,
+                   "kernel": "matern32" if spec["kernel"] == 1 else spec["kernel"], "theta": list(theta),
+                   "eps": spec["eps"], "eps_peel": spec["eps"], "leaf": spec["leaf"], "n_prox": spec["n_prox"],
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "kernel": "gemm_tiles_kernel (batched FP64 MFMA GEMM)",
+                     "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "launches": launches, "kernel_ms_per_step": ms / args.steps,
+                     "flops_per_launch": flops / max(launches, 1),
+                     "avg_launch_us": 1000.0 * ms / max(launches, 1)},
+        "result": {"loglik": ell, "grad": g, "peel_cols": list(info.peel_cols)[:12],
+                   "peel_rank": list(info.peel_rank)[:12]},
+    }
+    if not args.no_cpu_baseline:
+        print("timing the CPU oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(spec, name)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

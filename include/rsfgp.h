@@ -165,6 +165,18 @@ rsf_status rsf_tree_export(rsf_factor f, int32_t* perm, rsf_tree_info* info);
 rsf_status rsf_skeleton_export(rsf_factor f, int level, int32_t* offsets, int32_t* idx,
                                int32_t* nbox_out);
 
+/* Launch tracing (the library's profiling hook).  While enabled, every launch
+ * of the batched matrix-core GEMM kernel (the kernel behind the sweeps and
+ * the peeling products) is bracketed by HIP events recorded on the stream it
+ * is launched on, and its algorithmic work is counted: 2 M N K flops and
+ * 8 (M K + K N + M N [+ M N when C is read]) bytes per problem.
+ * rsf_trace_read synchronises on the recorded events and returns the summed
+ * kernel time (ms), flops, bytes and launch count (any output may be NULL);
+ * reset != 0 clears the counters.  Not thread-safe: one tracing client at a time. */
+rsf_status rsf_trace_enable(int on);
+rsf_status rsf_trace_read(double* gemm_ms, double* gemm_flops, double* gemm_bytes, int64_t* gemm_launches,
+                          int reset);
+
 /* Message describing the last error on this thread ("" if none). */
 const char* rsf_last_error(void);
 

@@ -65,6 +65,8 @@ def load():
         "rsf_skeleton_export": ([vp, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)], C.c_int),
         "rsf_last_error": ([], C.c_char_p),
+        "rsf_trace_enable": ([C.c_int], C.c_int),
+        "rsf_trace_read": ([dp, dp, dp, C.POINTER(C.c_int64), C.c_int], C.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -105,6 +107,18 @@ def _colmajor(b, n):
     if b.dim() == 1:
         return b.reshape(1, n).contiguous(), 1, True
     return b.t().contiguous(), b.shape[1], False
+
+
+def trace_enable(on=True):
+    """Starts / stops event tracing of the batched matrix-core GEMM launches."""
+    _check(load().rsf_trace_enable(1 if on else 0))
+
+
+def trace_read(reset=False):
+    """(kernel ms, flops, bytes, launches) accumulated while tracing was on."""
+    ms, fl, by, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
+    _check(load().rsf_trace_read(C.byref(ms), C.byref(fl), C.byref(by), C.byref(n), 1 if reset else 0))
+    return ms.value, fl.value, by.value, n.value
 
 
 class Factor:

@@ -255,6 +255,19 @@ rsf_status rsf_skeleton_export(rsf_factor f, int level, int32_t* offsets, int32_
   });
 }
 
+rsf_status rsf_trace_enable(int on) {
+  return guarded([&] { trace_enable(on != 0); });
+}
+
+rsf_status rsf_trace_read(double* gemm_ms, double* gemm_flops, double* gemm_bytes, int64_t* gemm_launches,
+                          int reset) {
+  return guarded([&] {
+    long long l = 0;
+    trace_read(gemm_ms, gemm_flops, gemm_bytes, &l, reset != 0);
+    if (gemm_launches) *gemm_launches = l;
+  });
+}
+
 rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
                     rsf_grad_info* info, void* stream) {
   return guarded([&] { grad_eval(f, d_z, eps_peel, seed, g, info, stream); });

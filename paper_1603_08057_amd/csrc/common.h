@@ -125,6 +125,11 @@ inline GemmDesc gemm_desc(int M, int N, int K, double alpha, Mat A, Mat B, doubl
 // empty output are skipped).  The descriptors are copied to the device.
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s);
 
+// Tracing of the batched GEMM launches: HIP events around every launch on
+// its stream, with the algorithmic flops (2 M N K) and operand bytes counted.
+void trace_enable(bool on);
+void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset);
+
 // Reproducible sum of n doubles (fixed reduction tree) into *out (device).
 void device_sum(const double* x, long long n, double* out, Scratch& scr, hipStream_t s);
 // out[0] = sum_i x[i] * y[i] (fixed reduction tree).

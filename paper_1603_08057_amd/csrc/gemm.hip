@@ -130,11 +130,46 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
   store_block(d, acc11, i0 + rb + 16, j0 + cb + 16, lane);
 }
 
+// ---- launch tracing of the batched GEMM (events on the launch stream)
+namespace {
+struct GemmTrace {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  double ms = 0.0, flops = 0.0, bytes = 0.0;
+  long long launches = 0;
+} g_trace;
+}
+
+void trace_enable(bool on) { g_trace.on = on; }
+
+void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset) {
+  for (auto& e : g_trace.ev) {
+    float t = 0.f;
+    RSF_HIP(hipEventSynchronize(e.second));
+    RSF_HIP(hipEventElapsedTime(&t, e.first, e.second));
+    g_trace.ms += t;
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  g_trace.ev.clear();
+  if (ms) *ms = g_trace.ms;
+  if (flops) *flops = g_trace.flops;
+  if (bytes) *bytes = g_trace.bytes;
+  if (launches) *launches = g_trace.launches;
+  if (reset) {
+    g_trace.ms = g_trace.flops = g_trace.bytes = 0.0;
+    g_trace.launches = 0;
+  }
+}
+
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s) {
   std::vector<int4> tiles;
   std::vector<GemmDesc> live;
+  double flops = 0.0, bytes = 0.0;
   for (const GemmDesc& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
+    flops += 2.0 * d.M * d.N * d.K;
+    bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     const int p = (int)live.size();
     live.push_back(d);
     const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
@@ -147,8 +182,21 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   upload(dd, live, s);
   upload(dt, tiles, s);
   // the grid is limited to 2^31 - 1 blocks in x; tile lists here stay far below
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (g_trace.on) {
+    RSF_HIP(hipEventCreate(&e0));
+    RSF_HIP(hipEventCreate(&e1));
+    RSF_HIP(hipEventRecord(e0, s));
+  }
   hipLaunchKernelGGL(gemm_tiles_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, s, dd, dt);
   RSF_HIP(hipGetLastError());
+  if (g_trace.on) {
+    RSF_HIP(hipEventRecord(e1, s));
+    g_trace.ev.emplace_back(e0, e1);
+    g_trace.flops += flops;
+    g_trace.bytes += bytes;
+    g_trace.launches += 1;
+  }
 }
 
 // Single-workgroup reduction in a fixed order: thread t sums elements

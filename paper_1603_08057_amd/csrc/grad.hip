@@ -159,31 +159,47 @@ __device__ void wg_tri_inv_lower(const double* L, long long ldl, double* Li, lon
 // Pivoted Cholesky of the Gram matrix G = Y^T Y: the same pivots and rank as
 // column-pivoted QR of Y in exact arithmetic (residual diagonal = squared
 // residual column norm); stops when the largest residual diagonal is
-// <= tol^2 times the first pivot's.  Writes the rank, the pivots, and
-// Linv = (leading k x k lower factor)^-1.
+// <= tol^2 times the first pivot's.  Left-looking: column s of the factor is
+// formed from the original Gram column of the pivot and the previous columns,
+// L(j, s) = (G(j, p) - sum_{l<s} L(j, l) L(p, l)) / sqrt(d_p), and the residual
+// diagonal d is updated in LDS, so each step streams the factor once.
+// Writes the rank, the pivots, and Linv = (leading k x k factor in pivot
+// order)^-1 (ld n).
 struct PcholJob {
-  double* G;
+  const double* G;  // n x n, ld n (read only)
   int n;
   int* piv;
   int* kout;
-  double* Linv;  // ldi = n
+  double* Lw;       // n x n work: column s holds L(:, s) indexed by original row
+  double* L1;       // n x n work: leading factor in pivot order
+  double* Linv;     // ld n
 };
 
+constexpr int PCHOL_MAXN = 4096;
+
 __global__ __launch_bounds__(256) void pchol_kernel(const PcholJob* __restrict__ jobs, double tol2) {
+  __shared__ double d[PCHOL_MAXN];
+  __shared__ unsigned char done[PCHOL_MAXN];
+  __shared__ double lp[PCHOL_MAXN];
   __shared__ double red_v[256];
   __shared__ int red_i[256];
   const PcholJob J = jobs[blockIdx.x];
   const int n = J.n, tid = threadIdx.x, nt = blockDim.x;
-  double* G = J.G;
-  for (int j = tid; j < n; j += nt) J.piv[j] = j;
+  const double* G = J.G;
+  double* L = J.Lw;
+  for (int j = tid; j < n; j += nt) {
+    d[j] = G[(long long)j * n + j];
+    done[j] = 0;
+  }
   __syncthreads();
   double d1 = 0.0;
   int k = 0;
   for (int s = 0; s < n; ++s) {
     double bv = -1.0;
     int bi = 0x7fffffff;
-    for (int j = s + tid; j < n; j += nt) {
-      const double v = G[(long long)j * n + j];
+    for (int j = tid; j < n; j += nt) {
+      if (done[j]) continue;
+      const double v = d[j];
       if (v > bv || (v == bv && j < bi)) {
         bv = v;
         bi = j;
@@ -208,42 +224,38 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholJob* __restrict__
     __syncthreads();
     if (s == 0) d1 = dp;
     if (!(dp > tol2 * d1) || !(dp > 0.0)) break;
-    if (p != s) {
-      // symmetric swap of rows / columns s and p in the lower triangle, kept as a full matrix
-      for (int i = tid; i < n; i += nt) {
-        const double t = G[(long long)s * n + i];
-        G[(long long)s * n + i] = G[(long long)p * n + i];
-        G[(long long)p * n + i] = t;
-      }
-      __syncthreads();
-      for (int j = tid; j < n; j += nt) {
-        const double t = G[(long long)j * n + s];
-        G[(long long)j * n + s] = G[(long long)j * n + p];
-        G[(long long)j * n + p] = t;
-      }
-      if (tid == 0) {
-        const int t = J.piv[s];
-        J.piv[s] = J.piv[p];
-        J.piv[p] = t;
-      }
-      __syncthreads();
+    for (int l = tid; l < s; l += nt) lp[l] = L[(long long)l * n + p];
+    if (tid == 0) {
+      J.piv[s] = p;
+      done[p] = 1;
     }
-    const double lss = sqrt(G[(long long)s * n + s]);
     __syncthreads();
-    for (int i = s + 1 + tid; i < n; i += nt) G[(long long)s * n + i] /= lss;
-    if (tid == 0) G[(long long)s * n + s] = lss;
-    __syncthreads();
-    // trailing update of the full symmetric remainder
-    const long long rem = n - s - 1;
-    for (long long e = tid; e < rem * rem; e += nt) {
-      const int ii = s + 1 + (int)(e % rem), jj = s + 1 + (int)(e / rem);
-      G[(long long)jj * n + ii] -= G[(long long)s * n + ii] * G[(long long)s * n + jj];
+    const double lss = sqrt(dp);
+    for (int j = tid; j < n; j += nt) {
+      double x;
+      if (j == p) {
+        x = lss;
+      } else if (done[j]) {
+        x = 0.0;
+      } else {
+        x = G[(long long)p * n + j];
+        for (int l = 0; l < s; ++l) x -= L[(long long)l * n + j] * lp[l];
+        x /= lss;
+        d[j] -= x * x;
+      }
+      L[(long long)s * n + j] = x;
     }
     __syncthreads();
     k = s + 1;
   }
+  // leading factor in pivot order: L1(a, b) = L(piv[a], b), lower triangular
+  for (long long e = tid; e < (long long)k * k; e += nt) {
+    const int a = (int)(e % k), b = (int)(e / k);
+    J.L1[(long long)b * n + a] = (a >= b) ? L[(long long)b * n + J.piv[a]] : 0.0;
+  }
+  for (int j = k + tid; j < n; j += nt) J.piv[j] = -1;
   __syncthreads();
-  wg_tri_inv_lower(G, n, J.Linv, n, k);
+  wg_tri_inv_lower(J.L1, n, J.Linv, n, k);
   if (tid == 0) *J.kout = k;
 }
 
@@ -447,8 +459,12 @@ struct Peeler {
         // ranks of every sample block by pivoted Cholesky of its Gram matrix
         goff.assign(2 * nblk + 1, 0);
         for (int e = 0; e < 2 * nblk; ++e) goff[e + 1] = goff[e] + (long long)total * total;
+        RSF_CHECK(total <= PCHOL_MAXN, RSF_E_INVALID,
+                  "peeling needs more than " + std::to_string(PCHOL_MAXN) + " probe columns per block");
         Gram = scr.make<double>(goff[2 * nblk]);
         Ginv = scr.make<double>(goff[2 * nblk]);
+        double* Lw = scr.make<double>(goff[2 * nblk]);
+        double* L1 = scr.make<double>(goff[2 * nblk]);
         dk = scr.make<int>(2 * nblk);
         dpiv = scr.make<int>((size_t)2 * nblk * total);
         std::vector<GemmDesc> g;
@@ -460,12 +476,16 @@ struct Peeler {
             const int idx = op * nblk + e;
             g.push_back(gemm_desc(total, total, t.count[rb], 1.0, Mat{Yb, 1, 4LL * total, nullptr},
                                   panel(Yb, 4LL * total), 0.0, colmaj(Gram + goff[idx], total)));
-            pj.push_back(PcholJob{Gram + goff[idx], total, dpiv + (long long)idx * total, dk + idx, Ginv + goff[idx]});
+            pj.push_back(PcholJob{Gram + goff[idx], total, dpiv + (long long)idx * total, dk + idx, Lw + goff[idx],
+                                  L1 + goff[idx], Ginv + goff[idx]});
           }
         gemm_batched(g, scr, s);
         PcholJob* dj = scr.make<PcholJob>(pj.size());
         upload(dj, pj, s);
-        hipLaunchKernelGGL(pchol_kernel, dim3((unsigned)pj.size()), dim3(256), 0, s, dj, eps_peel * eps_peel);
+        // relative pivots below ~1e-13 of the Gram diagonal are rounding noise
+        // (the Gram squares the singular values), so the threshold is floored there
+        const double tol2 = std::max(eps_peel * eps_peel, 1e-13);
+        hipLaunchKernelGGL(pchol_kernel, dim3((unsigned)pj.size()), dim3(256), 0, s, dj, tol2);
         RSF_HIP(hipGetLastError());
         RSF_HIP(hipMemcpyAsync(rk.data(), dk, rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
         RSF_HIP(hipStreamSynchronize(s));

@@ -1,10 +1,13 @@
-"""Writes the dense-oracle reference values for the n = 65536 log-likelihood +
-score workload (Matern 3/2, theta = (0.05, 1, 1e-4), points uniform in
-[0,1]^2 with seed 31, z = N(0, I) draws with seed 32) into
-c3_matern32_n65536_dense.json.
+"""Writes dense-oracle reference values for the named workloads into
+tests/golden/<workload>_dense.json.  Calls only oracle.dense (dense FP64
+Cholesky).  The n = 65536 workload needs about 35 GB of host memory and tens
+of minutes on 8 cores.
 
-Calls only oracle.dense (dense FP64 Cholesky, about 35 GB of host memory and
-tens of minutes on 8 cores).  Usage:  python tests/golden/make_dense_golden.py [n]
+  python tests/golden/make_dense_golden.py c3_matern32_n65536
+  python tests/golden/make_dense_golden.py c2_rq_n16384
+
+Observations z are N(0, I) draws (workloads.gaussian(n, w_seed)); the
+log-likelihood and its score are defined for any z.
 """
 import json
 import os
@@ -21,29 +24,32 @@ import workloads as W  # noqa: E402
 
 
 def main():
-    spec = W.WORKLOADS["c3_matern32_n65536"]
-    n = int(sys.argv[1]) if len(sys.argv) > 1 else spec["n"]
-    P = W.workload_points("c3_matern32_n65536", n)
-    z = W.gaussian(n, spec["w_seed"])
+    name = sys.argv[1] if len(sys.argv) > 1 else "c3_matern32_n65536"
+    spec = W.WORKLOADS[name]
+    n = int(sys.argv[2]) if len(sys.argv) > 2 else spec["n"]
+    P = W.workload_points(name, n)
+    nrhs = spec.get("nrhs", 1)
+    Z = W.gaussian((n, nrhs), spec["w_seed"]) if nrhs > 1 else W.gaussian(n, spec["w_seed"])
+    z = Z if nrhs == 1 else Z[:, 0]
     t0 = time.time()
     o = dense.loglik_and_grad(P, z, spec["theta"], spec["kernel"], spec["alpha"], block=2048, want_terms=True)
     secs = time.time() - t0
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(n, size=min(n, 64), replace=False))
     out = {
-        "workload": "c3_matern32_n65536" if n == spec["n"] else "c3_recipe_n%d" % n,
-        "n": n, "kernel": spec["kernel"], "theta": list(spec["theta"]), "points_seed": spec["points"][1],
-        "z": "workloads.gaussian(n, %d)" % spec["w_seed"],
+        "workload": name if n == spec["n"] else "%s_recipe_n%d" % (name, n),
+        "n": n, "kernel": spec["kernel"], "theta": list(spec["theta"]), "alpha_rq": spec["alpha"],
+        "z": "workloads.gaussian(n, %d) (first column when several)" % spec["w_seed"],
         "ell": o["ell"], "logdet": o["logdet"], "ztSinvz": float(z @ o["alpha"]),
         "g": list(map(float, o["g"])), "q": list(map(float, o["q"])), "t": list(map(float, o["t"])),
         "alpha_index": sample.tolist(), "alpha_value": [float(o["alpha"][i]) for i in sample],
         "oracle_seconds": secs,
         "generator": "tests/golden/make_dense_golden.py (oracle.dense only)",
     }
-    name = "c3_matern32_n65536_dense.json" if n == spec["n"] else "c3_recipe_n%d_dense.json" % n
-    with open(os.path.join(HERE, name), "w") as f:
+    fname = ("%s_dense.json" % name) if n == spec["n"] else ("%s_recipe_n%d_dense.json" % (name, n))
+    with open(os.path.join(HERE, fname), "w") as f:
         json.dump(out, f, indent=1)
-    print("wrote", name, "in %.1f s" % secs)
+    print("wrote", fname, "in %.1f s" % secs)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,178 @@
+"""Parity of the HIP factorization, sweeps and log-likelihood with the oracle.
+
+Two references on the same seeded inputs:
+  * the oracle RSF (oracle/rsf.py): the same approximation written out plainly.
+    Integer / index results (tree permutation, skeleton lists) must match
+    bit for bit; floating-point results must agree to rounding, bounded by
+    kappa(F) * u * growth ~ 1e6 * 1e-16 * 1e2 = 1e-8 for solves and 1e-11 for
+    log|F| (a sum of logs of well-conditioned diagonal factors).
+  * the dense oracle (oracle/dense.py): the exact definitions; the RSF must be
+    within its tolerance eps of them (log|F| within 10 eps relative; the solve
+    within kappa * eps, reported).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1603_08057_amd as R
+from oracle import dense, rsf
+from oracle import kernels as K
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SOLVE_RTOL = 1e-8
+LOGDET_RTOL = 1e-11
+
+
+def _t(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+
+
+def _check_parity(P, theta, kernel, eps, leaf, n_prox=256, rings=4, alpha=1.0, nrhs=3, seed=5):
+    n = P.shape[0]
+    print("case n=%d kernel=%d eps=%g leaf=%d n_prox=%d" % (n, kernel, eps, leaf, n_prox), flush=True)
+    F = R.Factor(_t(P), theta, kernel=kernel, eps=eps, leaf=leaf, n_prox=n_prox, prox_rings=rings,
+                 rq_alpha=alpha)
+    O = rsf.Factor(P, theta, kernel, eps, leaf, alpha=alpha, n_prox=n_prox, prox_rings=rings)
+    info = F.tree_info(want_perm=True)
+    assert info["depth"] == O.tree.max_depth
+    assert info["nbox"] == O.tree.nbox
+    assert np.array_equal(np.array(info["perm"]), O.tree.perm)
+    assert info["root_size"] == O.Iroot.shape[0]
+    for lev in range(1, info["depth"] + 1):
+        offs, idx = F.skeletons(lev)
+        boxes = O.tree.levels[lev]
+        assert len(offs) == len(boxes) + 1
+        for i, b in enumerate(boxes):
+            assert np.array_equal(np.array(idx[offs[i]:offs[i + 1]], dtype=np.int64), O.tree.perm[O.S[int(b)]])
+    assert F.logdet == pytest.approx(O.logdet, rel=LOGDET_RTOL, abs=1e-12)
+    B = W.gaussian((n, nrhs), seed)
+    X = F.solve(_t(B)).cpu().numpy()
+    Xo = O.from_tree(O.solve(O.to_tree(B)))
+    assert np.linalg.norm(X - Xo) <= SOLVE_RTOL * np.linalg.norm(Xo)
+    x1 = F.solve(_t(B[:, 0])).cpu().numpy()
+    assert np.linalg.norm(x1 - Xo[:, 0]) <= SOLVE_RTOL * np.linalg.norm(Xo[:, 0])
+    Y = F.apply(_t(B)).cpu().numpy()
+    Yo = O.from_tree(O.apply(O.to_tree(B)))
+    assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
+    V = F.apply_sqrt(_t(B)).cpu().numpy()
+    Vo = O.from_tree(O.sqrt(O.to_tree(B)))
+    assert np.linalg.norm(V - Vo) <= 1e-12 * np.linalg.norm(Vo)
+    z = B[:, 0]
+    ell = F.loglik(_t(z))
+    ello = -0.5 * float(z @ Xo[:, 0]) - 0.5 * O.logdet - 0.5 * n * math.log(2 * math.pi)
+    assert ell == pytest.approx(ello, rel=1e-10)
+    return F, O
+
+
+def test_small_matern32_single_ring():
+    # n = 1024, Matern 3/2, rho 0.1, nugget 1e-4, a 64-point proxy ring, eps 1e-9
+    spec = W.WORKLOADS["c1_matern32_n1024"]
+    P = W.workload_points("c1_matern32_n1024")
+    F, O = _check_parity(P, spec["theta"], spec["kernel"], spec["eps"], spec["leaf"], n_prox=64, rings=1)
+    # the approximation itself: log|F| within 10 eps of the dense log|Sigma|
+    z = dense.sample(P, W.gaussian(1024, spec["w_seed"]), spec["theta"], spec["kernel"])
+    ell_d, logdet_d, a_d = dense.loglik(P, z, spec["theta"], spec["kernel"])
+    assert abs(F.logdet - logdet_d) <= 10 * spec["eps"] * abs(logdet_d)
+    ell = F.loglik(_t(z))
+    assert abs(ell - ell_d) <= 10 * spec["eps"] * abs(ell_d)
+
+
+def test_ragged_matern52():
+    P = W.uniform_points(3001, 41)
+    _check_parity(P, (0.07, 1.3, 1e-3), K.MATERN52, 1e-7, 50)
+
+
+def test_rq_alpha_one_eight_rhs():
+    P = W.uniform_points(4096, 21)
+    _check_parity(P, (0.05, 1.0, 1e-3), K.RQ, 1e-6, 64, nrhs=8)
+
+
+def test_rq_general_alpha_and_matern12():
+    P = W.uniform_points(1500, 43)
+    _check_parity(P, (0.08, 0.7, 1e-2), K.RQ, 1e-8, 40, alpha=0.5)
+    _check_parity(P, (0.08, 0.7, 1e-2), K.MATERN12, 1e-8, 40)
+
+
+def test_clustered_points_adaptive_tree():
+    P = W.mixed_points(4000, 6, 0.02, 44, 45)
+    F, O = _check_parity(P, (0.05, 1.0, 1e-4), K.MATERN32, 1e-7, 32)
+    leaf_depths = {int(O.tree.depth[b]) for b in range(O.tree.nbox) if O.tree.is_leaf[b]}
+    assert len(leaf_depths) > 1
+
+
+def test_single_box_is_dense_cholesky():
+    for n in (1, 2, 37, 64):
+        P = W.uniform_points(n, 46)
+        theta = (0.3, 1.1, 1e-3)
+        F = R.Factor(_t(P), theta, kernel=K.MATERN32, eps=1e-6, leaf=64)
+        assert F.tree_info()["depth"] == 0
+        z = W.gaussian(n, 47)
+        ell, logdet, a = dense.loglik(P, z, theta, K.MATERN32)
+        assert F.logdet == pytest.approx(logdet, rel=1e-13, abs=1e-13)
+        assert F.loglik(_t(z)) == pytest.approx(ell, rel=1e-12)
+        np.testing.assert_allclose(F.solve(_t(z)).cpu().numpy(), a, rtol=1e-9, atol=1e-12)
+
+
+def test_diagonal_covariance_is_exact():
+    g = np.arange(24.0)
+    P = np.stack(np.meshgrid(g, g), axis=-1).reshape(-1, 2)
+    n = P.shape[0]
+    theta = (1e-3, 1.3, 0.2)
+    F = R.Factor(_t(P), theta, kernel=K.MATERN32, eps=1e-9, leaf=16)
+    assert F.tree_info()["depth"] >= 3
+    assert F.logdet == pytest.approx(n * math.log(1.5), rel=1e-14)
+    z = W.gaussian(n, 48)
+    np.testing.assert_allclose(F.solve(_t(z)).cpu().numpy(), z / 1.5, rtol=1e-15)
+    for lev in range(1, F.tree_info()["depth"] + 1):
+        offs, idx = F.skeletons(lev)
+        assert offs[-1] == 0
+
+
+def test_sweep_identities_and_determinism():
+    P = W.uniform_points(2048, 49)
+    F = R.Factor(_t(P), (0.06, 1.0, 1e-4), kernel=K.MATERN32, eps=1e-7, leaf=64)
+    B = _t(W.gaussian((2048, 4), 50))
+    X = F.solve(B)
+    np.testing.assert_allclose(F.apply(X).cpu().numpy(), B.cpu().numpy(), atol=1e-8)
+    u, v = B[:, 0], B[:, 1]
+    a = float(u @ F.solve(v))
+    b = float(v @ F.solve(u))
+    assert a == pytest.approx(b, rel=1e-10)
+    # identical inputs give bitwise identical outputs (no atomics in the sums)
+    assert torch.equal(F.solve(B), X)
+    F2 = R.Factor(_t(P), (0.06, 1.0, 1e-4), kernel=K.MATERN32, eps=1e-7, leaf=64)
+    assert F2.logdet == F.logdet
+    assert torch.equal(F2.solve(B), X)
+
+
+def test_errors_are_reported():
+    P = W.uniform_points(500, 51)
+    with pytest.raises(R.RsfError) as e:
+        R.Factor(_t(np.vstack([P, P[:1]])), (0.1, 1.0, 1e-4))
+    assert e.value.name == "RSF_E_DUPLICATE"
+    Q = P.copy()
+    Q[3, 0] = np.nan
+    with pytest.raises(R.RsfError) as e:
+        R.Factor(_t(Q), (0.1, 1.0, 1e-4))
+    assert e.value.name == "RSF_E_NONFINITE"
+    with pytest.raises(R.RsfError) as e:
+        R.Factor(_t(P), (0.3, 1.0, -0.5), eps=1e-6, leaf=32)
+    assert e.value.name == "RSF_E_NOT_SPD"
+    with pytest.raises(R.RsfError) as e:
+        R.Factor(_t(P), (0.1, 1.0, 1e-4), mem_cap_bytes=4096)
+    assert e.value.name == "RSF_E_OOM"
+    with pytest.raises(R.RsfError) as e:
+        R.Factor(_t(P), (0.1, 1.0, 1e-4), n_prox=30, prox_rings=4)
+    assert e.value.name == "RSF_E_INVALID"
+    # a failed call leaves a valid handle valid
+    F = R.Factor(_t(P), (0.1, 1.0, 1e-4), eps=1e-6, leaf=32)
+    import ctypes as C
+    buf = _t(np.zeros(500))
+    lib = R.load()
+    assert lib.rsf_solve(F._h, C.c_void_p(buf.data_ptr()), C.c_void_p(buf.data_ptr()), 1, 499, None) == -1
+    assert lib.rsf_skeleton_export(F._h, 99, None, None, None) == -1
+    assert np.isfinite(F.loglik(_t(W.gaussian(500, 52))))

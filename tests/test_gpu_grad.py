@@ -1,0 +1,96 @@
+"""Parity of the HIP score equations (peeled traces) with the oracle.
+
+The oracle's peeling (oracle/peel.py) draws the same Philox probes and follows
+the same adaptive rule, so the per-level probe counts must match exactly and
+the traces / quadratic terms agree to rounding (relative 1e-8: the peeled
+low-rank blocks are formed from the same samples through different but
+equivalent range finders, so the difference is rounding amplified by the
+conditioning of the core matrices).  Against the dense definitions the traces
+must be within a few eps_peel.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1603_08057_amd as R
+from oracle import dense, rsf
+from oracle import kernels as K
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _t(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("n,eps,n_prox,rings,kernel,theta", [
+    (1024, 1e-9, 64, 1, K.MATERN32, (0.1, 1.0, 1e-4)),
+    (2500, 1e-7, 256, 4, K.MATERN52, (0.06, 1.2, 1e-3)),
+    (4096, 1e-6, 256, 4, K.MATERN32, (0.05, 1.0, 1e-4)),
+])
+def test_grad_matches_oracle_and_dense(n, eps, n_prox, rings, kernel, theta):
+    print("grad case n=%d eps=%g" % (n, eps), flush=True)
+    P = W.uniform_points(n, 11)
+    z = dense.sample(P, W.gaussian(n, 12), theta, kernel)
+    eps_peel = 1e-6
+    F = R.Factor(_t(P), theta, kernel=kernel, eps=eps, leaf=64, n_prox=n_prox, prox_rings=rings)
+    g, info = F.grad(_t(z), eps_peel, 33)
+    o = rsf.loglik_grad(P, z, theta, kernel, eps, 64, eps_peel=eps_peel, seed=33, n_prox=n_prox,
+                        prox_rings=rings)
+    for lev, c in o["peel_cols"].items():
+        assert info.peel_cols[lev] == c
+        assert info.peel_rank[lev] == o["peel_ranks"][lev]
+    np.testing.assert_allclose(list(info.q), o["q"], rtol=1e-9)
+    np.testing.assert_allclose(list(info.t), o["t"], rtol=1e-8)
+    np.testing.assert_allclose(g, o["g"], rtol=1e-8, atol=1e-8 * np.abs(o["g"]).max())
+    d = dense.loglik_and_grad(P, z, theta, kernel, want_terms=True)
+    np.testing.assert_allclose(list(info.t), d["t"], rtol=20 * eps_peel)
+    # the score itself: relative to the scale of its two halves (they cancel)
+    scale = np.abs(d["q"]) + 0.5 * np.abs(d["t"])
+    assert np.all(np.abs(np.array(g) - d["g"]) <= 1e3 * eps * scale + 50 * eps_peel * scale)
+    # repeatable: same seed, same answer
+    g2, _ = F.grad(_t(z), eps_peel, 33)
+    assert g2 == g
+
+
+def test_grad_diagonal_covariance_exact():
+    g0 = np.arange(16.0)
+    P = np.stack(np.meshgrid(g0, g0), axis=-1).reshape(-1, 2)
+    n = P.shape[0]
+    theta = (1e-3, 1.3, 0.2)
+    z = W.gaussian(n, 3)
+    F = R.Factor(_t(P), theta, kernel=K.MATERN32, eps=1e-9, leaf=16)
+    g, info = F.grad(_t(z), 1e-8, 1)
+    s = 1.5
+    gs = 0.5 * float(z @ z) / s ** 2 - n / (2 * s)
+    np.testing.assert_allclose(g, [0.0, gs, gs], rtol=1e-12, atol=1e-9)
+
+
+def test_autograd_function_backward():
+    P = W.uniform_points(1200, 13)
+    theta = (0.08, 1.0, 1e-3)
+    z = dense.sample(P, W.gaussian(1200, 14), theta, K.MATERN32)
+    th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+    ell = R.loglik_fn(th, _t(P), _t(z), kernel=K.MATERN32, eps=1e-8, leaf=64, eps_peel=1e-7, seed=5)
+    ell.backward()
+    d = dense.loglik_and_grad(P, z, theta, K.MATERN32)
+    assert float(ell) == pytest.approx(d["ell"], rel=1e-7)
+    np.testing.assert_allclose(th.grad.numpy(), d["g"], rtol=1e-4, atol=1e-4 * np.abs(d["g"]).max())
+
+
+def test_grad_matches_central_difference_of_frozen_loglik():
+    # the score of the approximate log-likelihood, with every ID tolerance tight,
+    # against a central difference of the dense log-likelihood (relative step 1e-5)
+    P = W.uniform_points(900, 15)
+    theta = np.array([0.09, 1.0, 1e-3])
+    z = dense.sample(P, W.gaussian(900, 16), theta, K.MATERN32)
+    F = R.Factor(_t(P), tuple(theta), kernel=K.MATERN32, eps=1e-10, leaf=64)
+    g, _ = F.grad(_t(z), 1e-9, 2)
+    for i in range(3):
+        h = 1e-5 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (dense.loglik(P, z, tp, K.MATERN32)[0] - dense.loglik(P, z, tm, K.MATERN32)[0]) / (2 * h)
+        assert g[i] == pytest.approx(fd, rel=1e-4, abs=1e-3)
