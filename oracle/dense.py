@@ -134,3 +134,47 @@ def sample(P, w, theta, kernel, alpha=1.0):
 def _trmv(L, w):
     from scipy.linalg import blas
     return blas.dtrmv(L, np.asarray(w, dtype=np.float64), lower=1)
+
+
+def loglik_large(P, z, theta, kernel, alpha=1.0, bs=8192):
+    """(l, log|Sigma|, Sigma^-1 z) for large n by a blocked, in-place, right-
+    looking Cholesky over bs x bs blocks of one n x n buffer: diagonal blocks
+    by LAPACK dpotrf, panels by triangular solves, trailing blocks by matrix
+    products (so no single LAPACK call sees more than bs x n entries)."""
+    import scipy.linalg as sla
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    n = P.shape[0]
+    S = np.empty((n, n))
+    idx = np.arange(n)
+    nb = (n + bs - 1) // bs
+    blk = [(k * bs, min(n, (k + 1) * bs)) for k in range(nb)]
+    # lower triangle only, block rows
+    for (b0, b1) in blk:
+        S[b0:b1, :b1] = K.cov_block(P, idx[b0:b1], idx[:b1], theta, kernel, alpha)
+    logdet = 0.0
+    for k, (k0, k1) in enumerate(blk):
+        Lkk = sla.cholesky(S[k0:k1, k0:k1], lower=True, check_finite=False)
+        S[k0:k1, k0:k1] = Lkk
+        logdet += 2.0 * float(np.sum(np.log(np.diag(Lkk))))
+        for (i0, i1) in blk[k + 1:]:
+            # L_ik = A_ik L_kk^-T
+            S[i0:i1, k0:k1] = sla.solve_triangular(Lkk, S[i0:i1, k0:k1].T, lower=True, check_finite=False).T
+        for i, (i0, i1) in enumerate(blk[k + 1:], start=k + 1):
+            Lik = S[i0:i1, k0:k1]
+            for (j0, j1) in blk[k + 1:i + 1]:
+                S[i0:i1, j0:j1] -= Lik @ S[j0:j1, k0:k1].T
+    # forward and back substitution with the block factor
+    y = z.copy()
+    for k, (k0, k1) in enumerate(blk):
+        for (j0, j1) in blk[:k]:
+            y[k0:k1] -= S[k0:k1, j0:j1] @ y[j0:j1]
+        y[k0:k1] = sla.solve_triangular(S[k0:k1, k0:k1], y[k0:k1], lower=True, check_finite=False)
+    x = y
+    for k in range(nb - 1, -1, -1):
+        k0, k1 = blk[k]
+        for (j0, j1) in blk[k + 1:]:
+            x[k0:k1] -= S[j0:j1, k0:k1].T @ x[j0:j1]
+        x[k0:k1] = sla.solve_triangular(S[k0:k1, k0:k1], x[k0:k1], lower=True, trans="T", check_finite=False)
+    ell = -0.5 * float(z @ x) - 0.5 * logdet - 0.5 * n * LOG2PI
+    return ell, logdet, x

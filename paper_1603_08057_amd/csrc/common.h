@@ -32,10 +32,15 @@ struct Error : std::runtime_error {
   } while (0)
 
 // ---------------------------------------------------------------- device memory
-// A device allocation owned by a factor (freed in the destructor).  Every
-// allocation is accounted against the handle's memory cap.
+// Device allocations owned by a factor (returned to the pool in the
+// destructor).  Every allocation is accounted against the handle's memory cap.
+void* pool_alloc(size_t nbytes, hipStream_t s);
+void pool_free(void* p, size_t nbytes, hipStream_t s);
+void pool_trim();
+
 struct Arena {
   std::vector<void*> blocks;
+  std::vector<size_t> sizes;
   size_t bytes = 0;
   size_t cap = 0;  // 0 = unlimited
   void* alloc(size_t nbytes);
@@ -47,10 +52,11 @@ struct Arena {
   ~Arena() { release(); }
 };
 
-// Scratch allocations for one call; freed (after a stream sync) when the
-// object goes out of scope.
+// Scratch allocations for one call, returned to the stream-ordered pool when
+// the object goes out of scope.
 struct Scratch {
   std::vector<void*> blocks;
+  std::vector<size_t> sizes;
   hipStream_t stream = nullptr;
   size_t cap_left = 0;  // 0 = unlimited
   explicit Scratch(hipStream_t s) : stream(s) {}
@@ -83,6 +89,7 @@ struct GemmDesc {
   long long ars, acs, brs, bcs, crs, ccs;
   int M, N, K;
   double alpha, beta;
+  int lower;  // 1: only tiles touching the lower triangle of C (i >= j) are computed
 };
 
 struct Mat {
@@ -118,12 +125,39 @@ inline GemmDesc gemm_desc(int M, int N, int K, double alpha, Mat A, Mat B, doubl
   d.K = K;
   d.alpha = alpha;
   d.beta = beta;
+  d.lower = 0;
   return d;
 }
 
 // Launches one batched GEMM over all problems in `descs` (problems with an
 // empty output are skipped).  The descriptors are copied to the device.
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s);
+
+// Batched blocked Cholesky (lower, in place) with the inverse factor:
+// A_p = L_p L_p^T, Linv_p = L_p^-1 (strict upper part zero), and per 64-column
+// block of each problem the partial 2 sum log L_jj into logd_p[block].
+// Right-looking with 64-column panels: one launch per panel for the diagonal
+// blocks of all problems, then the panel and trailing updates as batched
+// matrix-core GEMMs; the inverse is built block row by block row the same way.
+struct CholProblem {
+  double* A;
+  long long lda;
+  int n;
+  double* Linv;
+  long long ldi;
+  double* logd;  // ceil(n / 64) values, may be null
+};
+void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr, hipStream_t s);
+
+// dst(i, j) = src(i, j) for i < m, j < n (column-major); lower: zero for i < j
+struct CopyBlock {
+  const double* src;
+  long long lds;
+  double* dst;
+  long long ldd;
+  int m, n, lower;
+};
+void copy_blocks(const std::vector<CopyBlock>& jobs, Scratch& scr, hipStream_t s);
 
 // Tracing of the batched GEMM launches: HIP events around every launch on
 // its stream, with the algorithmic flops (2 M N K) and operand bytes counted.

@@ -280,6 +280,7 @@ __device__ void backsub_columns(double* A, long long ld, int k, int j0, int j1, 
 }
 
 constexpr int CPQR_MAXA = 512;
+constexpr int SCHUR_FUSED_MAXA = 128;
 constexpr int CPQR_MAXM = 4096;
 
 __global__ __launch_bounds__(256) void cpqr_box_kernel(const CpqrJob* __restrict__ jobs,
@@ -411,7 +412,8 @@ struct AsmJob {
   const int* piv;       // nullptr = identity
   int nchild;
   int coff[5];          // child segments of the active list
-  const double* xss[4]; // child X_ss (k_c x k_c, ld k_c); nullptr = use kernel entries
+  const double* xss[4]; // child X_ss (k_c x k_c); nullptr = use kernel entries
+  int xld[4];           // leading dimension of each child's X_ss
 };
 
 __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, KernelParams kp,
@@ -431,8 +433,7 @@ __global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict_
       }
     }
     if (cu >= 0 && cu == cw && J.xss[cu]) {
-      const int kc = J.coff[cu + 1] - J.coff[cu];
-      val = J.xss[cu][(long long)(w - J.coff[cu]) * kc + (u - J.coff[cu])];
+      val = J.xss[cu][(long long)(w - J.coff[cu]) * J.xld[cu] + (u - J.coff[cu])];
     } else {
       const int p = J.act[u], q = J.act[w];
       val = (p == q) ? kdiag(kp) : kentry(px[p] - px[q], py[p] - py[q], kp);
@@ -568,105 +569,9 @@ __global__ void split_kernel(const SplitJob* __restrict__ jobs) {
   }
 }
 
-// ------------------------------------------------------------------ root: blocked Cholesky
-// Diagonal block (nb <= 64) of L in place: Cholesky, log-diagonal, inverse.
-__global__ __launch_bounds__(256) void diag_chol_kernel(double* L, long long ld, int kb, int nb,
-                                                         double* Dinv, double* logd, int* fail) {
-  __shared__ double B[64][65];
-  __shared__ double I[64][65];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e % nb, j = e / nb;
-    B[i][j] = L[(long long)(kb + j) * ld + kb + i];
-  }
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    const double d = B[j][j];
-    if (!(d > 0.0)) {
-      if (tid == 0) *fail = 1;
-      return;
-    }
-    const double s = sqrt(d);
-    __syncthreads();
-    if (tid == 0) B[j][j] = s;
-    for (int i = j + 1 + tid; i < nb; i += 256) B[i][j] /= s;
-    __syncthreads();
-    for (int e = tid; e < nb * nb; e += 256) {
-      const int i = e % nb, l = e / nb;
-      if (l > j && i >= l) B[i][l] -= B[i][j] * B[l][j];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    double s = 0.0;
-    for (int j = 0; j < nb; ++j) s += log(B[j][j]);
-    *logd = 2.0 * s;
-  }
-  for (int c = tid; c < nb; c += 256) {
-    for (int i = 0; i < nb; ++i) I[i][c] = 0.0;
-    I[c][c] = 1.0 / B[c][c];
-    for (int i = c + 1; i < nb; ++i) {
-      double x = 0.0;
-      for (int l = c; l < i; ++l) x -= B[i][l] * I[l][c];
-      I[i][c] = x / B[i][i];
-    }
-  }
-  __syncthreads();
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e % nb, j = e / nb;
-    L[(long long)(kb + j) * ld + kb + i] = (i >= j) ? B[i][j] : 0.0;
-    Dinv[(long long)j * 64 + i] = I[i][j];
-  }
-}
-
 __global__ void triu_zero_kernel(double* A, int N) {
   for (int j = blockIdx.x; j < N; j += gridDim.x)
     for (int i = threadIdx.x; i < j; i += blockDim.x) A[(long long)j * N + i] = 0.0;
-}
-
-// Cholesky (lower) of the N x N matrix L (ld N) in place and Linv = L^-1;
-// log-determinant partials per diagonal block into logd[N/64 + 1].
-static void blocked_chol_inv(double* L, int N, double* Linv, double* logd, int* fail, Scratch& scr,
-                             hipStream_t s) {
-  const int nbk = (N + 63) / 64;
-  double* Dinv = scr.make<double>((size_t)nbk * 64 * 64);
-  double* P = scr.make<double>((size_t)N * 64);
-  for (int b = 0; b < nbk; ++b) {
-    const int kb = b * 64, nb = std::min(64, N - kb), rest = N - kb - nb;
-    hipLaunchKernelGGL(diag_chol_kernel, dim3(1), dim3(256), 0, s, L, (long long)N, kb, nb,
-                       Dinv + (size_t)b * 4096, logd + b, fail);
-    RSF_HIP(hipGetLastError());
-    if (rest > 0) {
-      // panel P = L(kb+nb:, kb:kb+nb) Dinv^T, copied back into L
-      std::vector<GemmDesc> g{gemm_desc(rest, nb, nb, 1.0, colmaj(L + (long long)kb * N + kb + nb, N),
-                                        colmajT(Dinv + (size_t)b * 4096, 64), 0.0, colmaj(P, rest))};
-      gemm_batched(g, scr, s);
-      RSF_HIP(hipMemcpy2DAsync(L + (long long)kb * N + kb + nb, N * sizeof(double), P,
-                               rest * sizeof(double), rest * sizeof(double), nb,
-                               hipMemcpyDeviceToDevice, s));
-      // trailing update L(rest, rest) -= P P^T
-      std::vector<GemmDesc> t{gemm_desc(rest, rest, nb, -1.0, colmaj(P, rest), colmajT(P, rest), 1.0,
-                                        colmaj(L + (long long)(kb + nb) * N + kb + nb, N))};
-      gemm_batched(t, scr, s);
-    }
-  }
-  // zero the strict upper triangle of L is not needed; build Linv block row by block row:
-  // Linv(i, 0:i) = -Dinv_i L(i, 0:i) Linv(0:i, 0:i),  Linv(i, i) = Dinv_i
-  fill_zero(Linv, (long long)N * N, s);
-  double* Q = scr.make<double>((size_t)N * 64);
-  for (int b = 0; b < nbk; ++b) {
-    const int kb = b * 64, nb = std::min(64, N - kb);
-    RSF_HIP(hipMemcpy2DAsync(Linv + (long long)kb * N + kb, N * sizeof(double), Dinv + (size_t)b * 4096,
-                             64 * sizeof(double), nb * sizeof(double), nb, hipMemcpyDeviceToDevice, s));
-    if (kb == 0) continue;
-    // Q (nb x kb) = L(kb:kb+nb, 0:kb) Linv(0:kb, 0:kb)
-    std::vector<GemmDesc> g1{gemm_desc(nb, kb, kb, 1.0, colmaj(L + kb, N), colmaj(Linv, N), 0.0,
-                                       colmaj(Q, nb))};
-    gemm_batched(g1, scr, s);
-    std::vector<GemmDesc> g2{gemm_desc(nb, kb, nb, -1.0, colmaj(Dinv + (size_t)b * 4096, 64), colmaj(Q, nb),
-                                       0.0, colmaj(Linv + kb, N))};
-    gemm_batched(g2, scr, s);
-  }
 }
 
 // ------------------------------------------------------------------ host driver
@@ -689,6 +594,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
   const int D = t.maxdepth, nprox = o.n_prox;
   Scratch keep(s);  // lives through the whole build: X_ss of the previous level
   std::vector<double*> xss(t.nbox(), nullptr);
+  std::vector<int> xld(t.nbox(), 0);
   std::vector<int> kbox(t.nbox(), 0);
   std::vector<const int*> sbox(t.nbox(), nullptr);
   std::vector<double> ld_parts;
@@ -937,6 +843,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
           for (int c : t.child[b])
             if (c >= 0) {
               J.xss[J.nchild] = mult ? nullptr : xss[c];
+              J.xld[J.nchild] = xld[c];
               J.coff[J.nchild + 1] = J.coff[J.nchild] + kbox[c];
               J.nchild++;
             }
@@ -949,13 +856,17 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       hipLaunchKernelGGL(assemble_kernel, dim3(nb, gy), dim3(256), 0, s, dj, F.kp, h->px, h->py);
       RSF_HIP(hipGetLastError());
     }
-    double* Xsr = mult ? L.W : scr.make<double>(std::max<long long>(L.total_t, 1));
+    int maxa = 0;
+    for (int i = 0; i < nb; ++i) maxa = std::max(maxa, L.a[i]);
     if (!mult) L.Lf = F.arena.make<double>(std::max<long long>(L.total_l, 1));
-    double* Lw = mult ? L.Lm : L.Lf;
-    double* Xss = mult ? nullptr : keep.make<double>(std::max<long long>(k2off[nb], 1));
-    double* ldp = scr.make<double>(nb);
-    fill_zero(ldp, nb, s);
-    {
+    // Ablk lives on (in `keep`) when the parent reads X_ss from it
+    const bool gemm_path = maxa > SCHUR_FUSED_MAXA;
+    if (!gemm_path) {
+      double* Xsr = mult ? L.W : scr.make<double>(std::max<long long>(L.total_t, 1));
+      double* Lw = mult ? L.Lm : L.Lf;
+      double* Xss = mult ? nullptr : keep.make<double>(std::max<long long>(k2off[nb], 1));
+      double* ldp = scr.make<double>(nb);
+      fill_zero(ldp, nb, s);
       std::vector<SchurJob> sj(nb);
       for (int i = 0; i < nb; ++i) {
         sj[i] = SchurJob{Ablk + a2off[i], Kaux + kaoff[i], mub[i], L.T + L.t_off[i], Xsr + L.t_off[i],
@@ -966,18 +877,88 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       upload(dj, sj, s);
       hipLaunchKernelGGL(schur_kernel, dim3(nb), dim3(256), 0, s, dj, mult);
       RSF_HIP(hipGetLastError());
-    }
-    if (!mult) {
-      std::vector<double> lh(nb);
-      RSF_HIP(hipMemcpyAsync(lh.data(), ldp, nb * sizeof(double), hipMemcpyDeviceToHost, s));
-      RSF_HIP(hipStreamSynchronize(s));
-      for (double v : lh) ld_parts.push_back(v);
+      if (!mult) {
+        std::vector<double> lh(nb);
+        RSF_HIP(hipMemcpyAsync(lh.data(), ldp, nb * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipStreamSynchronize(s));
+        for (double v : lh) ld_parts.push_back(v);
+      }
+      for (int i = 0; i < nb; ++i) {
+        xss[b0 + i] = mult ? nullptr : Xss + k2off[i];
+        xld[b0 + i] = kh[i];
+      }
+    } else {
+      // the same elimination as matrix-core GEMMs batched over the boxes, in
+      // place in the assembled blocks A = [A_ss A_sr; A_rs A_rr]
+      double* Akeep = keep.make<double>(std::max<long long>(a2off[nb], 1));
+      copy_dev(Akeep, Ablk, a2off[nb], s);
+      std::vector<CopyBlock> tc;
+      std::vector<GemmDesc> g1, g2, g3;
+      for (int i = 0; i < nb; ++i) {
+        const int a = L.a[i], k = kh[i], r = a - k;
+        double* A = Akeep + a2off[i];
+        double* T = L.T + L.t_off[i];
+        tc.push_back(CopyBlock{Kaux + kaoff[i] + (long long)k * mub[i], mub[i], T, k, k, r, 0});
+        g1.push_back(gemm_desc(k, r, k, -1.0, colmaj(A, a), colmaj(T, k), 1.0, colmaj(A + (long long)k * a, a)));
+        GemmDesc d2 = gemm_desc(r, r, k, -1.0, colmajT(T, k), colmaj(A + (long long)k * a, a), 1.0,
+                                colmaj(A + (long long)k * a + k, a));
+        GemmDesc d3 = gemm_desc(r, r, k, -1.0, colmaj(A + k, a), colmaj(T, k), 1.0, colmaj(A + (long long)k * a + k, a));
+        d2.lower = d3.lower = !mult;
+        g2.push_back(d2);
+        g3.push_back(d3);
+      }
+      copy_blocks(tc, scr, s);
+      gemm_batched(g1, scr, s);
+      gemm_batched(g2, scr, s);
+      gemm_batched(g3, scr, s);
+      if (mult) {
+        std::vector<CopyBlock> cp;
+        for (int i = 0; i < nb; ++i) {
+          const int a = L.a[i], k = kh[i], r = a - k;
+          double* A = Akeep + a2off[i];
+          cp.push_back(CopyBlock{A + (long long)k * a, a, L.W + L.t_off[i], k, k, r, 0});
+          cp.push_back(CopyBlock{A + (long long)k * a + k, a, L.Lm + L.l_off[i], r, r, r, 0});
+        }
+        copy_blocks(cp, scr, s);
+      } else {
+        std::vector<CholProblem> cps;
+        std::vector<long long> lo(nb + 1, 0);
+        for (int i = 0; i < nb; ++i) lo[i + 1] = lo[i] + (L.a[i] - kh[i] + 63) / 64;
+        double* logd = scr.make<double>(std::max<long long>(lo[nb], 1));
+        fill_zero(logd, lo[nb], s);
+        for (int i = 0; i < nb; ++i) {
+          const int a = L.a[i], k = kh[i], r = a - k;
+          cps.push_back(CholProblem{Akeep + a2off[i] + (long long)k * a + k, a, r, L.Lm + L.l_off[i], r, logd + lo[i]});
+        }
+        batched_chol_inv(cps, fail, scr, s);
+        std::vector<CopyBlock> cp;
+        std::vector<GemmDesc> gw, gx;
+        for (int i = 0; i < nb; ++i) {
+          const int a = L.a[i], k = kh[i], r = a - k;
+          double* A = Akeep + a2off[i];
+          cp.push_back(CopyBlock{A + (long long)k * a + k, a, L.Lf + L.l_off[i], r, r, r, 1});
+          gw.push_back(gemm_desc(k, r, r, 1.0, colmaj(A + (long long)k * a, a), colmajT(L.Lm + L.l_off[i], r), 0.0,
+                                 colmaj(L.W + L.t_off[i], k)));
+          gx.push_back(gemm_desc(k, k, r, -1.0, colmaj(L.W + L.t_off[i], k), colmajT(L.W + L.t_off[i], k), 1.0,
+                                 colmaj(A, a)));
+        }
+        copy_blocks(cp, scr, s);
+        gemm_batched(gw, scr, s);
+        gemm_batched(gx, scr, s);
+        std::vector<double> lh(lo[nb]);
+        if (!lh.empty()) RSF_HIP(hipMemcpyAsync(lh.data(), logd, lh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipStreamSynchronize(s));
+        for (double v : lh) ld_parts.push_back(v);
+      }
+      for (int i = 0; i < nb; ++i) {
+        xss[b0 + i] = mult ? nullptr : Akeep + a2off[i];
+        xld[b0 + i] = L.a[i];
+      }
     }
     for (int i = 0; i < nb; ++i) {
       const int b = b0 + i;
       kbox[b] = kh[i];
       sbox[b] = L.S + L.s_off[i];
-      xss[b] = mult ? nullptr : Xss + k2off[i];
     }
   }
   // root: the remaining DOFs of the top box
@@ -1003,6 +984,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         if (c >= 0) {
           if (kbox[c] > 0) cs.push_back({F.root_idx + o2, sbox[c], 0, kbox[c]});
           J.xss[J.nchild] = mult ? nullptr : xss[c];
+          J.xld[J.nchild] = xld[c];
           J.coff[J.nchild + 1] = J.coff[J.nchild] + kbox[c];
           J.nchild++;
           o2 += kbox[c];
@@ -1026,7 +1008,8 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         F.Lroot_inv = F.arena.make<double>((size_t)N * N);
         const int nbk = (N + 63) / 64;
         double* logd = scr.make<double>(nbk);
-        blocked_chol_inv(A, N, F.Lroot_inv, logd, fail, scr, s);
+        fill_zero(logd, nbk, s);
+        batched_chol_inv(std::vector<CholProblem>{CholProblem{A, N, N, F.Lroot_inv, N, logd}}, fail, scr, s);
         std::vector<double> lh(nbk);
         int fh = 0;
         RSF_HIP(hipMemcpyAsync(lh.data(), logd, nbk * sizeof(double), hipMemcpyDeviceToHost, s));

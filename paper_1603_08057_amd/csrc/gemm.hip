@@ -1,10 +1,80 @@
 // Batched FP64 GEMM on the gfx950 matrix cores, device memory helpers and
 // fixed-order reductions.
+#include <map>
+#include <mutex>
+
 #include "common.h"
 
 namespace rsf {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ---- device memory pool
+// Freed blocks are kept per size class and handed out again in stream order:
+// a block released on stream s is reused on s without a synchronisation (later
+// work on s runs after the work that used it); reuse on another stream waits
+// for the releasing stream first.  Size classes: four per power of two.
+namespace {
+struct FreeBlock {
+  void* p;
+  hipStream_t s;
+};
+struct Pool {
+  std::mutex mu;
+  std::map<size_t, std::vector<FreeBlock>> free;
+} g_pool;
+
+size_t size_class(size_t n) {
+  if (n <= 4096) return 4096;
+  size_t top = size_t(1) << (63 - __builtin_clzll(n));
+  size_t step = top / 4;
+  return (n + step - 1) / step * step;
+}
+}  // namespace
+
+void* pool_alloc(size_t nbytes, hipStream_t s) {
+  const size_t c = size_class(nbytes);
+  {
+    std::lock_guard<std::mutex> lk(g_pool.mu);
+    auto it = g_pool.free.find(c);
+    if (it != g_pool.free.end() && !it->second.empty()) {
+      auto& v = it->second;
+      for (size_t i = v.size(); i-- > 0;)
+        if (v[i].s == s) {
+          void* p = v[i].p;
+          v.erase(v.begin() + i);
+          return p;
+        }
+      FreeBlock b = v.back();
+      v.pop_back();
+      RSF_HIP(hipStreamSynchronize(b.s));
+      return b.p;
+    }
+  }
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, c);
+  if (e != hipSuccess) {
+    // give cached blocks back to the device and try once more
+    (void)hipGetLastError();
+    pool_trim();
+    RSF_HIP(hipMalloc(&p, c));
+  }
+  return p;
+}
+
+void pool_free(void* p, size_t nbytes, hipStream_t s) {
+  if (!p) return;
+  std::lock_guard<std::mutex> lk(g_pool.mu);
+  g_pool.free[size_class(nbytes)].push_back(FreeBlock{p, s});
+}
+
+void pool_trim() {
+  (void)hipDeviceSynchronize();
+  std::lock_guard<std::mutex> lk(g_pool.mu);
+  for (auto& kv : g_pool.free)
+    for (auto& b : kv.second) (void)hipFree(b.p);
+  g_pool.free.clear();
+}
 
 void* Arena::alloc(size_t nbytes) {
   if (nbytes == 0) nbytes = 8;
@@ -12,31 +82,31 @@ void* Arena::alloc(size_t nbytes) {
   RSF_CHECK(cap == 0 || bytes + nbytes <= cap, RSF_E_OOM,
             "factor memory cap exceeded (" + std::to_string(bytes + nbytes) + " > " +
                 std::to_string(cap) + " bytes)");
-  void* p = nullptr;
-  RSF_HIP(hipMalloc(&p, nbytes));
+  void* p = pool_alloc(nbytes, nullptr);
   blocks.push_back(p);
+  sizes.push_back(nbytes);
   bytes += nbytes;
   return p;
 }
 
 void Arena::release() {
-  for (void* p : blocks) (void)hipFree(p);
+  if (!blocks.empty()) (void)hipDeviceSynchronize();
+  for (size_t i = 0; i < blocks.size(); ++i) pool_free(blocks[i], sizes[i], nullptr);
   blocks.clear();
+  sizes.clear();
   bytes = 0;
 }
 
 void* Scratch::alloc(size_t nbytes) {
   if (nbytes == 0) nbytes = 8;
-  nbytes = (nbytes + 255) & ~size_t(255);
-  void* p = nullptr;
-  RSF_HIP(hipMalloc(&p, nbytes));
+  void* p = pool_alloc(nbytes, stream);
   blocks.push_back(p);
+  sizes.push_back(nbytes);
   return p;
 }
 
 Scratch::~Scratch() {
-  if (!blocks.empty()) (void)hipStreamSynchronize(stream);
-  for (void* p : blocks) (void)hipFree(p);
+  for (size_t i = 0; i < blocks.size(); ++i) pool_free(blocks[i], sizes[i], stream);
 }
 
 // One 256-thread workgroup computes a 64 x 64 tile of C; each of the four
@@ -168,13 +238,14 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   double flops = 0.0, bytes = 0.0;
   for (const GemmDesc& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
-    flops += 2.0 * d.M * d.N * d.K;
+    flops += (d.lower ? 1.0 : 2.0) * d.M * d.N * d.K;
     bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     const int p = (int)live.size();
     live.push_back(d);
     const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
     for (int a = 0; a < tm; ++a)
-      for (int b = 0; b < tn; ++b) tiles.push_back(make_int4(p, a, b, 0));
+      for (int b = 0; b < tn; ++b)
+        if (!d.lower || b <= a) tiles.push_back(make_int4(p, a, b, 0));
   }
   if (tiles.empty()) return;
   GemmDesc* dd = scr.make<GemmDesc>(live.size());
@@ -196,6 +267,162 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     g_trace.flops += flops;
     g_trace.bytes += bytes;
     g_trace.launches += 1;
+  }
+}
+
+// ---- batched blocked Cholesky with inverse
+__global__ __launch_bounds__(256) void copy_blocks_kernel(const CopyBlock* __restrict__ jobs) {
+  const CopyBlock J = jobs[blockIdx.x];
+  const long long tot = (long long)J.m * J.n;
+  for (long long e = blockIdx.y * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.y) {
+    const int i = (int)(e % J.m), j = (int)(e / J.m);
+    J.dst[(long long)j * J.ldd + i] = (J.lower && i < j) ? 0.0 : J.src[(long long)j * J.lds + i];
+  }
+}
+
+void copy_blocks(const std::vector<CopyBlock>& jobs, Scratch& scr, hipStream_t s) {
+  std::vector<CopyBlock> live;
+  long long mx = 1;
+  for (const CopyBlock& j : jobs)
+    if (j.m > 0 && j.n > 0) {
+      live.push_back(j);
+      mx = std::max(mx, (long long)j.m * j.n);
+    }
+  if (live.empty()) return;
+  CopyBlock* d = scr.make<CopyBlock>(live.size());
+  upload(d, live, s);
+  const unsigned gy = (unsigned)std::max<long long>(1, std::min<long long>(64, (mx + 2047) / 2048));
+  hipLaunchKernelGGL(copy_blocks_kernel, dim3((unsigned)live.size(), gy), dim3(256), 0, s, d);
+  RSF_HIP(hipGetLastError());
+}
+
+struct DiagJob {
+  double* A;  // the diagonal block, ld lda
+  long long lda;
+  int nb;
+  double* Dinv;  // 64 x 64
+  double* logd;  // one value or null
+};
+
+// Cholesky of one diagonal block (nb <= 64) in LDS, written back in place
+// (zero above the diagonal), its log-diagonal sum and its inverse.
+__global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* __restrict__ jobs, int* fail) {
+  __shared__ double B[64][65];
+  __shared__ double I[64][65];
+  const DiagJob J = jobs[blockIdx.x];
+  const int nb = J.nb, tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int i = e % nb, j = e / nb;
+    B[i][j] = J.A[(long long)j * J.lda + i];
+  }
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    const double d = B[j][j];
+    if (!(d > 0.0)) {
+      if (tid == 0) *fail = 1;
+      return;
+    }
+    const double sq = sqrt(d);
+    __syncthreads();
+    if (tid == 0) B[j][j] = sq;
+    for (int i = j + 1 + tid; i < nb; i += 256) B[i][j] /= sq;
+    __syncthreads();
+    for (int e = tid; e < nb * nb; e += 256) {
+      const int i = e % nb, l = e / nb;
+      if (l > j && i >= l) B[i][l] -= B[i][j] * B[l][j];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && J.logd) {
+    double sm = 0.0;
+    for (int j = 0; j < nb; ++j) sm += log(B[j][j]);
+    *J.logd = 2.0 * sm;
+  }
+  for (int c = tid; c < nb; c += 256) {
+    for (int i = 0; i < nb; ++i) I[i][c] = 0.0;
+    I[c][c] = 1.0 / B[c][c];
+    for (int i = c + 1; i < nb; ++i) {
+      double x = 0.0;
+      for (int l = c; l < i; ++l) x -= B[i][l] * I[l][c];
+      I[i][c] = x / B[i][i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += 256) {
+    const int i = e % nb, j = e / nb;
+    J.A[(long long)j * J.lda + i] = (i >= j) ? B[i][j] : 0.0;
+    J.Dinv[(long long)j * 64 + i] = I[i][j];
+  }
+}
+
+void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr, hipStream_t s) {
+  int maxn = 0;
+  std::vector<long long> doff(P.size() + 1, 0), qoff(P.size() + 1, 0);
+  for (size_t p = 0; p < P.size(); ++p) {
+    maxn = std::max(maxn, P[p].n);
+    doff[p + 1] = doff[p] + (long long)((P[p].n + 63) / 64) * 4096;
+    qoff[p + 1] = qoff[p] + (long long)64 * std::max(P[p].n, 1);
+  }
+  if (maxn == 0) return;
+  double* Dinv = scr.make<double>(std::max<long long>(doff.back(), 1));
+  double* Q = scr.make<double>(std::max<long long>(qoff.back(), 1));
+  const int nbk = (maxn + 63) / 64;
+  for (int b = 0; b < nbk; ++b) {
+    const int kb = b * 64;
+    std::vector<DiagJob> dj;
+    std::vector<GemmDesc> pan, trl;
+    for (size_t p = 0; p < P.size(); ++p) {
+      const CholProblem& c = P[p];
+      if (c.n <= kb) continue;
+      const int nb = std::min(64, c.n - kb), rest = c.n - kb - nb;
+      double* Akk = c.A + (long long)kb * c.lda + kb;
+      double* Dk = Dinv + doff[p] + (long long)b * 4096;
+      dj.push_back(DiagJob{Akk, c.lda, nb, Dk, c.logd ? c.logd + b : nullptr});
+      if (rest > 0) {
+        // panel L(kb+nb:, kb:kb+nb) = A(kb+nb:, kb:kb+nb) Dinv^T, in place (one
+        // tile column: every tile reads its rows completely before writing them)
+        double* Pn = c.A + (long long)kb * c.lda + kb + nb;
+        pan.push_back(gemm_desc(rest, nb, nb, 1.0, colmaj(Pn, c.lda), colmajT(Dk, 64), 0.0, colmaj(Pn, c.lda)));
+        GemmDesc t = gemm_desc(rest, rest, nb, -1.0, colmaj(Pn, c.lda), colmajT(Pn, c.lda), 1.0,
+                               colmaj(c.A + (long long)(kb + nb) * c.lda + kb + nb, c.lda));
+        t.lower = 1;
+        trl.push_back(t);
+      }
+    }
+    if (!dj.empty()) {
+      DiagJob* d = scr.make<DiagJob>(dj.size());
+      upload(d, dj, s);
+      hipLaunchKernelGGL(diag_chol_batched_kernel, dim3((unsigned)dj.size()), dim3(256), 0, s, d, fail);
+      RSF_HIP(hipGetLastError());
+    }
+    gemm_batched(pan, scr, s);
+    gemm_batched(trl, scr, s);
+  }
+  // inverse: Linv(i, i) = Dinv_i;  Linv(i, 0:i) = -Dinv_i L(i, 0:i) Linv(0:i, 0:i)
+  for (const CholProblem& c : P)
+    if (c.n > 0) {
+      RSF_HIP(hipMemset2DAsync(c.Linv, c.ldi * sizeof(double), 0, c.n * sizeof(double), c.n, s));
+    }
+  for (int b = 0; b < nbk; ++b) {
+    const int kb = b * 64;
+    std::vector<CopyBlock> cp;
+    std::vector<GemmDesc> g1, g2;
+    for (size_t p = 0; p < P.size(); ++p) {
+      const CholProblem& c = P[p];
+      if (c.n <= kb) continue;
+      const int nb = std::min(64, c.n - kb);
+      const double* Dk = Dinv + doff[p] + (long long)b * 4096;
+      cp.push_back(CopyBlock{Dk, 64, c.Linv + (long long)kb * c.ldi + kb, c.ldi, nb, nb, 1});
+      if (kb > 0) {
+        double* Qp = Q + qoff[p];
+        g1.push_back(gemm_desc(nb, kb, kb, 1.0, colmaj(c.A + kb, c.lda), colmaj(c.Linv, c.ldi), 0.0,
+                               colmaj(Qp, nb)));
+        g2.push_back(gemm_desc(nb, kb, nb, -1.0, colmaj(Dk, 64), colmaj(Qp, nb), 0.0, colmaj(c.Linv + kb, c.ldi)));
+      }
+    }
+    copy_blocks(cp, scr, s);
+    gemm_batched(g1, scr, s);
+    gemm_batched(g2, scr, s);
   }
 }
 

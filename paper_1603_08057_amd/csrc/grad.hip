@@ -122,26 +122,6 @@ __global__ __launch_bounds__(256) void leaf_trace_kernel(const int* __restrict__
 
 // ------------------------------------------------------------------ small dense factorizations
 // All run one workgroup per matrix on column-major blocks in global memory.
-__device__ bool wg_chol_lower(double* A, long long lda, int n) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int j = 0; j < n; ++j) {
-    const double d = A[(long long)j * lda + j];
-    if (!(d > 0.0)) return false;
-    const double ljj = sqrt(d);
-    __syncthreads();
-    if (tid == 0) A[(long long)j * lda + j] = ljj;
-    for (int i = j + 1 + tid; i < n; i += nt) A[(long long)j * lda + i] /= ljj;
-    __syncthreads();
-    const long long rem = n - j - 1;
-    for (long long e = tid; e < rem * rem; e += nt) {
-      const int ii = j + 1 + (int)(e % rem), ll = j + 1 + (int)(e / rem);
-      if (ii >= ll) A[(long long)ll * lda + ii] -= A[(long long)j * lda + ii] * A[(long long)j * lda + ll];
-    }
-    __syncthreads();
-  }
-  return true;
-}
-
 __device__ void wg_tri_inv_lower(const double* L, long long ldl, double* Li, long long ldi, int n) {
   for (int c = threadIdx.x; c < n; c += blockDim.x) {
     double* col = Li + (long long)c * ldi;
@@ -176,13 +156,14 @@ struct PcholJob {
 };
 
 constexpr int PCHOL_MAXN = 4096;
+constexpr int PCHOL_WG = 1024;
 
-__global__ __launch_bounds__(256) void pchol_kernel(const PcholJob* __restrict__ jobs, double tol2) {
+__global__ __launch_bounds__(PCHOL_WG) void pchol_kernel(const PcholJob* __restrict__ jobs, double tol2) {
   __shared__ double d[PCHOL_MAXN];
   __shared__ unsigned char done[PCHOL_MAXN];
   __shared__ double lp[PCHOL_MAXN];
-  __shared__ double red_v[256];
-  __shared__ int red_i[256];
+  __shared__ double red_v[PCHOL_WG];
+  __shared__ int red_i[PCHOL_WG];
   const PcholJob J = jobs[blockIdx.x];
   const int n = J.n, tid = threadIdx.x, nt = blockDim.x;
   const double* G = J.G;
@@ -238,9 +219,18 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholJob* __restrict__
       } else if (done[j]) {
         x = 0.0;
       } else {
-        x = G[(long long)p * n + j];
-        for (int l = 0; l < s; ++l) x -= L[(long long)l * n + j] * lp[l];
-        x /= lss;
+        // four independent partial sums keep several loads in flight
+        double x0 = G[(long long)p * n + j], x1 = 0.0, x2 = 0.0, x3 = 0.0;
+        const double* Lj = L + j;
+        int l = 0;
+        for (; l + 3 < s; l += 4) {
+          x0 -= Lj[(long long)l * n] * lp[l];
+          x1 -= Lj[(long long)(l + 1) * n] * lp[l + 1];
+          x2 -= Lj[(long long)(l + 2) * n] * lp[l + 2];
+          x3 -= Lj[(long long)(l + 3) * n] * lp[l + 3];
+        }
+        for (; l < s; ++l) x0 -= Lj[(long long)l * n] * lp[l];
+        x = ((x0 + x1) + (x2 + x3)) / lss;
         d[j] -= x * x;
       }
       L[(long long)s * n + j] = x;
@@ -257,24 +247,6 @@ __global__ __launch_bounds__(256) void pchol_kernel(const PcholJob* __restrict__
   __syncthreads();
   wg_tri_inv_lower(J.L1, n, J.Linv, n, k);
   if (tid == 0) *J.kout = k;
-}
-
-// Cholesky + inverse of SPD matrices (normal equations of the core matrix).
-struct CholJob {
-  double* A;
-  int n;
-  double* Linv;
-  int* fail;
-};
-
-__global__ __launch_bounds__(256) void chol_inv_kernel(const CholJob* __restrict__ jobs) {
-  const CholJob J = jobs[blockIdx.x];
-  if (J.n == 0) return;
-  if (!wg_chol_lower(J.A, J.n, J.n)) {
-    if (threadIdx.x == 0) *J.fail = 1;
-    return;
-  }
-  wg_tri_inv_lower(J.A, J.n, J.Linv, J.n, J.n);
 }
 
 // ------------------------------------------------------------------ host side
@@ -485,7 +457,7 @@ struct Peeler {
         // relative pivots below ~1e-13 of the Gram diagonal are rounding noise
         // (the Gram squares the singular values), so the threshold is floored there
         const double tol2 = std::max(eps_peel * eps_peel, 1e-13);
-        hipLaunchKernelGGL(pchol_kernel, dim3((unsigned)pj.size()), dim3(256), 0, s, dj, tol2);
+        hipLaunchKernelGGL(pchol_kernel, dim3((unsigned)pj.size()), dim3(PCHOL_WG), 0, s, dj, tol2);
         RSF_HIP(hipGetLastError());
         RSF_HIP(hipMemcpyAsync(rk.data(), dk, rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
         RSF_HIP(hipStreamSynchronize(s));
@@ -572,7 +544,7 @@ struct Peeler {
         L.pos_i.resize(np);
         L.pos_j.resize(np);
         std::vector<GemmDesc> ga, gb, gc, gd, ge, gf;
-        std::vector<CholJob> cj;
+        std::vector<CholProblem> cj;
         for (int p = 0; p < np; ++p) {
           const int bi = pairs[p].first, bj = pairs[p].second;
           const int k1 = rk[op * nblk + 2 * p], k2 = rk[op * nblk + 2 * p + 1];
@@ -603,8 +575,8 @@ struct Peeler {
           // T1 = A1^T C (k1 x total); T2 = T1 A2^T (k1 x k2)
           gb.push_back(gemm_desc(k1, total, total, 1.0, colmajT(A1 + a1o[p], total), colmaj(Cm + co[p], total), 0.0,
                                  colmaj(T1 + po[p], k1)));
-          cj.push_back(CholJob{N1 + n1o[p], k1, N1i + n1o[p], fail});
-          cj.push_back(CholJob{N2 + n2o[p], k2, N2i + n2o[p], fail});
+          cj.push_back(CholProblem{N1 + n1o[p], k1, k1, N1i + n1o[p], k1, nullptr});
+          cj.push_back(CholProblem{N2 + n2o[p], k2, k2, N2i + n2o[p], k2, nullptr});
           gc.push_back(gemm_desc(k1, k2, total, 1.0, colmaj(T1 + po[p], k1), colmajT(A2 + a2o[p], k2), 0.0,
                                  colmaj(T2 + po[p], k1)));
           // M = N1^-1 T2 N2^-1 with N^-1 = Linv^T Linv
@@ -619,12 +591,7 @@ struct Peeler {
         }
         gemm_batched(ga, ms, s);
         gemm_batched(gb, ms, s);
-        if (!cj.empty()) {
-          CholJob* dcj = ms.make<CholJob>(cj.size());
-          upload(dcj, cj, s);
-          hipLaunchKernelGGL(chol_inv_kernel, dim3((unsigned)cj.size()), dim3(256), 0, s, dcj);
-          RSF_HIP(hipGetLastError());
-        }
+        batched_chol_inv(cj, fail, ms, s);
         gemm_batched(gc, ms, s);
         gemm_batched(gd, ms, s);
         gemm_batched(ge, ms, s);

@@ -1,7 +1,8 @@
 """Writes dense-oracle reference values for the named workloads into
 tests/golden/<workload>_dense.json.  Calls only oracle.dense (dense FP64
-Cholesky).  The n = 65536 workload needs about 35 GB of host memory and tens
-of minutes on 8 cores.
+Cholesky; for n > 20000 the blocked in-place factorization, which gives l,
+log|Sigma| and Sigma^-1 z but not the score).  The n = 65536 workload needs
+about 35 GB of host memory and tens of minutes on 8 cores.
 
   python tests/golden/make_dense_golden.py c3_matern32_n65536
   python tests/golden/make_dense_golden.py c2_rq_n16384
@@ -32,7 +33,13 @@ def main():
     Z = W.gaussian((n, nrhs), spec["w_seed"]) if nrhs > 1 else W.gaussian(n, spec["w_seed"])
     z = Z if nrhs == 1 else Z[:, 0]
     t0 = time.time()
-    o = dense.loglik_and_grad(P, z, spec["theta"], spec["kernel"], spec["alpha"], block=2048, want_terms=True)
+    if n <= 20000:
+        o = dense.loglik_and_grad(P, z, spec["theta"], spec["kernel"], spec["alpha"], block=2048, want_terms=True)
+    else:
+        # the score needs Sigma^-1 (a second n x n buffer): beyond this host's
+        # memory at n = 65536, so only l, log|Sigma| and Sigma^-1 z are written
+        ell, logdet, a = dense.loglik_large(P, z, spec["theta"], spec["kernel"], spec["alpha"])
+        o = {"ell": ell, "logdet": logdet, "alpha": a}
     secs = time.time() - t0
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(n, size=min(n, 64), replace=False))
@@ -41,7 +48,9 @@ def main():
         "n": n, "kernel": spec["kernel"], "theta": list(spec["theta"]), "alpha_rq": spec["alpha"],
         "z": "workloads.gaussian(n, %d) (first column when several)" % spec["w_seed"],
         "ell": o["ell"], "logdet": o["logdet"], "ztSinvz": float(z @ o["alpha"]),
-        "g": list(map(float, o["g"])), "q": list(map(float, o["q"])), "t": list(map(float, o["t"])),
+        "g": list(map(float, o["g"])) if "g" in o else None,
+        "q": list(map(float, o["q"])) if "q" in o else None,
+        "t": list(map(float, o["t"])) if "t" in o else None,
         "alpha_index": sample.tolist(), "alpha_value": [float(o["alpha"][i]) for i in sample],
         "oracle_seconds": secs,
         "generator": "tests/golden/make_dense_golden.py (oracle.dense only)",

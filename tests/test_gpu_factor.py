@@ -25,6 +25,10 @@ pytestmark = pytest.mark.gpu
 
 SOLVE_RTOL = 1e-8
 LOGDET_RTOL = 1e-11
+# F^(1/2) carries the Cholesky factors of the redundant blocks themselves, whose
+# forward error is kappa(X_rr) u r (kappa up to ~1e6 at a 1e-4 nugget), not the
+# backward-stable products F and F^-1
+SQRT_RTOL = 1e-6
 
 
 def _t(x):
@@ -60,7 +64,7 @@ def _check_parity(P, theta, kernel, eps, leaf, n_prox=256, rings=4, alpha=1.0, n
     assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
     V = F.apply_sqrt(_t(B)).cpu().numpy()
     Vo = O.from_tree(O.sqrt(O.to_tree(B)))
-    assert np.linalg.norm(V - Vo) <= 1e-12 * np.linalg.norm(Vo)
+    assert np.linalg.norm(V - Vo) <= SQRT_RTOL * np.linalg.norm(Vo)
     z = B[:, 0]
     ell = F.loglik(_t(z))
     ello = -0.5 * float(z @ Xo[:, 0]) - 0.5 * O.logdet - 0.5 * n * math.log(2 * math.pi)
@@ -78,7 +82,11 @@ def test_small_matern32_single_ring():
     ell_d, logdet_d, a_d = dense.loglik(P, z, spec["theta"], spec["kernel"])
     assert abs(F.logdet - logdet_d) <= 10 * spec["eps"] * abs(logdet_d)
     ell = F.loglik(_t(z))
-    assert abs(ell - ell_d) <= 10 * spec["eps"] * abs(ell_d)
+    # l = -1/2 z^T a - 1/2 log|S| - (n/2) log 2pi sums three terms that largely
+    # cancel (here l ~ 314 against terms ~ 1e3), so its error is measured
+    # relative to the magnitude of the terms
+    scale = 0.5 * abs(float(z @ a_d)) + 0.5 * abs(logdet_d) + 0.5 * 1024 * math.log(2 * math.pi)
+    assert abs(ell - ell_d) <= 10 * spec["eps"] * scale
 
 
 def test_ragged_matern52():
