@@ -113,7 +113,7 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.time() - t0
     R.trace_enable(False)
-    ms, flops, nbytes, launches = R.trace_read(reset=True)
+    ms, flops, nbytes, launches, phases = R.trace_read(reset=True, phases=True)
     ms_per_step = 1000.0 * elapsed / args.steps
     achieved = (flops / (ms * 1e-3)) / 1e12 if ms > 0 else 0.0
     out = {
@@ -138,7 +138,10 @@ def main():
                      "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
                      "launches": launches, "kernel_ms_per_step": ms / args.steps,
                      "flops_per_launch": flops / max(launches, 1),
-                     "avg_launch_us": 1000.0 * ms / max(launches, 1)},
+                     "avg_launch_us": 1000.0 * ms / max(launches, 1),
+                     "phases": {k: {"ms_per_step": v[0] / args.steps,
+                                    "tflops": (v[1] / (v[0] * 1e-3) / 1e12) if v[0] > 0 else 0.0}
+                                for k, v in sorted(phases.items())}},
         "result": {"loglik": ell, "grad": g, "peel_cols": list(info.peel_cols)[:12],
                    "peel_rank": list(info.peel_rank)[:12]},
     }

@@ -132,7 +132,7 @@ typedef struct {
 } rsf_grad_info;
 
 /* Score equations g (eq. gradient; Algorithm 1): for theta = (rho, sigma2,
- * nugget),
+ * nugget) (eps_peel <= 0 selects the factorization tolerance eps),
  *   g_i = q_i - t_i / 2,  q_i = 1/2 alpha^T Sigma_i alpha,  t_i = Tr(F^-1 Sigma_i),
  * with Sigma_rho represented by its own skeletonization (multiply-only form),
  * Sigma_sigma2 = (Sigma - nugget I) / sigma2 and Sigma_nugget = I, and the
@@ -176,6 +176,11 @@ rsf_status rsf_skeleton_export(rsf_factor f, int level, int32_t* offsets, int32_
 rsf_status rsf_trace_enable(int on);
 rsf_status rsf_trace_read(double* gemm_ms, double* gemm_flops, double* gemm_bytes, int64_t* gemm_launches,
                           int reset);
+/* The same GEMM time split by phase, as "phase:ms:flops;..." (NUL-terminated,
+ * truncated to len - 1 characters); call after rsf_trace_read without reset.
+ * Phases: factor, factor_rho, chol, sweep_solve, sweep_mult, sweep_sqrt,
+ * peel_subtract, peel_gram, peel_lowrank. */
+rsf_status rsf_trace_phases(char* buf, size_t len);
 
 /* Message describing the last error on this thread ("" if none). */
 const char* rsf_last_error(void);

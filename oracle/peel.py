@@ -17,8 +17,9 @@ factorization (boxes are contiguous ranges of tree order):
   with orth by column-pivoted QR truncated where |R_jj| <= eps_peel |R_11|.
 * ranks are found adaptively (the paper says "an adaptive procedure is used"):
   c columns per quadrant block are drawn; if some sibling block needs rank
-  k > c - oversample (and c is still below the block's column count), another
-  c columns are drawn and only the new ones are applied.
+  k > c - oversample (and c is still below the block's column count), the
+  count grows by half (at least to the rank found plus twice the
+  oversampling) and only the new columns are applied.
 * extraction (Section 3.2.4): E has one identity block per leaf in n_L columns,
   H = (G - sum_m G^(m)) E, and Tr G ~= sum over leaves of Tr H(I_i, 1:n_i).
 
@@ -49,13 +50,30 @@ def orth(Y, eps):
     return Q[:, :k]
 
 
-def next_cols(prev_rank):
-    """Initial probe count per quadrant block at the next level: three quarters
-    of the largest rank found above plus the oversampling, rounded up to a
-    multiple of 8, at least MIN_COLS."""
-    c = (3 * prev_rank + 3) // 4 + OVERSAMPLE
-    c = max(MIN_COLS, c)
+def round8(c):
     return (c + 7) // 8 * 8
+
+
+def first_cols(n):
+    """Probe count at the first peeled level: the top-level sibling blocks have
+    ranks that grow like sqrt(n) (Section 3.3), so 4.5 sqrt(n), at least
+    FIRST_COLS, rounded up to a multiple of 8."""
+    import math
+    return round8(max(FIRST_COLS, 9 * math.isqrt(n) // 2))
+
+
+def next_cols(prev_rank):
+    """Initial probe count per quadrant block at the next level: the largest
+    rank found above scaled by 0.85, plus the oversampling, at least MIN_COLS,
+    rounded up to a multiple of 8."""
+    c = (17 * prev_rank + 19) // 20 + OVERSAMPLE
+    return round8(max(MIN_COLS, c))
+
+
+def grow_cols(total, maxrank):
+    """Probe count after a level whose ranks were not resolved: 1.5x, at least
+    the largest rank found plus twice the oversampling."""
+    return round8(max((3 * total + 1) // 2, maxrank + 2 * OVERSAMPLE))
 
 
 class Peeler:
@@ -107,7 +125,7 @@ class Peeler:
                 for op in range(self.nop):
                     self.blocks[op].append({})
                 continue
-            c = FIRST_COLS if prev is None else next_cols(prev)
+            c = first_cols(n) if prev is None else next_cols(prev)
             total = 0
             Om = {b: np.zeros((t.count[b], 0)) for b in boxes}
             Y = [{b: np.zeros((t.count[b], 0)) for b in boxes} for _ in range(self.nop)]
@@ -142,7 +160,7 @@ class Peeler:
                                 need = True
                 if not need:
                     break
-                c = 2 * total
+                c = grow_cols(total, maxrank)
             prev = maxrank
             self.cols[lev] = total
             self.ranks[lev] = maxrank

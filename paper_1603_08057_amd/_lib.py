@@ -67,6 +67,7 @@ def load():
         "rsf_last_error": ([], C.c_char_p),
         "rsf_trace_enable": ([C.c_int], C.c_int),
         "rsf_trace_read": ([dp, dp, dp, C.POINTER(C.c_int64), C.c_int], C.c_int),
+        "rsf_trace_phases": ([C.c_char_p, C.c_size_t], C.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -114,11 +115,23 @@ def trace_enable(on=True):
     _check(load().rsf_trace_enable(1 if on else 0))
 
 
-def trace_read(reset=False):
-    """(kernel ms, flops, bytes, launches) accumulated while tracing was on."""
+def trace_read(reset=False, phases=False):
+    """(kernel ms, flops, bytes, launches) accumulated while tracing was on;
+    with phases=True also a dict phase -> (ms, flops)."""
     ms, fl, by, n = C.c_double(), C.c_double(), C.c_double(), C.c_int64()
-    _check(load().rsf_trace_read(C.byref(ms), C.byref(fl), C.byref(by), C.byref(n), 1 if reset else 0))
-    return ms.value, fl.value, by.value, n.value
+    _check(load().rsf_trace_read(C.byref(ms), C.byref(fl), C.byref(by), C.byref(n), 0))
+    ph = {}
+    if phases:
+        buf = C.create_string_buffer(8192)
+        _check(load().rsf_trace_phases(buf, 8192))
+        for item in buf.value.decode().split(";"):
+            if item:
+                name, t, f = item.split(":")
+                ph[name] = (float(t), float(f))
+    if reset:
+        _check(load().rsf_trace_read(None, None, None, None, 1))
+    out = (ms.value, fl.value, by.value, n.value)
+    return out + (ph,) if phases else out
 
 
 class Factor:

@@ -268,6 +268,15 @@ rsf_status rsf_trace_read(double* gemm_ms, double* gemm_flops, double* gemm_byte
   });
 }
 
+rsf_status rsf_trace_phases(char* buf, size_t len) {
+  return guarded([&] {
+    RSF_CHECK(buf != nullptr && len > 0, RSF_E_INVALID, "null buffer");
+    const std::string t = trace_tags();
+    std::strncpy(buf, t.c_str(), len - 1);
+    buf[len - 1] = 0;
+  });
+}
+
 rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
                     rsf_grad_info* info, void* stream) {
   return guarded([&] { grad_eval(f, d_z, eps_peel, seed, g, info, stream); });

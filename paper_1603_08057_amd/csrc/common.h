@@ -149,7 +149,8 @@ struct CholProblem {
 };
 void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr, hipStream_t s);
 
-// dst(i, j) = src(i, j) for i < m, j < n (column-major); lower: zero for i < j
+// dst(i, j) = src(i, j) for i < m, j < n (column-major); lower: zero for i < j;
+// src == nullptr: zero fill
 struct CopyBlock {
   const double* src;
   long long lds;
@@ -163,6 +164,14 @@ void copy_blocks(const std::vector<CopyBlock>& jobs, Scratch& scr, hipStream_t s
 // its stream, with the algorithmic flops (2 M N K) and operand bytes counted.
 void trace_enable(bool on);
 void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset);
+// "tag:ms:flops;..." per call-site tag (read after trace_read)
+std::string trace_tags();
+// Names the GEMM launches issued while it is alive (for the per-phase split).
+struct TraceTag {
+  std::string prev;
+  explicit TraceTag(const char* t);
+  ~TraceTag();
+};
 
 // Reproducible sum of n doubles (fixed reduction tree) into *out (device).
 void device_sum(const double* x, long long n, double* out, Scratch& scr, hipStream_t s);

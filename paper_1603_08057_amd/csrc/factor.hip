@@ -578,6 +578,7 @@ __global__ void triu_zero_kernel(double* A, int N) {
 static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
 
 void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
+  TraceTag tag(mult ? "factor_rho" : "factor");
   const Tree& t = h->tree;
   const Options& o = h->opt;
   F.mult = mult;

@@ -202,24 +202,34 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
 
 // ---- launch tracing of the batched GEMM (events on the launch stream)
 namespace {
+struct TraceEv {
+  hipEvent_t a, b;
+  std::string tag;
+};
 struct GemmTrace {
   bool on = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  std::vector<TraceEv> ev;
   double ms = 0.0, flops = 0.0, bytes = 0.0;
   long long launches = 0;
+  std::string tag = "other";
+  std::map<std::string, double> tag_ms, tag_flops;
 } g_trace;
-}
+}  // namespace
 
 void trace_enable(bool on) { g_trace.on = on; }
+
+TraceTag::TraceTag(const char* t) : prev(g_trace.tag) { g_trace.tag = t; }
+TraceTag::~TraceTag() { g_trace.tag = prev; }
 
 void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset) {
   for (auto& e : g_trace.ev) {
     float t = 0.f;
-    RSF_HIP(hipEventSynchronize(e.second));
-    RSF_HIP(hipEventElapsedTime(&t, e.first, e.second));
+    RSF_HIP(hipEventSynchronize(e.b));
+    RSF_HIP(hipEventElapsedTime(&t, e.a, e.b));
     g_trace.ms += t;
-    (void)hipEventDestroy(e.first);
-    (void)hipEventDestroy(e.second);
+    g_trace.tag_ms[e.tag] += t;
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
   }
   g_trace.ev.clear();
   if (ms) *ms = g_trace.ms;
@@ -229,11 +239,144 @@ void trace_read(double* ms, double* flops, double* bytes, long long* launches, b
   if (reset) {
     g_trace.ms = g_trace.flops = g_trace.bytes = 0.0;
     g_trace.launches = 0;
+    g_trace.tag_ms.clear();
+    g_trace.tag_flops.clear();
+  }
+}
+
+std::string trace_tags() {
+  std::string out;
+  for (auto& kv : g_trace.tag_ms) {
+    char buf[160];
+    snprintf(buf, sizeof(buf), "%s%s:%.3f:%.6g", out.empty() ? "" : ";", kv.first.c_str(), kv.second,
+             g_trace.tag_flops[kv.first]);
+    out += buf;
+  }
+  return out;
+}
+
+// 128 x 128 tiles for the large products: each wave owns a 64 x 64 quarter as
+// 4 x 4 blocks of v_mfma_f64_16x16x4 (16 accumulators), eight LDS reads feed
+// sixteen MFMAs per k-step, and the next 16-wide K chunk is fetched into
+// registers while the current one is multiplied.
+constexpr int BT = 128;
+
+template <bool A_ICONTIG, bool B_JCONTIG>
+__device__ __forceinline__ void big_fetch(const GemmDesc& d, int i0, int j0, int k0, int tid, double ra[8],
+                                          double rb[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    int i, kk;
+    if (A_ICONTIG) {
+      i = tid & 127;
+      kk = (tid >> 7) + 2 * r;
+    } else {
+      kk = tid & 15;
+      i = (tid >> 4) + 16 * r;
+    }
+    const int gi = i0 + i, gk = k0 + kk;
+    double v = 0.0;
+    if (gi < d.M && gk < d.K) {
+      const long long row = d.aidx ? (long long)d.aidx[gi] : (long long)gi;
+      v = d.A[row * d.ars + (long long)gk * d.acs];
+    }
+    ra[r] = v;
+  }
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    int j, kk;
+    if (B_JCONTIG) {
+      j = tid & 127;
+      kk = (tid >> 7) + 2 * r;
+    } else {
+      kk = tid & 15;
+      j = (tid >> 4) + 16 * r;
+    }
+    const int gj = j0 + j, gk = k0 + kk;
+    double v = 0.0;
+    if (gj < d.N && gk < d.K) {
+      const long long row = d.bidx ? (long long)d.bidx[gk] : (long long)gk;
+      v = d.B[row * d.brs + (long long)gj * d.bcs];
+    }
+    rb[r] = v;
+  }
+}
+
+template <bool A_ICONTIG, bool B_JCONTIG>
+__device__ __forceinline__ void big_stash(double (*As)[BT + 4], double (*Bs)[BT + 4], int tid, const double ra[8],
+                                          const double rb[8]) {
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (A_ICONTIG)
+      As[(tid >> 7) + 2 * r][tid & 127] = ra[r];
+    else
+      As[tid & 15][(tid >> 4) + 16 * r] = ra[r];
+    if (B_JCONTIG)
+      Bs[(tid >> 7) + 2 * r][tid & 127] = rb[r];
+    else
+      Bs[tid & 15][(tid >> 4) + 16 * r] = rb[r];
+  }
+}
+
+template <bool A_ICONTIG, bool B_JCONTIG>
+__device__ void gemm_big_body(const GemmDesc& d, int i0, int j0) {
+  __shared__ double As[16][BT + 4];
+  __shared__ double Bs[16][BT + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rb0 = (wave >> 1) * 64, cb0 = (wave & 1) * 64;
+  v4d acc[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[m][q] = v4d{0, 0, 0, 0};
+  double ra[8], rbv[8];
+  big_fetch<A_ICONTIG, B_JCONTIG>(d, i0, j0, 0, tid, ra, rbv);
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    __syncthreads();
+    big_stash<A_ICONTIG, B_JCONTIG>(As, Bs, tid, ra, rbv);
+    __syncthreads();
+    if (k0 + 16 < d.K) big_fetch<A_ICONTIG, B_JCONTIG>(d, i0, j0, k0 + 16, tid, ra, rbv);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      double a[4], b[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) a[m] = As[kk][rb0 + m * 16 + (lane & 15)];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) b[q] = Bs[kk][cb0 + q * 16 + (lane & 15)];
+#pragma unroll
+      for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) store_block(d, acc[m][q], i0 + rb0 + m * 16, j0 + cb0 + q * 16, lane);
+}
+
+__global__ __launch_bounds__(256) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
+                                                        const int4* __restrict__ tiles) {
+  const int4 t = tiles[blockIdx.x];
+  const GemmDesc d = descs[t.x];
+  const int i0 = t.y * BT, j0 = t.z * BT;
+  const bool ai = (d.ars == 1 && d.aidx == nullptr), bj = (d.bcs == 1);
+  if (ai) {
+    if (bj)
+      gemm_big_body<true, true>(d, i0, j0);
+    else
+      gemm_big_body<true, false>(d, i0, j0);
+  } else {
+    if (bj)
+      gemm_big_body<false, true>(d, i0, j0);
+    else
+      gemm_big_body<false, false>(d, i0, j0);
   }
 }
 
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s) {
-  std::vector<int4> tiles;
+  std::vector<int4> tiles, btiles;
   std::vector<GemmDesc> live;
   double flops = 0.0, bytes = 0.0;
   for (const GemmDesc& d : descs) {
@@ -242,31 +385,44 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     const int p = (int)live.size();
     live.push_back(d);
-    const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
-    for (int a = 0; a < tm; ++a)
-      for (int b = 0; b < tn; ++b)
-        if (!d.lower || b <= a) tiles.push_back(make_int4(p, a, b, 0));
+    if (d.M >= BT && d.N >= BT && d.K >= 32) {
+      const int tm = (d.M + BT - 1) / BT, tn = (d.N + BT - 1) / BT;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b)
+          if (!d.lower || b <= a) btiles.push_back(make_int4(p, a, b, 0));
+    } else {
+      const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b)
+          if (!d.lower || b <= a) tiles.push_back(make_int4(p, a, b, 0));
+    }
   }
-  if (tiles.empty()) return;
+  if (tiles.empty() && btiles.empty()) return;
   GemmDesc* dd = scr.make<GemmDesc>(live.size());
-  int4* dt = scr.make<int4>(tiles.size());
   upload(dd, live, s);
+  int4* dt = tiles.empty() ? nullptr : scr.make<int4>(tiles.size());
+  int4* dbt = btiles.empty() ? nullptr : scr.make<int4>(btiles.size());
   upload(dt, tiles, s);
-  // the grid is limited to 2^31 - 1 blocks in x; tile lists here stay far below
+  upload(dbt, btiles, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_trace.on) {
     RSF_HIP(hipEventCreate(&e0));
     RSF_HIP(hipEventCreate(&e1));
     RSF_HIP(hipEventRecord(e0, s));
   }
-  hipLaunchKernelGGL(gemm_tiles_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, s, dd, dt);
+  // the grid is limited to 2^31 - 1 blocks in x; tile lists here stay far below
+  if (!btiles.empty())
+    hipLaunchKernelGGL(gemm_big_kernel, dim3((unsigned)btiles.size()), dim3(256), 0, s, dd, dbt);
+  if (!tiles.empty())
+    hipLaunchKernelGGL(gemm_tiles_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, s, dd, dt);
   RSF_HIP(hipGetLastError());
   if (g_trace.on) {
     RSF_HIP(hipEventRecord(e1, s));
-    g_trace.ev.emplace_back(e0, e1);
+    g_trace.ev.push_back(TraceEv{e0, e1, g_trace.tag});
     g_trace.flops += flops;
     g_trace.bytes += bytes;
     g_trace.launches += 1;
+    g_trace.tag_flops[g_trace.tag] += flops;
   }
 }
 
@@ -276,7 +432,7 @@ __global__ __launch_bounds__(256) void copy_blocks_kernel(const CopyBlock* __res
   const long long tot = (long long)J.m * J.n;
   for (long long e = blockIdx.y * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.y) {
     const int i = (int)(e % J.m), j = (int)(e / J.m);
-    J.dst[(long long)j * J.ldd + i] = (J.lower && i < j) ? 0.0 : J.src[(long long)j * J.lds + i];
+    J.dst[(long long)j * J.ldd + i] = (J.src == nullptr || (J.lower && i < j)) ? 0.0 : J.src[(long long)j * J.lds + i];
   }
 }
 
@@ -356,6 +512,7 @@ __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* _
 }
 
 void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr, hipStream_t s) {
+  TraceTag tag("chol");
   int maxn = 0;
   std::vector<long long> doff(P.size() + 1, 0), qoff(P.size() + 1, 0);
   for (size_t p = 0; p < P.size(); ++p) {
@@ -399,10 +556,11 @@ void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr
     gemm_batched(trl, scr, s);
   }
   // inverse: Linv(i, i) = Dinv_i;  Linv(i, 0:i) = -Dinv_i L(i, 0:i) Linv(0:i, 0:i)
-  for (const CholProblem& c : P)
-    if (c.n > 0) {
-      RSF_HIP(hipMemset2DAsync(c.Linv, c.ldi * sizeof(double), 0, c.n * sizeof(double), c.n, s));
-    }
+  {
+    std::vector<CopyBlock> z;
+    for (const CholProblem& c : P) z.push_back(CopyBlock{nullptr, 0, c.Linv, c.ldi, c.n, c.n, 0});
+    copy_blocks(z, scr, s);
+  }
   for (int b = 0; b < nbk; ++b) {
     const int kb = b * 64;
     std::vector<CopyBlock> cp;

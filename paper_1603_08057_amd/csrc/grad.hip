@@ -260,11 +260,34 @@ constexpr int OVERSAMPLE = 10;
 constexpr int FIRST_COLS = 64;
 constexpr int MIN_COLS = 24;
 
-int next_cols(int prev_rank) {
-  int c = (3 * prev_rank + 3) / 4 + OVERSAMPLE;
-  c = std::max(MIN_COLS, c);
-  return (c + 7) / 8 * 8;
+int round8(int c) { return (c + 7) / 8 * 8; }
+
+long long isqrt(long long n) {
+  long long r = (long long)std::sqrt((double)n);
+  while (r * r > n) --r;
+  while ((r + 1) * (r + 1) <= n) ++r;
+  return r;
 }
+
+// Probe columns at the first peeled level: sibling blocks of the top level
+// have ranks that grow like sqrt(n) (Section 3.3), so start at 4.5 sqrt(n),
+// at least FIRST_COLS.
+int first_cols(long long n) { return round8((int)std::max<long long>(FIRST_COLS, 9 * isqrt(n) / 2)); }
+
+// Probe columns at the next level: the largest rank found at this level
+// scaled by 0.85 (ranks shrink slowly from level to level) plus the
+// oversampling, at least MIN_COLS, rounded up to a multiple of 8.
+int next_cols(int prev_rank) {
+  int c = (17 * prev_rank + 19) / 20 + OVERSAMPLE;
+  return round8(std::max(MIN_COLS, c));
+}
+
+// Growth when some block's rank is not resolved: 1.5x, at least the rank
+// found plus twice the oversampling.
+int grow_cols(int total, int maxrank) { return round8(std::max((3 * total + 1) / 2, maxrank + 2 * OVERSAMPLE)); }
+
+}  // namespace
+namespace {
 
 struct PairLR {
   int i, j;     // box ids (i before j in sibling order)
@@ -311,6 +334,7 @@ struct Peeler {
 
   // out -= sum_{m < upto} G^(m) X  for operator op
   void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr) {
+    TraceTag tag("peel_subtract");
     for (int m = 1; m < upto && m < (int)lr[op].size(); ++m) {
       const LevelLR& L = lr[op][m];
       if (!L.any) continue;
@@ -374,7 +398,7 @@ struct Peeler {
         for (int u = 0; u < t.count[b]; ++u) qd[t.begin[b] + u] = t.quad[b];
       int* dqd = scr.make<int>(n);
       upload(dqd, qd, s);
-      int c = prev < 0 ? FIRST_COLS : next_cols(prev);
+      int c = prev < 0 ? first_cols(n) : next_cols(prev);
       int total = 0, Ccap = 0;
       double* Om = nullptr;
       double* Y[2] = {nullptr, nullptr};
@@ -451,7 +475,10 @@ struct Peeler {
             pj.push_back(PcholJob{Gram + goff[idx], total, dpiv + (long long)idx * total, dk + idx, Lw + goff[idx],
                                   L1 + goff[idx], Ginv + goff[idx]});
           }
-        gemm_batched(g, scr, s);
+        {
+          TraceTag tg("peel_gram");
+          gemm_batched(g, scr, s);
+        }
         PcholJob* dj = scr.make<PcholJob>(pj.size());
         upload(dj, pj, s);
         // relative pivots below ~1e-13 of the Gram diagonal are rounding noise
@@ -470,7 +497,7 @@ struct Peeler {
             if (k + OVERSAMPLE > total && total < t.count[blocks[e].second]) need = true;
           }
         if (!need) break;
-        c = 2 * total;
+        c = grow_cols(total, maxrank);
       }
       prev = maxrank;
       if (st && lev < 32) {
@@ -478,6 +505,7 @@ struct Peeler {
         st->rank[lev] = maxrank;
       }
       // bases U = Y(:, piv[:k]) Linv^T, stored per box as [U_(b, sibling) ...]
+      TraceTag tg("peel_lowrank");
       for (int op = 0; op < 2; ++op) {
         LevelLR& L = lr[op][lev];
         L.any = true;

@@ -95,6 +95,7 @@ static void level_gemm(const LevelFactor& L, int nc, double alpha, AFn afn, Rows
 
 void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
                  hipStream_t s) {
+  TraceTag tag("sweep_solve");
   const int D = h->tree.maxdepth;
   long long maxr = 1;
   for (int d = 1; d <= D; ++d) maxr = std::max(maxr, F.levels[d].total_r);
@@ -139,6 +140,7 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
 
 void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double* Out, int nc, long long ld,
                   Scratch& scr, hipStream_t s) {
+  TraceTag tag("sweep_sqrt");
   const int D = h->tree.maxdepth;
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
@@ -161,6 +163,7 @@ void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double*
 
 void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, double* V, int nc, long long ld,
                 Scratch& scr, hipStream_t s) {
+  TraceTag tag("sweep_sqrt");
   const int D = h->tree.maxdepth;
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
@@ -186,6 +189,7 @@ void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, dou
 
 void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, double* Y, int nc, long long ld,
                       Scratch& scr, hipStream_t s) {
+  TraceTag tag("sweep_mult");
   const int D = h->tree.maxdepth;
   fill_zero(Y, h->tree.n * ld, s);
   for (int d = D; d >= 1; --d) {
