@@ -258,84 +258,76 @@ std::string trace_tags() {
 // 128 x 128 tiles for the large products: each wave owns a 64 x 64 quarter as
 // 4 x 4 blocks of v_mfma_f64_16x16x4 (16 accumulators), eight LDS reads feed
 // sixteen MFMAs per k-step, and the next 16-wide K chunk is fetched into
-// registers while the current one is multiplied.
+// registers while the current one is multiplied.  One kernel per operand
+// layout (A: rows contiguous or k contiguous; B: columns contiguous or k
+// contiguous), chosen on the host, so addresses are precomputed per thread.
 constexpr int BT = 128;
 
-template <bool A_ICONTIG, bool B_JCONTIG>
-__device__ __forceinline__ void big_fetch(const GemmDesc& d, int i0, int j0, int k0, int tid, double ra[8],
-                                          double rb[8]) {
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    int i, kk;
-    if (A_ICONTIG) {
-      i = tid & 127;
-      kk = (tid >> 7) + 2 * r;
-    } else {
-      kk = tid & 15;
-      i = (tid >> 4) + 16 * r;
-    }
-    const int gi = i0 + i, gk = k0 + kk;
-    double v = 0.0;
-    if (gi < d.M && gk < d.K) {
-      const long long row = d.aidx ? (long long)d.aidx[gi] : (long long)gi;
-      v = d.A[row * d.ars + (long long)gk * d.acs];
-    }
-    ra[r] = v;
-  }
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    int j, kk;
-    if (B_JCONTIG) {
-      j = tid & 127;
-      kk = (tid >> 7) + 2 * r;
-    } else {
-      kk = tid & 15;
-      j = (tid >> 4) + 16 * r;
-    }
-    const int gj = j0 + j, gk = k0 + kk;
-    double v = 0.0;
-    if (gj < d.N && gk < d.K) {
-      const long long row = d.bidx ? (long long)d.bidx[gk] : (long long)gk;
-      v = d.B[row * d.brs + (long long)gj * d.bcs];
-    }
-    rb[r] = v;
-  }
-}
-
-template <bool A_ICONTIG, bool B_JCONTIG>
-__device__ __forceinline__ void big_stash(double (*As)[BT + 4], double (*Bs)[BT + 4], int tid, const double ra[8],
-                                          const double rb[8]) {
-#pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    if (A_ICONTIG)
-      As[(tid >> 7) + 2 * r][tid & 127] = ra[r];
-    else
-      As[tid & 15][(tid >> 4) + 16 * r] = ra[r];
-    if (B_JCONTIG)
-      Bs[(tid >> 7) + 2 * r][tid & 127] = rb[r];
-    else
-      Bs[tid & 15][(tid >> 4) + 16 * r] = rb[r];
-  }
-}
-
-template <bool A_ICONTIG, bool B_JCONTIG>
-__device__ void gemm_big_body(const GemmDesc& d, int i0, int j0) {
+template <bool AI, bool BJ>
+__global__ __launch_bounds__(256, 1) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
+                                                           const int4* __restrict__ tiles) {
   __shared__ double As[16][BT + 4];
   __shared__ double Bs[16][BT + 4];
+  const int4 t = tiles[blockIdx.x];
+  const GemmDesc d = descs[t.x];
+  const int i0 = t.y * BT, j0 = t.z * BT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rb0 = (wave >> 1) * 64, cb0 = (wave & 1) * 64;
+  // per-thread fetch geometry
+  const int a_i = AI ? (tid & 127) : (tid >> 4);       // + 16 r when !AI
+  const int a_k = AI ? (tid >> 7) : (tid & 15);        // + 2 r when AI
+  const int b_j = BJ ? (tid & 127) : (tid >> 4);
+  const int b_k = BJ ? (tid >> 7) : (tid & 15);
+  long long aoff[8];
+  bool aok[8];
+  long long boff[8];
+  bool bok[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int gi = i0 + (AI ? a_i : a_i + 16 * r);
+    aok[r] = gi < d.M;
+    const long long row = aok[r] ? (d.aidx ? (long long)d.aidx[gi] : (long long)gi) : 0;
+    aoff[r] = row * d.ars;  // AI: the same for all r
+    const int gj = j0 + (BJ ? b_j : b_j + 16 * r);
+    bok[r] = gj < d.N;
+    boff[r] = bok[r] ? (long long)gj * d.bcs : 0;
+  }
   v4d acc[4][4];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[m][q] = v4d{0, 0, 0, 0};
   double ra[8], rbv[8];
-  big_fetch<A_ICONTIG, B_JCONTIG>(d, i0, j0, 0, tid, ra, rbv);
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      const int gk = k0 + (AI ? a_k + 2 * r : a_k);
+      ra[r] = (aok[r] && gk < d.K) ? d.A[aoff[r] + (long long)gk * d.acs] : 0.0;
+      const int gkb = k0 + (BJ ? b_k + 2 * r : b_k);
+      double v = 0.0;
+      if (bok[r] && gkb < d.K) {
+        const long long row = d.bidx ? (long long)d.bidx[gkb] : (long long)gkb;
+        v = d.B[row * d.brs + boff[r]];
+      }
+      rbv[r] = v;
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < d.K; k0 += 16) {
     __syncthreads();
-    big_stash<A_ICONTIG, B_JCONTIG>(As, Bs, tid, ra, rbv);
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+      if (AI)
+        As[a_k + 2 * r][a_i] = ra[r];
+      else
+        As[a_k][a_i + 16 * r] = ra[r];
+      if (BJ)
+        Bs[b_k + 2 * r][b_j] = rbv[r];
+      else
+        Bs[b_k][b_j + 16 * r] = rbv[r];
+    }
     __syncthreads();
-    if (k0 + 16 < d.K) big_fetch<A_ICONTIG, B_JCONTIG>(d, i0, j0, k0 + 16, tid, ra, rbv);
+    if (k0 + 16 < d.K) fetch(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
@@ -356,27 +348,18 @@ __device__ void gemm_big_body(const GemmDesc& d, int i0, int j0) {
     for (int q = 0; q < 4; ++q) store_block(d, acc[m][q], i0 + rb0 + m * 16, j0 + cb0 + q * 16, lane);
 }
 
-__global__ __launch_bounds__(256) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
-                                                        const int4* __restrict__ tiles) {
-  const int4 t = tiles[blockIdx.x];
-  const GemmDesc d = descs[t.x];
-  const int i0 = t.y * BT, j0 = t.z * BT;
-  const bool ai = (d.ars == 1 && d.aidx == nullptr), bj = (d.bcs == 1);
-  if (ai) {
-    if (bj)
-      gemm_big_body<true, true>(d, i0, j0);
-    else
-      gemm_big_body<true, false>(d, i0, j0);
-  } else {
-    if (bj)
-      gemm_big_body<false, true>(d, i0, j0);
-    else
-      gemm_big_body<false, false>(d, i0, j0);
-  }
+// layout class of a problem for the 128 x 128 kernels: bit 1 = A rows
+// contiguous (else k contiguous), bit 0 = B columns contiguous (else k
+// contiguous); -1 = neither layout fits, use the 64 x 64 kernel
+static int big_class(const GemmDesc& d) {
+  const bool ai = (d.ars == 1 && d.aidx == nullptr), ak = (d.acs == 1);
+  const bool bj = (d.bcs == 1), bk = (d.brs == 1 && d.bidx == nullptr);
+  if (!(ai || ak) || !(bj || bk)) return -1;
+  return (ai ? 2 : 0) | (bj ? 1 : 0);
 }
 
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s) {
-  std::vector<int4> tiles, btiles;
+  std::vector<int4> tiles, btiles[4];
   std::vector<GemmDesc> live;
   double flops = 0.0, bytes = 0.0;
   for (const GemmDesc& d : descs) {
@@ -385,11 +368,12 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     const int p = (int)live.size();
     live.push_back(d);
-    if (d.M >= BT && d.N >= BT && d.K >= 32) {
+    const int cls = big_class(d);
+    if (cls >= 0 && d.M >= 96 && d.N >= 96 && d.K >= 32) {
       const int tm = (d.M + BT - 1) / BT, tn = (d.N + BT - 1) / BT;
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b)
-          if (!d.lower || b <= a) btiles.push_back(make_int4(p, a, b, 0));
+          if (!d.lower || b <= a) btiles[cls].push_back(make_int4(p, a, b, 0));
     } else {
       const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
       for (int a = 0; a < tm; ++a)
@@ -397,13 +381,20 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
           if (!d.lower || b <= a) tiles.push_back(make_int4(p, a, b, 0));
     }
   }
-  if (tiles.empty() && btiles.empty()) return;
+  size_t nt = tiles.size();
+  for (auto& v : btiles) nt += v.size();
+  if (nt == 0) return;
   GemmDesc* dd = scr.make<GemmDesc>(live.size());
   upload(dd, live, s);
-  int4* dt = tiles.empty() ? nullptr : scr.make<int4>(tiles.size());
-  int4* dbt = btiles.empty() ? nullptr : scr.make<int4>(btiles.size());
-  upload(dt, tiles, s);
-  upload(dbt, btiles, s);
+  std::vector<int4> all(tiles);
+  size_t boff[5];
+  boff[0] = all.size();
+  for (int c = 0; c < 4; ++c) {
+    all.insert(all.end(), btiles[c].begin(), btiles[c].end());
+    boff[c + 1] = all.size();
+  }
+  int4* dt = scr.make<int4>(all.size());
+  upload(dt, all, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_trace.on) {
     RSF_HIP(hipEventCreate(&e0));
@@ -411,8 +402,14 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     RSF_HIP(hipEventRecord(e0, s));
   }
   // the grid is limited to 2^31 - 1 blocks in x; tile lists here stay far below
-  if (!btiles.empty())
-    hipLaunchKernelGGL(gemm_big_kernel, dim3((unsigned)btiles.size()), dim3(256), 0, s, dd, dbt);
+  if (!btiles[3].empty())
+    hipLaunchKernelGGL((gemm_big_kernel<true, true>), dim3((unsigned)btiles[3].size()), dim3(256), 0, s, dd, dt + boff[3]);
+  if (!btiles[2].empty())
+    hipLaunchKernelGGL((gemm_big_kernel<true, false>), dim3((unsigned)btiles[2].size()), dim3(256), 0, s, dd, dt + boff[2]);
+  if (!btiles[1].empty())
+    hipLaunchKernelGGL((gemm_big_kernel<false, true>), dim3((unsigned)btiles[1].size()), dim3(256), 0, s, dd, dt + boff[1]);
+  if (!btiles[0].empty())
+    hipLaunchKernelGGL((gemm_big_kernel<false, false>), dim3((unsigned)btiles[0].size()), dim3(256), 0, s, dd, dt + boff[0]);
   if (!tiles.empty())
     hipLaunchKernelGGL(gemm_tiles_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, s, dd, dt);
   RSF_HIP(hipGetLastError());
