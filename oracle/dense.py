@@ -136,6 +136,55 @@ def _trmv(L, w):
     return blas.dtrmv(L, np.asarray(w, dtype=np.float64), lower=1)
 
 
+def _blocked_cholesky(P, theta, kernel, alpha, bs):
+    """Lower Cholesky factor of Sigma in one n x n buffer (lower triangle),
+    right-looking over bs x bs blocks; returns (S, blocks, log|Sigma|)."""
+    import scipy.linalg as sla
+    n = P.shape[0]
+    S = np.empty((n, n))
+    idx = np.arange(n)
+    nb = (n + bs - 1) // bs
+    blk = [(k * bs, min(n, (k + 1) * bs)) for k in range(nb)]
+    for (b0, b1) in blk:
+        S[b0:b1, :b1] = K.cov_block(P, idx[b0:b1], idx[:b1], theta, kernel, alpha)
+    logdet = 0.0
+    for k, (k0, k1) in enumerate(blk):
+        Lkk = sla.cholesky(S[k0:k1, k0:k1], lower=True, check_finite=False)
+        S[k0:k1, k0:k1] = Lkk
+        logdet += 2.0 * float(np.sum(np.log(np.diag(Lkk))))
+        for (i0, i1) in blk[k + 1:]:
+            S[i0:i1, k0:k1] = sla.solve_triangular(Lkk, S[i0:i1, k0:k1].T, lower=True, check_finite=False).T
+        for i, (i0, i1) in enumerate(blk[k + 1:], start=k + 1):
+            Lik = S[i0:i1, k0:k1]
+            for (j0, j1) in blk[k + 1:i + 1]:
+                S[i0:i1, j0:j1] -= Lik @ S[j0:j1, k0:k1].T
+    return S, blk, logdet
+
+
+def sample_loglik_large(P, w, theta, kernel, alpha=1.0, bs=8192):
+    """For large n: z = L w (a draw from N(0, Sigma) given w ~ N(0, I)) with the
+    blocked Cholesky factor L, and for that z the exact l, log|Sigma| and
+    Sigma^-1 z = L^-T w (so z^T Sigma^-1 z = w^T w)."""
+    import scipy.linalg as sla
+    P = np.ascontiguousarray(P, dtype=np.float64)
+    w = np.asarray(w, dtype=np.float64)
+    n = P.shape[0]
+    S, blk, logdet = _blocked_cholesky(P, theta, kernel, alpha, bs)
+    z = np.zeros(n)
+    for k, (k0, k1) in enumerate(blk):
+        for (j0, j1) in blk[:k + 1]:
+            Lkj = np.tril(S[k0:k1, j0:j1]) if j0 == k0 else S[k0:k1, j0:j1]
+            z[k0:k1] += Lkj @ w[j0:j1]
+    x = w.copy()
+    for k in range(len(blk) - 1, -1, -1):
+        k0, k1 = blk[k]
+        for (j0, j1) in blk[k + 1:]:
+            x[k0:k1] -= S[j0:j1, k0:k1].T @ x[j0:j1]
+        x[k0:k1] = sla.solve_triangular(S[k0:k1, k0:k1], x[k0:k1], lower=True, trans="T", check_finite=False)
+    ell = -0.5 * float(w @ w) - 0.5 * logdet - 0.5 * n * LOG2PI
+    return z, ell, logdet, x
+
+
 def loglik_large(P, z, theta, kernel, alpha=1.0, bs=8192):
     """(l, log|Sigma|, Sigma^-1 z) for large n by a blocked, in-place, right-
     looking Cholesky over bs x bs blocks of one n x n buffer: diagonal blocks

@@ -259,38 +259,40 @@ std::string trace_tags() {
 // 4 x 4 blocks of v_mfma_f64_16x16x4 (16 accumulators), eight LDS reads feed
 // sixteen MFMAs per k-step, and the next 16-wide K chunk is fetched into
 // registers while the current one is multiplied.  One kernel per operand
-// layout (A: rows contiguous or k contiguous; B: columns contiguous or k
-// contiguous), chosen on the host, so addresses are precomputed per thread.
+// layout (A: rows contiguous or k contiguous; B: columns contiguous, with or
+// without a row map, or k contiguous), chosen on the host.  Interior tiles
+// and full K chunks take unchecked loads through per-thread pointers that
+// advance by a fixed stride per chunk; only edge tiles pay for bounds checks.
 constexpr int BT = 128;
 
-template <bool AI, bool BJ>
-__global__ __launch_bounds__(256, 1) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
+template <bool AI, bool BJ, bool BIDX>
+__global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
                                                            const int4* __restrict__ tiles) {
   __shared__ double As[16][BT + 4];
   __shared__ double Bs[16][BT + 4];
   const int4 t = tiles[blockIdx.x];
-  const GemmDesc d = descs[t.x];
+  const GemmDesc& dg = descs[t.x];
+  const int M = dg.M, N = dg.N, K = dg.K;
   const int i0 = t.y * BT, j0 = t.z * BT;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int rb0 = (wave >> 1) * 64, cb0 = (wave & 1) * 64;
-  // per-thread fetch geometry
-  const int a_i = AI ? (tid & 127) : (tid >> 4);       // + 16 r when !AI
-  const int a_k = AI ? (tid >> 7) : (tid & 15);        // + 2 r when AI
+  const int tid = threadIdx.x;
+  const bool full = (i0 + BT <= M) && (j0 + BT <= N);
+  // fetch geometry (see the layout note above):
+  //   AI: A(i0 + (tid & 127), k0 + (tid >> 7) + 2 r)   else A(i0 + (tid >> 4) + 16 r, k0 + (tid & 15))
+  //   BJ: B(k0 + (tid >> 7) + 2 r, j0 + (tid & 127))   else B(k0 + (tid & 15), j0 + (tid >> 4) + 16 r)
+  const int a_i = AI ? (tid & 127) : (tid >> 4);
+  const int a_k = AI ? (tid >> 7) : (tid & 15);
   const int b_j = BJ ? (tid & 127) : (tid >> 4);
   const int b_k = BJ ? (tid >> 7) : (tid & 15);
-  long long aoff[8];
-  bool aok[8];
-  long long boff[8];
-  bool bok[8];
+  const long long astr = AI ? dg.acs : dg.ars;  // AI: step along k; else: step between the 8 rows (x16)
+  const long long bstr = BJ ? dg.brs : dg.bcs;
+  const double* __restrict__ pa = dg.A + (long long)(i0 + a_i) * (AI ? 1 : dg.ars);
+  const double* __restrict__ pb = dg.B + (long long)(j0 + b_j) * (BJ ? 1 : dg.bcs);
+  const int* __restrict__ bidx = dg.bidx;
+  unsigned amask = 0, bmask = 0;  // bit r: row / column r of this thread is inside the problem
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
-    const int gi = i0 + (AI ? a_i : a_i + 16 * r);
-    aok[r] = gi < d.M;
-    const long long row = aok[r] ? (d.aidx ? (long long)d.aidx[gi] : (long long)gi) : 0;
-    aoff[r] = row * d.ars;  // AI: the same for all r
-    const int gj = j0 + (BJ ? b_j : b_j + 16 * r);
-    bok[r] = gj < d.N;
-    boff[r] = bok[r] ? (long long)gj * d.bcs : 0;
+    if (i0 + (AI ? a_i : a_i + 16 * r) < M) amask |= 1u << r;
+    if (j0 + (BJ ? b_j : b_j + 16 * r) < N) bmask |= 1u << r;
   }
   v4d acc[4][4];
 #pragma unroll
@@ -299,21 +301,36 @@ __global__ __launch_bounds__(256, 1) void gemm_big_kernel(const GemmDesc* __rest
     for (int q = 0; q < 4; ++q) acc[m][q] = v4d{0, 0, 0, 0};
   double ra[8], rbv[8];
   auto fetch = [&](int k0) {
+    if (full && k0 + 16 <= K) {
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int gk = k0 + (AI ? a_k + 2 * r : a_k);
-      ra[r] = (aok[r] && gk < d.K) ? d.A[aoff[r] + (long long)gk * d.acs] : 0.0;
-      const int gkb = k0 + (BJ ? b_k + 2 * r : b_k);
-      double v = 0.0;
-      if (bok[r] && gkb < d.K) {
-        const long long row = d.bidx ? (long long)d.bidx[gkb] : (long long)gkb;
-        v = d.B[row * d.brs + boff[r]];
+      for (int r = 0; r < 8; ++r) {
+        ra[r] = AI ? pa[(long long)(k0 + a_k + 2 * r) * astr] : pa[(long long)(16 * r) * astr + k0 + a_k];
+        if (BJ) {
+          const int kb = k0 + b_k + 2 * r;
+          rbv[r] = pb[(long long)(BIDX ? bidx[kb] : kb) * bstr];
+        } else {
+          rbv[r] = pb[(long long)(16 * r) * bstr + k0 + b_k];
+        }
       }
-      rbv[r] = v;
+    } else {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int ka = k0 + a_k + (AI ? 2 * r : 0);
+        ra[r] = ((amask >> r) & 1u) && ka < K
+                    ? (AI ? pa[(long long)ka * astr] : pa[(long long)(16 * r) * astr + ka])
+                    : 0.0;
+        const int kb = k0 + b_k + (BJ ? 2 * r : 0);
+        double v = 0.0;
+        if (((bmask >> r) & 1u) && kb < K)
+          v = BJ ? pb[(long long)(BIDX ? bidx[kb] : kb) * bstr] : pb[(long long)(16 * r) * bstr + kb];
+        rbv[r] = v;
+      }
     }
   };
   fetch(0);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  const int lane = tid & 63, wave = tid >> 6;
+  const int rb0 = (wave >> 1) * 64, cb0 = (wave & 1) * 64;
+  for (int k0 = 0; k0 < K; k0 += 16) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -327,7 +344,7 @@ __global__ __launch_bounds__(256, 1) void gemm_big_kernel(const GemmDesc* __rest
         Bs[b_k][b_j + 16 * r] = rbv[r];
     }
     __syncthreads();
-    if (k0 + 16 < d.K) fetch(k0 + 16);
+    if (k0 + 16 < K) fetch(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
@@ -342,24 +359,42 @@ __global__ __launch_bounds__(256, 1) void gemm_big_kernel(const GemmDesc* __rest
         for (int q = 0; q < 4; ++q) acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
     }
   }
+  const double alpha = dg.alpha, beta = dg.beta;
+  const int* __restrict__ cidx = dg.cidx;
+  double* __restrict__ Cb = dg.C;
+  const long long crs = dg.crs, ccs = dg.ccs;
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) store_block(d, acc[m][q], i0 + rb0 + m * 16, j0 + cb0 + q * 16, lane);
+    for (int r = 0; r < 4; ++r) {
+      const int gi = i0 + rb0 + m * 16 + 4 * r + (lane >> 4);
+      if (!full && gi >= M) continue;
+      const long long row = cidx ? (long long)cidx[gi] : (long long)gi;
+      double* crow = Cb + row * crs;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gj = j0 + cb0 + q * 16 + (lane & 15);
+        if (!full && gj >= N) continue;
+        double* c = crow + (long long)gj * ccs;
+        const double v = acc[m][q][r];
+        *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+      }
+    }
 }
 
-// layout class of a problem for the 128 x 128 kernels: bit 1 = A rows
-// contiguous (else k contiguous), bit 0 = B columns contiguous (else k
-// contiguous); -1 = neither layout fits, use the 64 x 64 kernel
+// layout class of a problem for the 128 x 128 kernels: bit 2 = A rows
+// contiguous (else k contiguous), bit 1 = B columns contiguous (else k
+// contiguous), bit 0 = B has a row map (only with contiguous columns);
+// -1 = no fitting layout, use the 64 x 64 kernel
 static int big_class(const GemmDesc& d) {
-  const bool ai = (d.ars == 1 && d.aidx == nullptr), ak = (d.acs == 1);
+  const bool ai = (d.ars == 1 && d.aidx == nullptr), ak = (d.acs == 1 && d.aidx == nullptr);
   const bool bj = (d.bcs == 1), bk = (d.brs == 1 && d.bidx == nullptr);
   if (!(ai || ak) || !(bj || bk)) return -1;
-  return (ai ? 2 : 0) | (bj ? 1 : 0);
+  return (ai ? 4 : 0) | (bj ? 2 : 0) | ((bj && d.bidx) ? 1 : 0);
 }
 
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s) {
-  std::vector<int4> tiles, btiles[4];
+  std::vector<int4> tiles, btiles[8];
   std::vector<GemmDesc> live;
   double flops = 0.0, bytes = 0.0;
   for (const GemmDesc& d : descs) {
@@ -387,9 +422,9 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   GemmDesc* dd = scr.make<GemmDesc>(live.size());
   upload(dd, live, s);
   std::vector<int4> all(tiles);
-  size_t boff[5];
+  size_t boff[9];
   boff[0] = all.size();
-  for (int c = 0; c < 4; ++c) {
+  for (int c = 0; c < 8; ++c) {
     all.insert(all.end(), btiles[c].begin(), btiles[c].end());
     boff[c + 1] = all.size();
   }
@@ -402,14 +437,17 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     RSF_HIP(hipEventRecord(e0, s));
   }
   // the grid is limited to 2^31 - 1 blocks in x; tile lists here stay far below
-  if (!btiles[3].empty())
-    hipLaunchKernelGGL((gemm_big_kernel<true, true>), dim3((unsigned)btiles[3].size()), dim3(256), 0, s, dd, dt + boff[3]);
-  if (!btiles[2].empty())
-    hipLaunchKernelGGL((gemm_big_kernel<true, false>), dim3((unsigned)btiles[2].size()), dim3(256), 0, s, dd, dt + boff[2]);
-  if (!btiles[1].empty())
-    hipLaunchKernelGGL((gemm_big_kernel<false, true>), dim3((unsigned)btiles[1].size()), dim3(256), 0, s, dd, dt + boff[1]);
-  if (!btiles[0].empty())
-    hipLaunchKernelGGL((gemm_big_kernel<false, false>), dim3((unsigned)btiles[0].size()), dim3(256), 0, s, dd, dt + boff[0]);
+#define RSF_BIG(c, AI, BJ, BX)                                                                        \
+  if (!btiles[c].empty())                                                                             \
+    hipLaunchKernelGGL((gemm_big_kernel<AI, BJ, BX>), dim3((unsigned)btiles[c].size()), dim3(256), 0, s, dd, \
+                       dt + boff[c]);
+  RSF_BIG(7, true, true, true)
+  RSF_BIG(6, true, true, false)
+  RSF_BIG(4, true, false, false)
+  RSF_BIG(3, false, true, true)
+  RSF_BIG(2, false, true, false)
+  RSF_BIG(0, false, false, false)
+#undef RSF_BIG
   if (!tiles.empty())
     hipLaunchKernelGGL(gemm_tiles_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, s, dd, dt);
   RSF_HIP(hipGetLastError());

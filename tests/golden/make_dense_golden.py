@@ -6,6 +6,12 @@ about 35 GB of host memory and tens of minutes on 8 cores.
 
   python tests/golden/make_dense_golden.py c3_matern32_n65536
   python tests/golden/make_dense_golden.py c2_rq_n16384
+  python tests/golden/make_dense_golden.py c3_matern32_n65536 model
+
+With "model", z is a draw from the model itself, z = L w with the dense
+Cholesky factor L of Sigma and w = workloads.gaussian(n, w_seed); z is written
+next to the reference as <workload>_model_z.npy (the log-likelihood is then
+exact for that z: z^T Sigma^-1 z = w^T w).
 
 Observations z are N(0, I) draws (workloads.gaussian(n, w_seed)); the
 log-likelihood and its score are defined for any z.
@@ -27,6 +33,8 @@ import workloads as W  # noqa: E402
 def main():
     name = sys.argv[1] if len(sys.argv) > 1 else "c3_matern32_n65536"
     spec = W.WORKLOADS[name]
+    if len(sys.argv) > 2 and sys.argv[2] == "model":
+        return model(name, spec)
     n = int(sys.argv[2]) if len(sys.argv) > 2 else spec["n"]
     P = W.workload_points(name, n)
     nrhs = spec.get("nrhs", 1)
@@ -59,6 +67,29 @@ def main():
     with open(os.path.join(HERE, fname), "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", fname, "in %.1f s" % secs)
+
+
+def model(name, spec):
+    n = spec["n"]
+    P = W.workload_points(name, n)
+    w = W.gaussian(n, spec["w_seed"])
+    t0 = time.time()
+    z, ell, logdet, a = dense.sample_loglik_large(P, w, spec["theta"], spec["kernel"], spec["alpha"])
+    secs = time.time() - t0
+    rng = np.random.default_rng(7)
+    sample = np.sort(rng.choice(n, size=min(n, 64), replace=False))
+    np.save(os.path.join(HERE, "%s_model_z.npy" % name), z)
+    out = {
+        "workload": name, "n": n, "kernel": spec["kernel"], "theta": list(spec["theta"]),
+        "z": "%s_model_z.npy: z = L w, Sigma = L L^T (dense), w = workloads.gaussian(n, %d)" % (name, spec["w_seed"]),
+        "ell": ell, "logdet": logdet, "ztSinvz": float(w @ w),
+        "alpha_index": sample.tolist(), "alpha_value": [float(a[i]) for i in sample],
+        "oracle_seconds": secs,
+        "generator": "tests/golden/make_dense_golden.py %s model (oracle.dense only)" % name,
+    }
+    with open(os.path.join(HERE, "%s_model_dense.json" % name), "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote %s_model_dense.json in %.1f s" % (name, secs))
 
 
 if __name__ == "__main__":
