@@ -120,133 +120,193 @@ __global__ __launch_bounds__(256) void leaf_trace_kernel(const int* __restrict__
   if (threadIdx.x == 0) *out = part[0];
 }
 
-// ------------------------------------------------------------------ small dense factorizations
-// All run one workgroup per matrix on column-major blocks in global memory.
-__device__ void wg_tri_inv_lower(const double* L, long long ldl, double* Li, long long ldi, int n) {
-  for (int c = threadIdx.x; c < n; c += blockDim.x) {
-    double* col = Li + (long long)c * ldi;
-    for (int i = 0; i < c; ++i) col[i] = 0.0;
-    col[c] = 1.0 / L[(long long)c * ldl + c];
-    for (int i = c + 1; i < n; ++i) {
-      double x = 0.0;
-      for (int l = c; l < i; ++l) x -= L[(long long)l * ldl + i] * col[l];
-      col[i] = x / L[(long long)i * ldl + i];
-    }
-  }
-  __syncthreads();
-}
-
-// Pivoted Cholesky of the Gram matrix G = Y^T Y: the same pivots and rank as
-// column-pivoted QR of Y in exact arithmetic (residual diagonal = squared
-// residual column norm); stops when the largest residual diagonal is
-// <= tol^2 times the first pivot's.  Left-looking: column s of the factor is
-// formed from the original Gram column of the pivot and the previous columns,
-// L(j, s) = (G(j, p) - sum_{l<s} L(j, l) L(p, l)) / sqrt(d_p), and the residual
-// diagonal d is updated in LDS, so each step streams the factor once.
-// Writes the rank, the pivots, and Linv = (leading k x k factor in pivot
-// order)^-1 (ld n).
-struct PcholJob {
-  const double* G;  // n x n, ld n (read only)
-  int n;
-  int* piv;
-  int* kout;
-  double* Lw;       // n x n work: column s holds L(:, s) indexed by original row
-  double* L1;       // n x n work: leading factor in pivot order
-  double* Linv;     // ld n
+// ------------------------------------------------------------------ pivoted Cholesky of the sample Gram matrices
+// The range finder of the low-rank step needs, for each sample block Y, the
+// column pivots and the numerical rank of column-pivoted QR of Y.  Pivoted
+// Cholesky of the Gram matrix G = Y^T Y picks the same pivots in exact
+// arithmetic (the residual diagonal is the squared residual column norm) and
+// stops when the largest residual diagonal is <= tol^2 times the first pivot's.
+// Blocked right-looking form: one launch factors up to NB further columns of
+// every unfinished Gram matrix in one workgroup (the panel lives in registers,
+// one row per thread and panel column), then the trailing matrix takes
+// Gw -= Lp Lp^T as a batched matrix-core GEMM.  Rows are never swapped: the
+// panel and the residual diagonal stay indexed by the original column, and a
+// row that has been chosen as pivot is marked in the residual diagonal.
+struct PpanelJob {
+  const double* Gw;  // c x c (ld c), the Gram matrix minus the previous panels' products
+  double* d;         // c residual diagonal; PIV_DONE marks chosen rows
+  double* Lp;        // c x NB panel (ld c): this launch's columns of the factor
+  int* piv;          // c pivots in order
+  int* state;        // [0] columns factored so far, [1] finished
+  double* d1;        // residual of the first pivot
+  int c;
 };
 
 constexpr int PCHOL_MAXN = 4096;
 constexpr int PCHOL_WG = 1024;
+constexpr double PIV_DONE = -1.0e300;
 
-__global__ __launch_bounds__(PCHOL_WG) void pchol_kernel(const PcholJob* __restrict__ jobs, double tol2) {
-  __shared__ double d[PCHOL_MAXN];
-  __shared__ unsigned char done[PCHOL_MAXN];
-  __shared__ double lp[PCHOL_MAXN];
-  __shared__ double red_v[PCHOL_WG];
-  __shared__ int red_i[PCHOL_WG];
-  const PcholJob J = jobs[blockIdx.x];
-  const int n = J.n, tid = threadIdx.x, nt = blockDim.x;
-  const double* G = J.G;
-  double* L = J.Lw;
-  for (int j = tid; j < n; j += nt) {
-    d[j] = G[(long long)j * n + j];
-    done[j] = 0;
+template <int RPT, int NB>
+__global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __restrict__ jobs, double tol2) {
+  __shared__ double wv[PCHOL_WG / 64];
+  __shared__ int wi[PCHOL_WG / 64];
+  __shared__ double lp[NB];
+  __shared__ double sel_v;
+  __shared__ int sel_i;
+  const PpanelJob J = jobs[blockIdx.x];
+  if (J.state[1]) return;
+  const int c = J.c, tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int s0 = J.state[0];
+  double d1 = *J.d1;
+  // dl: residual diagonal of the thread's rows; lr: their panel entries, zero
+  // in the columns not yet formed, so the full-width dot below sums only the
+  // previous columns and no register array is indexed at run time
+  double dl[RPT];
+  double lr[RPT][NB];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = tid + r * PCHOL_WG;
+    dl[r] = i < c ? J.d[i] : PIV_DONE;
+#pragma unroll
+    for (int t = 0; t < NB; ++t) lr[r][t] = 0.0;
   }
-  __syncthreads();
-  double d1 = 0.0;
-  int k = 0;
-  for (int s = 0; s < n; ++s) {
-    double bv = -1.0;
+  if (tid < NB) lp[tid] = 0.0;
+  int steps = 0;
+  bool fin = false;
+#pragma unroll 1
+  for (int j = 0; j < NB && !fin; ++j) {
+    // largest residual diagonal among unchosen rows, ties to the lowest index
+    double bv = 0.0;
     int bi = 0x7fffffff;
-    for (int j = tid; j < n; j += nt) {
-      if (done[j]) continue;
-      const double v = d[j];
-      if (v > bv || (v == bv && j < bi)) {
-        bv = v;
-        bi = j;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * PCHOL_WG;
+      if (dl[r] != PIV_DONE && (bi == 0x7fffffff || dl[r] > bv)) {
+        bv = dl[r];
+        bi = i;
       }
     }
-    red_v[tid] = bv;
-    red_i[tid] = bi;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double v2 = __shfl_xor(bv, o, 64);
+      const int i2 = __shfl_xor(bi, o, 64);
+      if (i2 != 0x7fffffff && (bi == 0x7fffffff || v2 > bv || (v2 == bv && i2 < bi))) {
+        bv = v2;
+        bi = i2;
+      }
+    }
+    if (lane == 0) {
+      wv[wid] = bv;
+      wi[wid] = bi;
+    }
     __syncthreads();
-    for (int w = nt / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        const double v2 = red_v[tid + w];
-        const int i2 = red_i[tid + w];
-        if (v2 > red_v[tid] || (v2 == red_v[tid] && i2 < red_i[tid])) {
-          red_v[tid] = v2;
-          red_i[tid] = i2;
+    if (wid == 0) {
+      bv = lane < PCHOL_WG / 64 ? wv[lane] : 0.0;
+      bi = lane < PCHOL_WG / 64 ? wi[lane] : 0x7fffffff;
+#pragma unroll
+      for (int o = 8; o > 0; o >>= 1) {
+        const double v2 = __shfl_xor(bv, o, 64);
+        const int i2 = __shfl_xor(bi, o, 64);
+        if (i2 != 0x7fffffff && (bi == 0x7fffffff || v2 > bv || (v2 == bv && i2 < bi))) {
+          bv = v2;
+          bi = i2;
         }
       }
-      __syncthreads();
+      if (lane == 0) {
+        sel_v = bv;
+        sel_i = bi;
+      }
     }
-    const double dp = red_v[0];
-    const int p = red_i[0];
     __syncthreads();
-    if (s == 0) d1 = dp;
-    if (!(dp > tol2 * d1) || !(dp > 0.0)) break;
-    for (int l = tid; l < s; l += nt) lp[l] = L[(long long)l * n + p];
-    if (tid == 0) {
-      J.piv[s] = p;
-      done[p] = 1;
+    const double dp = sel_v;
+    const int p = sel_i;
+    if (s0 + j == 0 && p != 0x7fffffff) d1 = dp;
+    if (p == 0x7fffffff || !(dp > 0.0) || !(dp > tol2 * d1)) {
+      fin = true;
+      break;
+    }
+    // the pivot row's entries of this panel's earlier columns
+    if (tid == (p & (PCHOL_WG - 1))) {
+#pragma unroll
+      for (int r = 0; r < RPT; ++r)
+        if (r == p / PCHOL_WG) {
+#pragma unroll
+          for (int t = 0; t < NB; ++t) lp[t] = lr[r][t];
+        }
     }
     __syncthreads();
     const double lss = sqrt(dp);
-    for (int j = tid; j < n; j += nt) {
-      double x;
-      if (j == p) {
+    const double* Gp = J.Gw + (long long)p * c;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + r * PCHOL_WG;
+      double x = 0.0;
+      if (i == p) {
         x = lss;
-      } else if (done[j]) {
-        x = 0.0;
-      } else {
-        // four independent partial sums keep several loads in flight
-        double x0 = G[(long long)p * n + j], x1 = 0.0, x2 = 0.0, x3 = 0.0;
-        const double* Lj = L + j;
-        int l = 0;
-        for (; l + 3 < s; l += 4) {
-          x0 -= Lj[(long long)l * n] * lp[l];
-          x1 -= Lj[(long long)(l + 1) * n] * lp[l + 1];
-          x2 -= Lj[(long long)(l + 2) * n] * lp[l + 2];
-          x3 -= Lj[(long long)(l + 3) * n] * lp[l + 3];
+        dl[r] = PIV_DONE;
+      } else if (dl[r] != PIV_DONE) {
+        double a0 = Gp[i], a1 = 0.0;
+#pragma unroll
+        for (int t = 0; t < NB; t += 2) {
+          a0 -= lr[r][t] * lp[t];
+          a1 -= lr[r][t + 1] * lp[t + 1];
         }
-        for (; l < s; ++l) x0 -= Lj[(long long)l * n] * lp[l];
-        x = ((x0 + x1) + (x2 + x3)) / lss;
-        d[j] -= x * x;
+        x = (a0 + a1) / lss;
+        dl[r] -= x * x;
       }
-      L[(long long)s * n + j] = x;
+#pragma unroll
+      for (int t = 0; t < NB; ++t)
+        if (t == j) lr[r][t] = x;
     }
+    if (tid == 0) J.piv[s0 + j] = p;
+    steps = j + 1;
     __syncthreads();
-    k = s + 1;
   }
-  // leading factor in pivot order: L1(a, b) = L(piv[a], b), lower triangular
-  for (long long e = tid; e < (long long)k * k; e += nt) {
-    const int a = (int)(e % k), b = (int)(e / k);
-    J.L1[(long long)b * n + a] = (a >= b) ? L[(long long)b * n + J.piv[a]] : 0.0;
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int i = tid + r * PCHOL_WG;
+    if (i < c) {
+      J.d[i] = dl[r];
+#pragma unroll
+      for (int t = 0; t < NB; ++t) J.Lp[(long long)t * c + i] = lr[r][t];
+    }
   }
-  for (int j = k + tid; j < n; j += nt) J.piv[j] = -1;
-  __syncthreads();
-  wg_tri_inv_lower(J.L1, n, J.Linv, n, k);
-  if (tid == 0) *J.kout = k;
+  if (tid == 0) {
+    J.state[0] = s0 + steps;
+    if (fin) J.state[1] = 1;
+    if (s0 == 0) *J.d1 = d1;
+  }
+}
+
+// d[e * c + i] = G_e(i, i); state and d1 cleared
+__global__ void ppanel_init_kernel(const double* __restrict__ G, int c, int nj, double* __restrict__ d,
+                                   int* __restrict__ state, double* __restrict__ d1) {
+  const long long tot = (long long)nj * c;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const long long b = e / c, i = e - b * c;
+    d[e] = G[b * c * c + i * c + i];
+    if (i == 0) {
+      state[2 * b] = 0;
+      state[2 * b + 1] = 0;
+      d1[b] = 0.0;
+    }
+  }
+}
+
+// out_e(a, b) = G_e(piv_e[a], piv_e[b]) for a, b < k_e (all ld c)
+struct GatherJob {
+  const double* G;
+  const int* piv;
+  double* out;
+  int k;
+};
+__global__ void gather_sym_kernel(const GatherJob* __restrict__ jobs, int c) {
+  const GatherJob J = jobs[blockIdx.y];
+  const long long tot = (long long)J.k * J.k;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const int a = (int)(e % J.k), b = (int)(e / J.k);
+    J.out[(long long)b * c + a] = J.G[(long long)J.piv[b] * c + J.piv[a]];
+  }
 }
 
 // ------------------------------------------------------------------ host side
@@ -375,6 +435,93 @@ struct Peeler {
     }
   }
 
+  // Pivots (dpiv, nj x c) and ranks (rk) of nj Gram matrices (c x c each,
+  // consecutive, ld c) by blocked pivoted Cholesky; G is preserved.
+  void pivot_ranks(const double* G, int c, int nj, double tol2, int* dpiv, std::vector<int>& rk, Scratch& scr) {
+    TraceTag tag("peel_pivot");
+    RSF_CHECK(c <= PCHOL_MAXN, RSF_E_INVALID,
+              "peeling needs more than " + std::to_string(PCHOL_MAXN) + " probe columns per block");
+    const int NB = c <= 1024 ? 32 : c <= 2048 ? 16 : 8;
+    const long long cc = (long long)c * c;
+    double* Gw = scr.make<double>(cc * nj);
+    copy_dev(Gw, G, cc * nj, s);
+    double* d = scr.make<double>((long long)c * nj);
+    double* Lp = scr.make<double>((long long)c * NB * nj);
+    double* d1 = scr.make<double>(nj);
+    int* state = scr.make<int>(2 * nj);
+    hipLaunchKernelGGL(ppanel_init_kernel, dim3(grid_of((long long)c * nj)), dim3(256), 0, s, G, c, nj, d, state, d1);
+    RSF_HIP(hipGetLastError());
+    std::vector<int> active(nj);
+    for (int e = 0; e < nj; ++e) active[e] = e;
+    std::vector<int> hs(2 * nj, 0);
+    const int npanel = (c + NB - 1) / NB;
+    for (int pnl = 0; pnl <= npanel && !active.empty(); ++pnl) {
+      std::vector<PpanelJob> jobs;
+      for (int e : active)
+        jobs.push_back(PpanelJob{Gw + cc * e, d + (long long)c * e, Lp + (long long)c * NB * e,
+                                 dpiv + (long long)c * e, state + 2 * e, d1 + e, c});
+      PpanelJob* dj = scr.make<PpanelJob>(jobs.size());
+      upload(dj, jobs, s);
+      const dim3 grid((unsigned)jobs.size()), blk(PCHOL_WG);
+      if (c <= 1024)
+        hipLaunchKernelGGL((ppanel_kernel<1, 32>), grid, blk, 0, s, dj, tol2);
+      else if (c <= 2048)
+        hipLaunchKernelGGL((ppanel_kernel<2, 16>), grid, blk, 0, s, dj, tol2);
+      else
+        hipLaunchKernelGGL((ppanel_kernel<4, 8>), grid, blk, 0, s, dj, tol2);
+      RSF_HIP(hipGetLastError());
+      // every few panels, drop the matrices that have reached their rank
+      if (pnl % 4 == 3 || pnl + 1 >= npanel) {
+        RSF_HIP(hipMemcpyAsync(hs.data(), state, hs.size() * sizeof(int), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipStreamSynchronize(s));
+        std::vector<int> still;
+        for (int e : active)
+          if (!hs[2 * e + 1]) still.push_back(e);
+        active.swap(still);
+        if (active.empty()) break;
+      }
+      std::vector<GemmDesc> tg;
+      for (int e : active)
+        tg.push_back(gemm_desc(c, c, NB, -1.0, colmaj(Lp + (long long)c * NB * e, c),
+                               colmajT(Lp + (long long)c * NB * e, c), 1.0, colmaj(Gw + cc * e, c)));
+      gemm_batched(tg, scr, s);
+    }
+    RSF_CHECK(active.empty(), RSF_E_INVALID, "pivoted Cholesky did not terminate");
+    rk.assign(nj, 0);
+    for (int e = 0; e < nj; ++e) rk[e] = hs[2 * e];
+  }
+
+  // Linv_e = L1_e^-1 with L1_e L1_e^T = G_e(piv_e[:k_e], piv_e[:k_e]) (ld c): the
+  // leading factor of the pivoted Cholesky, recomputed by the batched blocked
+  // Cholesky on the gathered pivot block.
+  void leading_factors(const double* G, int c, int nj, const int* dpiv, const std::vector<int>& rk, double* Linv,
+                       Scratch& scr) {
+    const long long cc = (long long)c * c;
+    double* G11 = scr.make<double>(cc * nj);
+    std::vector<GatherJob> gj;
+    std::vector<CholProblem> cp;
+    int kmax = 0;
+    for (int e = 0; e < nj; ++e) {
+      if (rk[e] == 0) continue;
+      gj.push_back(GatherJob{G + cc * e, dpiv + (long long)c * e, G11 + cc * e, rk[e]});
+      cp.push_back(CholProblem{G11 + cc * e, c, rk[e], Linv + cc * e, c, nullptr});
+      kmax = std::max(kmax, rk[e]);
+    }
+    if (gj.empty()) return;
+    GatherJob* dg = scr.make<GatherJob>(gj.size());
+    upload(dg, gj, s);
+    hipLaunchKernelGGL(gather_sym_kernel, dim3(grid_of((long long)kmax * kmax), (unsigned)gj.size()), dim3(256), 0, s,
+                       dg, c);
+    RSF_HIP(hipGetLastError());
+    int* fail = scr.make<int>(1);
+    RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
+    batched_chol_inv(cp, fail, scr, s);
+    int fh = 0;
+    RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
+    RSF_HIP(hipStreamSynchronize(s));
+    RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: pivot block of a sample Gram matrix is not positive definite");
+  }
+
   void run(double eps_peel, uint64_t seed, double* tr_inv, double* tr_rho, PeelStats* st) {
     const long long n = t.n;
     const int D = t.maxdepth;
@@ -410,7 +557,6 @@ struct Peeler {
       }
       const int nblk = (int)blocks.size();
       std::vector<int> rk(2 * nblk);
-      int* dk = nullptr;
       int* dpiv = nullptr;
       double* Gram = nullptr;
       double* Ginv = nullptr;
@@ -458,13 +604,8 @@ struct Peeler {
         RSF_CHECK(total <= PCHOL_MAXN, RSF_E_INVALID,
                   "peeling needs more than " + std::to_string(PCHOL_MAXN) + " probe columns per block");
         Gram = scr.make<double>(goff[2 * nblk]);
-        Ginv = scr.make<double>(goff[2 * nblk]);
-        double* Lw = scr.make<double>(goff[2 * nblk]);
-        double* L1 = scr.make<double>(goff[2 * nblk]);
-        dk = scr.make<int>(2 * nblk);
         dpiv = scr.make<int>((size_t)2 * nblk * total);
         std::vector<GemmDesc> g;
-        std::vector<PcholJob> pj;
         for (int op = 0; op < 2; ++op)
           for (int e = 0; e < nblk; ++e) {
             const int rb = blocks[e].first, cbx = blocks[e].second;
@@ -472,22 +613,15 @@ struct Peeler {
             const int idx = op * nblk + e;
             g.push_back(gemm_desc(total, total, t.count[rb], 1.0, Mat{Yb, 1, 4LL * total, nullptr},
                                   panel(Yb, 4LL * total), 0.0, colmaj(Gram + goff[idx], total)));
-            pj.push_back(PcholJob{Gram + goff[idx], total, dpiv + (long long)idx * total, dk + idx, Lw + goff[idx],
-                                  L1 + goff[idx], Ginv + goff[idx]});
           }
         {
           TraceTag tg("peel_gram");
           gemm_batched(g, scr, s);
         }
-        PcholJob* dj = scr.make<PcholJob>(pj.size());
-        upload(dj, pj, s);
         // relative pivots below ~1e-13 of the Gram diagonal are rounding noise
         // (the Gram squares the singular values), so the threshold is floored there
         const double tol2 = std::max(eps_peel * eps_peel, 1e-13);
-        hipLaunchKernelGGL(pchol_kernel, dim3((unsigned)pj.size()), dim3(PCHOL_WG), 0, s, dj, tol2);
-        RSF_HIP(hipGetLastError());
-        RSF_HIP(hipMemcpyAsync(rk.data(), dk, rk.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-        RSF_HIP(hipStreamSynchronize(s));
+        pivot_ranks(Gram, total, 2 * nblk, tol2, dpiv, rk, scr);
         bool need = false;
         maxrank = 0;
         for (int op = 0; op < 2; ++op)
@@ -499,6 +633,9 @@ struct Peeler {
         if (!need) break;
         c = grow_cols(total, maxrank);
       }
+      // leading factor L1 of each Gram matrix in pivot order and its inverse
+      Ginv = scr.make<double>(goff[2 * nblk]);
+      leading_factors(Gram, total, 2 * nblk, dpiv, rk, Ginv, scr);
       prev = maxrank;
       if (st && lev < 32) {
         st->cols[lev] = total;

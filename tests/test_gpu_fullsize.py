@@ -62,17 +62,28 @@ def test_fullsize_loglik_model_sample_against_dense(c3):
         pytest.skip("model-sample reference not generated (tests/golden/make_dense_golden.py ... model)")
     z = np.load(zpath)
     eps = spec["eps"]
+    th = spec["theta"]
     ell, alpha = F.loglik(_t(z), want_alpha=True)
+    a = alpha.cpu().numpy()
     rel_ld = abs(F.logdet - gold["logdet"]) / abs(gold["logdet"])
     rel_l = abs(ell - gold["ell"]) / abs(gold["ell"])
     idx = np.array(gold["alpha_index"])
     ref = np.array(gold["alpha_value"])
-    rel_a = np.linalg.norm(alpha.cpu().numpy()[idx] - ref) / np.linalg.norm(ref)
-    print("n=65536 model z: logdet rel %.2e, l rel %.2e, sampled alpha rel %.2e" % (rel_ld, rel_l, rel_a), flush=True)
+    rel_a = np.linalg.norm(a[idx] - ref) / np.linalg.norm(ref)
+    # backward error of alpha on sampled rows of Sigma (the oracle's rows, one
+    # by one): |(Sigma a - z)_i| <= |(Sigma - F)_i,:| |a| <= |Sigma - F| |a|
+    rows = K.cov_block(P, idx, np.arange(spec["n"]), th, spec["kernel"])
+    res = rows @ a - z[idx]
+    norm_est = float(np.max(np.abs(rows).sum(axis=1)))        # ~ |Sigma|_2 (Gershgorin)
+    back = float(np.max(np.abs(res))) / (norm_est * np.linalg.norm(a))
+    kappa = norm_est / th[2]                                   # lambda_min >= nugget
+    print("n=65536 model z: logdet rel %.2e, l rel %.2e, sampled alpha rel %.2e, backward %.2e, kappa <= %.1e"
+          % (rel_ld, rel_l, rel_a, back, kappa), flush=True)
     assert rel_ld <= 10 * eps
     assert rel_l <= 10 * eps
-    # Sigma^-1 z carries kappa(Sigma) (~1e4 .. 1e6 at a 1e-4 nugget) times eps
-    assert rel_a <= 1e4 * eps
+    assert back <= 10 * eps
+    # forward error <= kappa * backward error
+    assert rel_a <= 10 * eps * kappa
 
 
 def test_fullsize_logdet_white_noise_against_dense(c3):
