@@ -115,6 +115,18 @@ def main():
     R.trace_enable(False)
     ms, flops, nbytes, launches, phases = R.trace_read(reset=True, phases=True)
     ms_per_step = 1000.0 * elapsed / args.steps
+    # phases are "<phase>" or "<phase>/<sweep direction><depth>": the JSON line
+    # carries the phase totals, stderr the per-level split
+    totals = {}
+    for k, v in sorted(phases.items()):
+        top = k.split("/")[0]
+        a = totals.setdefault(top, [0.0, 0.0])
+        a[0] += v[0]
+        a[1] += v[1]
+        if "/" in k:
+            print("  %-24s %9.2f ms/step %7.2f TFLOP/s" % (k, v[0] / args.steps,
+                  (v[1] / (v[0] * 1e-3) / 1e12) if v[0] > 0 else 0.0), file=sys.stderr)
+    phases = totals
     achieved = (flops / (ms * 1e-3)) / 1e12 if ms > 0 else 0.0
     out = {
         "metric": "loglik+grad evals/sec at n=%d (eps=%g)" % (n, spec["eps"]),

@@ -122,8 +122,8 @@ def trace_read(reset=False, phases=False):
     _check(load().rsf_trace_read(C.byref(ms), C.byref(fl), C.byref(by), C.byref(n), 0))
     ph = {}
     if phases:
-        buf = C.create_string_buffer(8192)
-        _check(load().rsf_trace_phases(buf, 8192))
+        buf = C.create_string_buffer(1 << 16)
+        _check(load().rsf_trace_phases(buf, 1 << 16))
         for item in buf.value.decode().split(";"):
             if item:
                 name, t, f = item.split(":")

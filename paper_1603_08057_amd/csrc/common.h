@@ -74,6 +74,9 @@ inline void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
     RSF_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
 }
 
+// accumulator of one 16 x 16 x 4 FP64 matrix-core product (4 doubles per lane)
+typedef double v4d __attribute__((ext_vector_type(4)));
+
 // ---------------------------------------------------------------- batched GEMM
 // C(i, j) = alpha * sum_p A(i, p) B(p, j) + beta * C(i, j) for one problem.
 // Element (i, j) of an operand X lives at X.ptr[row(i) * rs + j * cs] where
@@ -166,6 +169,17 @@ void trace_enable(bool on);
 void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset);
 // "tag:ms:flops;..." per call-site tag (read after trace_read)
 std::string trace_tags();
+// The current phase name.
+std::string trace_current();
+// Times the launches issued on stream s while it is alive (HIP events) and
+// counts their algorithmic flops and bytes under the current phase name.
+struct TraceLaunch {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipStream_t s;
+  double flops, bytes;
+  TraceLaunch(hipStream_t st, double fl, double by);
+  ~TraceLaunch();
+};
 // Names the GEMM launches issued while it is alive (for the per-phase split).
 struct TraceTag {
   std::string prev;

@@ -807,6 +807,13 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
     L.total_r = L.r_off[nb];
     L.total_t = L.t_off[nb];
     L.total_l = L.l_off[nb];
+    {
+      std::vector<BoxRec> br(nb);
+      for (int i = 0; i < nb; ++i)
+        br[i] = BoxRec{kh[i], L.a[i] - kh[i], L.s_off[i], L.r_off[i], L.t_off[i], L.l_off[i]};
+      L.box = F.arena.make<BoxRec>(std::max(nb, 1));
+      upload(L.box, br, s);
+    }
     L.S = F.arena.make<int>(std::max<long long>(L.total_s, 1));
     L.R = F.arena.make<int>(std::max<long long>(L.total_r, 1));
     L.T = F.arena.make<double>(std::max<long long>(L.total_t, 1));

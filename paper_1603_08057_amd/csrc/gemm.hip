@@ -7,7 +7,6 @@
 
 namespace rsf {
 
-typedef double v4d __attribute__((ext_vector_type(4)));
 
 // ---- device memory pool
 // Freed blocks are kept per size class and handed out again in stream order:
@@ -218,6 +217,23 @@ struct GemmTrace {
 
 void trace_enable(bool on) { g_trace.on = on; }
 
+std::string trace_current() { return g_trace.tag; }
+
+TraceLaunch::TraceLaunch(hipStream_t st, double fl, double by) : s(st), flops(fl), bytes(by) {
+  if (!g_trace.on) return;
+  RSF_HIP(hipEventCreate(&e0));
+  RSF_HIP(hipEventCreate(&e1));
+  RSF_HIP(hipEventRecord(e0, s));
+}
+TraceLaunch::~TraceLaunch() {
+  if (!e0) return;
+  (void)hipEventRecord(e1, s);
+  g_trace.ev.push_back(TraceEv{e0, e1, g_trace.tag});
+  g_trace.flops += flops;
+  g_trace.bytes += bytes;
+  g_trace.launches += 1;
+  g_trace.tag_flops[g_trace.tag] += flops;
+}
 TraceTag::TraceTag(const char* t) : prev(g_trace.tag) { g_trace.tag = t; }
 TraceTag::~TraceTag() { g_trace.tag = prev; }
 

@@ -34,8 +34,15 @@ Tree build_tree(const double* xy_host, int64_t n, int leaf);
 //   T (k x r)       interpolation matrix of the ID,
 //   chol mode:  Linv (r x r) = L^-1 with X_rr = L L^T,  W (k x r) = X_sr L^-T,
 //   mult mode:  Xsr (k x r), Xrr (r x r).
+// One box of a level as the fused sweep kernels see it (device copy).
+struct BoxRec {
+  int k, r;
+  long long s_off, r_off, t_off, l_off;
+};
+
 struct LevelFactor {
   int depth = 0, box0 = 0, nb = 0;
+  BoxRec* box = nullptr;                   // device, nb records
   std::vector<int> a, k;
   std::vector<long long> s_off, r_off;     // offsets into S / R (ints)
   std::vector<long long> t_off, l_off;     // offsets into T/W/Xsr and Linv/Xrr (doubles)

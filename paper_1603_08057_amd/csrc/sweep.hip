@@ -65,10 +65,265 @@ static void scatter_rows(const int* rows, long long nrows, const double* Tmp, in
   RSF_HIP(hipGetLastError());
 }
 
+// ---------------------------------------------------------------- fused level sweeps for small boxes
+// When every box of a level has at most BS_AMAX active DOFs, one workgroup
+// takes one box and BS_NCT columns: it gathers the box's S and R rows into
+// LDS, applies the level's steps there with matrix-core products (the box's
+// dense blocks are read from global memory / L2) and scatters the rows back,
+// so the panel is read and written once per level instead of once per step.
+constexpr int BS_AMAX = 128;
+constexpr int BS_NCT = 32;
+constexpr int BS_KC = 8;  // k-steps per batch of operand loads
+enum BoxOp { BS_SOLVE_UP = 0, BS_SOLVE_DOWN = 1, BS_MULT_UP = 2, BS_MULT_DOWN = 3 };
+
+// LDS position of (row, col) in a BS_NCT-wide buffer: odd rows swap their
+// 16-column halves, so the 4 rows x 16 columns read by one matrix-core operand
+// load (and the row pairs of the gathers) spread over all banks.
+__device__ __forceinline__ int bsi(int row, int col) { return row * BS_NCT + (col ^ ((row & 1) << 4)); }
+
+// acc[p][q] += sum_kk A(16 (wave + 4 p) + row, kk) B(row0 + kk, 16 q + col) for
+// the row blocks of this wave (M <= 128 rows in 8 blocks over 4 waves) and the
+// two 16-column blocks.  B must hold finite values in rows [row0 + K, row0 + K + 4).
+template <class AF>
+__device__ __forceinline__ void box_mm(int M, int K, AF A, const double* Bl, int row0, v4d (&acc)[2][2],
+                                       int wave, int lane) {
+  if (16 * wave >= M) return;
+  const int i0 = 16 * wave + (lane & 15), i1 = i0 + 64;
+  const bool two = 16 * (wave + 4) < M;
+  const int kl = lane >> 4, cl = lane & 15;
+  // the A fragments of BS_KC k-steps are loaded together (one wait for the
+  // global / L2 latency), then fed to the matrix cores
+  for (int c0 = 0; c0 < K; c0 += 4 * BS_KC) {
+    double a0[BS_KC], a1[BS_KC];
+#pragma unroll
+    for (int t = 0; t < BS_KC; ++t) {
+      const int kk = c0 + 4 * t + kl;
+      a0[t] = (kk < K && i0 < M) ? A(i0, kk) : 0.0;
+      a1[t] = (two && kk < K && i1 < M) ? A(i1, kk) : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < BS_KC; ++t) {
+      if (c0 + 4 * t < K) {
+        const int kk = c0 + 4 * t + kl;
+        const double b0 = Bl[bsi(row0 + kk, cl)], b1 = Bl[bsi(row0 + kk, 16 + cl)];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[t], b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[t], b1, acc[0][1], 0, 0, 0);
+        if (two) {
+          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b1, acc[1][1], 0, 0, 0);
+        }
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void zero_acc(v4d (&acc)[2][2]) {
+#pragma unroll
+  for (int p = 0; p < 2; ++p)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) acc[p][q] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+// Calls f(row, col, value) for every accumulator entry with row < M.
+template <class EF>
+__device__ __forceinline__ void box_epilogue(int M, const v4d (&acc)[2][2], int wave, int lane, EF f) {
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int rb = 16 * (wave + 4 * p);
+    if (rb >= M) continue;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = rb + 4 * v + (lane >> 4);
+        if (row < M) f(row, 16 * q + (lane & 15), acc[p][q][v]);
+      }
+  }
+}
+
+template <int OP>
+__global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict__ boxes, int nbox, int ntile,
+                                                        const int* __restrict__ S, const int* __restrict__ R,
+                                                        const double* __restrict__ Tm,
+                                                        const double* __restrict__ Wm,
+                                                        const double* __restrict__ Lm, double* __restrict__ X,
+                                                        double* __restrict__ Y, int nc, long long ld,
+                                                        int amax) {
+  // LDS: Xl and Tl, (amax + 4) rows of BS_NCT each (amax = the level's largest box)
+  extern __shared__ double bs_smem[];
+  double* Xl = bs_smem;
+  double* Tl = bs_smem + (amax + 4) * BS_NCT;
+  // tiles of one box stay on one XCD (consecutive workgroup ids alternate XCDs)
+  const long long total = (long long)nbox * ntile;
+  const long long per = (long long)gridDim.x / 8;
+  const long long item = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (item >= total) return;
+  const int bx = (int)(item / ntile), tile = (int)(item - (long long)bx * ntile);
+  const BoxRec b = boxes[bx];
+  const int k = b.k, r = b.r, a = k + r;
+  if (r == 0) return;
+  const int j0 = tile * BS_NCT, ncol = min(BS_NCT, nc - j0);
+  const int* Sb = S + b.s_off;
+  const int* Rb = R + b.r_off;
+  const double* T = Tm + b.t_off;  // k x r
+  const double* W = Wm + b.t_off;  // k x r
+  const double* L = Lm + b.l_off;  // r x r
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  // gather [X_S; X_R] (and Y_S for the multiply down-sweep), zero rows up to a + 4
+  for (int e = tid; e < (a + 4) * BS_NCT; e += 256) {
+    const int row = e / BS_NCT, col = e - row * BS_NCT;
+    double v = 0.0, w = 0.0;
+    if (row < a && col < ncol) {
+      const long long g = row < k ? Sb[row] : Rb[row - k];
+      if (OP == BS_MULT_DOWN && row < k)
+        w = Y[g * ld + j0 + col];  // X_S is not used by this step
+      else
+        v = X[g * ld + j0 + col];
+    }
+    Xl[bsi(row, col)] = v;
+    if (OP == BS_MULT_DOWN) Tl[bsi(row, col)] = w;
+  }
+  if (OP == BS_SOLVE_UP || OP == BS_SOLVE_DOWN) {
+    for (int e = tid; e < 4 * BS_NCT; e += 256) Tl[bsi(r + e / BS_NCT, e % BS_NCT)] = 0.0;
+  }
+  __syncthreads();
+  v4d acc[2][2];
+  if (OP == BS_SOLVE_UP) {
+    // X_R -= T^T X_S
+    zero_acc(acc);
+    box_mm(r, k, [&](int i, int q) { return T[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
+    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(k + i, c)] -= v; });
+    __syncthreads();
+    // tmp = L^-1 X_R
+    zero_acc(acc);
+    box_mm(r, r, [&](int i, int q) { return L[i + (long long)q * r]; }, Xl, k, acc, wave, lane);
+    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Tl[bsi(i, c)] = v; });
+    __syncthreads();
+    // X_S -= W tmp
+    zero_acc(acc);
+    box_mm(k, r, [&](int i, int q) { return W[i + (long long)q * k]; }, Tl, 0, acc, wave, lane);
+    box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(i, c)] -= v; });
+    __syncthreads();
+  } else if (OP == BS_SOLVE_DOWN) {
+    // X_R -= W^T X_S
+    zero_acc(acc);
+    box_mm(r, k, [&](int i, int q) { return W[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
+    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(k + i, c)] -= v; });
+    __syncthreads();
+    // tmp = L^-T X_R
+    zero_acc(acc);
+    box_mm(r, r, [&](int i, int q) { return L[q + (long long)i * r]; }, Xl, k, acc, wave, lane);
+    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Tl[bsi(i, c)] = v; });
+    __syncthreads();
+    // X_S -= T tmp
+    zero_acc(acc);
+    box_mm(k, r, [&](int i, int q) { return T[i + (long long)q * k]; }, Tl, 0, acc, wave, lane);
+    box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(i, c)] -= v; });
+    __syncthreads();
+  } else if (OP == BS_MULT_UP) {
+    // X_S += T X_R
+    zero_acc(acc);
+    box_mm(k, r, [&](int i, int q) { return T[i + (long long)q * k]; }, Xl, k, acc, wave, lane);
+    box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(i, c)] += v; });
+    __syncthreads();
+    // Y_R += X_rr X_R + X_sr^T X_S
+    zero_acc(acc);
+    box_mm(r, r, [&](int i, int q) { return L[i + (long long)q * r]; }, Xl, k, acc, wave, lane);
+    box_mm(r, k, [&](int i, int q) { return W[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
+    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) {
+      if (c < ncol) Y[(long long)Rb[i] * ld + j0 + c] += v;
+    });
+  } else {
+    // Y_S += X_sr X_R
+    zero_acc(acc);
+    box_mm(k, r, [&](int i, int q) { return W[i + (long long)q * k]; }, Xl, k, acc, wave, lane);
+    box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Tl[bsi(i, c)] += v; });
+    __syncthreads();
+    // Y_R += T^T Y_S
+    zero_acc(acc);
+    box_mm(r, k, [&](int i, int q) { return T[q + (long long)i * k]; }, Tl, 0, acc, wave, lane);
+    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) {
+      if (c < ncol) Y[(long long)Rb[i] * ld + j0 + c] += v;
+    });
+  }
+  // scatter the changed rows back
+  if (OP == BS_SOLVE_UP || OP == BS_SOLVE_DOWN) {
+    for (int e = tid; e < a * BS_NCT; e += 256) {
+      const int row = e / BS_NCT, col = e - row * BS_NCT;
+      if (col >= ncol) continue;
+      if (row < k)
+        X[(long long)Sb[row] * ld + j0 + col] = Xl[bsi(row, col)];
+      else
+        X[(long long)Rb[row - k] * ld + j0 + col] = Tl[bsi(row - k, col)];
+    }
+  } else if (OP == BS_MULT_UP) {
+    for (int e = tid; e < k * BS_NCT; e += 256) {
+      const int row = e / BS_NCT, col = e - row * BS_NCT;
+      if (col < ncol) X[(long long)Sb[row] * ld + j0 + col] = Xl[bsi(row, col)];
+    }
+  } else {
+    for (int e = tid; e < k * BS_NCT; e += 256) {
+      const int row = e / BS_NCT, col = e - row * BS_NCT;
+      if (col < ncol) Y[(long long)Sb[row] * ld + j0 + col] = Tl[bsi(row, col)];
+    }
+  }
+}
+
+// Runs one level step with the fused kernel when every box fits; false otherwise.
+static bool box_sweep(const LevelFactor& L, int op, double* X, double* Y, int nc, long long ld, hipStream_t s) {
+  if (L.nb == 0 || nc <= 0) return true;
+  for (int i = 0; i < L.nb; ++i)
+    if (L.a[i] > BS_AMAX) return false;
+  int amax = 0;
+  for (int i = 0; i < L.nb; ++i) amax = std::max(amax, L.a[i]);
+  amax = (amax + 3) / 4 * 4;
+  const size_t lds = (size_t)(op == BS_MULT_UP ? 1 : 2) * (amax + 4) * BS_NCT * sizeof(double);
+  const int ntile = (nc + BS_NCT - 1) / BS_NCT;
+  const long long total = (long long)L.nb * ntile;
+  const long long grid = (total + 7) / 8 * 8;
+  RSF_CHECK(grid < (1LL << 31), RSF_E_INVALID, "panel too wide for the fused sweep");
+  const dim3 g((unsigned)grid), blk(256);
+  double fl = 0.0, by = 0.0;
+  for (int i = 0; i < L.nb; ++i) {
+    const double k = L.k[i], r = L.a[i] - L.k[i];
+    if (r == 0) continue;
+    fl += 2.0 * nc * (op == BS_MULT_DOWN ? 2.0 * k * r : op == BS_MULT_UP ? r * (2.0 * k + r) : r * (2.0 * k + r));
+    by += 8.0 * nc * (op == BS_SOLVE_UP || op == BS_SOLVE_DOWN ? 2.0 * (k + r) : 2.0 * k + 3.0 * r);
+  }
+  TraceLaunch tl(s, fl, by);
+  // the largest box needs more than the default dynamic LDS limit of 64 KiB
+  static bool lds_set[4] = {false, false, false, false};
+  const int max_lds = 2 * (BS_AMAX + 4) * BS_NCT * (int)sizeof(double);
+#define RSF_BOX(OPV)                                                                                          \
+  if (!lds_set[OPV]) {                                                                                        \
+    RSF_HIP(hipFuncSetAttribute((const void*)box_sweep_kernel<OPV>,                                          \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));                        \
+    lds_set[OPV] = true;                                                                                      \
+  }                                                                                                           \
+  hipLaunchKernelGGL(box_sweep_kernel<OPV>, g, blk, lds, s, L.box, L.nb, ntile, L.S, L.R, L.T, L.W, L.Lm, X, Y, \
+                     nc, ld, amax)
+  switch (op) {
+    case BS_SOLVE_UP: RSF_BOX(BS_SOLVE_UP); break;
+    case BS_SOLVE_DOWN: RSF_BOX(BS_SOLVE_DOWN); break;
+    case BS_MULT_UP: RSF_BOX(BS_MULT_UP); break;
+    default: RSF_BOX(BS_MULT_DOWN); break;
+  }
+#undef RSF_BOX
+  RSF_HIP(hipGetLastError());
+  return true;
+}
+
 // One batched GEMM over the boxes of a level:
 //   C_b = alpha op(A_b) B_b + beta C_b
 // with A_b a per-box dense block and B_b / C_b row sets of panels.
 enum Rows { RS, RR, RTMP };
+
+// Names the GEMMs of one level of a sweep "<phase>/<dir><depth>" in the trace.
+struct LevelTag {
+  TraceTag t;
+  static std::string name(int d, const char* dir) { return trace_current() + "/" + dir + std::to_string(d); }
+  LevelTag(int d, const char* dir) : t(name(d, dir).c_str()) {}
+};
 
 template <class AFn>
 static void level_gemm(const LevelFactor& L, int nc, double alpha, AFn afn, Rows brows, const double* Bp,
@@ -103,6 +358,8 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
   double* tmp = scr.make<double>((size_t)maxr * nc);
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "up");
+    if (box_sweep(L, BS_SOLVE_UP, X, nullptr, nc, ld, s)) continue;
     // X_R -= T^T X_S
     level_gemm(L, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, X, ld, scr, s);
@@ -125,6 +382,8 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
   }
   for (int d = 1; d <= D; ++d) {
     const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "down");
+    if (box_sweep(L, BS_SOLVE_DOWN, X, nullptr, nc, ld, s)) continue;
     // X_R -= W^T X_S
     level_gemm(L, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, X, ld, scr, s);
@@ -144,6 +403,7 @@ void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double*
   const int D = h->tree.maxdepth;
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "up");
     // X_S += T X_R
     level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
                RR, X, ld, 1.0, RS, X, ld, scr, s);
@@ -167,6 +427,7 @@ void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, dou
   const int D = h->tree.maxdepth;
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "up");
     level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lf + L.l_off[i], r); },
                RR, Y, ld, 0.0, RR, V, ld, scr, s);
   }
@@ -178,6 +439,7 @@ void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, dou
   }
   for (int d = 1; d <= D; ++d) {
     const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "down");
     // V_S += W Y_R
     level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
                RR, Y, ld, 1.0, RS, V, ld, scr, s);
@@ -194,6 +456,8 @@ void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, dou
   fill_zero(Y, h->tree.n * ld, s);
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "up");
+    if (box_sweep(L, BS_MULT_UP, X, Y, nc, ld, s)) continue;
     // X_S += T X_R
     level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
                RR, X, ld, 1.0, RS, X, ld, scr, s);
@@ -211,6 +475,8 @@ void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, dou
   }
   for (int d = 1; d <= D; ++d) {
     const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "down");
+    if (box_sweep(L, BS_MULT_DOWN, X, Y, nc, ld, s)) continue;
     // Y_S += X_sr X_R  (after the coarser levels' L operators)
     level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
                RR, X, ld, 1.0, RS, Y, ld, scr, s);
