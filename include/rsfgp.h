@@ -69,10 +69,17 @@ typedef struct {
   double prox_r_out;    /*   (Fig. 3: 1.75 and 2.45) */
   double rq_alpha;      /* shape alpha of the rational quadratic kernel */
   size_t mem_cap_bytes; /* 0 = unlimited; otherwise RSF_E_OOM beyond this many bytes */
+  int precision;        /* RSF_FP64 (default) or RSF_MIXED: kernel entries evaluated in
+                           FP32 and the Schur-complement products of the elimination
+                           (X_sr, X_rr, W, X_ss) on FP32 matrix cores with FP32
+                           accumulation; the IDs, the Cholesky factors of the redundant
+                           blocks and of the root, log|F| and every sweep stay FP64 */
 } rsf_opts;
 
+enum { RSF_FP64 = 0, RSF_MIXED = 1 };
+
 /* Fills *opts with the defaults above (n_prox 256, 4 rings, 1.8, 1.75, 2.45,
- * alpha 1, no cap).  Errors: RSF_E_INVALID if opts is NULL. */
+ * alpha 1, no cap, FP64).  Errors: RSF_E_INVALID if opts is NULL. */
 rsf_status rsf_opts_default(rsf_opts* opts);
 
 /* Builds F ~= Sigma(theta) (Section 2, eq. rskelf; Algorithm 1, step "factor").
@@ -145,6 +152,41 @@ typedef struct {
  *   info_or_null  host; receives the split terms and peeling statistics. */
 rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
                     rsf_grad_info* info_or_null, void* stream);
+
+/* ---- batches of independent instances ------------------------------------
+ * One handle holds nb independent GP instances (their own sites, sizes and
+ * theta; one kernel, eps, leaf and options).  Their quadtrees form one forest
+ * whose depth-0 boxes are the instances' roots, so every level of the
+ * factorization, of every sweep and of the peeling is one set of launches
+ * over the boxes of all instances (the boxes of one level are independent,
+ * Section 2.2).  Instance i occupies the caller-order range
+ * [sum_{j<i} n_j, sum_{j<=i} n_j) of the single-vector calls above, which
+ * act on the block-diagonal operator (rsf_logdet and rsf_loglik then return
+ * the sums over the instances, rsf_grad is refused).  Ownership and errors as
+ * for the single-instance calls.
+ *   d_points  host array of nb device pointers, instance i: n[i] x 2 row-major.
+ *   n         host, nb sizes (>= 1 each).
+ *   theta     host, nb x p values (p = 3: rho, sigma2, nugget per instance). */
+rsf_status rsf_factor_create_batched(const double* const* d_points, const int64_t* n, int nb,
+                                     const double* theta, int p, int kernel, double eps, int leaf,
+                                     const rsf_opts* opts, void* stream, rsf_factor* out);
+
+/* *nb = number of instances of f (1 for a single-instance handle). */
+rsf_status rsf_batch_size(rsf_factor f, int* nb);
+
+/* out_nb (host, nb values) = log|F_i| per instance. */
+rsf_status rsf_logdet_batched(rsf_factor f, double* out_nb);
+
+/* out_nb (host, nb values) = l_i(theta_i) per instance; d_z: host array of nb
+ * device pointers, instance i holds n[i] observations. */
+rsf_status rsf_loglik_batched(rsf_factor f, const double* const* d_z, double* out_nb, void* stream);
+
+/* g_nb_p (host, nb x 3 values) = the score of every instance, as rsf_grad.
+ * The peeling of all instances shares its probe counts per level (the largest
+ * rank over all instances' sibling blocks decides); info_or_null receives
+ * instance 0's split terms and the shared peeling statistics. */
+rsf_status rsf_grad_batched(rsf_factor f, const double* const* d_z, double eps_peel, uint64_t seed,
+                            double* g_nb_p, rsf_grad_info* info_or_null, void* stream);
 
 typedef struct {
   int64_t n;

@@ -10,6 +10,7 @@ device memory and the current stream.  There is no CPU fallback: without the
 built library, or without a HIP device, the calls raise.
 """
 from ._lib import (  # noqa: F401
-    MATERN12, MATERN32, MATERN52, RQ, RsfError, Factor, Options, GradInfo, library_path, load, trace_enable, trace_read,
+    MATERN12, MATERN32, MATERN52, RQ, PRECISIONS, RsfError, Factor, BatchedFactor, Options, GradInfo, library_path, load,
+    trace_enable, trace_read,
 )
 from .autograd import loglik_fn  # noqa: F401

@@ -16,10 +16,13 @@ class RsfError(RuntimeError):
         self.name = _ERRORS.get(code, str(code))
 
 
+PRECISIONS = {"fp64": 0, "mixed": 1}
+
+
 class Options(C.Structure):
     _fields_ = [("n_prox", C.c_int), ("prox_rings", C.c_int), ("r_near", C.c_double),
                 ("prox_r_in", C.c_double), ("prox_r_out", C.c_double), ("rq_alpha", C.c_double),
-                ("mem_cap_bytes", C.c_size_t)]
+                ("mem_cap_bytes", C.c_size_t), ("precision", C.c_int)]
 
 
 class GradInfo(C.Structure):
@@ -65,6 +68,12 @@ def load():
         "rsf_skeleton_export": ([vp, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                  C.POINTER(C.c_int32)], C.c_int),
         "rsf_last_error": ([], C.c_char_p),
+        "rsf_factor_create_batched": ([C.POINTER(vp), C.POINTER(i64), C.c_int, dp, C.c_int, C.c_int, C.c_double,
+                                       C.c_int, C.POINTER(Options), vp, C.POINTER(vp)], C.c_int),
+        "rsf_batch_size": ([vp, C.POINTER(C.c_int)], C.c_int),
+        "rsf_logdet_batched": ([vp, dp], C.c_int),
+        "rsf_loglik_batched": ([vp, C.POINTER(vp), dp, vp], C.c_int),
+        "rsf_grad_batched": ([vp, C.POINTER(vp), C.c_double, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
         "rsf_trace_enable": ([C.c_int], C.c_int),
         "rsf_trace_read": ([dp, dp, dp, C.POINTER(C.c_int64), C.c_int], C.c_int),
         "rsf_trace_phases": ([C.c_char_p, C.c_size_t], C.c_int),
@@ -138,7 +147,8 @@ class Factor:
     """F ~= Sigma(theta) for observation sites `points` (n x 2)."""
 
     def __init__(self, points, theta, kernel=MATERN32, eps=1e-6, leaf=64, n_prox=256, prox_rings=4,
-                 r_near=1.8, prox_r_in=1.75, prox_r_out=2.45, rq_alpha=1.0, mem_cap_bytes=0):
+                 r_near=1.8, prox_r_in=1.75, prox_r_out=2.45, rq_alpha=1.0, mem_cap_bytes=0,
+                 precision="fp64"):
         lib = load()
         torch = _torch()
         if not torch.cuda.is_available():
@@ -153,6 +163,10 @@ class Factor:
         opts.n_prox, opts.prox_rings, opts.r_near = n_prox, prox_rings, r_near
         opts.prox_r_in, opts.prox_r_out, opts.rq_alpha = prox_r_in, prox_r_out, rq_alpha
         opts.mem_cap_bytes = mem_cap_bytes
+        if precision not in PRECISIONS:
+            raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
+        opts.precision = PRECISIONS[precision]
+        self.precision = precision
         th = (C.c_double * 3)(*[float(v) for v in theta])
         h = C.c_void_p()
         _check(lib.rsf_factor_create(C.c_void_p(pts.data_ptr()), self.n, th, 3, int(kernel), float(eps),
@@ -230,3 +244,83 @@ class Factor:
         idx = (C.c_int32 * max(1, offs[nb.value]))()
         _check(load().rsf_skeleton_export(self._h, level, offs, idx, C.byref(nb)))
         return list(offs), list(idx)[:offs[nb.value]]
+
+
+class BatchedFactor:
+    """F_i ~= Sigma_i(theta_i) for independent instances, factored together:
+    every quadtree level of all instances is one set of launches."""
+
+    def __init__(self, points_list, thetas, kernel=MATERN32, eps=1e-6, leaf=64, n_prox=256, prox_rings=4,
+                 r_near=1.8, prox_r_in=1.75, prox_r_out=2.45, rq_alpha=1.0, mem_cap_bytes=0,
+                 precision="fp64"):
+        lib = load()
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("rsfgp needs a HIP device")
+        pts = [_dev_f64(p) for p in points_list]
+        for p in pts:
+            if p.dim() != 2 or p.shape[1] != 2:
+                raise ValueError("points must be n x 2")
+        self.nb = len(pts)
+        self.ns = [int(p.shape[0]) for p in pts]
+        self.points = pts
+        th = [float(v) for t in thetas for v in t]
+        if len(th) != 3 * self.nb:
+            raise ValueError("need 3 parameters per instance")
+        opts = Options()
+        lib.rsf_opts_default(C.byref(opts))
+        opts.n_prox, opts.prox_rings, opts.r_near = n_prox, prox_rings, r_near
+        opts.prox_r_in, opts.prox_r_out, opts.rq_alpha = prox_r_in, prox_r_out, rq_alpha
+        opts.mem_cap_bytes = mem_cap_bytes
+        opts.precision = PRECISIONS[precision]
+        ptrs = (C.c_void_p * self.nb)(*[p.data_ptr() for p in pts])
+        ns = (C.c_int64 * self.nb)(*self.ns)
+        tharr = (C.c_double * len(th))(*th)
+        h = C.c_void_p()
+        _check(lib.rsf_factor_create_batched(ptrs, ns, self.nb, tharr, 3, int(kernel), float(eps), int(leaf),
+                                             C.byref(opts), _stream(), C.byref(h)))
+        self._h = h
+        self.thetas = [tuple(t) for t in thetas]
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().rsf_factor_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _ptrs(self, zs):
+        zs = [_dev_f64(z).reshape(-1) for z in zs]
+        if len(zs) != self.nb or any(z.numel() != m for z, m in zip(zs, self.ns)):
+            raise ValueError("need one vector of n_i values per instance")
+        return zs, (C.c_void_p * self.nb)(*[z.data_ptr() for z in zs])
+
+    @property
+    def logdets(self):
+        out = (C.c_double * self.nb)()
+        _check(load().rsf_logdet_batched(self._h, out))
+        return list(out)
+
+    def loglik(self, zs):
+        zs, ptrs = self._ptrs(zs)
+        out = (C.c_double * self.nb)()
+        _check(load().rsf_loglik_batched(self._h, ptrs, out, _stream()))
+        return list(out)
+
+    def grad(self, zs, eps_peel=0.0, seed=0):
+        """(nb x 3 scores, GradInfo of instance 0 and the shared peeling)."""
+        zs, ptrs = self._ptrs(zs)
+        g = (C.c_double * (3 * self.nb))()
+        info = GradInfo()
+        _check(load().rsf_grad_batched(self._h, ptrs, float(eps_peel), int(seed), g, C.byref(info), _stream()))
+        return [tuple(g[3 * i:3 * i + 3]) for i in range(self.nb)], info
+
+    def tree_info(self):
+        info = TreeInfo()
+        _check(load().rsf_tree_export(self._h, None, C.byref(info)))
+        return {"n": info.n, "depth": info.depth, "nbox": info.nbox, "root_size": info.root_size,
+                "factor_bytes": info.factor_bytes}

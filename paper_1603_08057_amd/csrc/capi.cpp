@@ -1,4 +1,5 @@
 // The C ABI of rsfgp (declared in include/rsfgp.h).
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -65,71 +66,126 @@ rsf_status rsf_opts_default(rsf_opts* o) {
   o->prox_r_out = 2.45;
   o->rq_alpha = 1.0;
   o->mem_cap_bytes = 0;
+  o->precision = RSF_FP64;
   return RSF_OK;
+}
+
+static void check_theta(const double* theta) {
+  for (int i = 0; i < 3; ++i) RSF_CHECK(std::isfinite(theta[i]), RSF_E_NONFINITE, "non-finite theta");
+  RSF_CHECK(theta[0] > 0.0, RSF_E_INVALID, "rho must be > 0");
+  RSF_CHECK(theta[1] > 0.0, RSF_E_INVALID, "sigma2 must be > 0");
+}
+
+// Shared by the single and the batched constructor: host copies of every
+// instance's sites, 3 parameters per instance.
+// Argument checks that need no device access (run before any copy).
+static void check_args(const double* thetas, int ni, int kernel, double eps, int leaf) {
+  RSF_CHECK(leaf >= 1, RSF_E_INVALID, "leaf must be >= 1");
+  RSF_CHECK(kernel >= RSF_MATERN12 && kernel <= RSF_RQ, RSF_E_INVALID, "unknown kernel");
+  RSF_CHECK(std::isfinite(eps), RSF_E_NONFINITE, "non-finite eps");
+  RSF_CHECK(eps > 0.0, RSF_E_INVALID, "eps must be > 0");
+  for (int i = 0; i < ni; ++i) check_theta(thetas + 3 * i);
+}
+
+static rsf_factor_s* create_handle(const std::vector<std::vector<double>>& xy, const std::vector<int64_t>& ns,
+                                   const double* thetas, int kernel, double eps, int leaf, const rsf_opts* opts,
+                                   hipStream_t s) {
+  const int ni = (int)ns.size();
+  check_args(thetas, ni, kernel, eps, leaf);
+  rsf_opts o;
+  if (opts)
+    o = *opts;
+  else
+    rsf_opts_default(&o);
+  RSF_CHECK(o.n_prox >= 1 && o.prox_rings >= 1 && o.n_prox % o.prox_rings == 0, RSF_E_INVALID,
+            "n_prox must be a positive multiple of prox_rings");
+  RSF_CHECK(o.r_near > 0 && o.prox_r_in > 0 && o.prox_r_out >= o.prox_r_in && o.rq_alpha > 0, RSF_E_INVALID,
+            "bad proxy geometry or rq_alpha");
+  RSF_CHECK(o.precision == RSF_FP64 || o.precision == RSF_MIXED, RSF_E_INVALID, "unknown precision");
+  std::unique_ptr<rsf_factor_s> h(new rsf_factor_s());
+  h->opt.n_prox = o.n_prox;
+  h->opt.prox_rings = o.prox_rings;
+  h->opt.r_near = o.r_near;
+  h->opt.r_in = o.prox_r_in;
+  h->opt.r_out = o.prox_r_out;
+  h->opt.rq_alpha = o.rq_alpha;
+  h->opt.mem_cap = o.mem_cap_bytes;
+  h->opt.mixed = o.precision == RSF_MIXED;
+  h->arena.cap = o.mem_cap_bytes;
+  h->kernel = kernel;
+  h->eps = eps;
+  h->leaf = leaf;
+  h->thetas.assign(thetas, thetas + 3 * ni);
+  for (int i = 0; i < 3; ++i) h->theta[i] = thetas[i];
+  std::vector<const double*> ptrs(ni);
+  for (int i = 0; i < ni; ++i) ptrs[i] = xy[i].data();
+  h->tree = build_forest(ptrs, ns, leaf);
+  const int64_t n = h->tree.n;
+  std::vector<double> px(n), py(n);
+  for (int64_t t = 0; t < n; ++t) {
+    // caller index c = ioff[i] + local index of instance i
+    const int64_t c = h->tree.perm[t];
+    const int i = (int)(std::upper_bound(h->tree.ioff.begin(), h->tree.ioff.end(), c) - h->tree.ioff.begin()) - 1;
+    const int64_t u = c - h->tree.ioff[i];
+    px[t] = xy[i][2 * (size_t)u];
+    py[t] = xy[i][2 * (size_t)u + 1];
+  }
+  h->px = h->arena.make<double>(n);
+  h->py = h->arena.make<double>(n);
+  h->perm = h->arena.make<int>(n);
+  RSF_HIP(hipMemcpy(h->px, px.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  RSF_HIP(hipMemcpy(h->py, py.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  RSF_HIP(hipMemcpy(h->perm, h->tree.perm.data(), n * sizeof(int), hipMemcpyHostToDevice));
+  make_proxy_table(h.get());
+  build_factor(h.get(), h->F, 0, s);
+  RSF_HIP(hipStreamSynchronize(s));
+  return h.release();
 }
 
 rsf_status rsf_factor_create(const double* d_points, int64_t n, const double* theta, int p, int kernel,
                              double eps, int leaf, const rsf_opts* opts, void* stream, rsf_factor* out) {
-  rsf_factor_s* h = nullptr;
-  int rc = guarded([&] {
+  return guarded([&] {
     RSF_CHECK(out != nullptr && d_points != nullptr && theta != nullptr, RSF_E_INVALID, "null argument");
     RSF_CHECK(p == 3, RSF_E_INVALID, "theta must hold 3 values (rho, sigma2, nugget)");
     RSF_CHECK(n >= 1, RSF_E_INVALID, "n must be >= 1");
-    RSF_CHECK(leaf >= 1, RSF_E_INVALID, "leaf must be >= 1");
-    RSF_CHECK(kernel >= RSF_MATERN12 && kernel <= RSF_RQ, RSF_E_INVALID, "unknown kernel");
-    for (int i = 0; i < 3; ++i) RSF_CHECK(std::isfinite(theta[i]), RSF_E_NONFINITE, "non-finite theta");
-    RSF_CHECK(std::isfinite(eps), RSF_E_NONFINITE, "non-finite eps");
-    RSF_CHECK(eps > 0.0, RSF_E_INVALID, "eps must be > 0");
-    RSF_CHECK(theta[0] > 0.0, RSF_E_INVALID, "rho must be > 0");
-    RSF_CHECK(theta[1] > 0.0, RSF_E_INVALID, "sigma2 must be > 0");
-    rsf_opts o;
-    if (opts)
-      o = *opts;
-    else
-      rsf_opts_default(&o);
-    RSF_CHECK(o.n_prox >= 1 && o.prox_rings >= 1 && o.n_prox % o.prox_rings == 0, RSF_E_INVALID,
-              "n_prox must be a positive multiple of prox_rings");
-    RSF_CHECK(o.r_near > 0 && o.prox_r_in > 0 && o.prox_r_out >= o.prox_r_in && o.rq_alpha > 0, RSF_E_INVALID,
-              "bad proxy geometry or rq_alpha");
+    check_args(theta, 1, kernel, eps, leaf);
     hipStream_t s = as_stream(stream);
-    std::vector<double> xy(2 * (size_t)n);
-    RSF_HIP(hipMemcpyAsync(xy.data(), d_points, xy.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    std::vector<std::vector<double>> xy(1, std::vector<double>(2 * (size_t)n));
+    RSF_HIP(hipMemcpyAsync(xy[0].data(), d_points, xy[0].size() * sizeof(double), hipMemcpyDeviceToHost, s));
     RSF_HIP(hipStreamSynchronize(s));
-    h = new rsf_factor_s();
-    h->opt.n_prox = o.n_prox;
-    h->opt.prox_rings = o.prox_rings;
-    h->opt.r_near = o.r_near;
-    h->opt.r_in = o.prox_r_in;
-    h->opt.r_out = o.prox_r_out;
-    h->opt.rq_alpha = o.rq_alpha;
-    h->opt.mem_cap = o.mem_cap_bytes;
-    h->arena.cap = o.mem_cap_bytes;
-    h->kernel = kernel;
-    h->eps = eps;
-    h->leaf = leaf;
-    for (int i = 0; i < 3; ++i) h->theta[i] = theta[i];
-    h->tree = build_tree(xy.data(), n, leaf);
-    std::vector<double> px(n), py(n);
-    for (int64_t t = 0; t < n; ++t) {
-      px[t] = xy[2 * (size_t)h->tree.perm[t]];
-      py[t] = xy[2 * (size_t)h->tree.perm[t] + 1];
-    }
-    h->px = h->arena.make<double>(n);
-    h->py = h->arena.make<double>(n);
-    h->perm = h->arena.make<int>(n);
-    RSF_HIP(hipMemcpy(h->px, px.data(), n * sizeof(double), hipMemcpyHostToDevice));
-    RSF_HIP(hipMemcpy(h->py, py.data(), n * sizeof(double), hipMemcpyHostToDevice));
-    RSF_HIP(hipMemcpy(h->perm, h->tree.perm.data(), n * sizeof(int), hipMemcpyHostToDevice));
-    make_proxy_table(h);
-    build_factor(h, h->F, 0, s);
-    RSF_HIP(hipStreamSynchronize(s));
+    *out = create_handle(xy, std::vector<int64_t>{n}, theta, kernel, eps, leaf, opts, s);
   });
-  if (rc != RSF_OK) {
-    delete h;
-    return rc;
-  }
-  *out = h;
-  return RSF_OK;
+}
+
+rsf_status rsf_factor_create_batched(const double* const* d_points, const int64_t* n, int nb, const double* theta,
+                                     int p, int kernel, double eps, int leaf, const rsf_opts* opts, void* stream,
+                                     rsf_factor* out) {
+  return guarded([&] {
+    RSF_CHECK(out != nullptr && d_points != nullptr && n != nullptr && theta != nullptr, RSF_E_INVALID,
+              "null argument");
+    RSF_CHECK(nb >= 1, RSF_E_INVALID, "nb must be >= 1");
+    RSF_CHECK(p == 3, RSF_E_INVALID, "theta must hold 3 values per instance (rho, sigma2, nugget)");
+    check_args(theta, nb, kernel, eps, leaf);
+    hipStream_t s = as_stream(stream);
+    std::vector<std::vector<double>> xy(nb);
+    std::vector<int64_t> ns(n, n + nb);
+    for (int i = 0; i < nb; ++i) {
+      RSF_CHECK(d_points[i] != nullptr, RSF_E_INVALID, "null point array of instance " + std::to_string(i));
+      RSF_CHECK(ns[i] >= 1, RSF_E_INVALID, "n must be >= 1 (instance " + std::to_string(i) + ")");
+      xy[i].resize(2 * (size_t)ns[i]);
+      RSF_HIP(hipMemcpyAsync(xy[i].data(), d_points[i], xy[i].size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    }
+    RSF_HIP(hipStreamSynchronize(s));
+    *out = create_handle(xy, ns, theta, kernel, eps, leaf, opts, s);
+  });
+}
+
+rsf_status rsf_batch_size(rsf_factor f, int* nb) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(nb != nullptr, RSF_E_INVALID, "null output");
+    *nb = f->tree.ninst;
+  });
 }
 
 void rsf_factor_destroy(rsf_factor f) {
@@ -142,7 +198,17 @@ rsf_status rsf_logdet(rsf_factor f, double* out) {
   return guarded([&] {
     check_handle(f);
     RSF_CHECK(out != nullptr, RSF_E_INVALID, "null output");
-    *out = f->F.logdet;
+    double sum = 0.0;
+    for (double v : f->F.logdet) sum += v;
+    *out = sum;
+  });
+}
+
+rsf_status rsf_logdet_batched(rsf_factor f, double* out_nb) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(out_nb != nullptr, RSF_E_INVALID, "null output");
+    for (int i = 0; i < f->tree.ninst; ++i) out_nb[i] = f->F.logdet[i];
   });
 }
 
@@ -202,26 +268,64 @@ rsf_status rsf_apply_sqrt(rsf_factor f, const double* d_w, double* d_z, int64_t 
   });
 }
 
+// l_i = -1/2 z_i^T alpha_i - 1/2 log|F_i| - (n_i / 2) log 2 pi for every
+// instance, alpha = F^-1 z (eq. loglikelihood); d_z in caller order (all
+// instances concatenated).
+static void loglik_all(rsf_factor f, const double* d_z, double* out, double* d_alpha, hipStream_t s) {
+  Scratch scr(s);
+  const Tree& t = f->tree;
+  const long long n = t.n;
+  const int ni = t.ninst;
+  double* Z = scr.make<double>(n);
+  double* A = scr.make<double>(n);
+  double* dot = scr.make<double>(ni);
+  to_panel(f, d_z, n, Z, 1, 1, s);
+  copy_dev(A, Z, n, s);
+  sweep_solve(f, f->F, A, 1, 1, scr, s);
+  // instance i is the tree-order range [ioff[i], ioff[i + 1])
+  for (int i = 0; i < ni; ++i)
+    device_dot(Z + t.ioff[i], A + t.ioff[i], t.ioff[i + 1] - t.ioff[i], dot + i, scr, s);
+  std::vector<double> zt(ni);
+  RSF_HIP(hipMemcpyAsync(zt.data(), dot, ni * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSF_HIP(hipStreamSynchronize(s));
+  if (d_alpha) from_panel(f, A, 1, 1, d_alpha, n, s);
+  const double log2pi = 1.8378770664093454835606594728112;
+  for (int i = 0; i < ni; ++i)
+    out[i] = -0.5 * zt[i] - 0.5 * f->F.logdet[i] - 0.5 * (double)(t.ioff[i + 1] - t.ioff[i]) * log2pi;
+}
+
+// The caller's per-instance vectors, concatenated in caller order.
+static double* gather_instances(rsf_factor f, const double* const* d_z, Scratch& scr, hipStream_t s) {
+  const Tree& t = f->tree;
+  double* Z = scr.make<double>(t.n);
+  for (int i = 0; i < t.ninst; ++i) {
+    RSF_CHECK(d_z[i] != nullptr, RSF_E_INVALID, "null vector of instance " + std::to_string(i));
+    RSF_HIP(hipMemcpyAsync(Z + t.ioff[i], d_z[i], (t.ioff[i + 1] - t.ioff[i]) * sizeof(double),
+                           hipMemcpyDeviceToDevice, s));
+  }
+  return Z;
+}
+
 rsf_status rsf_loglik(rsf_factor f, const double* d_z, double* out, double* d_alpha_or_null, void* stream) {
   return guarded([&] {
     check_handle(f);
     RSF_CHECK(d_z != nullptr && out != nullptr, RSF_E_INVALID, "null argument");
+    std::vector<double> l(f->tree.ninst);
+    loglik_all(f, d_z, l.data(), d_alpha_or_null, as_stream(stream));
+    double sum = 0.0;  // independent instances: the joint log-likelihood
+    for (double v : l) sum += v;
+    *out = sum;
+  });
+}
+
+rsf_status rsf_loglik_batched(rsf_factor f, const double* const* d_z, double* out_nb, void* stream) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(d_z != nullptr && out_nb != nullptr, RSF_E_INVALID, "null argument");
     hipStream_t s = as_stream(stream);
     Scratch scr(s);
-    const long long n = f->tree.n;
-    double* Z = scr.make<double>(n);
-    double* A = scr.make<double>(n);
-    double* dot = scr.make<double>(1);
-    to_panel(f, d_z, n, Z, 1, 1, s);
-    copy_dev(A, Z, n, s);
-    sweep_solve(f, f->F, A, 1, 1, scr, s);
-    device_dot(Z, A, n, dot, scr, s);
-    double zt = 0.0;
-    RSF_HIP(hipMemcpyAsync(&zt, dot, sizeof(double), hipMemcpyDeviceToHost, s));
-    RSF_HIP(hipStreamSynchronize(s));
-    if (d_alpha_or_null) from_panel(f, A, 1, 1, d_alpha_or_null, n, s);
-    const double log2pi = 1.8378770664093454835606594728112;
-    *out = -0.5 * zt - 0.5 * f->F.logdet - 0.5 * (double)n * log2pi;
+    const double* Z = gather_instances(f, d_z, scr, s);
+    loglik_all(f, Z, out_nb, nullptr, s);
   });
 }
 
@@ -279,7 +383,23 @@ rsf_status rsf_trace_phases(char* buf, size_t len) {
 
 rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
                     rsf_grad_info* info, void* stream) {
-  return guarded([&] { grad_eval(f, d_z, eps_peel, seed, g, info, stream); });
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(f->tree.ninst == 1, RSF_E_INVALID, "a batched handle takes rsf_grad_batched");
+    grad_eval(f, d_z, eps_peel, seed, g, info, stream);
+  });
+}
+
+rsf_status rsf_grad_batched(rsf_factor f, const double* const* d_z, double eps_peel, uint64_t seed,
+                            double* g_nb_p, rsf_grad_info* info_or_null, void* stream) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(d_z != nullptr && g_nb_p != nullptr, RSF_E_INVALID, "null argument");
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const double* Z = gather_instances(f, d_z, scr, s);
+    grad_eval(f, Z, eps_peel, seed, g_nb_p, info_or_null, stream);
+  });
 }
 
 }  // extern "C"

@@ -65,6 +65,9 @@ struct Scratch {
   T* make(size_t count) {
     return static_cast<T*>(alloc(count * sizeof(T)));
   }
+  // Returns one block to the pool early (stream-ordered: later work on the
+  // stream may reuse it).  Null or unknown pointers are ignored.
+  void release(const void* p);
   ~Scratch();
 };
 
@@ -93,6 +96,8 @@ struct GemmDesc {
   int M, N, K;
   double alpha, beta;
   int lower;  // 1: only tiles touching the lower triangle of C (i >= j) are computed
+  int f32;    // 1: operands rounded to FP32, FP32 matrix-core products with FP32
+              //    accumulation; alpha * acc + beta * C is formed in FP64
 };
 
 struct Mat {
@@ -129,6 +134,7 @@ inline GemmDesc gemm_desc(int M, int N, int K, double alpha, Mat A, Mat B, doubl
   d.alpha = alpha;
   d.beta = beta;
   d.lower = 0;
+  d.f32 = 0;
   return d;
 }
 
@@ -200,6 +206,7 @@ struct KernelParams {
   int kernel;
   double rho, sigma2, nugget, alpha;
   int deriv;  // 0: Sigma entries, 1: d/drho entries
+  int f32;    // 1: entries evaluated in FP32 arithmetic (mixed precision)
 };
 
 __device__ __forceinline__ double corr_dev(double s, int kernel, double alpha) {
@@ -230,8 +237,45 @@ __device__ __forceinline__ double dcorr_drho_dev(double r, double rho, int kerne
   return (r * r / (rho * rho * rho)) * pow(1.0 + s * s / (2.0 * alpha), -alpha - 1.0);
 }
 
+// FP32 forms of the two functions above (mixed precision).
+__device__ __forceinline__ float corr_dev32(float s, int kernel, float alpha) {
+  if (kernel == K_MATERN12) return expf(-s);
+  if (kernel == K_MATERN32) {
+    const float t = 1.7320508f * s;
+    return (1.0f + t) * expf(-t);
+  }
+  if (kernel == K_MATERN52) {
+    const float t = 2.2360680f * s;
+    return (1.0f + t + (5.0f / 3.0f) * s * s) * expf(-t);
+  }
+  if (alpha == 1.0f) return 1.0f / (1.0f + 0.5f * s * s);
+  return powf(1.0f + s * s / (2.0f * alpha), -alpha);
+}
+
+__device__ __forceinline__ float dcorr_drho_dev32(float r, float rho, int kernel, float alpha) {
+  const float s = r / rho, c = r * r / (rho * rho * rho);
+  if (kernel == K_MATERN12) return (r / (rho * rho)) * expf(-s);
+  if (kernel == K_MATERN32) return 3.0f * c * expf(-1.7320508f * s);
+  if (kernel == K_MATERN52) return (5.0f / 3.0f) * c * (1.0f + 2.2360680f * s) * expf(-2.2360680f * s);
+  if (alpha == 1.0f) {
+    const float b = 1.0f / (1.0f + 0.5f * s * s);
+    return c * b * b;
+  }
+  return c * powf(1.0f + s * s / (2.0f * alpha), -alpha - 1.0f);
+}
+
 // Kernel entry between two distinct sites at distance components (dx, dy).
+// The components are differences of FP64 coordinates (exact for nearby
+// sites); in mixed precision the distance and the kernel are then evaluated
+// in FP32.
 __device__ __forceinline__ double kentry(double dx, double dy, const KernelParams& kp) {
+  if (kp.f32) {
+    const float fx = (float)dx, fy = (float)dy;
+    const float r = sqrtf(fx * fx + fy * fy);
+    const float v = kp.deriv ? dcorr_drho_dev32(r, (float)kp.rho, kp.kernel, (float)kp.alpha)
+                             : corr_dev32(r / (float)kp.rho, kp.kernel, (float)kp.alpha);
+    return (double)((float)kp.sigma2 * v);
+  }
   double r = sqrt(dx * dx + dy * dy);
   if (kp.deriv) return kp.sigma2 * dcorr_drho_dev(r, kp.rho, kp.kernel, kp.alpha);
   return kp.sigma2 * corr_dev(r / kp.rho, kp.kernel, kp.alpha);

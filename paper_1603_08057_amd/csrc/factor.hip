@@ -109,18 +109,20 @@ __global__ __launch_bounds__(256) void near_kernel(const NearJob* __restrict__ j
 struct KauxJob {
   double* A;
   long long ld;
-  int a;
+  int a, inst;
   const int* act;
   const int* near;
   const int* ncnt;
   double cx, cy, h;
 };
 
-__global__ __launch_bounds__(256) void kaux_kernel(const KauxJob* __restrict__ jobs, KernelParams kp,
+__global__ __launch_bounds__(256) void kaux_kernel(const KauxJob* __restrict__ jobs,
+                                                    const KernelParams* __restrict__ kps,
                                                     const double* __restrict__ px,
                                                     const double* __restrict__ py,
                                                     const double* __restrict__ pu, int nprox) {
   const KauxJob J = jobs[blockIdx.x];
+  const KernelParams kp = kps[J.inst];
   const int nc = *J.ncnt;
   const long long m = nc + nprox;
   const long long tot = m * J.a;
@@ -394,6 +396,18 @@ __global__ __launch_bounds__(256) void cpqr_big_update_kernel(const CpqrJob* __r
   reflect_columns(J.A, J.ld, m, s, j0, j1, v, J.scal[0], J.norms);
 }
 
+// The same for compression matrices taller than BIG_MAXM rows: the reflector
+// is read from global memory (it stays in L2 across the columns).
+__global__ __launch_bounds__(256) void cpqr_big_update_tall_kernel(const CpqrJob* __restrict__ jobs,
+                                                                    int s, int nprox) {
+  const CpqrJob J = jobs[blockIdx.x];
+  if (*J.done) return;
+  const int j0 = std::max(s + 1, (int)blockIdx.y * 16), j1 = std::min(J.a, (int)blockIdx.y * 16 + 16);
+  if (j0 >= j1) return;
+  const long long m = (long long)*J.ncnt + nprox;
+  reflect_columns(J.A, J.ld, m, s, j0, j1, J.v, J.scal[0], J.norms);
+}
+
 __global__ __launch_bounds__(256) void cpqr_backsub_kernel(const CpqrJob* __restrict__ jobs) {
   const CpqrJob J = jobs[blockIdx.x];
   const int k = *J.kout;
@@ -407,7 +421,7 @@ __global__ __launch_bounds__(256) void cpqr_backsub_kernel(const CpqrJob* __rest
 // children; elsewhere kernel entries (the nugget on the diagonal).
 struct AsmJob {
   double* A;  // a x a, ld a
-  int a;
+  int a, inst;
   const int* act;
   const int* piv;       // nullptr = identity
   int nchild;
@@ -416,10 +430,12 @@ struct AsmJob {
   int xld[4];           // leading dimension of each child's X_ss
 };
 
-__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs, KernelParams kp,
+__global__ __launch_bounds__(256) void assemble_kernel(const AsmJob* __restrict__ jobs,
+                                                        const KernelParams* __restrict__ kps,
                                                         const double* __restrict__ px,
                                                         const double* __restrict__ py) {
   const AsmJob J = jobs[blockIdx.x];
+  const KernelParams kp = kps[J.inst];
   const long long tot = (long long)J.a * J.a;
   for (long long e = blockIdx.y * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.y) {
     const int j = (int)(e / J.a), i = (int)(e - (long long)j * J.a);
@@ -582,23 +598,33 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
   const Tree& t = h->tree;
   const Options& o = h->opt;
   F.mult = mult;
-  F.kp.kernel = h->kernel;
-  F.kp.rho = h->theta[0];
-  F.kp.sigma2 = h->theta[1];
-  F.kp.nugget = h->theta[2];
-  F.kp.alpha = o.rq_alpha;
-  F.kp.deriv = mult;
   F.arena.release();
   F.arena.cap = o.mem_cap == 0 ? 0 : std::max<long long>(1, (long long)o.mem_cap - (long long)h->arena.bytes);
   F.levels.assign(t.maxdepth + 1, LevelFactor());
-  F.logdet = 0.0;
+  const int ni = t.ninst;
+  F.kp.assign(ni, KernelParams{});
+  for (int i = 0; i < ni; ++i) {
+    KernelParams& kp = F.kp[i];
+    kp.kernel = h->kernel;
+    kp.rho = h->thetas[3 * i];
+    kp.sigma2 = h->thetas[3 * i + 1];
+    kp.nugget = h->thetas[3 * i + 2];
+    kp.alpha = o.rq_alpha;
+    kp.deriv = mult;
+    kp.f32 = o.mixed ? 1 : 0;
+  }
+  F.dkp = F.arena.make<KernelParams>(ni);
+  upload(F.dkp, F.kp, s);
+  F.logdet.assign(ni, 0.0);
   const int D = t.maxdepth, nprox = o.n_prox;
   Scratch keep(s);  // lives through the whole build: X_ss of the previous level
   std::vector<double*> xss(t.nbox(), nullptr);
   std::vector<int> xld(t.nbox(), 0);
   std::vector<int> kbox(t.nbox(), 0);
   std::vector<const int*> sbox(t.nbox(), nullptr);
+  // partial log-determinants in a fixed order, with their instance
   std::vector<double> ld_parts;
+  std::vector<int> ld_inst;
   int* fail = keep.make<int>(1);
   RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
 
@@ -662,7 +688,9 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
     run_copy_segs(cs, scr, s);
     const int* act = dofs;  // the first aoff[nb] entries
 
-    // candidate groups per box (geometry only)
+    // candidate groups per box (geometry only, within the box's instance)
+    std::vector<std::vector<int>> inst_segs(ni);
+    for (size_t g = 0; g < seg_off.size(); ++g) inst_segs[t.inst[seg_box[g]]].push_back((int)g);
     std::vector<int> cand;
     std::vector<NearJob> nj(nb);
     std::vector<long long> mub(nb), kaoff(nb + 1, 0), noff(nb + 1, 0);
@@ -675,7 +703,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       nj[i].owner = b;
       nj[i].cand0 = (int)cand.size();
       long long ub = 0;
-      for (size_t g = 0; g < seg_off.size(); ++g) {
+      for (int g : inst_segs[t.inst[b]]) {
         const int gb = seg_box[g];
         if (gb == b || seg_len[g] == 0) continue;
         const double dx = std::max(std::fabs(t.cx[gb] - t.cx[b]) - t.half[gb], 0.0);
@@ -716,7 +744,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       std::vector<KauxJob> kj(nb);
       for (int i = 0; i < nb; ++i) {
         const int b = b0 + i;
-        kj[i] = KauxJob{Kaux + kaoff[i], mub[i], L.a[i], act + aoff[i], near + noff[i], ncnt + i,
+        kj[i] = KauxJob{Kaux + kaoff[i], mub[i], L.a[i], t.inst[b], act + aoff[i], near + noff[i], ncnt + i,
                         t.cx[b], t.cy[b], t.half[b]};
       }
       KauxJob* dk = scr.make<KauxJob>(nb);
@@ -724,7 +752,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       long long maxe = 0;
       for (int i = 0; i < nb; ++i) maxe = std::max(maxe, mub[i] * L.a[i]);
       const int gy = std::max(1, std::min(64, ceil_div(maxe, 256 * 8)));
-      hipLaunchKernelGGL(kaux_kernel, dim3(nb, gy), dim3(256), 0, s, dk, F.kp, h->px, h->py, h->prox_u, nprox);
+      hipLaunchKernelGGL(kaux_kernel, dim3(nb, gy), dim3(256), 0, s, dk, F.dkp, h->px, h->py, h->prox_u, nprox);
       RSF_HIP(hipGetLastError());
     }
     // interpolative decompositions
@@ -754,8 +782,6 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         hipLaunchKernelGGL(cpqr_box_kernel, dim3(nb), dim3(256), 0, s, dj, h->eps, nprox);
         RSF_HIP(hipGetLastError());
       } else {
-        RSF_CHECK(maxm <= BIG_MAXM, RSF_E_INVALID,
-                  "compression matrix too tall (" + std::to_string(maxm) + " rows)");
         int* ndone = done + nb;
         RSF_HIP(hipMemsetAsync(ndone, 0, sizeof(int), s));
         const int chunks = std::max(1, ceil_div(maxa, 16));
@@ -767,7 +793,10 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
           hipLaunchKernelGGL(cpqr_big_pivot_kernel, dim3(nb), dim3(256), 0, s, dj, st, h->eps, nprox, ndone);
           RSF_HIP(hipGetLastError());
           if (st == steps) break;
-          hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, st, nprox);
+          if (maxm <= BIG_MAXM)
+            hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, st, nprox);
+          else
+            hipLaunchKernelGGL(cpqr_big_update_tall_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, st, nprox);
           RSF_HIP(hipGetLastError());
           if ((st & 15) == 15) {
             int nd = 0;
@@ -843,6 +872,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         AsmJob& J = aj[i];
         J.A = Ablk + a2off[i];
         J.a = L.a[i];
+        J.inst = t.inst[b];
         J.act = act + aoff[i];
         J.piv = piv + aoff[i];
         J.nchild = 0;
@@ -861,14 +891,15 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       AsmJob* dj = scr.make<AsmJob>(nb);
       upload(dj, aj, s);
       const int gy = std::max(1, std::min(64, ceil_div(maxe, 256 * 8)));
-      hipLaunchKernelGGL(assemble_kernel, dim3(nb, gy), dim3(256), 0, s, dj, F.kp, h->px, h->py);
+      hipLaunchKernelGGL(assemble_kernel, dim3(nb, gy), dim3(256), 0, s, dj, F.dkp, h->px, h->py);
       RSF_HIP(hipGetLastError());
     }
     int maxa = 0;
     for (int i = 0; i < nb; ++i) maxa = std::max(maxa, L.a[i]);
     if (!mult) L.Lf = F.arena.make<double>(std::max<long long>(L.total_l, 1));
     // Ablk lives on (in `keep`) when the parent reads X_ss from it
-    const bool gemm_path = maxa > SCHUR_FUSED_MAXA;
+    // mixed precision takes every level through the GEMM path, whose products run in FP32
+    const bool gemm_path = maxa > SCHUR_FUSED_MAXA || o.mixed;
     if (!gemm_path) {
       double* Xsr = mult ? L.W : scr.make<double>(std::max<long long>(L.total_t, 1));
       double* Lw = mult ? L.Lm : L.Lf;
@@ -889,7 +920,10 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         std::vector<double> lh(nb);
         RSF_HIP(hipMemcpyAsync(lh.data(), ldp, nb * sizeof(double), hipMemcpyDeviceToHost, s));
         RSF_HIP(hipStreamSynchronize(s));
-        for (double v : lh) ld_parts.push_back(v);
+        for (int i = 0; i < nb; ++i) {
+          ld_parts.push_back(lh[i]);
+          ld_inst.push_back(t.inst[b0 + i]);
+        }
       }
       for (int i = 0; i < nb; ++i) {
         xss[b0 + i] = mult ? nullptr : Xss + k2off[i];
@@ -912,6 +946,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
                                 colmaj(A + (long long)k * a + k, a));
         GemmDesc d3 = gemm_desc(r, r, k, -1.0, colmaj(A + k, a), colmaj(T, k), 1.0, colmaj(A + (long long)k * a + k, a));
         d2.lower = d3.lower = !mult;
+        g1.back().f32 = d2.f32 = d3.f32 = o.mixed;
         g2.push_back(d2);
         g3.push_back(d3);
       }
@@ -951,12 +986,18 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
                                  colmaj(A, a)));
         }
         copy_blocks(cp, scr, s);
+        for (GemmDesc& g : gw) g.f32 = o.mixed;
+        for (GemmDesc& g : gx) g.f32 = o.mixed;
         gemm_batched(gw, scr, s);
         gemm_batched(gx, scr, s);
         std::vector<double> lh(lo[nb]);
         if (!lh.empty()) RSF_HIP(hipMemcpyAsync(lh.data(), logd, lh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         RSF_HIP(hipStreamSynchronize(s));
-        for (double v : lh) ld_parts.push_back(v);
+        for (int i = 0; i < nb; ++i)
+          for (long long q = lo[i]; q < lo[i + 1]; ++q) {
+            ld_parts.push_back(lh[q]);
+            ld_inst.push_back(t.inst[b0 + i]);
+          }
       }
       for (int i = 0; i < nb; ++i) {
         xss[b0 + i] = mult ? nullptr : Akeep + a2off[i];
@@ -969,71 +1010,107 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       sbox[b] = L.S + L.s_off[i];
     }
   }
-  // root: the remaining DOFs of the top box
+  // roots: the remaining DOFs of each instance's top box, factored together
   {
     Scratch scr(s);
     std::vector<CopySeg> cs;
+    std::vector<AsmJob> aj;
+    F.roots.assign(ni, RootBlock{});
     int N = 0;
-    AsmJob J{};
-    J.nchild = 0;
-    J.coff[0] = 0;
-    std::vector<int> segk;
-    if (D == 0) N = t.count[0];
-    else
-      for (int c : t.child[0])
-        if (c >= 0) N += kbox[c];
+    for (int i = 0; i < ni; ++i) {
+      const int b = i;  // the depth-0 boxes are the instances' roots
+      RootBlock& rb = F.roots[i];
+      rb.off = N;
+      AsmJob J{};
+      J.nchild = 0;
+      J.coff[0] = 0;
+      J.inst = i;
+      if (t.leaf[b]) {
+        rb.N = t.count[b];
+      } else {
+        for (int c : t.child[b])
+          if (c >= 0) {
+            J.xss[J.nchild] = mult ? nullptr : xss[c];
+            J.xld[J.nchild] = xld[c];
+            J.coff[J.nchild + 1] = J.coff[J.nchild] + kbox[c];
+            J.nchild++;
+            rb.N += kbox[c];
+          }
+      }
+      N += rb.N;
+      if (rb.N > 0) {
+        J.a = rb.N;
+        J.piv = nullptr;
+        aj.push_back(J);
+      }
+    }
     F.nroot = N;
     F.root_idx = F.arena.make<int>(std::max(N, 1));
-    if (D == 0) {
-      cs.push_back({F.root_idx, nullptr, 0, N});
-    } else {
-      int o2 = 0;
-      for (int c : t.child[0])
-        if (c >= 0) {
-          if (kbox[c] > 0) cs.push_back({F.root_idx + o2, sbox[c], 0, kbox[c]});
-          J.xss[J.nchild] = mult ? nullptr : xss[c];
-          J.xld[J.nchild] = xld[c];
-          J.coff[J.nchild + 1] = J.coff[J.nchild] + kbox[c];
-          J.nchild++;
-          o2 += kbox[c];
-        }
+    for (int i = 0; i < ni; ++i) {
+      const int b = i;
+      RootBlock& rb = F.roots[i];
+      if (t.leaf[b]) {
+        if (rb.N > 0) cs.push_back({F.root_idx + rb.off, nullptr, t.begin[b], rb.N});
+      } else {
+        int o2 = rb.off;
+        for (int c : t.child[b])
+          if (c >= 0 && kbox[c] > 0) {
+            cs.push_back({F.root_idx + o2, sbox[c], 0, kbox[c]});
+            o2 += kbox[c];
+          }
+      }
     }
     run_copy_segs(cs, scr, s);
-    if (N > 0) {
-      double* A = F.arena.make<double>((size_t)N * N);
-      if (mult) F.Aroot = A;
-      else F.Lroot = A;
-      J.A = A;
-      J.a = N;
-      J.act = F.root_idx;
-      J.piv = nullptr;
-      AsmJob* dj = scr.make<AsmJob>(1);
-      upload(dj, std::vector<AsmJob>{J}, s);
-      const int gy = std::max(1, std::min(1024, ceil_div((long long)N * N, 256 * 8)));
-      hipLaunchKernelGGL(assemble_kernel, dim3(1, gy), dim3(256), 0, s, dj, F.kp, h->px, h->py);
+    if (!aj.empty()) {
+      long long maxe = 1;
+      std::vector<CholProblem> cp;
+      std::vector<long long> lo(1, 0);
+      std::vector<int> lo_inst;
+      for (AsmJob& J : aj) {
+        RootBlock& rb = F.roots[J.inst];
+        rb.L = F.arena.make<double>((size_t)rb.N * rb.N);
+        J.A = rb.L;
+        J.act = F.root_idx + rb.off;
+        maxe = std::max(maxe, (long long)rb.N * rb.N);
+        if (!mult) {
+          rb.Linv = F.arena.make<double>((size_t)rb.N * rb.N);
+          lo.push_back(lo.back() + (rb.N + 63) / 64);
+          lo_inst.push_back(J.inst);
+        }
+      }
+      AsmJob* dj = scr.make<AsmJob>(aj.size());
+      upload(dj, aj, s);
+      const int gy = std::max(1, std::min(1024, ceil_div(maxe, 256 * 8)));
+      hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)aj.size(), gy), dim3(256), 0, s, dj, F.dkp, h->px, h->py);
       RSF_HIP(hipGetLastError());
       if (!mult) {
-        F.Lroot_inv = F.arena.make<double>((size_t)N * N);
-        const int nbk = (N + 63) / 64;
-        double* logd = scr.make<double>(nbk);
-        fill_zero(logd, nbk, s);
-        batched_chol_inv(std::vector<CholProblem>{CholProblem{A, N, N, F.Lroot_inv, N, logd}}, fail, scr, s);
-        std::vector<double> lh(nbk);
+        double* logd = scr.make<double>(std::max<long long>(lo.back(), 1));
+        fill_zero(logd, lo.back(), s);
+        for (size_t q = 0; q < aj.size(); ++q) {
+          RootBlock& rb = F.roots[aj[q].inst];
+          cp.push_back(CholProblem{rb.L, rb.N, rb.N, rb.Linv, rb.N, logd + lo[q]});
+        }
+        batched_chol_inv(cp, fail, scr, s);
+        std::vector<double> lh(lo.back());
         int fh = 0;
-        RSF_HIP(hipMemcpyAsync(lh.data(), logd, nbk * sizeof(double), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipMemcpyAsync(lh.data(), logd, lh.size() * sizeof(double), hipMemcpyDeviceToHost, s));
         RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
         RSF_HIP(hipStreamSynchronize(s));
         RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "covariance factor lost positive definiteness (root or a redundant block)");
-        hipLaunchKernelGGL(triu_zero_kernel, dim3(std::min(N, 4096)), dim3(256), 0, s, A, N);
-        RSF_HIP(hipGetLastError());
-        for (double v : lh) ld_parts.push_back(v);
+        for (size_t q = 0; q < aj.size(); ++q) {
+          const RootBlock& rb = F.roots[aj[q].inst];
+          hipLaunchKernelGGL(triu_zero_kernel, dim3(std::min(rb.N, 4096)), dim3(256), 0, s, rb.L, rb.N);
+          RSF_HIP(hipGetLastError());
+          for (long long u = lo[q]; u < lo[q + 1]; ++u) {
+            ld_parts.push_back(lh[u]);
+            ld_inst.push_back(lo_inst[q]);
+          }
+        }
       }
     }
   }
   if (!mult) {
-    double sum = 0.0;
-    for (double v : ld_parts) sum += v;
-    F.logdet = sum;
+    for (size_t q = 0; q < ld_parts.size(); ++q) F.logdet[ld_inst[q]] += ld_parts[q];
   }
 }
 

@@ -104,6 +104,16 @@ void* Scratch::alloc(size_t nbytes) {
   return p;
 }
 
+void Scratch::release(const void* p) {
+  for (size_t i = 0; i < blocks.size(); ++i)
+    if (blocks[i] == p) {
+      pool_free(blocks[i], sizes[i], stream);
+      blocks.erase(blocks.begin() + i);
+      sizes.erase(sizes.begin() + i);
+      return;
+    }
+}
+
 Scratch::~Scratch() {
   for (size_t i = 0; i < blocks.size(); ++i) pool_free(blocks[i], sizes[i], stream);
 }
@@ -197,6 +207,96 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
   store_block(d, acc01, i0 + rb, j0 + cb + 16, lane);
   store_block(d, acc10, i0 + rb + 16, j0 + cb, lane);
   store_block(d, acc11, i0 + rb + 16, j0 + cb + 16, lane);
+}
+
+// The 64 x 64 tile kernel in mixed precision: operands are rounded to FP32 as
+// they are staged in LDS, the products run on v_mfma_f32_16x16x4f32 with FP32
+// accumulation, and C = alpha * acc + beta * C is formed in FP64.  The FP32
+// accumulator of lane l holds rows 4 (l / 16) + v, column l mod 16.
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void store_block32(const GemmDesc& d, const v4f& acc, int ib, int jb, int lane) {
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int gi = ib + 4 * (lane >> 4) + v;
+    const int gj = jb + (lane & 15);
+    if (gi < d.M && gj < d.N) {
+      const long long row = d.cidx ? (long long)d.cidx[gi] : (long long)gi;
+      double* c = d.C + row * d.crs + (long long)gj * d.ccs;
+      const double a = (double)acc[v];
+      *c = (d.beta == 0.0) ? d.alpha * a : d.alpha * a + d.beta * *c;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void gemm_tiles_f32_kernel(const GemmDesc* __restrict__ descs,
+                                                              const int4* __restrict__ tiles) {
+  __shared__ float As[16][68];  // As[k][i]
+  __shared__ float Bs[16][68];  // Bs[k][j]
+  const int4 t = tiles[blockIdx.x];
+  const GemmDesc d = descs[t.x];
+  const int i0 = t.y * 64, j0 = t.z * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int rb = (wave >> 1) * 32, cb = (wave & 1) * 32;
+  v4f acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
+  const bool a_icontig = (d.ars == 1 && d.aidx == nullptr);
+  const bool b_jcontig = (d.bcs == 1);
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int i, kk;
+      if (a_icontig) {
+        i = tid & 63;
+        kk = (tid >> 6) + 4 * r;
+      } else {
+        kk = tid & 15;
+        i = (tid >> 4) + 16 * r;
+      }
+      const int gi = i0 + i, gk = k0 + kk;
+      float v = 0.0f;
+      if (gi < d.M && gk < d.K) {
+        const long long row = d.aidx ? (long long)d.aidx[gi] : (long long)gi;
+        v = (float)d.A[row * d.ars + (long long)gk * d.acs];
+      }
+      As[kk][i] = v;
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int j, kk;
+      if (b_jcontig) {
+        j = tid & 63;
+        kk = (tid >> 6) + 4 * r;
+      } else {
+        kk = tid & 15;
+        j = (tid >> 4) + 16 * r;
+      }
+      const int gj = j0 + j, gk = k0 + kk;
+      float v = 0.0f;
+      if (gj < d.N && gk < d.K) {
+        const long long row = d.bidx ? (long long)d.bidx[gk] : (long long)gk;
+        v = (float)d.B[row * d.brs + (long long)gj * d.bcs];
+      }
+      Bs[kk][j] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      const float a0 = As[kk][rb + (lane & 15)];
+      const float a1 = As[kk][rb + 16 + (lane & 15)];
+      const float b0 = Bs[kk][cb + (lane & 15)];
+      const float b1 = Bs[kk][cb + 16 + (lane & 15)];
+      acc00 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc00, 0, 0, 0);
+      acc01 = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc01, 0, 0, 0);
+      acc10 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc10, 0, 0, 0);
+      acc11 = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc11, 0, 0, 0);
+    }
+  }
+  store_block32(d, acc00, i0 + rb, j0 + cb, lane);
+  store_block32(d, acc01, i0 + rb, j0 + cb + 16, lane);
+  store_block32(d, acc10, i0 + rb + 16, j0 + cb, lane);
+  store_block32(d, acc11, i0 + rb + 16, j0 + cb + 16, lane);
 }
 
 // ---- launch tracing of the batched GEMM (events on the launch stream)
@@ -410,7 +510,7 @@ static int big_class(const GemmDesc& d) {
 }
 
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s) {
-  std::vector<int4> tiles, btiles[8];
+  std::vector<int4> tiles, btiles[8], tiles32;
   std::vector<GemmDesc> live;
   double flops = 0.0, bytes = 0.0;
   for (const GemmDesc& d : descs) {
@@ -420,7 +520,12 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     const int p = (int)live.size();
     live.push_back(d);
     const int cls = big_class(d);
-    if (cls >= 0 && d.M >= 96 && d.N >= 96 && d.K >= 32) {
+    if (d.f32) {
+      const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
+      for (int a = 0; a < tm; ++a)
+        for (int b = 0; b < tn; ++b)
+          if (!d.lower || b <= a) tiles32.push_back(make_int4(p, a, b, 0));
+    } else if (cls >= 0 && d.M >= 96 && d.N >= 96 && d.K >= 32) {
       const int tm = (d.M + BT - 1) / BT, tn = (d.N + BT - 1) / BT;
       for (int a = 0; a < tm; ++a)
         for (int b = 0; b < tn; ++b)
@@ -432,7 +537,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
           if (!d.lower || b <= a) tiles.push_back(make_int4(p, a, b, 0));
     }
   }
-  size_t nt = tiles.size();
+  size_t nt = tiles.size() + tiles32.size();
   for (auto& v : btiles) nt += v.size();
   if (nt == 0) return;
   GemmDesc* dd = scr.make<GemmDesc>(live.size());
@@ -444,6 +549,8 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     all.insert(all.end(), btiles[c].begin(), btiles[c].end());
     boff[c + 1] = all.size();
   }
+  const size_t off32 = all.size();
+  all.insert(all.end(), tiles32.begin(), tiles32.end());
   int4* dt = scr.make<int4>(all.size());
   upload(dt, all, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -466,14 +573,18 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
 #undef RSF_BIG
   if (!tiles.empty())
     hipLaunchKernelGGL(gemm_tiles_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, s, dd, dt);
+  if (!tiles32.empty())
+    hipLaunchKernelGGL(gemm_tiles_f32_kernel, dim3((unsigned)tiles32.size()), dim3(256), 0, s, dd, dt + off32);
   RSF_HIP(hipGetLastError());
   if (g_trace.on) {
     RSF_HIP(hipEventRecord(e1, s));
-    g_trace.ev.push_back(TraceEv{e0, e1, g_trace.tag});
+    // launches with FP32 products are booked under "<phase>/f32"
+    const std::string tag = tiles32.empty() ? g_trace.tag : g_trace.tag + "/f32";
+    g_trace.ev.push_back(TraceEv{e0, e1, tag});
     g_trace.flops += flops;
     g_trace.bytes += bytes;
     g_trace.launches += 1;
-    g_trace.tag_flops[g_trace.tag] += flops;
+    g_trace.tag_flops[tag] += flops;
   }
 }
 

@@ -317,6 +317,8 @@ static unsigned grid_of(long long tot) {
 namespace {
 
 constexpr int OVERSAMPLE = 10;
+// device memory for the work panels of one chunk of probe columns
+constexpr long long PEEL_CHUNK_BYTES = 24LL << 30;
 constexpr int FIRST_COLS = 64;
 constexpr int MIN_COLS = 24;
 
@@ -439,16 +441,18 @@ struct Peeler {
   // consecutive, ld c) by blocked pivoted Cholesky; G is preserved.
   void pivot_ranks(const double* G, int c, int nj, double tol2, int* dpiv, std::vector<int>& rk, Scratch& scr) {
     TraceTag tag("peel_pivot");
+    (void)scr;
+    Scratch ws(s);  // work buffers live only through this call
     RSF_CHECK(c <= PCHOL_MAXN, RSF_E_INVALID,
               "peeling needs more than " + std::to_string(PCHOL_MAXN) + " probe columns per block");
     const int NB = c <= 1024 ? 32 : c <= 2048 ? 16 : 8;
     const long long cc = (long long)c * c;
-    double* Gw = scr.make<double>(cc * nj);
+    double* Gw = ws.make<double>(cc * nj);
     copy_dev(Gw, G, cc * nj, s);
-    double* d = scr.make<double>((long long)c * nj);
-    double* Lp = scr.make<double>((long long)c * NB * nj);
-    double* d1 = scr.make<double>(nj);
-    int* state = scr.make<int>(2 * nj);
+    double* d = ws.make<double>((long long)c * nj);
+    double* Lp = ws.make<double>((long long)c * NB * nj);
+    double* d1 = ws.make<double>(nj);
+    int* state = ws.make<int>(2 * nj);
     hipLaunchKernelGGL(ppanel_init_kernel, dim3(grid_of((long long)c * nj)), dim3(256), 0, s, G, c, nj, d, state, d1);
     RSF_HIP(hipGetLastError());
     std::vector<int> active(nj);
@@ -460,7 +464,7 @@ struct Peeler {
       for (int e : active)
         jobs.push_back(PpanelJob{Gw + cc * e, d + (long long)c * e, Lp + (long long)c * NB * e,
                                  dpiv + (long long)c * e, state + 2 * e, d1 + e, c});
-      PpanelJob* dj = scr.make<PpanelJob>(jobs.size());
+      PpanelJob* dj = ws.make<PpanelJob>(jobs.size());
       upload(dj, jobs, s);
       const dim3 grid((unsigned)jobs.size()), blk(PCHOL_WG);
       if (c <= 1024)
@@ -484,7 +488,7 @@ struct Peeler {
       for (int e : active)
         tg.push_back(gemm_desc(c, c, NB, -1.0, colmaj(Lp + (long long)c * NB * e, c),
                                colmajT(Lp + (long long)c * NB * e, c), 1.0, colmaj(Gw + cc * e, c)));
-      gemm_batched(tg, scr, s);
+      gemm_batched(tg, ws, s);
     }
     RSF_CHECK(active.empty(), RSF_E_INVALID, "pivoted Cholesky did not terminate");
     rk.assign(nj, 0);
@@ -545,7 +549,10 @@ struct Peeler {
         for (int u = 0; u < t.count[b]; ++u) qd[t.begin[b] + u] = t.quad[b];
       int* dqd = scr.make<int>(n);
       upload(dqd, qd, s);
-      int c = prev < 0 ? first_cols(n) : next_cols(prev);
+      // the largest instance sets the first level's probe count
+      long long nmax = 0;
+      for (int i = 0; i < t.ninst; ++i) nmax = std::max<long long>(nmax, t.ioff[i + 1] - t.ioff[i]);
+      int c = prev < 0 ? first_cols(nmax) : next_cols(prev);
       int total = 0, Ccap = 0;
       double* Om = nullptr;
       double* Y[2] = {nullptr, nullptr};
@@ -575,27 +582,40 @@ struct Peeler {
                                  Y2[op], c);
             RSF_HIP(hipGetLastError());
           }
+          scr.release(Om);
+          scr.release(Y[0]);
+          scr.release(Y[1]);
           Om = Om2;
           Y[0] = Y2[0];
           Y[1] = Y2[1];
           Ccap = c;
         }
         {
-          Scratch rs(s);
-          const long long sz = n * 4LL * newc;
-          double* Wm = rs.make<double>(sz);
-          fill_zero(Wm, sz, s);
-          hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * newc)), dim3(256), 0, s, dqd, n, newc, total, lev, seed,
-                             Wm, Om, (long long)c);
-          RSF_HIP(hipGetLastError());
-          double* B0 = rs.make<double>(sz);
-          double* B1 = rs.make<double>(sz);
-          apply_ops(Wm, 4 * newc, B0, B1, rs);
-          subtract_lowrank(0, lev, Wm, 4 * newc, B0, rs);
-          subtract_lowrank(1, lev, Wm, 4 * newc, B1, rs);
-          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, newc, total, c, B0, Y[0]);
-          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, newc, total, c, B1, Y[1]);
-          RSF_HIP(hipGetLastError());
+          // the new probe columns go through the operators in chunks, so the
+          // six n x 4 cw work panels stay within PEEL_CHUNK_BYTES
+          const long long per_col = 6LL * n * 4 * (long long)sizeof(double);
+          int cw = (int)std::max<long long>(8, PEEL_CHUNK_BYTES / per_col / 8 * 8);
+          cw = std::min(cw, newc);
+          for (int t0 = 0; t0 < newc; t0 += cw) {
+            const int nc = std::min(cw, newc - t0);
+            Scratch rs(s);
+            const long long sz = n * 4LL * nc;
+            double* Wm = rs.make<double>(sz);
+            fill_zero(Wm, sz, s);
+            hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * nc)), dim3(256), 0, s, dqd, n, nc, total + t0, lev,
+                               seed, Wm, Om, (long long)c);
+            RSF_HIP(hipGetLastError());
+            double* B0 = rs.make<double>(sz);
+            double* B1 = rs.make<double>(sz);
+            apply_ops(Wm, 4 * nc, B0, B1, rs);
+            subtract_lowrank(0, lev, Wm, 4 * nc, B0, rs);
+            subtract_lowrank(1, lev, Wm, 4 * nc, B1, rs);
+            hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, nc, total + t0, c, B0,
+                               Y[0]);
+            hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, nc, total + t0, c, B1,
+                               Y[1]);
+            RSF_HIP(hipGetLastError());
+          }
         }
         total = c;
         // ranks of every sample block by pivoted Cholesky of its Gram matrix
@@ -603,6 +623,8 @@ struct Peeler {
         for (int e = 0; e < 2 * nblk; ++e) goff[e + 1] = goff[e] + (long long)total * total;
         RSF_CHECK(total <= PCHOL_MAXN, RSF_E_INVALID,
                   "peeling needs more than " + std::to_string(PCHOL_MAXN) + " probe columns per block");
+        scr.release(Gram);
+        scr.release(dpiv);
         Gram = scr.make<double>(goff[2 * nblk]);
         dpiv = scr.make<int>((size_t)2 * nblk * total);
         std::vector<GemmDesc> g;
@@ -771,16 +793,20 @@ struct Peeler {
         RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: singular normal equations of a core matrix");
       }
     }
-    // extraction at the leaves
+    // extraction at the leaves: traces of every instance over its own leaves
     Scratch scr(s);
-    std::vector<int> lbeg, lcnt;
+    const int ni = t.ninst;
+    std::vector<int> lbeg, lcnt, lfirst(ni + 1, 0);
     int nL = 1;
-    for (int b = 0; b < t.nbox(); ++b)
-      if (t.leaf[b]) {
-        lbeg.push_back(t.begin[b]);
-        lcnt.push_back(t.count[b]);
-        nL = std::max(nL, t.count[b]);
-      }
+    for (int i = 0; i < ni; ++i) {
+      for (int b = 0; b < t.nbox(); ++b)
+        if (t.leaf[b] && t.inst[b] == i) {
+          lbeg.push_back(t.begin[b]);
+          lcnt.push_back(t.count[b]);
+          nL = std::max(nL, t.count[b]);
+        }
+      lfirst[i + 1] = (int)lbeg.size();
+    }
     const int nleaf = (int)lbeg.size();
     int* dlb = scr.make<int>(nleaf);
     int* dlc = scr.make<int>(nleaf);
@@ -796,15 +822,20 @@ struct Peeler {
     apply_ops(E, nL, H0, H1, scr);
     subtract_lowrank(0, D + 1, E, nL, H0, scr);
     subtract_lowrank(1, D + 1, E, nL, H1, scr);
-    double* tr = scr.make<double>(2);
-    hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb, dlc, nleaf, H0, nL, tr);
-    hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb, dlc, nleaf, H1, nL, tr + 1);
+    double* tr = scr.make<double>(2 * ni);
+    for (int i = 0; i < ni; ++i) {
+      const int l0 = lfirst[i], nl = lfirst[i + 1] - lfirst[i];
+      hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb + l0, dlc + l0, nl, H0, nL, tr + i);
+      hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb + l0, dlc + l0, nl, H1, nL, tr + ni + i);
+    }
     RSF_HIP(hipGetLastError());
-    double th[2];
-    RSF_HIP(hipMemcpyAsync(th, tr, sizeof(th), hipMemcpyDeviceToHost, s));
+    std::vector<double> th(2 * ni);
+    RSF_HIP(hipMemcpyAsync(th.data(), tr, th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     RSF_HIP(hipStreamSynchronize(s));
-    *tr_inv = th[0];
-    *tr_rho = th[1];
+    for (int i = 0; i < ni; ++i) {
+      tr_inv[i] = th[i];
+      tr_rho[i] = th[ni + i];
+    }
     if (st) {
       st->levels = D;
       st->leaf_cols = nL;
@@ -831,6 +862,8 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   RSF_CHECK(d_z != nullptr && g != nullptr, RSF_E_INVALID, "null argument");
   if (!(eps_peel > 0.0)) eps_peel = f->eps;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const Tree& tr = f->tree;
+  const int ni = tr.ninst;
   const auto t0 = clk::now();
   if (!f->Frho) {
     f->Frho.reset(new FactorData());
@@ -839,38 +872,51 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   RSF_HIP(hipStreamSynchronize(s));
   const auto t1 = clk::now();
   Scratch scr(s);
-  const long long n = f->tree.n;
+  const long long n = tr.n;
   double* Z = scr.make<double>(n);
   double* A = scr.make<double>(n);
   double* X = scr.make<double>(n);
   double* Y = scr.make<double>(n);
-  double* dots = scr.make<double>(3);
+  double* dots = scr.make<double>(3 * ni);
   to_panel(f, d_z, n, Z, 1, 1, s);
   copy_dev(A, Z, n, s);
   sweep_solve(f, f->F, A, 1, 1, scr, s);
   copy_dev(X, A, n, s);
   sweep_apply_mult(f, *f->Frho, X, Y, 1, 1, scr, s);
-  device_dot(A, Y, n, dots, scr, s);
-  device_dot(Z, A, n, dots + 1, scr, s);
-  device_dot(A, A, n, dots + 2, scr, s);
-  double hd[3];
-  RSF_HIP(hipMemcpyAsync(hd, dots, sizeof(hd), hipMemcpyDeviceToHost, s));
+  // per instance (tree-order range [ioff[i], ioff[i + 1])): a^T F_rho a, z^T a, a^T a
+  for (int i = 0; i < ni; ++i) {
+    const long long o = tr.ioff[i], m = tr.ioff[i + 1] - tr.ioff[i];
+    device_dot(A + o, Y + o, m, dots + 3 * i, scr, s);
+    device_dot(Z + o, A + o, m, dots + 3 * i + 1, scr, s);
+    device_dot(A + o, A + o, m, dots + 3 * i + 2, scr, s);
+  }
+  std::vector<double> hd(3 * ni);
+  RSF_HIP(hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   RSF_HIP(hipStreamSynchronize(s));
   const auto t2 = clk::now();
-  const double s2 = f->theta[1], nug = f->theta[2];
-  double q[3] = {0.5 * hd[0], 0.5 * (hd[1] - nug * hd[2]) / s2, 0.5 * hd[2]};
-  double trinv = 0.0, trrho = 0.0;
+  std::vector<double> trinv(ni), trrho(ni);
   PeelStats ps;
-  peel_traces(f, eps_peel, seed, &trinv, &trrho, &ps, s);
+  peel_traces(f, eps_peel, seed, trinv.data(), trrho.data(), &ps, s);
   const auto t3 = clk::now();
-  double tt[3] = {trrho, ((double)n - nug * trinv) / s2, trinv};
-  for (int i = 0; i < 3; ++i) g[i] = q[i] - 0.5 * tt[i];
+  double q0[3] = {0, 0, 0}, tt0[3] = {0, 0, 0};
+  for (int i = 0; i < ni; ++i) {
+    const double s2 = f->thetas[3 * i + 1], nug = f->thetas[3 * i + 2];
+    const double m = (double)(tr.ioff[i + 1] - tr.ioff[i]);
+    const double q[3] = {0.5 * hd[3 * i], 0.5 * (hd[3 * i + 1] - nug * hd[3 * i + 2]) / s2, 0.5 * hd[3 * i + 2]};
+    const double tt[3] = {trrho[i], (m - nug * trinv[i]) / s2, trinv[i]};
+    for (int j = 0; j < 3; ++j) g[3 * i + j] = q[j] - 0.5 * tt[j];
+    if (i == 0)
+      for (int j = 0; j < 3; ++j) {
+        q0[j] = q[j];
+        tt0[j] = tt[j];
+      }
+  }
   if (info) {
     for (int i = 0; i < 3; ++i) {
-      info->q[i] = q[i];
-      info->t[i] = tt[i];
+      info->q[i] = q0[i];
+      info->t[i] = tt0[i];
     }
-    info->trace_inv = trinv;
+    info->trace_inv = trinv[0];
     info->peel_levels = ps.levels;
     for (int i = 0; i < 32; ++i) {
       info->peel_cols[i] = ps.cols[i];

@@ -20,6 +20,11 @@ struct Tree {
   std::vector<int> lev;   // size maxdepth + 2
   std::vector<int> perm;  // perm[t] = caller index of tree position t
   int maxdepth = 0;
+  // independent instances (a forest): instance of each box, and the
+  // tree-order (= caller-order) range [ioff[i], ioff[i + 1]) of instance i
+  std::vector<int> inst;
+  std::vector<int64_t> ioff{0, 0};
+  int ninst = 1;
   int nbox() const { return (int)cx.size(); }
 };
 
@@ -27,6 +32,8 @@ struct Tree {
 // box holds more than `leaf` points, x >= cx east, y >= cy north, children
 // NW, NE, SW, SE, stable partition).  Throws on duplicate sites.
 Tree build_tree(const double* xy_host, int64_t n, int leaf);
+// The same for independent instances (host n_i x 2 arrays), roots at depth 0.
+Tree build_forest(const std::vector<const double*>& xy_host, const std::vector<int64_t>& n, int leaf);
 
 // Factors of the boxes of one depth.  Per box b (local index within the level):
 // k skeleton DOFs S, r = a - k redundant DOFs R (tree-order DOF ids, pivot
@@ -56,16 +63,22 @@ struct LevelFactor {
   int max_k = 0, max_r = 0;
 };
 
+// The DOFs left at the root of one instance and their dense block.
+struct RootBlock {
+  int off = 0, N = 0;           // rows root_idx[off, off + N)
+  double* L = nullptr;          // chol: Cholesky factor (lower); mult: the block itself
+  double* Linv = nullptr;       // chol: its inverse (lower)
+};
+
 struct FactorData {
   int mult = 0;             // 0: Schur/Cholesky form of Sigma; 1: multiply-only form
-  KernelParams kp{};
+  std::vector<KernelParams> kp;     // per instance
+  KernelParams* dkp = nullptr;      // device copy
   std::vector<LevelFactor> levels;  // index = depth (0 unused)
-  int nroot = 0;
+  int nroot = 0;                    // sum of the roots' N
   int* root_idx = nullptr;
-  double* Lroot_inv = nullptr;  // chol: inverse Cholesky factor of the root block (lower)
-  double* Lroot = nullptr;      // chol: Cholesky factor of the root block (lower)
-  double* Aroot = nullptr;      // mult: the root block
-  double logdet = 0.0;
+  std::vector<RootBlock> roots;     // per instance (N may be 0)
+  std::vector<double> logdet;       // per instance: log|F_i| (chol form)
   Arena arena;
 };
 
@@ -73,6 +86,7 @@ struct Options {
   int n_prox = 256, prox_rings = 4;
   double r_near = 1.8, r_in = 1.75, r_out = 2.45, rq_alpha = 1.0;
   size_t mem_cap = 0;
+  bool mixed = false;  // FP32 kernel entries and Schur-complement products
 };
 
 }  // namespace rsf
@@ -83,7 +97,8 @@ struct rsf_factor_s {
   int kernel = 0;
   double eps = 0.0;
   int leaf = 0;
-  double theta[3] = {0, 0, 0};
+  double theta[3] = {0, 0, 0};  // instance 0
+  std::vector<double> thetas;   // 3 per instance
   double* px = nullptr;  // device, tree order
   double* py = nullptr;
   int* perm = nullptr;   // device copy of tree.perm
@@ -115,7 +130,8 @@ void to_panel(const rsf_factor_s* h, const double* src, long long ld, double* P,
 void from_panel(const rsf_factor_s* h, const double* P, int nc, long long ldp, double* dst,
                 long long ld, hipStream_t s);
 
-// Peeled traces of F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1) (Section 3.2).
+// Peeled traces of F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1) (Section 3.2), one
+// value per instance in tr_inv and tr_rho.
 struct PeelStats {
   int levels = 0;
   int cols[32] = {0};
@@ -125,7 +141,9 @@ struct PeelStats {
 void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv,
                  double* tr_rho, PeelStats* st, hipStream_t s);
 
-// Score equations: g (3 values) and the split terms in info (may be null).
+// Score equations of every instance: g (3 values per instance, host); d_z in
+// caller order (instances concatenated).  info (may be null) gets instance 0's
+// split terms and the peeling statistics.
 void grad_eval(rsf_factor_s* f, const double* d_z, double eps_peel, uint64_t seed, double* g,
                rsf_grad_info* info, void* stream);
 

@@ -372,12 +372,16 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
     scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
   }
   if (F.nroot > 0) {
-    const int N = F.nroot;
-    std::vector<GemmDesc> g1{gemm_desc(N, nc, N, 1.0, colmaj(F.Lroot_inv, N), panel(X, ld, F.root_idx), 0.0,
-                                       panel(tmp, nc))};
+    std::vector<GemmDesc> g1, g2;
+    for (const RootBlock& rb : F.roots) {
+      if (rb.N == 0) continue;
+      const int N = rb.N;
+      const int* ri = F.root_idx + rb.off;
+      double* tr = tmp + (long long)rb.off * nc;
+      g1.push_back(gemm_desc(N, nc, N, 1.0, colmaj(rb.Linv, N), panel(X, ld, ri), 0.0, panel(tr, nc)));
+      g2.push_back(gemm_desc(N, nc, N, 1.0, colmajT(rb.Linv, N), panel(tr, nc), 0.0, panel(X, ld, ri)));
+    }
     gemm_batched(g1, scr, s);
-    std::vector<GemmDesc> g2{gemm_desc(N, nc, N, 1.0, colmajT(F.Lroot_inv, N), panel(tmp, nc), 0.0,
-                                       panel(X, ld, F.root_idx))};
     gemm_batched(g2, scr, s);
   }
   for (int d = 1; d <= D; ++d) {
@@ -414,9 +418,11 @@ void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double*
                RS, X, ld, 1.0, RR, Out, ld, scr, s);
   }
   if (F.nroot > 0) {
-    const int N = F.nroot;
-    std::vector<GemmDesc> g{gemm_desc(N, nc, N, 1.0, colmajT(F.Lroot, N), panel(X, ld, F.root_idx), 0.0,
-                                      panel(Out, ld, F.root_idx))};
+    std::vector<GemmDesc> g;
+    for (const RootBlock& rb : F.roots)
+      if (rb.N > 0)
+        g.push_back(gemm_desc(rb.N, nc, rb.N, 1.0, colmajT(rb.L, rb.N), panel(X, ld, F.root_idx + rb.off), 0.0,
+                              panel(Out, ld, F.root_idx + rb.off)));
     gemm_batched(g, scr, s);
   }
 }
@@ -432,9 +438,11 @@ void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, dou
                RR, Y, ld, 0.0, RR, V, ld, scr, s);
   }
   if (F.nroot > 0) {
-    const int N = F.nroot;
-    std::vector<GemmDesc> g{gemm_desc(N, nc, N, 1.0, colmaj(F.Lroot, N), panel(Y, ld, F.root_idx), 0.0,
-                                      panel(V, ld, F.root_idx))};
+    std::vector<GemmDesc> g;
+    for (const RootBlock& rb : F.roots)
+      if (rb.N > 0)
+        g.push_back(gemm_desc(rb.N, nc, rb.N, 1.0, colmaj(rb.L, rb.N), panel(Y, ld, F.root_idx + rb.off), 0.0,
+                              panel(V, ld, F.root_idx + rb.off)));
     gemm_batched(g, scr, s);
   }
   for (int d = 1; d <= D; ++d) {
@@ -468,9 +476,11 @@ void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, dou
                RS, X, ld, 1.0, RR, Y, ld, scr, s);
   }
   if (F.nroot > 0) {
-    const int N = F.nroot;
-    std::vector<GemmDesc> g{gemm_desc(N, nc, N, 1.0, colmaj(F.Aroot, N), panel(X, ld, F.root_idx), 1.0,
-                                      panel(Y, ld, F.root_idx))};
+    std::vector<GemmDesc> g;
+    for (const RootBlock& rb : F.roots)
+      if (rb.N > 0)
+        g.push_back(gemm_desc(rb.N, nc, rb.N, 1.0, colmaj(rb.L, rb.N), panel(X, ld, F.root_idx + rb.off), 1.0,
+                              panel(Y, ld, F.root_idx + rb.off)));
     gemm_batched(g, scr, s);
   }
   for (int d = 1; d <= D; ++d) {

@@ -1,0 +1,72 @@
+"""Mixed precision: kernel entries evaluated in FP32 and the Schur-complement
+products of the elimination on FP32 matrix cores with FP32 accumulation; the
+IDs, the Cholesky factors, log|F| and the sweeps stay FP64.
+
+Error model.  With u32 = 2^-24 each kernel entry carries a relative error of
+about u32, and a Schur product over an inner dimension K an absolute error of
+about sqrt(K) u32 |T| |X| (random rounding).  These perturb F by E with
+|E| ~ 10 u32 |Sigma_box|, and log|F|, l and Tr F^-1 by tr(F^-1 E) and its
+relatives.  The resulting relative errors of l and log|F| stay near 1e2 u32;
+the score, whose three components are differences of large terms (the
+quadratic term and half the trace, which nearly cancel), is judged on the
+scale |q| + |t|/2 of its halves, where the FP32 noise of the small-eigenvalue
+directions (nugget scale) reaches ~1e3 u32.  The bounds below allow 10x over
+that.
+"""
+import numpy as np
+import pytest
+import torch
+
+import paper_1603_08057_amd as R
+from oracle import dense
+from oracle import kernels as K
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+U32 = 2.0 ** -24
+
+
+def _t(x):
+    return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
+
+
+@pytest.mark.parametrize("n,kernel,theta", [
+    (4096, K.MATERN32, (0.05, 1.0, 1e-4)),
+    (2500, K.MATERN52, (0.06, 1.2, 1e-3)),
+])
+def test_mixed_against_dense_and_fp64(n, kernel, theta):
+    print("mixed case n=%d kernel=%d" % (n, kernel), flush=True)
+    P = W.uniform_points(n, 11)
+    z = dense.sample(P, W.gaussian(n, 12), theta, kernel)
+    d = dense.loglik_and_grad(P, z, theta, kernel, want_terms=True)
+    out = {}
+    for prec in ("fp64", "mixed"):
+        R.trace_read(reset=True)
+        R.trace_enable(True)
+        F = R.Factor(_t(P), theta, kernel=kernel, eps=1e-6, leaf=64, precision=prec)
+        R.trace_enable(False)
+        phases = R.trace_read(reset=True, phases=True)[4]
+        ell = F.loglik(_t(z))
+        g, info = F.grad(_t(z), 1e-6, 33)
+        out[prec] = (ell, F.logdet, np.array(g), phases)
+        F.close()
+    # the mixed factorization really ran FP32 products, the FP64 one none
+    assert any(k.endswith("/f32") and v[1] > 0 for k, v in out["mixed"][3].items())
+    assert not any(k.endswith("/f32") for k in out["fp64"][3])
+    scale = np.abs(d["q"]) + 0.5 * np.abs(d["t"])
+    for prec in ("mixed",):
+        ell, ld, g, _ = out[prec]
+        e_l = abs(ell - d["ell"]) / abs(d["ell"])
+        e_ld = abs(ld - d["logdet"]) / abs(d["logdet"])
+        e_g = np.abs(g - d["g"]) / scale
+        e_l64 = abs(ell - out["fp64"][0]) / abs(out["fp64"][0])
+        print("mixed n=%d: l rel %.2e, logdet rel %.2e, g/scale %s; l vs fp64 %.2e" % (n, e_l, e_ld, e_g, e_l64),
+              flush=True)
+        assert e_l <= 1e3 * U32
+        assert e_ld <= 1e3 * U32
+        assert np.all(e_g <= 1e4 * U32)
+        assert e_l64 <= 1e3 * U32
+    # repeatable
+    F = R.Factor(_t(P), theta, kernel=kernel, eps=1e-6, leaf=64, precision="mixed")
+    assert F.logdet == out["mixed"][1]
+    F.close()

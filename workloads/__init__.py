@@ -62,6 +62,36 @@ WORKLOADS = {
 }
 
 
+def batch_instances(count, master_seed, n_lo=2048, n_hi=32768, rho_lo=0.02, rho_hi=0.2, sigma2=1.0,
+                    nugget=1e-4):
+    """Independent instances: n_i log-uniform in [n_lo, n_hi]; points uniform
+    in a rectangle of unit area and aspect A_i ~ U[1, 4] (sqrt(A_i) x
+    1/sqrt(A_i), the two sides swapped with probability 1/2); length scale
+    rho_i ~ U[rho_lo, rho_hi].  The master seed draws the sizes, shapes and
+    length scales; instance i draws its points with seed 100 * master_seed + i.
+    Returns a list of (points, theta)."""
+    rng = np.random.default_rng(master_seed)
+    n = np.floor(np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count))).astype(int)
+    aspect = rng.uniform(1.0, 4.0, count)
+    swap = rng.random(count) < 0.5
+    rho = rng.uniform(rho_lo, rho_hi, count)
+    out = []
+    for i in range(count):
+        w, h = np.sqrt(aspect[i]), 1.0 / np.sqrt(aspect[i])
+        if swap[i]:
+            w, h = h, w
+        P = np.random.default_rng(100 * master_seed + i).random((int(n[i]), 2)) * np.array([w, h])
+        out.append((P, (float(rho[i]), sigma2, nugget)))
+    return out
+
+
+# batches of independent instances (Matern 3/2)
+BATCHES = {
+    "c4_batch64_matern32": dict(count=64, master_seed=41, w_seed=42, peel_seed=43, kernel=MATERN32,
+                                alpha=1.0, eps=1e-6, leaf=64, n_prox=256, prox_rings=4),
+}
+
+
 def workload_points(name, n=None):
     """Points of a named workload (optionally with a different n, same recipe)."""
     w = WORKLOADS[name]
