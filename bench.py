@@ -55,6 +55,73 @@ def cpu_baseline(spec, name, budget_s=20.0):
                       % (m, t, spec["n"], m)}
 
 
+def bench_batch(args):
+    """Independent instances: one batched handle per step (every level of all
+    instances in one launch set) against the same instances one by one."""
+    import numpy as np
+    import torch
+    import paper_1603_08057_amd as R
+    import workloads as W
+    spec = W.BATCHES[args.workload]
+    inst = W.batch_instances(spec["count"], spec["master_seed"])
+    dev = torch.device("cuda:0")
+    pts = [torch.tensor(p, dtype=torch.float64, device=dev) for p, _ in inst]
+    thetas = [th for _, th in inst]
+    kw = dict(kernel=spec["kernel"], eps=spec["eps"], leaf=spec["leaf"], n_prox=spec["n_prox"],
+              prox_rings=spec["prox_rings"], rq_alpha=spec["alpha"])
+    rng = np.random.default_rng(spec["w_seed"])
+    B0 = R.BatchedFactor(pts, thetas, **kw)
+    zs = B0.apply_sqrt([torch.tensor(rng.standard_normal(len(p)), device=dev) for p in pts])
+    B0.close()
+    torch.cuda.synchronize()
+    ntot = sum(len(p) for p in pts)
+    print("setup done: %d instances, %d points" % (len(pts), ntot), file=sys.stderr, flush=True)
+
+    def step_batched():
+        B = R.BatchedFactor(pts, thetas, **kw)
+        ls = B.loglik(zs)
+        gs, info = B.grad(zs, spec["eps"], spec["peel_seed"])
+        B.close()
+        return ls, gs
+
+    def step_single():
+        out = []
+        for P, th, z in zip(pts, thetas, zs):
+            F = R.Factor(P, th, **kw)
+            ell = F.loglik(z)
+            g, _ = F.grad(z, spec["eps"], spec["peel_seed"])
+            F.close()
+            out.append((ell, g))
+        return out
+
+    for i in range(args.warmup):
+        step_batched()
+    torch.cuda.synchronize()
+    t0 = time.time()
+    for i in range(args.steps):
+        ls, gs = step_batched()
+        print("batched step %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    tb = (time.time() - t0) / args.steps
+    t0 = time.time()
+    single = step_single()
+    torch.cuda.synchronize()
+    ts = time.time() - t0
+    print("one by one: %.3f s" % ts, file=sys.stderr, flush=True)
+    rel_l = max(abs(a - b[0]) / abs(b[0]) for a, b in zip(ls, single))
+    out = {
+        "metric": "loglik+grad evals/sec of a %d-instance batch (eps=%g)" % (len(pts), spec["eps"]),
+        "value": 1.0 / tb, "unit": "batch evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1000.0 * tb, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": args.workload, "instances": len(pts), "points": ntot,
+                   "n_range": [min(len(p) for p in pts), max(len(p) for p in pts)], "eps": spec["eps"],
+                   "leaf": spec["leaf"], "parallelism": "single GPU"},
+        "one_by_one": {"seconds": ts, "speedup_of_batching": ts / tb, "max_rel_diff_loglik": rel_l},
+    }
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +141,8 @@ def main():
     import paper_1603_08057_amd as R
     import workloads as W
 
+    if args.workload in W.BATCHES:
+        return bench_batch(args)
     spec = dict(W.WORKLOADS[args.workload])
     name = args.workload
     if args.n:

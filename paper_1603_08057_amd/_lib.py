@@ -299,6 +299,15 @@ class BatchedFactor:
             raise ValueError("need one vector of n_i values per instance")
         return zs, (C.c_void_p * self.nb)(*[z.data_ptr() for z in zs])
 
+    def apply_sqrt(self, ws):
+        """[F_i^(1/2) w_i] for one vector per instance (draws from N(0, F_i))."""
+        ws, _ = self._ptrs(ws)
+        w = _torch().cat(ws)
+        z = _torch().empty_like(w)
+        _check(load().rsf_apply_sqrt(self._h, C.c_void_p(w.data_ptr()), C.c_void_p(z.data_ptr()), 1, w.numel(),
+                                     _stream()))
+        return list(_torch().split(z, self.ns))
+
     @property
     def logdets(self):
         out = (C.c_double * self.nb)()

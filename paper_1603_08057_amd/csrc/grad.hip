@@ -47,32 +47,41 @@ __device__ __forceinline__ double probe_normal(uint32_t d, uint32_t j, uint32_t 
   return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
 }
 
-// W[d, q(d) * nc + t] = Om[d, j0 + t] = N(d, j0 + t, level) for the DOFs of the
-// depth-`level` boxes (qd[d] = quadrant, -1 elsewhere).  W is zero elsewhere.
-__global__ void probe_kernel(const int* __restrict__ qd, long long n, int nc, int j0, int level, uint64_t seed,
+// Probe columns of one chunk for the DOFs of the depth-`level` boxes (qd[d] =
+// quadrant of d's box, -1 elsewhere): for t < act[i] (i = instance of d),
+//   W[d, 4 t + q(d)] = Om[d, j0[i] + t] = N(d, j0[i] + t, level),
+// W is zero elsewhere.  W interleaves the quadrant blocks (column 4 t + q), so
+// every instance's active columns form a prefix of the panel.
+__global__ void probe_kernel(const int* __restrict__ qd, const int* __restrict__ rinst, const int* __restrict__ act,
+                             const int* __restrict__ j0, long long n, int ncw, int level, uint64_t seed,
                              double* __restrict__ W, double* __restrict__ Om, long long ldo) {
-  const long long tot = n * nc;
+  const long long tot = n * ncw;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
-    const long long d = e / nc;
-    const int t = (int)(e - d * nc);
+    const long long d = e / ncw;
+    const int t = (int)(e - d * ncw);
     const int q = qd[d];
     if (q < 0) continue;
-    const double v = probe_normal((uint32_t)d, (uint32_t)(j0 + t), (uint32_t)level, 0u, seed);
-    W[d * 4LL * nc + (long long)q * nc + t] = v;
-    Om[d * ldo + j0 + t] = v;
+    const int i = rinst[d];
+    if (t >= act[i]) continue;
+    const double v = probe_normal((uint32_t)d, (uint32_t)(j0[i] + t), (uint32_t)level, 0u, seed);
+    W[d * 4LL * ncw + 4LL * t + q] = v;
+    Om[d * ldo + j0[i] + t] = v;
   }
 }
 
-// Y[d, q * C + j0 + t] = B[d, q * nc + t] for the rows of the depth-`level` boxes.
-__global__ void store_samples_kernel(const int* __restrict__ qd, long long n, int nc, int j0, int C,
-                                     const double* __restrict__ B, double* __restrict__ Y) {
-  const long long tot = n * 4LL * nc;
+// Y[d, q * C + j0[i] + t] = B[d, 4 t + q] for the rows of the depth-`level`
+// boxes and t < act[i] (i = instance of d).
+__global__ void store_samples_kernel(const int* __restrict__ qd, const int* __restrict__ rinst,
+                                     const int* __restrict__ act, const int* __restrict__ j0, long long n, int ncw,
+                                     int C, const double* __restrict__ B, double* __restrict__ Y) {
+  const long long tot = n * 4LL * ncw;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
-    const long long d = e / (4LL * nc);
-    const int c = (int)(e - d * 4LL * nc);
+    const long long d = e / (4LL * ncw);
+    const int c = (int)(e - d * 4LL * ncw);
     if (qd[d] < 0) continue;
-    const int q = c / nc, t = c - q * nc;
-    Y[d * 4LL * C + (long long)q * C + j0 + t] = B[e];
+    const int i = rinst[d], t = c >> 2, q = c & 3;
+    if (t >= act[i]) continue;
+    Y[d * 4LL * C + (long long)q * C + j0[i] + t] = B[e];
   }
 }
 
@@ -278,34 +287,33 @@ __global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __res
   }
 }
 
-// d[e * c + i] = G_e(i, i); state and d1 cleared
-__global__ void ppanel_init_kernel(const double* __restrict__ G, int c, int nj, double* __restrict__ d,
-                                   int* __restrict__ state, double* __restrict__ d1) {
-  const long long tot = (long long)nj * c;
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
-    const long long b = e / c, i = e - b * c;
-    d[e] = G[b * c * c + i * c + i];
-    if (i == 0) {
-      state[2 * b] = 0;
-      state[2 * b + 1] = 0;
-      d1[b] = 0.0;
-    }
+// d_e(i) = Gw_e(i, i); state and d1 cleared (one workgroup per job)
+__global__ void ppanel_init_kernel(const PpanelJob* __restrict__ jobs) {
+  const PpanelJob J = jobs[blockIdx.x];
+  for (int i = threadIdx.x; i < J.c; i += blockDim.x) J.d[i] = J.Gw[(long long)i * J.c + i];
+  if (threadIdx.x == 0) {
+    J.state[0] = 0;
+    J.state[1] = 0;
+    *J.d1 = 0.0;
   }
 }
 
-// out_e(a, b) = G_e(piv_e[a], piv_e[b]) for a, b < k_e (all ld c)
-struct GatherJob {
-  const double* G;
+// out(u, j) = Y(u, piv[j]) for u < cnt, j < k: the pivot columns of a sample
+// block (row-major rows of ld doubles) as a column-major cnt x k matrix.
+struct GatherColsJob {
+  const double* Y;
+  long long ld;
   const int* piv;
+  int k, cnt;
   double* out;
-  int k;
 };
-__global__ void gather_sym_kernel(const GatherJob* __restrict__ jobs, int c) {
-  const GatherJob J = jobs[blockIdx.y];
-  const long long tot = (long long)J.k * J.k;
+__global__ void gather_cols_kernel(const GatherColsJob* __restrict__ jobs) {
+  const GatherColsJob J = jobs[blockIdx.y];
+  const long long tot = (long long)J.k * J.cnt;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
-    const int a = (int)(e % J.k), b = (int)(e / J.k);
-    J.out[(long long)b * c + a] = J.G[(long long)J.piv[b] * c + J.piv[a]];
+    const long long u = e / J.k;
+    const int j = (int)(e - u * J.k);
+    J.out[(long long)j * J.cnt + u] = J.Y[u * J.ld + J.piv[j]];
   }
 }
 
@@ -317,8 +325,12 @@ static unsigned grid_of(long long tot) {
 namespace {
 
 constexpr int OVERSAMPLE = 10;
-// device memory for the work panels of one chunk of probe columns
+// device memory for the work panels of one chunk of probe columns, for the
+// Gram matrices of one chunk of sample blocks and for the bases and core
+// matrices of one chunk of sibling pairs
 constexpr long long PEEL_CHUNK_BYTES = 24LL << 30;
+constexpr long long GRAM_CHUNK_BYTES = 8LL << 30;
+constexpr long long LOWRANK_CHUNK_BYTES = 8LL << 30;
 constexpr int FIRST_COLS = 64;
 constexpr int MIN_COLS = 24;
 
@@ -378,24 +390,28 @@ struct Peeler {
   Peeler(const rsf_factor_s* hh, hipStream_t ss) : h(hh), t(hh->tree), s(ss) {}
 
   // out_op = G_op X for both operators (X row-major n x nc); X is preserved.
-  void apply_ops(const double* X, int nc, double* out0, double* out1, Scratch& scr) {
+  // cols (host, per instance, or null): the leading columns each instance's
+  // rows take part in.
+  void apply_ops(const double* X, int nc, double* out0, double* out1, Scratch& scr, const int* cols) {
     const long long n = t.n, sz = n * nc;
     double* A = scr.make<double>(sz);
     double* V = scr.make<double>(sz);
     double* Z = scr.make<double>(sz);
     copy_dev(out0, X, sz, s);
-    sweep_solve(h, h->F, out0, nc, nc, scr, s);  // F^-1 X
+    sweep_solve(h, h->F, out0, nc, nc, scr, s, cols);  // F^-1 X
     copy_dev(A, X, sz, s);
-    sweep_apply_mult(h, *h->Frho, A, V, nc, nc, scr, s);  // F_rho X
-    sweep_solve(h, h->F, V, nc, nc, scr, s);               // F^-1 F_rho X
+    sweep_apply_mult(h, *h->Frho, A, V, nc, nc, scr, s, cols);  // F_rho X
+    sweep_solve(h, h->F, V, nc, nc, scr, s, cols);               // F^-1 F_rho X
     copy_dev(A, out0, sz, s);
-    sweep_apply_mult(h, *h->Frho, A, Z, nc, nc, scr, s);  // F_rho F^-1 X
+    sweep_apply_mult(h, *h->Frho, A, Z, nc, nc, scr, s, cols);  // F_rho F^-1 X
     hipLaunchKernelGGL(axpby_kernel, dim3(grid_of(sz)), dim3(256), 0, s, sz, 0.5, V, 0.5, Z, out1);
     RSF_HIP(hipGetLastError());
   }
 
-  // out -= sum_{m < upto} G^(m) X  for operator op
-  void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr) {
+  int cols_of(const int* cols, int box, int nc) const { return cols ? std::min(nc, cols[t.inst[box]]) : nc; }
+
+  // out -= sum_{m < upto} G^(m) X  for operator op (same column rule as apply_ops)
+  void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr, const int* cols) {
     TraceTag tag("peel_subtract");
     for (int m = 1; m < upto && m < (int)lr[op].size(); ++m) {
       const LevelLR& L = lr[op][m];
@@ -410,7 +426,7 @@ struct Peeler {
       std::vector<GemmDesc> g1;
       for (int b = 0; b < nbx; ++b) {
         const int box = L.boxes[b];
-        g1.push_back(gemm_desc(L.K[b], nc, t.count[box], 1.0, colmajT(L.U[b], t.count[box]),
+        g1.push_back(gemm_desc(L.K[b], cols_of(cols, box, nc), t.count[box], 1.0, colmajT(L.U[b], t.count[box]),
                                panel(X + (long long)t.begin[box] * nc, nc), 0.0, panel(P + poff[b], nc)));
       }
       gemm_batched(g1, scr, s);
@@ -418,11 +434,12 @@ struct Peeler {
       for (size_t p = 0; p < L.pairs.size(); ++p) {
         const PairLR& pr = L.pairs[p];
         if (pr.k1 == 0 || pr.k2 == 0) continue;
+        const int N = cols_of(cols, pr.i, nc);
         // Q_i[seg(i, j)] = M P_j[seg(j, i)],  Q_j[seg(j, i)] = M^T P_i[seg(i, j)]
-        g2.push_back(gemm_desc(pr.k1, nc, pr.k2, 1.0, colmaj(pr.M, pr.k1),
+        g2.push_back(gemm_desc(pr.k1, N, pr.k2, 1.0, colmaj(pr.M, pr.k1),
                                panel(P + poff[L.pos_j[p]] + (long long)L.off_j[p] * nc, nc), 0.0,
                                panel(Q + poff[L.pos_i[p]] + (long long)L.off_i[p] * nc, nc)));
-        g2.push_back(gemm_desc(pr.k2, nc, pr.k1, 1.0, colmajT(pr.M, pr.k1),
+        g2.push_back(gemm_desc(pr.k2, N, pr.k1, 1.0, colmajT(pr.M, pr.k1),
                                panel(P + poff[L.pos_i[p]] + (long long)L.off_i[p] * nc, nc), 0.0,
                                panel(Q + poff[L.pos_j[p]] + (long long)L.off_j[p] * nc, nc)));
       }
@@ -430,46 +447,55 @@ struct Peeler {
       std::vector<GemmDesc> g3;
       for (int b = 0; b < nbx; ++b) {
         const int box = L.boxes[b];
-        g3.push_back(gemm_desc(t.count[box], nc, L.K[b], -1.0, colmaj(L.U[b], t.count[box]), panel(Q + poff[b], nc),
-                               1.0, panel(out + (long long)t.begin[box] * nc, nc)));
+        g3.push_back(gemm_desc(t.count[box], cols_of(cols, box, nc), L.K[b], -1.0, colmaj(L.U[b], t.count[box]),
+                               panel(Q + poff[b], nc), 1.0, panel(out + (long long)t.begin[box] * nc, nc)));
       }
       gemm_batched(g3, scr, s);
     }
   }
 
-  // Pivots (dpiv, nj x c) and ranks (rk) of nj Gram matrices (c x c each,
-  // consecutive, ld c) by blocked pivoted Cholesky; G is preserved.
-  void pivot_ranks(const double* G, int c, int nj, double tol2, int* dpiv, std::vector<int>& rk, Scratch& scr) {
+  // Pivots and ranks of nj Gram matrices (G + goff[e], c[e] x c[e], ld c[e])
+  // by blocked pivoted Cholesky; pivots of matrix e go to dpiv + poff[e].
+  // G is preserved.
+  void pivot_ranks(const double* G, const std::vector<long long>& goff, const std::vector<int>& c,
+                   const std::vector<long long>& poff, double tol2, int* dpiv, std::vector<int>& rk) {
     TraceTag tag("peel_pivot");
-    (void)scr;
     Scratch ws(s);  // work buffers live only through this call
-    RSF_CHECK(c <= PCHOL_MAXN, RSF_E_INVALID,
+    const int nj = (int)c.size();
+    const int cmax = *std::max_element(c.begin(), c.end());
+    RSF_CHECK(cmax <= PCHOL_MAXN, RSF_E_INVALID,
               "peeling needs more than " + std::to_string(PCHOL_MAXN) + " probe columns per block");
-    const int NB = c <= 1024 ? 32 : c <= 2048 ? 16 : 8;
-    const long long cc = (long long)c * c;
-    double* Gw = ws.make<double>(cc * nj);
-    copy_dev(Gw, G, cc * nj, s);
-    double* d = ws.make<double>((long long)c * nj);
-    double* Lp = ws.make<double>((long long)c * NB * nj);
+    const int NB = cmax <= 1024 ? 32 : cmax <= 2048 ? 16 : 8;
+    std::vector<long long> doff(nj + 1, 0);
+    for (int e = 0; e < nj; ++e) doff[e + 1] = doff[e] + c[e];
+    double* Gw = ws.make<double>(std::max<long long>(goff[nj], 1));
+    copy_dev(Gw, G, goff[nj], s);
+    double* d = ws.make<double>(std::max<long long>(doff[nj], 1));
+    double* Lp = ws.make<double>(std::max<long long>(doff[nj] * NB, 1));
     double* d1 = ws.make<double>(nj);
     int* state = ws.make<int>(2 * nj);
-    hipLaunchKernelGGL(ppanel_init_kernel, dim3(grid_of((long long)c * nj)), dim3(256), 0, s, G, c, nj, d, state, d1);
-    RSF_HIP(hipGetLastError());
+    std::vector<PpanelJob> all(nj);
+    for (int e = 0; e < nj; ++e)
+      all[e] = PpanelJob{Gw + goff[e], d + doff[e], Lp + doff[e] * NB, dpiv + poff[e], state + 2 * e, d1 + e, c[e]};
+    {
+      PpanelJob* dj = ws.make<PpanelJob>(nj);
+      upload(dj, all, s);
+      hipLaunchKernelGGL(ppanel_init_kernel, dim3(nj), dim3(256), 0, s, dj);
+      RSF_HIP(hipGetLastError());
+    }
     std::vector<int> active(nj);
     for (int e = 0; e < nj; ++e) active[e] = e;
     std::vector<int> hs(2 * nj, 0);
-    const int npanel = (c + NB - 1) / NB;
+    const int npanel = (cmax + NB - 1) / NB;
     for (int pnl = 0; pnl <= npanel && !active.empty(); ++pnl) {
       std::vector<PpanelJob> jobs;
-      for (int e : active)
-        jobs.push_back(PpanelJob{Gw + cc * e, d + (long long)c * e, Lp + (long long)c * NB * e,
-                                 dpiv + (long long)c * e, state + 2 * e, d1 + e, c});
+      for (int e : active) jobs.push_back(all[e]);
       PpanelJob* dj = ws.make<PpanelJob>(jobs.size());
       upload(dj, jobs, s);
       const dim3 grid((unsigned)jobs.size()), blk(PCHOL_WG);
-      if (c <= 1024)
+      if (cmax <= 1024)
         hipLaunchKernelGGL((ppanel_kernel<1, 32>), grid, blk, 0, s, dj, tol2);
-      else if (c <= 2048)
+      else if (cmax <= 2048)
         hipLaunchKernelGGL((ppanel_kernel<2, 16>), grid, blk, 0, s, dj, tol2);
       else
         hipLaunchKernelGGL((ppanel_kernel<4, 8>), grid, blk, 0, s, dj, tol2);
@@ -486,8 +512,8 @@ struct Peeler {
       }
       std::vector<GemmDesc> tg;
       for (int e : active)
-        tg.push_back(gemm_desc(c, c, NB, -1.0, colmaj(Lp + (long long)c * NB * e, c),
-                               colmajT(Lp + (long long)c * NB * e, c), 1.0, colmaj(Gw + cc * e, c)));
+        tg.push_back(gemm_desc(c[e], c[e], NB, -1.0, colmaj(all[e].Lp, c[e]), colmajT(all[e].Lp, c[e]), 1.0,
+                               colmaj(Gw + goff[e], c[e])));
       gemm_batched(tg, ws, s);
     }
     RSF_CHECK(active.empty(), RSF_E_INVALID, "pivoted Cholesky did not terminate");
@@ -495,43 +521,136 @@ struct Peeler {
     for (int e = 0; e < nj; ++e) rk[e] = hs[2 * e];
   }
 
-  // Linv_e = L1_e^-1 with L1_e L1_e^T = G_e(piv_e[:k_e], piv_e[:k_e]) (ld c): the
-  // leading factor of the pivoted Cholesky, recomputed by the batched blocked
-  // Cholesky on the gathered pivot block.
-  void leading_factors(const double* G, int c, int nj, const int* dpiv, const std::vector<int>& rk, double* Linv,
-                       Scratch& scr) {
-    const long long cc = (long long)c * c;
-    double* G11 = scr.make<double>(cc * nj);
-    std::vector<GatherJob> gj;
-    std::vector<CholProblem> cp;
-    int kmax = 0;
-    for (int e = 0; e < nj; ++e) {
-      if (rk[e] == 0) continue;
-      gj.push_back(GatherJob{G + cc * e, dpiv + (long long)c * e, G11 + cc * e, rk[e]});
-      cp.push_back(CholProblem{G11 + cc * e, c, rk[e], Linv + cc * e, c, nullptr});
-      kmax = std::max(kmax, rk[e]);
-    }
-    if (gj.empty()) return;
-    GatherJob* dg = scr.make<GatherJob>(gj.size());
-    upload(dg, gj, s);
-    hipLaunchKernelGGL(gather_sym_kernel, dim3(grid_of((long long)kmax * kmax), (unsigned)gj.size()), dim3(256), 0, s,
-                       dg, c);
-    RSF_HIP(hipGetLastError());
-    int* fail = scr.make<int>(1);
+  // Bases and core matrices of the sibling pairs [p0, p1) of one level and
+  // operator (eq. lowrankapprox), the pairs' instances peeling tot[] columns:
+  //   U = orth(Y_ij): Yg = Y_ij(:, piv[:k]), U = Yg L1^-T with L1 L1^T = Yg^T Yg
+  //     (the leading factor of the pivoted Cholesky, recomputed on the pivot
+  //     columns by the batched blocked Cholesky);
+  //   M = (Om_i^T U1)^+ (Om_i^T Y_ij) (U2^T Om_j)^+ through the normal
+  //     equations, with (Om_i^T U1)^T (Om_i^T Y_ij) formed as (Om_i A1)^T Y_ij.
+  // Y: samples, row d holds quadrant block q at columns [q C, q C + tot); Om:
+  // probes (ld C); pivots of block e at dpiv + poff[e].
+  void lowrank_chunk(LevelLR& L, int p0, int p1, const std::vector<int>& tot, int C, const double* Yop,
+                     const double* Om, const int* dpiv, const std::vector<long long>& poff, int blk0) {
+    Scratch ms(s);
+    const long long ld = 4LL * C;
+    int* fail = ms.make<int>(1);
     RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
-    batched_chol_inv(cp, fail, scr, s);
+    struct Blk {
+      int e, k, cnt;
+      const double* Yb;
+      double *Yg, *G, *Li, *U;
+    };
+    std::vector<Blk> bl;
+    for (int p = p0; p < p1; ++p) {
+      const PairLR& pr = L.pairs[p];
+      for (int side = 0; side < 2; ++side) {
+        const int rb = side ? pr.j : pr.i, cb = side ? pr.i : pr.j, k = side ? pr.k2 : pr.k1;
+        if (k == 0) continue;
+        Blk b;
+        b.e = blk0 + 2 * p + side;
+        b.k = k;
+        b.cnt = t.count[rb];
+        b.Yb = Yop + (long long)t.begin[rb] * ld + (long long)t.quad[cb] * C;
+        b.Yg = ms.make<double>((size_t)b.cnt * k);
+        b.G = ms.make<double>((size_t)k * k);
+        b.Li = ms.make<double>((size_t)k * k);
+        b.U = side ? L.U[L.pos_j[p]] + (long long)L.off_j[p] * b.cnt : L.U[L.pos_i[p]] + (long long)L.off_i[p] * b.cnt;
+        bl.push_back(b);
+      }
+    }
+    if (!bl.empty()) {
+      std::vector<GatherColsJob> gj;
+      long long maxe = 1;
+      std::vector<GemmDesc> g1, g2;
+      std::vector<CholProblem> cp;
+      for (const Blk& b : bl) {
+        gj.push_back(GatherColsJob{b.Yb, ld, dpiv + poff[b.e], b.k, b.cnt, b.Yg});
+        maxe = std::max(maxe, (long long)b.cnt * b.k);
+        g1.push_back(gemm_desc(b.k, b.k, b.cnt, 1.0, colmajT(b.Yg, b.cnt), colmaj(b.Yg, b.cnt), 0.0, colmaj(b.G, b.k)));
+        cp.push_back(CholProblem{b.G, b.k, b.k, b.Li, b.k, nullptr});
+        g2.push_back(gemm_desc(b.cnt, b.k, b.k, 1.0, colmaj(b.Yg, b.cnt), colmajT(b.Li, b.k), 0.0, colmaj(b.U, b.cnt)));
+      }
+      GatherColsJob* dg = ms.make<GatherColsJob>(gj.size());
+      upload(dg, gj, s);
+      hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_of(maxe), (unsigned)gj.size()), dim3(256), 0, s, dg);
+      RSF_HIP(hipGetLastError());
+      gemm_batched(g1, ms, s);
+      batched_chol_inv(cp, fail, ms, s);
+      gemm_batched(g2, ms, s);
+    }
+    std::vector<GemmDesc> ga, gb, gc, gd, ge, gf, gg, gh;
+    std::vector<CholProblem> cn;
+    for (int p = p0; p < p1; ++p) {
+      PairLR& pr = L.pairs[p];
+      const int k1 = pr.k1, k2 = pr.k2;
+      if (k1 == 0 || k2 == 0) continue;
+      const int bi = pr.i, bj = pr.j, ci = t.count[bi], cj = t.count[bj];
+      const int total = tot[t.inst[bi]];
+      const double* U1 = L.U[L.pos_i[p]] + (long long)L.off_i[p] * ci;
+      const double* U2 = L.U[L.pos_j[p]] + (long long)L.off_j[p] * cj;
+      const Mat OmiT{Om + (long long)t.begin[bi] * C, 1, (long long)C, nullptr};
+      const Mat Omi = panel(Om + (long long)t.begin[bi] * C, C);
+      const Mat Omj = panel(Om + (long long)t.begin[bj] * C, C);
+      const double* Yij = Yop + (long long)t.begin[bi] * ld + (long long)t.quad[bj] * C;
+      double* A1 = ms.make<double>((size_t)total * k1);
+      double* A2 = ms.make<double>((size_t)k2 * total);
+      double* W1 = ms.make<double>((size_t)ci * k1);
+      double* N1 = ms.make<double>((size_t)k1 * k1);
+      double* N2 = ms.make<double>((size_t)k2 * k2);
+      double* N1i = ms.make<double>((size_t)k1 * k1);
+      double* N2i = ms.make<double>((size_t)k2 * k2);
+      double* T1 = ms.make<double>((size_t)k1 * total);
+      double* T2 = ms.make<double>((size_t)k1 * k2);
+      double* X = ms.make<double>((size_t)k1 * k2);
+      // A1 = Om_i^T U1, A2 = U2^T Om_j
+      ga.push_back(gemm_desc(total, k1, ci, 1.0, OmiT, colmaj(U1, ci), 0.0, colmaj(A1, total)));
+      ga.push_back(gemm_desc(k2, total, cj, 1.0, colmajT(U2, cj), Omj, 0.0, colmaj(A2, k2)));
+      // W1 = Om_i A1, N1 = A1^T A1, N2 = A2 A2^T
+      gb.push_back(gemm_desc(ci, k1, total, 1.0, Omi, colmaj(A1, total), 0.0, colmaj(W1, ci)));
+      gb.push_back(gemm_desc(k1, k1, total, 1.0, colmajT(A1, total), colmaj(A1, total), 0.0, colmaj(N1, k1)));
+      gb.push_back(gemm_desc(k2, k2, total, 1.0, colmaj(A2, k2), colmajT(A2, k2), 0.0, colmaj(N2, k2)));
+      cn.push_back(CholProblem{N1, k1, k1, N1i, k1, nullptr});
+      cn.push_back(CholProblem{N2, k2, k2, N2i, k2, nullptr});
+      // T1 = W1^T Y_ij, T2 = T1 A2^T
+      gc.push_back(gemm_desc(k1, total, ci, 1.0, colmajT(W1, ci), panel(Yij, ld), 0.0, colmaj(T1, k1)));
+      gd.push_back(gemm_desc(k1, k2, total, 1.0, colmaj(T1, k1), colmajT(A2, k2), 0.0, colmaj(T2, k1)));
+      // M = N1^-1 T2 N2^-1 with N^-1 = Linv^T Linv
+      ge.push_back(gemm_desc(k1, k2, k1, 1.0, colmaj(N1i, k1), colmaj(T2, k1), 0.0, colmaj(X, k1)));
+      gf.push_back(gemm_desc(k1, k2, k1, 1.0, colmajT(N1i, k1), colmaj(X, k1), 0.0, colmaj(T2, k1)));
+      gg.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(T2, k1), colmajT(N2i, k2), 0.0, colmaj(X, k1)));
+      gh.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(X, k1), colmaj(N2i, k2), 0.0, colmaj(pr.M, k1)));
+    }
+    gemm_batched(ga, ms, s);
+    gemm_batched(gb, ms, s);
+    batched_chol_inv(cn, fail, ms, s);
+    gemm_batched(gc, ms, s);
+    gemm_batched(gd, ms, s);
+    gemm_batched(ge, ms, s);
+    gemm_batched(gf, ms, s);
+    gemm_batched(gg, ms, s);
+    gemm_batched(gh, ms, s);
     int fh = 0;
     RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
     RSF_HIP(hipStreamSynchronize(s));
-    RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: pivot block of a sample Gram matrix is not positive definite");
+    RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: singular normal equations of a basis or core matrix");
   }
 
   void run(double eps_peel, uint64_t seed, double* tr_inv, double* tr_rho, PeelStats* st) {
     const long long n = t.n;
-    const int D = t.maxdepth;
+    const int D = t.maxdepth, ni = t.ninst;
     for (int op = 0; op < 2; ++op) lr[op].assign(D + 1, LevelLR());
-    int prev = -1;
-    std::vector<int> qd(n);
+    // relative pivots below ~1e-13 of the Gram diagonal are rounding noise
+    // (the Gram squares the singular values), so the threshold is floored there
+    const double tol2 = std::max(eps_peel * eps_peel, 1e-13);
+    // per instance: the largest sibling-block rank of the previous level (-1: none yet)
+    std::vector<int> prev(ni, -1);
+    std::vector<int> qd(n), rinst(n);
+    for (int i = 0; i < ni; ++i)
+      for (long long d = t.ioff[i]; d < t.ioff[i + 1]; ++d) rinst[d] = i;
+    Scratch keep(s);
+    int* drinst = keep.make<int>(n);
+    upload(drinst, rinst, s);
     for (int lev = 1; lev <= D; ++lev) {
       Scratch scr(s);
       const int b0 = t.lev[lev], b1 = t.lev[lev + 1];
@@ -549,13 +668,6 @@ struct Peeler {
         for (int u = 0; u < t.count[b]; ++u) qd[t.begin[b] + u] = t.quad[b];
       int* dqd = scr.make<int>(n);
       upload(dqd, qd, s);
-      // the largest instance sets the first level's probe count
-      long long nmax = 0;
-      for (int i = 0; i < t.ninst; ++i) nmax = std::max<long long>(nmax, t.ioff[i + 1] - t.ioff[i]);
-      int c = prev < 0 ? first_cols(nmax) : next_cols(prev);
-      int total = 0, Ccap = 0;
-      double* Om = nullptr;
-      double* Y[2] = {nullptr, nullptr};
       // per ordered sample block: (row box, column quadrant box)
       std::vector<std::pair<int, int>> blocks;
       for (auto& pr : pairs) {
@@ -563,23 +675,28 @@ struct Peeler {
         blocks.emplace_back(pr.second, pr.first);
       }
       const int nblk = (int)blocks.size();
-      std::vector<int> rk(2 * nblk);
+      // probe columns per quadrant block, per instance: target c, done tot
+      std::vector<int> has(ni, 0), cc(ni, 0), tot(ni, 0);
+      for (auto& pr : pairs) has[t.inst[pr.first]] = 1;
+      for (int i = 0; i < ni; ++i)
+        if (has[i]) cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i]);
+      int C = 0;  // capacity of the probe and sample stores (columns per quadrant block)
+      double* Om = nullptr;
+      double* Y[2] = {nullptr, nullptr};
+      std::vector<int> rk(2 * nblk), maxr(ni, 0);
+      std::vector<long long> poff(2 * nblk + 1, 0);
       int* dpiv = nullptr;
-      double* Gram = nullptr;
-      double* Ginv = nullptr;
-      std::vector<long long> goff;
-      int maxrank = 0;
       while (true) {
-        const int newc = c - total;
-        // grow the probe and sample stores to c columns per quadrant block
-        {
-          double* Om2 = scr.make<double>((size_t)n * c);
-          double* Y2[2] = {scr.make<double>((size_t)n * 4 * c), scr.make<double>((size_t)n * 4 * c)};
-          if (total > 0) {
-            hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * total)), dim3(256), 0, s, n, 1, total, Om, Ccap, Om2, c);
+        const int cnew = *std::max_element(cc.begin(), cc.end());
+        if (cnew > C) {
+          // grow the probe and sample stores
+          double* Om2 = scr.make<double>((size_t)n * cnew);
+          double* Y2[2] = {scr.make<double>((size_t)n * 4 * cnew), scr.make<double>((size_t)n * 4 * cnew)};
+          if (C > 0) {
+            hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * C)), dim3(256), 0, s, n, 1, C, Om, C, Om2, cnew);
             for (int op = 0; op < 2; ++op)
-              hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * 4 * total)), dim3(256), 0, s, n, 4, total, Y[op], Ccap,
-                                 Y2[op], c);
+              hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * 4 * C)), dim3(256), 0, s, n, 4, C, Y[op], C, Y2[op],
+                                 cnew);
             RSF_HIP(hipGetLastError());
           }
           scr.release(Om);
@@ -588,83 +705,118 @@ struct Peeler {
           Om = Om2;
           Y[0] = Y2[0];
           Y[1] = Y2[1];
-          Ccap = c;
+          C = cnew;
         }
-        {
-          // the new probe columns go through the operators in chunks, so the
-          // six n x 4 cw work panels stay within PEEL_CHUNK_BYTES
-          const long long per_col = 6LL * n * 4 * (long long)sizeof(double);
-          int cw = (int)std::max<long long>(8, PEEL_CHUNK_BYTES / per_col / 8 * 8);
-          cw = std::min(cw, newc);
-          for (int t0 = 0; t0 < newc; t0 += cw) {
-            const int nc = std::min(cw, newc - t0);
-            Scratch rs(s);
-            const long long sz = n * 4LL * nc;
-            double* Wm = rs.make<double>(sz);
-            fill_zero(Wm, sz, s);
-            hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * nc)), dim3(256), 0, s, dqd, n, nc, total + t0, lev,
-                               seed, Wm, Om, (long long)c);
-            RSF_HIP(hipGetLastError());
-            double* B0 = rs.make<double>(sz);
-            double* B1 = rs.make<double>(sz);
-            apply_ops(Wm, 4 * nc, B0, B1, rs);
-            subtract_lowrank(0, lev, Wm, 4 * nc, B0, rs);
-            subtract_lowrank(1, lev, Wm, 4 * nc, B1, rs);
-            hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, nc, total + t0, c, B0,
-                               Y[0]);
-            hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, n, nc, total + t0, c, B1,
-                               Y[1]);
-            RSF_HIP(hipGetLastError());
+        // the new probe columns of every instance go through the operators
+        // together, in chunks that keep the six n x 4 cw work panels within
+        // PEEL_CHUNK_BYTES
+        int newmax = 0;
+        for (int i = 0; i < ni; ++i) newmax = std::max(newmax, cc[i] - tot[i]);
+        const long long per_col = 6LL * n * 4 * (long long)sizeof(double);
+        const int cw = std::min(newmax, (int)std::max<long long>(8, PEEL_CHUNK_BYTES / per_col / 8 * 8));
+        int* dact = scr.make<int>(ni);
+        int* dj0 = scr.make<int>(ni);
+        for (int t0 = 0; t0 < newmax; t0 += cw) {
+          const int ncw = std::min(cw, newmax - t0);
+          std::vector<int> act(ni), j0(ni), pcols(ni);
+          for (int i = 0; i < ni; ++i) {
+            act[i] = std::max(0, std::min(ncw, cc[i] - tot[i] - t0));
+            j0[i] = tot[i] + t0;
+            pcols[i] = 4 * act[i];
           }
+          upload(dact, act, s);
+          upload(dj0, j0, s);
+          Scratch rs(s);
+          const long long sz = n * 4LL * ncw;
+          double* Wm = rs.make<double>(sz);
+          fill_zero(Wm, sz, s);
+          hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * ncw)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, lev,
+                             seed, Wm, Om, (long long)C);
+          RSF_HIP(hipGetLastError());
+          double* B0 = rs.make<double>(sz);
+          double* B1 = rs.make<double>(sz);
+          const int* pc = ni > 1 ? pcols.data() : nullptr;
+          apply_ops(Wm, 4 * ncw, B0, B1, rs, pc);
+          subtract_lowrank(0, lev, Wm, 4 * ncw, B0, rs, pc);
+          subtract_lowrank(1, lev, Wm, 4 * ncw, B1, rs, pc);
+          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, C,
+                             B0, Y[0]);
+          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, C,
+                             B1, Y[1]);
+          RSF_HIP(hipGetLastError());
         }
-        total = c;
-        // ranks of every sample block by pivoted Cholesky of its Gram matrix
-        goff.assign(2 * nblk + 1, 0);
-        for (int e = 0; e < 2 * nblk; ++e) goff[e + 1] = goff[e] + (long long)total * total;
-        RSF_CHECK(total <= PCHOL_MAXN, RSF_E_INVALID,
-                  "peeling needs more than " + std::to_string(PCHOL_MAXN) + " probe columns per block");
-        scr.release(Gram);
+        for (int i = 0; i < ni; ++i) tot[i] = cc[i];
+        // ranks of every sample block (both operators) by pivoted Cholesky of
+        // its Gram matrix, in chunks that bound the Gram storage
+        std::vector<int> bc(2 * nblk);
+        for (int idx = 0; idx < 2 * nblk; ++idx) {
+          bc[idx] = tot[t.inst[blocks[idx % nblk].first]];
+          poff[idx + 1] = poff[idx] + bc[idx];
+        }
         scr.release(dpiv);
-        Gram = scr.make<double>(goff[2 * nblk]);
-        dpiv = scr.make<int>((size_t)2 * nblk * total);
-        std::vector<GemmDesc> g;
-        for (int op = 0; op < 2; ++op)
-          for (int e = 0; e < nblk; ++e) {
-            const int rb = blocks[e].first, cbx = blocks[e].second;
-            const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * total + (long long)t.quad[cbx] * total;
-            const int idx = op * nblk + e;
-            g.push_back(gemm_desc(total, total, t.count[rb], 1.0, Mat{Yb, 1, 4LL * total, nullptr},
-                                  panel(Yb, 4LL * total), 0.0, colmaj(Gram + goff[idx], total)));
+        dpiv = scr.make<int>(std::max<long long>(poff[2 * nblk], 1));
+        for (int e0 = 0; e0 < 2 * nblk;) {
+          std::vector<long long> goff(1, 0);
+          std::vector<int> cs;
+          int e1 = e0;
+          while (e1 < 2 * nblk) {
+            const long long add = (long long)bc[e1] * bc[e1];
+            if (e1 > e0 && 8 * 2 * (goff.back() + add) > GRAM_CHUNK_BYTES) break;
+            goff.push_back(goff.back() + add);
+            cs.push_back(bc[e1]);
+            ++e1;
           }
-        {
-          TraceTag tg("peel_gram");
-          gemm_batched(g, scr, s);
+          Scratch gs(s);
+          double* Gram = gs.make<double>(std::max<long long>(goff.back(), 1));
+          std::vector<GemmDesc> g;
+          for (int idx = e0; idx < e1; ++idx) {
+            const int op = idx / nblk, e = idx % nblk;
+            const int rb = blocks[e].first, cbx = blocks[e].second, c = bc[idx];
+            const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * C + (long long)t.quad[cbx] * C;
+            g.push_back(gemm_desc(c, c, t.count[rb], 1.0, Mat{Yb, 1, 4LL * C, nullptr}, panel(Yb, 4LL * C), 0.0,
+                                  colmaj(Gram + goff[idx - e0], c)));
+          }
+          {
+            TraceTag tg("peel_gram");
+            gemm_batched(g, gs, s);
+          }
+          std::vector<long long> pv(poff.begin() + e0, poff.begin() + e1);
+          std::vector<int> rq;
+          pivot_ranks(Gram, goff, cs, pv, tol2, dpiv, rq);
+          for (int q = 0; q < e1 - e0; ++q) rk[e0 + q] = rq[q];
+          e0 = e1;
         }
-        // relative pivots below ~1e-13 of the Gram diagonal are rounding noise
-        // (the Gram squares the singular values), so the threshold is floored there
-        const double tol2 = std::max(eps_peel * eps_peel, 1e-13);
-        pivot_ranks(Gram, total, 2 * nblk, tol2, dpiv, rk, scr);
-        bool need = false;
-        maxrank = 0;
-        for (int op = 0; op < 2; ++op)
-          for (int e = 0; e < nblk; ++e) {
-            const int k = rk[op * nblk + e];
-            maxrank = std::max(maxrank, k);
-            if (k + OVERSAMPLE > total && total < t.count[blocks[e].second]) need = true;
+        // an instance needs more columns while a block's rank is not
+        // resolved (rank + oversampling above its columns, which are fewer
+        // than the block's own)
+        std::vector<int> need(ni, 0);
+        std::fill(maxr.begin(), maxr.end(), 0);
+        for (int idx = 0; idx < 2 * nblk; ++idx) {
+          const int e = idx % nblk, i = t.inst[blocks[e].first], k = rk[idx];
+          maxr[i] = std::max(maxr[i], k);
+          if (k + OVERSAMPLE > tot[i] && tot[i] < t.count[blocks[e].second]) need[i] = 1;
+        }
+        bool any = false;
+        for (int i = 0; i < ni; ++i)
+          if (need[i]) {
+            cc[i] = grow_cols(tot[i], maxr[i]);
+            any = true;
           }
-        if (!need) break;
-        c = grow_cols(total, maxrank);
+        if (!any) break;
       }
-      // leading factor L1 of each Gram matrix in pivot order and its inverse
-      Ginv = scr.make<double>(goff[2 * nblk]);
-      leading_factors(Gram, total, 2 * nblk, dpiv, rk, Ginv, scr);
-      prev = maxrank;
+      int colmax = 0, rankmax = 0;
+      for (int i = 0; i < ni; ++i)
+        if (has[i]) {
+          prev[i] = maxr[i];
+          colmax = std::max(colmax, tot[i]);
+          rankmax = std::max(rankmax, maxr[i]);
+        }
       if (st && lev < 32) {
-        st->cols[lev] = total;
-        st->rank[lev] = maxrank;
+        st->cols[lev] = colmax;
+        st->rank[lev] = rankmax;
       }
-      // bases U = Y(:, piv[:k]) Linv^T, stored per box as [U_(b, sibling) ...]
       TraceTag tg("peel_lowrank");
+      const int np = (int)pairs.size();
       for (int op = 0; op < 2; ++op) {
         LevelLR& L = lr[op][lev];
         L.any = true;
@@ -686,116 +838,45 @@ struct Peeler {
         L.U.assign(nbx, nullptr);
         for (int b = 0; b < nbx; ++b)
           L.U[b] = store.make<double>(std::max<long long>((long long)t.count[L.boxes[b]] * L.K[b], 1));
-        std::vector<GemmDesc> g;
-        for (int e = 0; e < nblk; ++e) {
-          const int k = rk[op * nblk + e];
-          if (k == 0) continue;
-          const int rb = blocks[e].first, cbx = blocks[e].second;
-          const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * total + (long long)t.quad[cbx] * total;
-          const int idx = op * nblk + e;
-          const int cnt = t.count[rb];
-          // U^T (k x cnt) = Linv (k x k) * Y(:, piv)^T
-          g.push_back(gemm_desc(k, cnt, k, 1.0, colmaj(Ginv + goff[idx], total),
-                                Mat{Yb, 1, 4LL * total, dpiv + (long long)idx * total}, 0.0,
-                                Mat{L.U[pos[rb]] + (long long)blk_off[e] * cnt, cnt, 1, nullptr}));
-        }
-        gemm_batched(g, scr, s);
-        // core matrices M = (Om_i^T U1)^+ (Om_i^T Y_ij) (U2^T Om_j)^+ per unordered pair
-        const int np = (int)pairs.size();
-        std::vector<long long> a1o(np + 1, 0), a2o(np + 1, 0), co(np + 1, 0), n1o(np + 1, 0), n2o(np + 1, 0),
-            po(np + 1, 0);
-        for (int p = 0; p < np; ++p) {
-          const int k1 = rk[op * nblk + 2 * p], k2 = rk[op * nblk + 2 * p + 1];
-          a1o[p + 1] = a1o[p] + (long long)total * k1;
-          a2o[p + 1] = a2o[p] + (long long)k2 * total;
-          co[p + 1] = co[p] + (long long)total * total;
-          n1o[p + 1] = n1o[p] + (long long)k1 * k1;
-          n2o[p + 1] = n2o[p] + (long long)k2 * k2;
-          po[p + 1] = po[p] + (long long)k1 * std::max(k2, total);
-        }
-        Scratch ms(s);
-        double* A1 = ms.make<double>(std::max<long long>(a1o[np], 1));
-        double* A2 = ms.make<double>(std::max<long long>(a2o[np], 1));
-        double* Cm = ms.make<double>(std::max<long long>(co[np], 1));
-        double* N1 = ms.make<double>(std::max<long long>(n1o[np], 1));
-        double* N2 = ms.make<double>(std::max<long long>(n2o[np], 1));
-        double* N1i = ms.make<double>(std::max<long long>(n1o[np], 1));
-        double* N2i = ms.make<double>(std::max<long long>(n2o[np], 1));
-        double* T1 = ms.make<double>(std::max<long long>(po[np], 1));
-        double* T2 = ms.make<double>(std::max<long long>(po[np], 1));
-        int* fail = ms.make<int>(1);
-        RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
         L.pairs.resize(np);
         L.off_i.resize(np);
         L.off_j.resize(np);
         L.pos_i.resize(np);
         L.pos_j.resize(np);
-        std::vector<GemmDesc> ga, gb, gc, gd, ge, gf;
-        std::vector<CholProblem> cj;
         for (int p = 0; p < np; ++p) {
-          const int bi = pairs[p].first, bj = pairs[p].second;
-          const int k1 = rk[op * nblk + 2 * p], k2 = rk[op * nblk + 2 * p + 1];
           PairLR& pr = L.pairs[p];
-          pr.i = bi;
-          pr.j = bj;
-          pr.k1 = k1;
-          pr.k2 = k2;
+          pr.i = pairs[p].first;
+          pr.j = pairs[p].second;
+          pr.k1 = rk[op * nblk + 2 * p];
+          pr.k2 = rk[op * nblk + 2 * p + 1];
           L.off_i[p] = blk_off[2 * p];
           L.off_j[p] = blk_off[2 * p + 1];
-          L.pos_i[p] = pos[bi];
-          L.pos_j[p] = pos[bj];
-          if (k1 == 0 || k2 == 0) continue;
-          pr.M = store.make<double>((size_t)k1 * k2);
-          const int ci = t.count[bi], cjn = t.count[bj];
-          const double* U1 = L.U[pos[bi]] + (long long)blk_off[2 * p] * ci;
-          const double* U2 = L.U[pos[bj]] + (long long)blk_off[2 * p + 1] * cjn;
-          const Mat OmiT{Om + (long long)t.begin[bi] * total, 1, (long long)total, nullptr};
-          const Mat Omj = panel(Om + (long long)t.begin[bj] * total, total);
-          const double* Yij = Y[op] + (long long)t.begin[bi] * 4 * total + (long long)t.quad[bj] * total;
-          ga.push_back(gemm_desc(total, k1, ci, 1.0, OmiT, colmaj(U1, ci), 0.0, colmaj(A1 + a1o[p], total)));
-          ga.push_back(gemm_desc(total, total, ci, 1.0, OmiT, panel(Yij, 4LL * total), 0.0, colmaj(Cm + co[p], total)));
-          ga.push_back(gemm_desc(k2, total, cjn, 1.0, colmajT(U2, cjn), Omj, 0.0, colmaj(A2 + a2o[p], k2)));
-          gb.push_back(gemm_desc(k1, k1, total, 1.0, colmajT(A1 + a1o[p], total), colmaj(A1 + a1o[p], total), 0.0,
-                                 colmaj(N1 + n1o[p], k1)));
-          gb.push_back(gemm_desc(k2, k2, total, 1.0, colmaj(A2 + a2o[p], k2), colmajT(A2 + a2o[p], k2), 0.0,
-                                 colmaj(N2 + n2o[p], k2)));
-          // T1 = A1^T C (k1 x total); T2 = T1 A2^T (k1 x k2)
-          gb.push_back(gemm_desc(k1, total, total, 1.0, colmajT(A1 + a1o[p], total), colmaj(Cm + co[p], total), 0.0,
-                                 colmaj(T1 + po[p], k1)));
-          cj.push_back(CholProblem{N1 + n1o[p], k1, k1, N1i + n1o[p], k1, nullptr});
-          cj.push_back(CholProblem{N2 + n2o[p], k2, k2, N2i + n2o[p], k2, nullptr});
-          gc.push_back(gemm_desc(k1, k2, total, 1.0, colmaj(T1 + po[p], k1), colmajT(A2 + a2o[p], k2), 0.0,
-                                 colmaj(T2 + po[p], k1)));
-          // M = N1^-1 T2 N2^-1 with N^-1 = Linv^T Linv
-          gd.push_back(gemm_desc(k1, k2, k1, 1.0, colmaj(N1i + n1o[p], k1), colmaj(T2 + po[p], k1), 0.0,
-                                 colmaj(T1 + po[p], k1)));
-          ge.push_back(gemm_desc(k1, k2, k1, 1.0, colmajT(N1i + n1o[p], k1), colmaj(T1 + po[p], k1), 0.0,
-                                 colmaj(T2 + po[p], k1)));
-          gf.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(T2 + po[p], k1), colmajT(N2i + n2o[p], k2), 0.0,
-                                 colmaj(T1 + po[p], k1)));
-          gf.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(T1 + po[p], k1), colmaj(N2i + n2o[p], k2), 0.0,
-                                 colmaj(pr.M, k1)));
+          L.pos_i[p] = pos[pr.i];
+          L.pos_j[p] = pos[pr.j];
+          if (pr.k1 > 0 && pr.k2 > 0) pr.M = store.make<double>((size_t)pr.k1 * pr.k2);
         }
-        gemm_batched(ga, ms, s);
-        gemm_batched(gb, ms, s);
-        batched_chol_inv(cj, fail, ms, s);
-        gemm_batched(gc, ms, s);
-        gemm_batched(gd, ms, s);
-        gemm_batched(ge, ms, s);
-        // the two products of gf depend on each other: run them in order
-        std::vector<GemmDesc> gf1, gf2;
-        for (size_t q = 0; q < gf.size(); ++q) (q % 2 == 0 ? gf1 : gf2).push_back(gf[q]);
-        gemm_batched(gf1, ms, s);
-        gemm_batched(gf2, ms, s);
-        int fh = 0;
-        RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
-        RSF_HIP(hipStreamSynchronize(s));
-        RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: singular normal equations of a core matrix");
+        // the pairs in chunks that bound the work memory
+        int p0 = 0;
+        while (p0 < np) {
+          long long bytes = 0;
+          int p1 = p0;
+          while (p1 < np) {
+            const PairLR& pr = L.pairs[p1];
+            const long long ci = t.count[pr.i], cj = t.count[pr.j], k1 = pr.k1, k2 = pr.k2;
+            const long long total = tot[t.inst[pr.i]];
+            const long long est = 8 * (2 * (ci * k1 + cj * k2) + 4 * (k1 * k1 + k2 * k2) + 2 * total * (k1 + k2) +
+                                       total * k1 + 3 * k1 * k2 + 64);
+            if (p1 > p0 && bytes + est > LOWRANK_CHUNK_BYTES) break;
+            bytes += est;
+            ++p1;
+          }
+          lowrank_chunk(L, p0, p1, tot, C, Y[op], Om, dpiv, poff, op * nblk);
+          p0 = p1;
+        }
       }
     }
     // extraction at the leaves: traces of every instance over its own leaves
     Scratch scr(s);
-    const int ni = t.ninst;
     std::vector<int> lbeg, lcnt, lfirst(ni + 1, 0);
     int nL = 1;
     for (int i = 0; i < ni; ++i) {
@@ -819,9 +900,9 @@ struct Peeler {
     RSF_HIP(hipGetLastError());
     double* H0 = scr.make<double>(sz);
     double* H1 = scr.make<double>(sz);
-    apply_ops(E, nL, H0, H1, scr);
-    subtract_lowrank(0, D + 1, E, nL, H0, scr);
-    subtract_lowrank(1, D + 1, E, nL, H1, scr);
+    apply_ops(E, nL, H0, H1, scr, nullptr);
+    subtract_lowrank(0, D + 1, E, nL, H0, scr, nullptr);
+    subtract_lowrank(1, D + 1, E, nL, H1, scr, nullptr);
     double* tr = scr.make<double>(2 * ni);
     for (int i = 0; i < ni; ++i) {
       const int l0 = lfirst[i], nl = lfirst[i + 1] - lfirst[i];
@@ -842,6 +923,7 @@ struct Peeler {
     }
   }
 };
+
 
 }  // namespace
 

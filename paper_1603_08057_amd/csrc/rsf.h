@@ -115,14 +115,17 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s);
 
 // Sweeps over vector panels in tree order, row-major n x nc with leading
 // dimension ld (row = DOF).  X is overwritten.
+// inst_cols (host, one value per instance, or null): the leading panel
+// columns each instance takes part in; the other columns of its rows are left
+// undefined.
 void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld,
-                 Scratch& scr, hipStream_t s);
+                 Scratch& scr, hipStream_t s, const int* inst_cols = nullptr);
 void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, double* V, int nc,
                 long long ld, Scratch& scr, hipStream_t s);
 void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double* Out, int nc,
                   long long ld, Scratch& scr, hipStream_t s);
 void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, double* Y, int nc,
-                      long long ld, Scratch& scr, hipStream_t s);
+                      long long ld, Scratch& scr, hipStream_t s, const int* inst_cols = nullptr);
 
 // user order column-major (ld) <-> tree order row-major panel (ldp)
 void to_panel(const rsf_factor_s* h, const double* src, long long ld, double* P, int nc,

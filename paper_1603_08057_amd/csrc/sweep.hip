@@ -142,7 +142,9 @@ __device__ __forceinline__ void box_epilogue(int M, const v4d (&acc)[2][2], int 
 }
 
 template <int OP>
-__global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict__ boxes, int nbox, int ntile,
+__global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict__ boxes, int nbox,
+                                                        const int* __restrict__ tile_off,
+                                                        const int* __restrict__ box_cols,
                                                         const int* __restrict__ S, const int* __restrict__ R,
                                                         const double* __restrict__ Tm,
                                                         const double* __restrict__ Wm,
@@ -153,16 +155,25 @@ __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict
   extern __shared__ double bs_smem[];
   double* Xl = bs_smem;
   double* Tl = bs_smem + (amax + 4) * BS_NCT;
-  // tiles of one box stay on one XCD (consecutive workgroup ids alternate XCDs)
-  const long long total = (long long)nbox * ntile;
-  const long long per = (long long)gridDim.x / 8;
-  const long long item = (long long)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  // tiles of one box stay on one XCD (consecutive workgroup ids alternate XCDs);
+  // box bx owns the tiles [tile_off[bx], tile_off[bx + 1]) of its box_cols[bx] columns
+  const int total = tile_off[nbox];
+  const int per = (int)(gridDim.x / 8);
+  const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (item >= total) return;
-  const int bx = (int)(item / ntile), tile = (int)(item - (long long)bx * ntile);
+  int lo = 0, hi = nbox;  // last box with tile_off[box] <= item
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_off[mid] <= item)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int bx = lo, tile = item - tile_off[bx];
   const BoxRec b = boxes[bx];
   const int k = b.k, r = b.r, a = k + r;
   if (r == 0) return;
-  const int j0 = tile * BS_NCT, ncol = min(BS_NCT, nc - j0);
+  const int j0 = tile * BS_NCT, ncol = min(BS_NCT, box_cols[bx] - j0);
   const int* Sb = S + b.s_off;
   const int* Rb = R + b.r_off;
   const double* T = Tm + b.t_off;  // k x r
@@ -270,7 +281,10 @@ __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict
 }
 
 // Runs one level step with the fused kernel when every box fits; false otherwise.
-static bool box_sweep(const LevelFactor& L, int op, double* X, double* Y, int nc, long long ld, hipStream_t s) {
+// bcols: the columns each box of the level takes part in (a prefix of the
+// panel's nc columns; empty = all nc).
+static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int op, double* X, double* Y, int nc,
+                      long long ld, Scratch& scr, hipStream_t s) {
   if (L.nb == 0 || nc <= 0) return true;
   for (int i = 0; i < L.nb; ++i)
     if (L.a[i] > BS_AMAX) return false;
@@ -278,18 +292,25 @@ static bool box_sweep(const LevelFactor& L, int op, double* X, double* Y, int nc
   for (int i = 0; i < L.nb; ++i) amax = std::max(amax, L.a[i]);
   amax = (amax + 3) / 4 * 4;
   const size_t lds = (size_t)(op == BS_MULT_UP ? 1 : 2) * (amax + 4) * BS_NCT * sizeof(double);
-  const int ntile = (nc + BS_NCT - 1) / BS_NCT;
-  const long long total = (long long)L.nb * ntile;
-  const long long grid = (total + 7) / 8 * 8;
-  RSF_CHECK(grid < (1LL << 31), RSF_E_INVALID, "panel too wide for the fused sweep");
-  const dim3 g((unsigned)grid), blk(256);
+  std::vector<int> toff(L.nb + 1, 0), cols(L.nb);
   double fl = 0.0, by = 0.0;
   for (int i = 0; i < L.nb; ++i) {
+    const int c = bcols.empty() ? nc : std::min(nc, bcols[i]);
     const double k = L.k[i], r = L.a[i] - L.k[i];
-    if (r == 0) continue;
-    fl += 2.0 * nc * (op == BS_MULT_DOWN ? 2.0 * k * r : op == BS_MULT_UP ? r * (2.0 * k + r) : r * (2.0 * k + r));
-    by += 8.0 * nc * (op == BS_SOLVE_UP || op == BS_SOLVE_DOWN ? 2.0 * (k + r) : 2.0 * k + 3.0 * r);
+    cols[i] = c;
+    const long long nt = r > 0 ? (c + BS_NCT - 1) / BS_NCT : 0;
+    RSF_CHECK(toff[i] + nt < (1LL << 30), RSF_E_INVALID, "panel too wide for the fused sweep");
+    toff[i + 1] = toff[i] + (int)nt;
+    fl += 2.0 * c * (op == BS_MULT_DOWN ? 2.0 * k * r : r * (2.0 * k + r));
+    if (r > 0) by += 8.0 * c * (op == BS_SOLVE_UP || op == BS_SOLVE_DOWN ? 2.0 * (k + r) : 2.0 * k + 3.0 * r);
   }
+  if (toff[L.nb] == 0) return true;
+  int* dtoff = scr.make<int>(L.nb + 1);
+  int* dcols = scr.make<int>(L.nb);
+  upload(dtoff, toff, s);
+  upload(dcols, cols, s);
+  const long long grid = ((long long)toff[L.nb] + 7) / 8 * 8;
+  const dim3 g((unsigned)grid), blk(256);
   TraceLaunch tl(s, fl, by);
   // the largest box needs more than the default dynamic LDS limit of 64 KiB
   static bool lds_set[4] = {false, false, false, false};
@@ -300,8 +321,8 @@ static bool box_sweep(const LevelFactor& L, int op, double* X, double* Y, int nc
                                 hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));                        \
     lds_set[OPV] = true;                                                                                      \
   }                                                                                                           \
-  hipLaunchKernelGGL(box_sweep_kernel<OPV>, g, blk, lds, s, L.box, L.nb, ntile, L.S, L.R, L.T, L.W, L.Lm, X, Y, \
-                     nc, ld, amax)
+  hipLaunchKernelGGL(box_sweep_kernel<OPV>, g, blk, lds, s, L.box, L.nb, dtoff, dcols, L.S, L.R, L.T, L.W, L.Lm, X, \
+                     Y, nc, ld, amax)
   switch (op) {
     case BS_SOLVE_UP: RSF_BOX(BS_SOLVE_UP); break;
     case BS_SOLVE_DOWN: RSF_BOX(BS_SOLVE_DOWN); break;
@@ -325,14 +346,29 @@ struct LevelTag {
   LevelTag(int d, const char* dir) : t(name(d, dir).c_str()) {}
 };
 
+// Columns each box of a level takes part in: inst_cols[instance of the box]
+// capped at nc (a batch whose instances peel different numbers of probe
+// columns); empty when every box takes all nc.
+static std::vector<int> box_cols(const rsf_factor_s* h, const LevelFactor& L, const int* inst_cols, int nc) {
+  std::vector<int> c;
+  if (!inst_cols) return c;
+  c.resize(L.nb);
+  for (int i = 0; i < L.nb; ++i) c[i] = std::min(nc, inst_cols[h->tree.inst[L.box0 + i]]);
+  return c;
+}
+
+static int root_cols(const int* inst_cols, int i, int nc) { return inst_cols ? std::min(nc, inst_cols[i]) : nc; }
+
 template <class AFn>
-static void level_gemm(const LevelFactor& L, int nc, double alpha, AFn afn, Rows brows, const double* Bp,
-                       long long ldb, double beta, Rows crows, double* Cp, long long ldc, Scratch& scr,
-                       hipStream_t s) {
+static void level_gemm(const LevelFactor& L, const std::vector<int>& bc, int nc, double alpha, AFn afn, Rows brows,
+                       const double* Bp, long long ldb, double beta, Rows crows, double* Cp, long long ldc,
+                       Scratch& scr, hipStream_t s) {
   std::vector<GemmDesc> g;
   g.reserve(L.nb);
   for (int i = 0; i < L.nb; ++i) {
     const int k = L.k[i], r = L.a[i] - L.k[i];
+    const int N = bc.empty() ? nc : bc[i];
+    if (N == 0) continue;
     int M, K;
     Mat A = afn(i, k, r, M, K);
     if (M == 0 || K == 0) {
@@ -343,13 +379,13 @@ static void level_gemm(const LevelFactor& L, int nc, double alpha, AFn afn, Rows
       if (w == RR) return panel(P, ld, L.R + L.r_off[i]);
       return panel(P + L.r_off[i] * nc, nc);
     };
-    g.push_back(gemm_desc(M, nc, K, alpha, A, rowsel(brows, Bp, ldb), beta, rowsel(crows, Cp, ldc)));
+    g.push_back(gemm_desc(M, N, K, alpha, A, rowsel(brows, Bp, ldb), beta, rowsel(crows, Cp, ldc)));
   }
   gemm_batched(g, scr, s);
 }
 
 void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
-                 hipStream_t s) {
+                 hipStream_t s, const int* inst_cols) {
   TraceTag tag("sweep_solve");
   const int D = h->tree.maxdepth;
   long long maxr = 1;
@@ -359,27 +395,29 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "up");
-    if (box_sweep(L, BS_SOLVE_UP, X, nullptr, nc, ld, s)) continue;
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
+    if (box_sweep(L, bc, BS_SOLVE_UP, X, nullptr, nc, ld, scr, s)) continue;
     // X_R -= T^T X_S
-    level_gemm(L, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, X, ld, scr, s);
     // tmp = L^-1 X_R
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
                RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
     // X_S -= W tmp
-    level_gemm(L, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
                RTMP, tmp, nc, 1.0, RS, X, ld, scr, s);
     scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
   }
   if (F.nroot > 0) {
     std::vector<GemmDesc> g1, g2;
-    for (const RootBlock& rb : F.roots) {
-      if (rb.N == 0) continue;
-      const int N = rb.N;
+    for (size_t i = 0; i < F.roots.size(); ++i) {
+      const RootBlock& rb = F.roots[i];
+      const int N = rb.N, cols = root_cols(inst_cols, (int)i, nc);
+      if (N == 0 || cols == 0) continue;
       const int* ri = F.root_idx + rb.off;
       double* tr = tmp + (long long)rb.off * nc;
-      g1.push_back(gemm_desc(N, nc, N, 1.0, colmaj(rb.Linv, N), panel(X, ld, ri), 0.0, panel(tr, nc)));
-      g2.push_back(gemm_desc(N, nc, N, 1.0, colmajT(rb.Linv, N), panel(tr, nc), 0.0, panel(X, ld, ri)));
+      g1.push_back(gemm_desc(N, cols, N, 1.0, colmaj(rb.Linv, N), panel(X, ld, ri), 0.0, panel(tr, nc)));
+      g2.push_back(gemm_desc(N, cols, N, 1.0, colmajT(rb.Linv, N), panel(tr, nc), 0.0, panel(X, ld, ri)));
     }
     gemm_batched(g1, scr, s);
     gemm_batched(g2, scr, s);
@@ -387,16 +425,17 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
   for (int d = 1; d <= D; ++d) {
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "down");
-    if (box_sweep(L, BS_SOLVE_DOWN, X, nullptr, nc, ld, s)) continue;
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
+    if (box_sweep(L, bc, BS_SOLVE_DOWN, X, nullptr, nc, ld, scr, s)) continue;
     // X_R -= W^T X_S
-    level_gemm(L, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, X, ld, scr, s);
     // tmp = L^-T X_R
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lm + L.l_off[i], r); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lm + L.l_off[i], r); },
                RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
     scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
     // X_S -= T tmp
-    level_gemm(L, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
                RTMP, tmp, nc, 1.0, RS, X, ld, scr, s);
   }
 }
@@ -404,17 +443,19 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
 void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double* Out, int nc, long long ld,
                   Scratch& scr, hipStream_t s) {
   TraceTag tag("sweep_sqrt");
+  const int* inst_cols = nullptr;
   const int D = h->tree.maxdepth;
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "up");
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
     // X_S += T X_R
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
                RR, X, ld, 1.0, RS, X, ld, scr, s);
     // Out_R = L^T X_R + W^T X_S
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lf + L.l_off[i], r); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lf + L.l_off[i], r); },
                RR, X, ld, 0.0, RR, Out, ld, scr, s);
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, Out, ld, scr, s);
   }
   if (F.nroot > 0) {
@@ -430,11 +471,13 @@ void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double*
 void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, double* V, int nc, long long ld,
                 Scratch& scr, hipStream_t s) {
   TraceTag tag("sweep_sqrt");
+  const int* inst_cols = nullptr;
   const int D = h->tree.maxdepth;
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "up");
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lf + L.l_off[i], r); },
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lf + L.l_off[i], r); },
                RR, Y, ld, 0.0, RR, V, ld, scr, s);
   }
   if (F.nroot > 0) {
@@ -448,50 +491,56 @@ void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, dou
   for (int d = 1; d <= D; ++d) {
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "down");
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
     // V_S += W Y_R
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
                RR, Y, ld, 1.0, RS, V, ld, scr, s);
     // V_R += T^T V_S
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
                RS, V, ld, 1.0, RR, V, ld, scr, s);
   }
 }
 
 void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, double* Y, int nc, long long ld,
-                      Scratch& scr, hipStream_t s) {
+                      Scratch& scr, hipStream_t s, const int* inst_cols) {
   TraceTag tag("sweep_mult");
   const int D = h->tree.maxdepth;
   fill_zero(Y, h->tree.n * ld, s);
   for (int d = D; d >= 1; --d) {
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "up");
-    if (box_sweep(L, BS_MULT_UP, X, Y, nc, ld, s)) continue;
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
+    if (box_sweep(L, bc, BS_MULT_UP, X, Y, nc, ld, scr, s)) continue;
     // X_S += T X_R
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
                RR, X, ld, 1.0, RS, X, ld, scr, s);
     // Y_R += X_rr X_R + X_sr^T X_S
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
                RR, X, ld, 1.0, RR, Y, ld, scr, s);
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, Y, ld, scr, s);
   }
   if (F.nroot > 0) {
     std::vector<GemmDesc> g;
-    for (const RootBlock& rb : F.roots)
-      if (rb.N > 0)
-        g.push_back(gemm_desc(rb.N, nc, rb.N, 1.0, colmaj(rb.L, rb.N), panel(X, ld, F.root_idx + rb.off), 1.0,
+    for (size_t i = 0; i < F.roots.size(); ++i) {
+      const RootBlock& rb = F.roots[i];
+      const int cols = root_cols(inst_cols, (int)i, nc);
+      if (rb.N > 0 && cols > 0)
+        g.push_back(gemm_desc(rb.N, cols, rb.N, 1.0, colmaj(rb.L, rb.N), panel(X, ld, F.root_idx + rb.off), 1.0,
                               panel(Y, ld, F.root_idx + rb.off)));
+    }
     gemm_batched(g, scr, s);
   }
   for (int d = 1; d <= D; ++d) {
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "down");
-    if (box_sweep(L, BS_MULT_DOWN, X, Y, nc, ld, s)) continue;
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
+    if (box_sweep(L, bc, BS_MULT_DOWN, X, Y, nc, ld, scr, s)) continue;
     // Y_S += X_sr X_R  (after the coarser levels' L operators)
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
                RR, X, ld, 1.0, RS, Y, ld, scr, s);
     // Y_R += T^T Y_S
-    level_gemm(L, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
                RS, Y, ld, 1.0, RR, Y, ld, scr, s);
   }
 }
