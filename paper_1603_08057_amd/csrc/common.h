@@ -41,8 +41,11 @@ void pool_trim();
 struct Arena {
   std::vector<void*> blocks;
   std::vector<size_t> sizes;
-  size_t bytes = 0;
-  size_t cap = 0;  // 0 = unlimited
+  size_t bytes = 0;  // bytes handed out (the cap applies to these)
+  size_t cap = 0;    // 0 = unlimited
+  // small requests are carved from 4 MiB slabs taken from the pool
+  char* slab = nullptr;
+  size_t slab_left = 0;
   void* alloc(size_t nbytes);
   template <class T>
   T* make(size_t count) {
@@ -59,6 +62,12 @@ struct Scratch {
   std::vector<size_t> sizes;
   hipStream_t stream = nullptr;
   size_t cap_left = 0;  // 0 = unlimited
+  // small requests (launch descriptors, index lists) are carved from
+  // SMALL_SLAB-byte slabs taken from the pool
+  static constexpr size_t SMALL_MAX = size_t(256) << 10, SMALL_SLAB = size_t(4) << 20;
+  std::vector<void*> slabs;
+  char* slab = nullptr;
+  size_t slab_left = 0;
   explicit Scratch(hipStream_t s) : stream(s) {}
   void* alloc(size_t nbytes);
   template <class T>
@@ -66,15 +75,19 @@ struct Scratch {
     return static_cast<T*>(alloc(count * sizeof(T)));
   }
   // Returns one block to the pool early (stream-ordered: later work on the
-  // stream may reuse it).  Null or unknown pointers are ignored.
+  // stream may reuse it).  Null pointers, unknown pointers and small requests
+  // (carved from a slab) are ignored.
   void release(const void* p);
   ~Scratch();
 };
 
+// Host-to-device copy of launch descriptors and index lists, staged through a
+// pinned ring buffer so that the copy is asynchronous on stream s.
+void upload_bytes(void* dst, const void* src, size_t nbytes, hipStream_t s);
+
 template <class T>
 inline void upload(T* dst, const std::vector<T>& src, hipStream_t s) {
-  if (!src.empty())
-    RSF_HIP(hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  if (!src.empty()) upload_bytes(dst, src.data(), src.size() * sizeof(T), s);
 }
 
 // accumulator of one 16 x 16 x 4 FP64 matrix-core product (4 doubles per lane)

@@ -1,7 +1,12 @@
 // Batched FP64 GEMM on the gfx950 matrix cores, device memory helpers and
 // fixed-order reductions.
+#include <chrono>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
+#include <tuple>
 
 #include "common.h"
 
@@ -9,70 +14,208 @@ namespace rsf {
 
 
 // ---- device memory pool
-// Freed blocks are kept per size class and handed out again in stream order:
-// a block released on stream s is reused on s without a synchronisation (later
-// work on s runs after the work that used it); reuse on another stream waits
-// for the releasing stream first.  Size classes: four per power of two.
+// Large regions are taken from the device once (hipMalloc of many gigabytes
+// costs milliseconds per gigabyte) and carved into blocks: best fit among the
+// free extents, neighbours coalesced on release.  Reuse is stream ordered: an
+// extent released on stream s is handed out again on s without a
+// synchronisation (later work on s runs after the work that used it); on
+// another stream the releasing stream is synchronised first, and extents
+// released on different streams are not merged.
 namespace {
-struct FreeBlock {
-  void* p;
+constexpr size_t POOL_ALIGN = 256;
+constexpr size_t REGION_MIN = size_t(2) << 30;
+struct Extent {
+  size_t size;
   hipStream_t s;
+};
+struct Region {
+  char* base;
+  size_t size;
+  size_t used = 0;
+  std::map<size_t, Extent> free;  // offset -> free extent
 };
 struct Pool {
   std::mutex mu;
-  std::map<size_t, std::vector<FreeBlock>> free;
+  std::vector<Region> regions;
+  std::map<const void*, std::pair<int, size_t>> live;  // block -> (region, size)
 } g_pool;
 
-size_t size_class(size_t n) {
-  if (n <= 4096) return 4096;
-  size_t top = size_t(1) << (63 - __builtin_clzll(n));
-  size_t step = top / 4;
-  return (n + step - 1) / step * step;
+// best-fitting free extent over all regions; false if none
+bool pool_find(size_t n, int& ri, size_t& off, Extent& ex) {
+  bool found = false;
+  for (int r = 0; r < (int)g_pool.regions.size(); ++r)
+    for (const auto& kv : g_pool.regions[r].free)
+      if (kv.second.size >= n && (!found || kv.second.size < ex.size)) {
+        found = true;
+        ri = r;
+        off = kv.first;
+        ex = kv.second;
+      }
+  return found;
+}
+
+// gives regions with no live block back to the device
+size_t pool_release_empty() {
+  size_t freed = 0;
+  std::vector<Region> keep;
+  for (Region& g : g_pool.regions) {
+    if (g.used == 0) {
+      for (const auto& kv : g.free) (void)hipStreamSynchronize(kv.second.s);
+      (void)hipFree(g.base);
+      freed += g.size;
+    } else {
+      keep.push_back(std::move(g));
+    }
+  }
+  g_pool.regions.swap(keep);
+  for (auto& kv : g_pool.live) {  // region indices moved: rebuild them
+    const char* p = static_cast<const char*>(kv.first);
+    for (int r = 0; r < (int)g_pool.regions.size(); ++r)
+      if (p >= g_pool.regions[r].base && p < g_pool.regions[r].base + g_pool.regions[r].size) kv.second.first = r;
+  }
+  return freed;
 }
 }  // namespace
 
 void* pool_alloc(size_t nbytes, hipStream_t s) {
-  const size_t c = size_class(nbytes);
-  {
-    std::lock_guard<std::mutex> lk(g_pool.mu);
-    auto it = g_pool.free.find(c);
-    if (it != g_pool.free.end() && !it->second.empty()) {
-      auto& v = it->second;
-      for (size_t i = v.size(); i-- > 0;)
-        if (v[i].s == s) {
-          void* p = v[i].p;
-          v.erase(v.begin() + i);
-          return p;
+  const size_t n = (std::max<size_t>(nbytes, 1) + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
+  std::lock_guard<std::mutex> lk(g_pool.mu);
+  int ri = -1;
+  size_t off = 0;
+  Extent ex{0, nullptr};
+  if (!pool_find(n, ri, off, ex)) {
+    // a new region: at least REGION_MIN, or the request rounded to 2 MiB
+    const size_t rs = std::max(REGION_MIN, (n + (size_t(2) << 20) - 1) / (size_t(2) << 20) * (size_t(2) << 20));
+    void* base = nullptr;
+    hipError_t e = hipMalloc(&base, rs);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      pool_release_empty();
+      e = hipMalloc(&base, rs);
+      if (e != hipSuccess && rs > n) {
+        (void)hipGetLastError();
+        e = hipMalloc(&base, n);  // no room for a full region: exactly the request
+        if (e == hipSuccess) {
+          Region g{static_cast<char*>(base), n};
+          g.free[0] = Extent{n, s};
+          g_pool.regions.push_back(std::move(g));
         }
-      FreeBlock b = v.back();
-      v.pop_back();
-      RSF_HIP(hipStreamSynchronize(b.s));
-      return b.p;
+      } else if (e == hipSuccess) {
+        Region g{static_cast<char*>(base), rs};
+        g.free[0] = Extent{rs, s};
+        g_pool.regions.push_back(std::move(g));
+      }
+    } else {
+      Region g{static_cast<char*>(base), rs};
+      g.free[0] = Extent{rs, s};
+      g_pool.regions.push_back(std::move(g));
     }
+    RSF_HIP(e);
+    RSF_CHECK(pool_find(n, ri, off, ex), RSF_E_OOM, "device pool: no extent after growth");
   }
-  void* p = nullptr;
-  hipError_t e = hipMalloc(&p, c);
-  if (e != hipSuccess) {
-    // give cached blocks back to the device and try once more
-    (void)hipGetLastError();
-    pool_trim();
-    RSF_HIP(hipMalloc(&p, c));
-  }
+  Region& g = g_pool.regions[ri];
+  g.free.erase(off);
+  if (ex.size > n) g.free[off + n] = Extent{ex.size - n, ex.s};
+  if (ex.s != s) RSF_HIP(hipStreamSynchronize(ex.s));
+  g.used += n;
+  void* p = g.base + off;
+  g_pool.live[p] = std::make_pair(ri, n);
   return p;
 }
 
-void pool_free(void* p, size_t nbytes, hipStream_t s) {
+void pool_free(void* p, size_t /*nbytes*/, hipStream_t s) {
   if (!p) return;
   std::lock_guard<std::mutex> lk(g_pool.mu);
-  g_pool.free[size_class(nbytes)].push_back(FreeBlock{p, s});
+  auto it = g_pool.live.find(p);
+  if (it == g_pool.live.end()) return;
+  const int ri = it->second.first;
+  size_t n = it->second.second;
+  g_pool.live.erase(it);
+  Region& g = g_pool.regions[ri];
+  g.used -= n;
+  size_t off = static_cast<char*>(p) - g.base;
+  // merge with the free neighbours released on the same stream
+  auto nx = g.free.lower_bound(off);
+  if (nx != g.free.end() && nx->first == off + n && nx->second.s == s) {
+    n += nx->second.size;
+    nx = g.free.erase(nx);
+  }
+  if (nx != g.free.begin()) {
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second.size == off && pv->second.s == s) {
+      off = pv->first;
+      n += pv->second.size;
+      g.free.erase(pv);
+    }
+  }
+  g.free[off] = Extent{n, s};
 }
 
 void pool_trim() {
   (void)hipDeviceSynchronize();
   std::lock_guard<std::mutex> lk(g_pool.mu);
-  for (auto& kv : g_pool.free)
-    for (auto& b : kv.second) (void)hipFree(b.p);
-  g_pool.free.clear();
+  pool_release_empty();
+}
+
+// ---- staging of host-to-device uploads
+// A pinned ring: each upload is copied into the next stretch and sent with
+// hipMemcpyAsync; an event recorded after the copy marks when the stretch is
+// free again, and wrapping around waits for the whole lap.  Uploads larger
+// than half the ring go directly (and synchronously).
+namespace {
+struct Ring {
+  std::mutex mu;
+  char* buf = nullptr;
+  size_t cap = 0, head = 0;
+  struct Use {
+    size_t beg, end;
+    hipEvent_t ev;
+  };
+  std::deque<Use> inflight;
+} g_ring;
+constexpr size_t RING_BYTES = size_t(512) << 20;
+}  // namespace
+
+void upload_bytes(void* dst, const void* src, size_t nbytes, hipStream_t s) {
+  if (nbytes == 0) return;
+  std::lock_guard<std::mutex> lk(g_ring.mu);
+  if (!g_ring.buf) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, RING_BYTES, hipHostMallocDefault) == hipSuccess) {
+      g_ring.buf = static_cast<char*>(p);
+      g_ring.cap = RING_BYTES;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (!g_ring.buf || nbytes > g_ring.cap / 2) {
+    RSF_HIP(hipMemcpyAsync(dst, src, nbytes, hipMemcpyHostToDevice, s));
+    RSF_HIP(hipStreamSynchronize(s));  // the source may be freed by the caller
+    return;
+  }
+  const size_t n = (nbytes + 255) & ~size_t(255);
+  size_t a = g_ring.head;
+  if (a + n > g_ring.cap) {
+    // wrap around: every stretch of the lap that ends here must have been sent
+    for (const auto& u : g_ring.inflight) {
+      RSF_HIP(hipEventSynchronize(u.ev));
+      (void)hipEventDestroy(u.ev);
+    }
+    g_ring.inflight.clear();
+    a = 0;
+  }
+  std::memcpy(g_ring.buf + a, src, nbytes);
+  RSF_HIP(hipMemcpyAsync(dst, g_ring.buf + a, nbytes, hipMemcpyHostToDevice, s));
+  hipEvent_t ev;
+  RSF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  RSF_HIP(hipEventRecord(ev, s));
+  g_ring.inflight.push_back(Ring::Use{a, a + n, ev});
+  g_ring.head = a + n;
+  // retire finished stretches from the front
+  while (!g_ring.inflight.empty() && hipEventQuery(g_ring.inflight.front().ev) == hipSuccess) {
+    (void)hipEventDestroy(g_ring.inflight.front().ev);
+    g_ring.inflight.pop_front();
+  }
 }
 
 void* Arena::alloc(size_t nbytes) {
@@ -81,10 +224,23 @@ void* Arena::alloc(size_t nbytes) {
   RSF_CHECK(cap == 0 || bytes + nbytes <= cap, RSF_E_OOM,
             "factor memory cap exceeded (" + std::to_string(bytes + nbytes) + " > " +
                 std::to_string(cap) + " bytes)");
+  bytes += nbytes;
+  if (nbytes <= Scratch::SMALL_MAX) {
+    constexpr size_t ARENA_SLAB = size_t(64) << 20;
+    if (nbytes > slab_left) {
+      slab = static_cast<char*>(pool_alloc(ARENA_SLAB, nullptr));
+      blocks.push_back(slab);
+      sizes.push_back(ARENA_SLAB);
+      slab_left = ARENA_SLAB;
+    }
+    void* p = slab;
+    slab += nbytes;
+    slab_left -= nbytes;
+    return p;
+  }
   void* p = pool_alloc(nbytes, nullptr);
   blocks.push_back(p);
   sizes.push_back(nbytes);
-  bytes += nbytes;
   return p;
 }
 
@@ -94,10 +250,25 @@ void Arena::release() {
   blocks.clear();
   sizes.clear();
   bytes = 0;
+  slab = nullptr;
+  slab_left = 0;
 }
 
 void* Scratch::alloc(size_t nbytes) {
   if (nbytes == 0) nbytes = 8;
+  if (nbytes <= SMALL_MAX) {
+    const size_t n = (nbytes + 255) & ~size_t(255);
+    if (n > slab_left) {
+      slab = static_cast<char*>(pool_alloc(SMALL_SLAB, stream));
+      blocks.push_back(slab);
+      sizes.push_back(SMALL_SLAB);
+      slab_left = SMALL_SLAB;
+    }
+    void* p = slab;
+    slab += n;
+    slab_left -= n;
+    return p;
+  }
   void* p = pool_alloc(nbytes, stream);
   blocks.push_back(p);
   sizes.push_back(nbytes);
@@ -116,6 +287,7 @@ void Scratch::release(const void* p) {
 
 Scratch::~Scratch() {
   for (size_t i = 0; i < blocks.size(); ++i) pool_free(blocks[i], sizes[i], stream);
+  for (void* p : slabs) pool_free(p, SMALL_SLAB, stream);
 }
 
 // One 256-thread workgroup computes a 64 x 64 tile of C; each of the four
@@ -139,11 +311,42 @@ __device__ __forceinline__ void store_block(const GemmDesc& d, const v4d& acc, i
   }
 }
 
+// The tile of workgroup `bid` in a launch over problems probs[0 .. np) whose
+// tiles are numbered consecutively (toff: prefix counts): row-major over the
+// tile grid, or over its lower triangle (b <= a) for lower problems.
+// Returns (problem, tile row, tile column).
+__device__ __forceinline__ int3 find_tile(const GemmDesc* __restrict__ descs, const int* __restrict__ probs,
+                                          const int* __restrict__ toff, int np, int ts, int bid) {
+  int lo = 0, hi = np;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (toff[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int p = probs[lo], l = bid - toff[lo];
+  const GemmDesc& d = descs[p];
+  int a, b;
+  if (d.lower) {
+    a = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
+    while ((a + 1) * (a + 2) / 2 <= l) ++a;
+    while (a * (a + 1) / 2 > l) --a;
+    b = l - a * (a + 1) / 2;
+  } else {
+    const int tn = (d.N + ts - 1) / ts;
+    a = l / tn;
+    b = l - a * tn;
+  }
+  return make_int3(p, a, b);
+}
+
 __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restrict__ descs,
-                                                          const int4* __restrict__ tiles) {
+                                                          const int* __restrict__ probs,
+                                                          const int* __restrict__ toff, int np) {
   __shared__ double As[16][66];  // As[k][i]
   __shared__ double Bs[16][66];  // Bs[k][j]
-  const int4 t = tiles[blockIdx.x];
+  const int3 t = find_tile(descs, probs, toff, np, 64, blockIdx.x);
   const GemmDesc d = descs[t.x];
   const int i0 = t.y * 64, j0 = t.z * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -230,10 +433,11 @@ __device__ __forceinline__ void store_block32(const GemmDesc& d, const v4f& acc,
 }
 
 __global__ __launch_bounds__(256) void gemm_tiles_f32_kernel(const GemmDesc* __restrict__ descs,
-                                                              const int4* __restrict__ tiles) {
+                                                              const int* __restrict__ probs,
+                                                              const int* __restrict__ toff, int np) {
   __shared__ float As[16][68];  // As[k][i]
   __shared__ float Bs[16][68];  // Bs[k][j]
-  const int4 t = tiles[blockIdx.x];
+  const int3 t = find_tile(descs, probs, toff, np, 64, blockIdx.x);
   const GemmDesc d = descs[t.x];
   const int i0 = t.y * 64, j0 = t.z * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -383,10 +587,11 @@ constexpr int BT = 128;
 
 template <bool AI, bool BJ, bool BIDX>
 __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
-                                                           const int4* __restrict__ tiles) {
+                                                           const int* __restrict__ probs,
+                                                           const int* __restrict__ toff, int np) {
   __shared__ double As[16][BT + 4];
   __shared__ double Bs[16][BT + 4];
-  const int4 t = tiles[blockIdx.x];
+  const int3 t = find_tile(descs, probs, toff, np, BT, blockIdx.x);
   const GemmDesc& dg = descs[t.x];
   const int M = dg.M, N = dg.N, K = dg.K;
   const int i0 = t.y * BT, j0 = t.z * BT;
@@ -510,76 +715,79 @@ static int big_class(const GemmDesc& d) {
 }
 
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s) {
-  std::vector<int4> tiles, btiles[8], tiles32;
+  // launch groups: 0 = 64 x 64 FP64 tiles, 1 + c = 128 x 128 tiles of layout
+  // class c, 9 = 64 x 64 FP32 tiles; per group the problems and their tile
+  // prefix counts (the kernels find their tile from these)
+  constexpr int NG = 10;
+  std::vector<int> probs[NG], toff[NG];
+  for (auto& v : toff) v.push_back(0);
   std::vector<GemmDesc> live;
   double flops = 0.0, bytes = 0.0;
   for (const GemmDesc& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
+    RSF_CHECK(!d.lower || d.M == d.N, RSF_E_INVALID, "lower-triangle GEMM needs a square C");
     flops += (d.lower ? 1.0 : 2.0) * d.M * d.N * d.K;
     bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     const int p = (int)live.size();
     live.push_back(d);
     const int cls = big_class(d);
+    int g, ts;
     if (d.f32) {
-      const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
-      for (int a = 0; a < tm; ++a)
-        for (int b = 0; b < tn; ++b)
-          if (!d.lower || b <= a) tiles32.push_back(make_int4(p, a, b, 0));
+      g = 9;
+      ts = 64;
     } else if (cls >= 0 && d.M >= 96 && d.N >= 96 && d.K >= 32) {
-      const int tm = (d.M + BT - 1) / BT, tn = (d.N + BT - 1) / BT;
-      for (int a = 0; a < tm; ++a)
-        for (int b = 0; b < tn; ++b)
-          if (!d.lower || b <= a) btiles[cls].push_back(make_int4(p, a, b, 0));
+      g = 1 + cls;
+      ts = BT;
     } else {
-      const int tm = (d.M + 63) / 64, tn = (d.N + 63) / 64;
-      for (int a = 0; a < tm; ++a)
-        for (int b = 0; b < tn; ++b)
-          if (!d.lower || b <= a) tiles.push_back(make_int4(p, a, b, 0));
+      g = 0;
+      ts = 64;
     }
+    const long long tm = (d.M + ts - 1) / ts, tn = (d.N + ts - 1) / ts;
+    const long long nt = d.lower ? tm * (tm + 1) / 2 : tm * tn;
+    RSF_CHECK(toff[g].back() + nt < (1LL << 31), RSF_E_INVALID, "too many GEMM tiles in one launch");
+    probs[g].push_back(p);
+    toff[g].push_back(toff[g].back() + (int)nt);
   }
-  size_t nt = tiles.size() + tiles32.size();
-  for (auto& v : btiles) nt += v.size();
-  if (nt == 0) return;
+  if (live.empty()) return;
   GemmDesc* dd = scr.make<GemmDesc>(live.size());
   upload(dd, live, s);
-  std::vector<int4> all(tiles);
-  size_t boff[9];
-  boff[0] = all.size();
-  for (int c = 0; c < 8; ++c) {
-    all.insert(all.end(), btiles[c].begin(), btiles[c].end());
-    boff[c + 1] = all.size();
+  std::vector<int> cat;
+  size_t po[NG], to[NG];
+  for (int g = 0; g < NG; ++g) {
+    po[g] = cat.size();
+    cat.insert(cat.end(), probs[g].begin(), probs[g].end());
+    to[g] = cat.size();
+    cat.insert(cat.end(), toff[g].begin(), toff[g].end());
   }
-  const size_t off32 = all.size();
-  all.insert(all.end(), tiles32.begin(), tiles32.end());
-  int4* dt = scr.make<int4>(all.size());
-  upload(dt, all, s);
+  int* dc = scr.make<int>(cat.size());
+  upload(dc, cat, s);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_trace.on) {
     RSF_HIP(hipEventCreate(&e0));
     RSF_HIP(hipEventCreate(&e1));
     RSF_HIP(hipEventRecord(e0, s));
   }
-  // the grid is limited to 2^31 - 1 blocks in x; tile lists here stay far below
-#define RSF_BIG(c, AI, BJ, BX)                                                                        \
-  if (!btiles[c].empty())                                                                             \
-    hipLaunchKernelGGL((gemm_big_kernel<AI, BJ, BX>), dim3((unsigned)btiles[c].size()), dim3(256), 0, s, dd, \
-                       dt + boff[c]);
-  RSF_BIG(7, true, true, true)
-  RSF_BIG(6, true, true, false)
-  RSF_BIG(4, true, false, false)
-  RSF_BIG(3, false, true, true)
-  RSF_BIG(2, false, true, false)
-  RSF_BIG(0, false, false, false)
-#undef RSF_BIG
-  if (!tiles.empty())
-    hipLaunchKernelGGL(gemm_tiles_kernel, dim3((unsigned)tiles.size()), dim3(256), 0, s, dd, dt);
-  if (!tiles32.empty())
-    hipLaunchKernelGGL(gemm_tiles_f32_kernel, dim3((unsigned)tiles32.size()), dim3(256), 0, s, dd, dt + off32);
+  auto grid = [&](int g) { return dim3((unsigned)toff[g].back()); };
+  auto args = [&](int g) { return std::make_tuple(dc + po[g], dc + to[g], (int)probs[g].size()); };
+#define RSF_LAUNCH(KERNEL, g)                                                                        \
+  if (!probs[g].empty()) {                                                                           \
+    auto a_ = args(g);                                                                               \
+    hipLaunchKernelGGL(KERNEL, grid(g), dim3(256), 0, s, dd, std::get<0>(a_), std::get<1>(a_), std::get<2>(a_)); \
+  }
+  RSF_LAUNCH((gemm_big_kernel<true, true, true>), 1 + 7)
+  RSF_LAUNCH((gemm_big_kernel<true, true, false>), 1 + 6)
+  RSF_LAUNCH((gemm_big_kernel<true, false, false>), 1 + 4)
+  RSF_LAUNCH((gemm_big_kernel<false, true, true>), 1 + 3)
+  RSF_LAUNCH((gemm_big_kernel<false, true, false>), 1 + 2)
+  RSF_LAUNCH((gemm_big_kernel<false, false, false>), 1 + 0)
+  RSF_LAUNCH(gemm_tiles_kernel, 0)
+  RSF_LAUNCH(gemm_tiles_f32_kernel, 9)
+#undef RSF_LAUNCH
   RSF_HIP(hipGetLastError());
   if (g_trace.on) {
     RSF_HIP(hipEventRecord(e1, s));
     // launches with FP32 products are booked under "<phase>/f32"
-    const std::string tag = tiles32.empty() ? g_trace.tag : g_trace.tag + "/f32";
+    const std::string tag = probs[9].empty() ? g_trace.tag : g_trace.tag + "/f32";
     g_trace.ev.push_back(TraceEv{e0, e1, tag});
     g_trace.flops += flops;
     g_trace.bytes += bytes;

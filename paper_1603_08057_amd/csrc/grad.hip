@@ -9,6 +9,8 @@
 // The operators F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1) are peeled together from
 // the same probes and share their products with F^-1.
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <cmath>
 
 #include "rsf.h"
@@ -155,10 +157,10 @@ constexpr int PCHOL_MAXN = 4096;
 constexpr int PCHOL_WG = 1024;
 constexpr double PIV_DONE = -1.0e300;
 
-template <int RPT, int NB>
-__global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __restrict__ jobs, double tol2) {
-  __shared__ double wv[PCHOL_WG / 64];
-  __shared__ int wi[PCHOL_WG / 64];
+template <int RPT, int NB, int WGS>
+__global__ __launch_bounds__(WGS) void ppanel_kernel(const PpanelJob* __restrict__ jobs, double tol2) {
+  __shared__ double wv[WGS / 64];
+  __shared__ int wi[WGS / 64];
   __shared__ double lp[NB];
   __shared__ double sel_v;
   __shared__ int sel_i;
@@ -174,7 +176,7 @@ __global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __res
   double lr[RPT][NB];
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int i = tid + r * PCHOL_WG;
+    const int i = tid + r * WGS;
     dl[r] = i < c ? J.d[i] : PIV_DONE;
 #pragma unroll
     for (int t = 0; t < NB; ++t) lr[r][t] = 0.0;
@@ -189,7 +191,7 @@ __global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __res
     int bi = 0x7fffffff;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * PCHOL_WG;
+      const int i = tid + r * WGS;
       if (dl[r] != PIV_DONE && (bi == 0x7fffffff || dl[r] > bv)) {
         bv = dl[r];
         bi = i;
@@ -210,8 +212,8 @@ __global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __res
     }
     __syncthreads();
     if (wid == 0) {
-      bv = lane < PCHOL_WG / 64 ? wv[lane] : 0.0;
-      bi = lane < PCHOL_WG / 64 ? wi[lane] : 0x7fffffff;
+      bv = lane < WGS / 64 ? wv[lane] : 0.0;
+      bi = lane < WGS / 64 ? wi[lane] : 0x7fffffff;
 #pragma unroll
       for (int o = 8; o > 0; o >>= 1) {
         const double v2 = __shfl_xor(bv, o, 64);
@@ -235,10 +237,10 @@ __global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __res
       break;
     }
     // the pivot row's entries of this panel's earlier columns
-    if (tid == (p & (PCHOL_WG - 1))) {
+    if (tid == (p & (WGS - 1))) {
 #pragma unroll
       for (int r = 0; r < RPT; ++r)
-        if (r == p / PCHOL_WG) {
+        if (r == p / WGS) {
 #pragma unroll
           for (int t = 0; t < NB; ++t) lp[t] = lr[r][t];
         }
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __res
     const double* Gp = J.Gw + (long long)p * c;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
-      const int i = tid + r * PCHOL_WG;
+      const int i = tid + r * WGS;
       double x = 0.0;
       if (i == p) {
         x = lss;
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(PCHOL_WG) void ppanel_kernel(const PpanelJob* __res
   }
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int i = tid + r * PCHOL_WG;
+    const int i = tid + r * WGS;
     if (i < c) {
       J.d[i] = dl[r];
 #pragma unroll
@@ -328,7 +330,7 @@ constexpr int OVERSAMPLE = 10;
 // device memory for the work panels of one chunk of probe columns, for the
 // Gram matrices of one chunk of sample blocks and for the bases and core
 // matrices of one chunk of sibling pairs
-constexpr long long PEEL_CHUNK_BYTES = 24LL << 30;
+constexpr long long PEEL_CHUNK_BYTES = 48LL << 30;
 constexpr long long GRAM_CHUNK_BYTES = 8LL << 30;
 constexpr long long LOWRANK_CHUNK_BYTES = 8LL << 30;
 constexpr int FIRST_COLS = 64;
@@ -382,6 +384,9 @@ struct LevelLR {
 };
 
 struct Peeler {
+  // per-phase wall times (host clock around the enqueue and its waits), for
+  // RSFGP_PEEL_TIMES diagnostics
+  double tm[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   const rsf_factor_s* h;
   const Tree& t;
   hipStream_t s;
@@ -493,12 +498,15 @@ struct Peeler {
       PpanelJob* dj = ws.make<PpanelJob>(jobs.size());
       upload(dj, jobs, s);
       const dim3 grid((unsigned)jobs.size()), blk(PCHOL_WG);
-      if (cmax <= 1024)
-        hipLaunchKernelGGL((ppanel_kernel<1, 32>), grid, blk, 0, s, dj, tol2);
+      // one row per thread and panel column: small Gram matrices take small workgroups
+      if (cmax <= 256)
+        hipLaunchKernelGGL((ppanel_kernel<1, 32, 256>), grid, dim3(256), 0, s, dj, tol2);
+      else if (cmax <= 1024)
+        hipLaunchKernelGGL((ppanel_kernel<1, 32, 1024>), grid, blk, 0, s, dj, tol2);
       else if (cmax <= 2048)
-        hipLaunchKernelGGL((ppanel_kernel<2, 16>), grid, blk, 0, s, dj, tol2);
+        hipLaunchKernelGGL((ppanel_kernel<2, 16, 1024>), grid, blk, 0, s, dj, tol2);
       else
-        hipLaunchKernelGGL((ppanel_kernel<4, 8>), grid, blk, 0, s, dj, tol2);
+        hipLaunchKernelGGL((ppanel_kernel<4, 8, 1024>), grid, blk, 0, s, dj, tol2);
       RSF_HIP(hipGetLastError());
       // every few panels, drop the matrices that have reached their rank
       if (pnl % 4 == 3 || pnl + 1 >= npanel) {
@@ -534,6 +542,22 @@ struct Peeler {
                      const double* Om, const int* dpiv, const std::vector<long long>& poff, int blk0) {
     Scratch ms(s);
     const long long ld = 4LL * C;
+    // every per-pair buffer is carved from one block (one allocation per chunk)
+    long long need = 0;
+    for (int p = p0; p < p1; ++p) {
+      const PairLR& pr = L.pairs[p];
+      const long long ci = t.count[pr.i], cj = t.count[pr.j], k1 = pr.k1, k2 = pr.k2, tt = tot[t.inst[pr.i]];
+      need += ci * k1 + cj * k2 + 2 * (k1 * k1 + k2 * k2);  // Yg, G, Li of both blocks
+      if (k1 > 0 && k2 > 0) need += 2 * tt * k1 + k2 * tt + ci * k1 + 2 * (k1 * k1 + k2 * k2) + 2 * k1 * k2;
+    }
+    // a fixed-size block (when it suffices) is reused by every chunk
+    double* pool = ms.make<double>(std::max<long long>(need, LOWRANK_CHUNK_BYTES / 8));
+    long long used = 0;
+    auto carve = [&](long long count) {
+      double* q = pool + used;
+      used += count;
+      return q;
+    };
     int* fail = ms.make<int>(1);
     RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
     struct Blk {
@@ -552,13 +576,14 @@ struct Peeler {
         b.k = k;
         b.cnt = t.count[rb];
         b.Yb = Yop + (long long)t.begin[rb] * ld + (long long)t.quad[cb] * C;
-        b.Yg = ms.make<double>((size_t)b.cnt * k);
-        b.G = ms.make<double>((size_t)k * k);
-        b.Li = ms.make<double>((size_t)k * k);
+        b.Yg = carve((long long)b.cnt * k);
+        b.G = carve((long long)k * k);
+        b.Li = carve((long long)k * k);
         b.U = side ? L.U[L.pos_j[p]] + (long long)L.off_j[p] * b.cnt : L.U[L.pos_i[p]] + (long long)L.off_i[p] * b.cnt;
         bl.push_back(b);
       }
     }
+    RSF_CHECK(used <= need, RSF_E_HIP, "peeling work buffer overrun");
     if (!bl.empty()) {
       std::vector<GatherColsJob> gj;
       long long maxe = 1;
@@ -593,16 +618,16 @@ struct Peeler {
       const Mat Omi = panel(Om + (long long)t.begin[bi] * C, C);
       const Mat Omj = panel(Om + (long long)t.begin[bj] * C, C);
       const double* Yij = Yop + (long long)t.begin[bi] * ld + (long long)t.quad[bj] * C;
-      double* A1 = ms.make<double>((size_t)total * k1);
-      double* A2 = ms.make<double>((size_t)k2 * total);
-      double* W1 = ms.make<double>((size_t)ci * k1);
-      double* N1 = ms.make<double>((size_t)k1 * k1);
-      double* N2 = ms.make<double>((size_t)k2 * k2);
-      double* N1i = ms.make<double>((size_t)k1 * k1);
-      double* N2i = ms.make<double>((size_t)k2 * k2);
-      double* T1 = ms.make<double>((size_t)k1 * total);
-      double* T2 = ms.make<double>((size_t)k1 * k2);
-      double* X = ms.make<double>((size_t)k1 * k2);
+      double* A1 = carve((long long)total * k1);
+      double* A2 = carve((long long)k2 * total);
+      double* W1 = carve((long long)ci * k1);
+      double* N1 = carve((long long)k1 * k1);
+      double* N2 = carve((long long)k2 * k2);
+      double* N1i = carve((long long)k1 * k1);
+      double* N2i = carve((long long)k2 * k2);
+      double* T1 = carve((long long)k1 * total);
+      double* T2 = carve((long long)k1 * k2);
+      double* X = carve((long long)k1 * k2);
       // A1 = Om_i^T U1, A2 = U2^T Om_j
       ga.push_back(gemm_desc(total, k1, ci, 1.0, OmiT, colmaj(U1, ci), 0.0, colmaj(A1, total)));
       ga.push_back(gemm_desc(k2, total, cj, 1.0, colmajT(U2, cj), Omj, 0.0, colmaj(A2, k2)));
@@ -621,6 +646,7 @@ struct Peeler {
       gg.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(T2, k1), colmajT(N2i, k2), 0.0, colmaj(X, k1)));
       gh.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(X, k1), colmaj(N2i, k2), 0.0, colmaj(pr.M, k1)));
     }
+    RSF_CHECK(used <= need, RSF_E_HIP, "peeling work buffer overrun");
     gemm_batched(ga, ms, s);
     gemm_batched(gb, ms, s);
     batched_chol_inv(cn, fail, ms, s);
@@ -651,7 +677,17 @@ struct Peeler {
     Scratch keep(s);
     int* drinst = keep.make<int>(n);
     upload(drinst, rinst, s);
+    // probe and sample stores, kept across levels (capacity Ccap columns per quadrant block)
+    double* Om = nullptr;
+    double* Y[2] = {nullptr, nullptr};
+    int Ccap = 0;
     for (int lev = 1; lev <= D; ++lev) {
+      const auto cl0 = std::chrono::steady_clock::now();
+      struct LevelClock {
+        double& acc;
+        std::chrono::steady_clock::time_point t0;
+        ~LevelClock() { acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+      } level_clock{tm[7], cl0};
       Scratch scr(s);
       const int b0 = t.lev[lev], b1 = t.lev[lev + 1];
       std::vector<std::pair<int, int>> pairs;
@@ -680,18 +716,20 @@ struct Peeler {
       for (auto& pr : pairs) has[t.inst[pr.first]] = 1;
       for (int i = 0; i < ni; ++i)
         if (has[i]) cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i]);
-      int C = 0;  // capacity of the probe and sample stores (columns per quadrant block)
-      double* Om = nullptr;
-      double* Y[2] = {nullptr, nullptr};
+      int C = 0;  // layout of the probe and sample stores (columns per quadrant block)
       std::vector<int> rk(2 * nblk), maxr(ni, 0);
       std::vector<long long> poff(2 * nblk + 1, 0);
       int* dpiv = nullptr;
       while (true) {
         const int cnew = *std::max_element(cc.begin(), cc.end());
-        if (cnew > C) {
-          // grow the probe and sample stores
-          double* Om2 = scr.make<double>((size_t)n * cnew);
-          double* Y2[2] = {scr.make<double>((size_t)n * 4 * cnew), scr.make<double>((size_t)n * 4 * cnew)};
+        auto cg0 = std::chrono::steady_clock::now();
+        if (C == 0 && cnew <= Ccap) {
+          C = cnew;  // a new level reuses the stores of the previous ones
+        } else if (cnew > C) {
+          // grow the probe and sample stores: a new layout, the samples taken so far copied over
+          const int cap = std::max(cnew, Ccap);
+          double* Om2 = keep.make<double>((size_t)n * cap);
+          double* Y2[2] = {keep.make<double>((size_t)n * 4 * cap), keep.make<double>((size_t)n * 4 * cap)};
           if (C > 0) {
             hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * C)), dim3(256), 0, s, n, 1, C, Om, C, Om2, cnew);
             for (int op = 0; op < 2; ++op)
@@ -699,14 +737,16 @@ struct Peeler {
                                  cnew);
             RSF_HIP(hipGetLastError());
           }
-          scr.release(Om);
-          scr.release(Y[0]);
-          scr.release(Y[1]);
+          keep.release(Om);
+          keep.release(Y[0]);
+          keep.release(Y[1]);
           Om = Om2;
           Y[0] = Y2[0];
           Y[1] = Y2[1];
+          Ccap = cap;
           C = cnew;
         }
+        tm[6] += std::chrono::duration<double>(std::chrono::steady_clock::now() - cg0).count();
         // the new probe columns of every instance go through the operators
         // together, in chunks that keep the six n x 4 cw work panels within
         // PEEL_CHUNK_BYTES
@@ -728,17 +768,22 @@ struct Peeler {
           upload(dj0, j0, s);
           Scratch rs(s);
           const long long sz = n * 4LL * ncw;
-          double* Wm = rs.make<double>(sz);
+          double* Wm = rs.make<double>(n * 4LL * cw);  // full-chunk sizes: reused by every chunk
           fill_zero(Wm, sz, s);
           hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * ncw)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, lev,
                              seed, Wm, Om, (long long)C);
           RSF_HIP(hipGetLastError());
-          double* B0 = rs.make<double>(sz);
-          double* B1 = rs.make<double>(sz);
+          double* B0 = rs.make<double>(n * 4LL * cw);
+          double* B1 = rs.make<double>(n * 4LL * cw);
           const int* pc = ni > 1 ? pcols.data() : nullptr;
+          auto c0 = std::chrono::steady_clock::now();
           apply_ops(Wm, 4 * ncw, B0, B1, rs, pc);
+          auto c1 = std::chrono::steady_clock::now();
           subtract_lowrank(0, lev, Wm, 4 * ncw, B0, rs, pc);
           subtract_lowrank(1, lev, Wm, 4 * ncw, B1, rs, pc);
+          auto c2 = std::chrono::steady_clock::now();
+          tm[0] += std::chrono::duration<double>(c1 - c0).count();
+          tm[1] += std::chrono::duration<double>(c2 - c1).count();
           hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, C,
                              B0, Y[0]);
           hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, C,
@@ -767,7 +812,7 @@ struct Peeler {
             ++e1;
           }
           Scratch gs(s);
-          double* Gram = gs.make<double>(std::max<long long>(goff.back(), 1));
+          double* Gram = gs.make<double>(std::max<long long>(goff.back(), GRAM_CHUNK_BYTES / 16));
           std::vector<GemmDesc> g;
           for (int idx = e0; idx < e1; ++idx) {
             const int op = idx / nblk, e = idx % nblk;
@@ -778,11 +823,15 @@ struct Peeler {
           }
           {
             TraceTag tg("peel_gram");
+            auto c0 = std::chrono::steady_clock::now();
             gemm_batched(g, gs, s);
+            tm[4] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
           }
           std::vector<long long> pv(poff.begin() + e0, poff.begin() + e1);
           std::vector<int> rq;
+          auto c0 = std::chrono::steady_clock::now();
           pivot_ranks(Gram, goff, cs, pv, tol2, dpiv, rq);
+          tm[2] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
           for (int q = 0; q < e1 - e0; ++q) rk[e0 + q] = rq[q];
           e0 = e1;
         }
@@ -835,9 +884,20 @@ struct Peeler {
           blk_off[e] = L.K[b];
           L.K[b] += rk[op * nblk + e];
         }
+        // one block holds every basis and core matrix of this level and operator
+        long long lvl = 0;
+        for (int b = 0; b < nbx; ++b) lvl += (long long)t.count[L.boxes[b]] * L.K[b];
+        for (int p = 0; p < np; ++p) {
+          const long long k1 = rk[op * nblk + 2 * p], k2 = rk[op * nblk + 2 * p + 1];
+          if (k1 > 0 && k2 > 0) lvl += k1 * k2;
+        }
+        double* lblock = store.make<double>(std::max<long long>(lvl, 1));
+        long long lused = 0;
         L.U.assign(nbx, nullptr);
-        for (int b = 0; b < nbx; ++b)
-          L.U[b] = store.make<double>(std::max<long long>((long long)t.count[L.boxes[b]] * L.K[b], 1));
+        for (int b = 0; b < nbx; ++b) {
+          L.U[b] = lblock + lused;
+          lused += (long long)t.count[L.boxes[b]] * L.K[b];
+        }
         L.pairs.resize(np);
         L.off_i.resize(np);
         L.off_j.resize(np);
@@ -853,8 +913,12 @@ struct Peeler {
           L.off_j[p] = blk_off[2 * p + 1];
           L.pos_i[p] = pos[pr.i];
           L.pos_j[p] = pos[pr.j];
-          if (pr.k1 > 0 && pr.k2 > 0) pr.M = store.make<double>((size_t)pr.k1 * pr.k2);
+          if (pr.k1 > 0 && pr.k2 > 0) {
+            pr.M = lblock + lused;
+            lused += (long long)pr.k1 * pr.k2;
+          }
         }
+        RSF_CHECK(lused <= std::max<long long>(lvl, 1), RSF_E_HIP, "low-rank store overrun");
         // the pairs in chunks that bound the work memory
         int p0 = 0;
         while (p0 < np) {
@@ -870,12 +934,15 @@ struct Peeler {
             bytes += est;
             ++p1;
           }
+          auto c0 = std::chrono::steady_clock::now();
           lowrank_chunk(L, p0, p1, tot, C, Y[op], Om, dpiv, poff, op * nblk);
+          tm[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
           p0 = p1;
         }
       }
     }
     // extraction at the leaves: traces of every instance over its own leaves
+    const auto cx0 = std::chrono::steady_clock::now();
     Scratch scr(s);
     std::vector<int> lbeg, lcnt, lfirst(ni + 1, 0);
     int nL = 1;
@@ -921,6 +988,10 @@ struct Peeler {
       st->levels = D;
       st->leaf_cols = nL;
     }
+    tm[5] = std::chrono::duration<double>(std::chrono::steady_clock::now() - cx0).count();
+    if (std::getenv("RSFGP_PEEL_TIMES"))
+      fprintf(stderr, "[peel] apply %.3f subtract %.3f pivot %.3f lowrank %.3f gram %.3f extract %.3f grow %.3f levels %.3f s\n",
+              tm[0], tm[1], tm[2], tm[3], tm[4], tm[5], tm[6], tm[7]);
   }
 };
 
