@@ -24,12 +24,36 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, HERE)
 
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
+DEFAULT = "c3_matern32_n65536"
+TRAFFIC = os.path.join(HERE, "profiles", "gemm_family_c3_matern32_n65536_traffic.json")
+FAMILY_SOURCES = ["paper_1603_08057_amd/csrc/gemm.hip", "paper_1603_08057_amd/csrc/sweep.hip",
+                  "paper_1603_08057_amd/csrc/common.h"]
 
 
-def cpu_baseline(spec, name, budget_s=20.0):
+def measured_traffic(launches_per_step):
+    """HBM bytes per launch of the kernel family from the committed FETCH_SIZE /
+    WRITE_SIZE counter runs (scaled by the copy-kernel calibration), or None
+    when the kernel sources changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(TRAFFIC))
+    except (OSError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for f in FAMILY_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("sources_sha256"):
+        return None
+    # the counted run holds the setup factorization and one step
+    return rec["family_hbm_bytes"] / (launches_per_step + rec["setup_launches_estimate"])
+
+
+def cpu_baseline(spec, name, budget_s=35.0):
     """The dense oracle (l and g by FP64 Cholesky) timed on the host on a
-    sample n chosen to take roughly budget_s, scaled to the workload's n by
-    the O(n^3) cost of the dense route."""
+    sample n of the same recipe: a 4096-point calibration run, then the
+    largest power-of-two n whose O(n^3) extrapolation stays within budget_s;
+    scaled to the workload's n by (n / m)^3."""
     import numpy as np
     from oracle import dense
     import workloads as W
@@ -38,17 +62,21 @@ def cpu_baseline(spec, name, budget_s=20.0):
         cores = len(os.sched_getaffinity(0))
     except Exception:
         pass
-    m = 2048
-    t = 0.0
-    while True:
+
+    def run(m):
         P = W.workload_points(name, m)
         z = W.gaussian(m, spec["w_seed"])
         t0 = time.time()
         dense.loglik_and_grad(P, z, spec["theta"], spec["kernel"], spec["alpha"], block=2048)
-        t = time.time() - t0
-        if t * 8 > budget_s or m * 2 > spec["n"]:
-            break
+        return time.time() - t0
+
+    m = 4096
+    t = run(m)
+    while t * 8 <= budget_s and m * 2 <= spec["n"]:
         m *= 2
+        t *= 8
+    if m > 4096:
+        t = run(m)
     scale = (spec["n"] / m) ** 3
     return {"value": 1.0 / (t * scale), "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": "dense FP64 oracle l+grad at n=%d (same recipe), %.2f s, scaled by (%d/%d)^3"
@@ -127,7 +155,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c3_matern32_n65536")
+    ap.add_argument("--workload", default=DEFAULT)
     ap.add_argument("--n", type=int, default=None, help="override n (same recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -214,9 +242,13 @@ def main():
                    "kernel": "matern32" if spec["kernel"] == 1 else spec["kernel"], "theta": list(theta),
                    "eps": spec["eps"], "eps_peel": spec["eps"], "leaf": spec["leaf"], "n_prox": spec["n_prox"],
                    "parallelism": "single GPU"},
-        "roofline": {"bound": "mfma", "kernel": "gemm_tiles_kernel (batched FP64 MFMA GEMM)",
+        "roofline": {"bound": "mfma",
+                     "kernel": "batched FP64 matrix-core products (gemm_big_kernel, gemm_tiles_kernel, "
+                               "box_sweep_kernel)",
                      "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS, "traffic": None,
+                     "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
+                     "traffic": measured_traffic(launches / args.steps) if not args.n and name == DEFAULT else None,
+                     "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
                      "launches": launches, "kernel_ms_per_step": ms / args.steps,
                      "flops_per_launch": flops / max(launches, 1),
                      "avg_launch_us": 1000.0 * ms / max(launches, 1),
