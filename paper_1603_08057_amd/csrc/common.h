@@ -199,6 +199,13 @@ struct TraceLaunch {
   TraceLaunch(hipStream_t st, double fl, double by);
   ~TraceLaunch();
 };
+// Suspends launch tracing while it is alive (work that is not part of the
+// computation, such as autotuning trials).
+struct TracePause {
+  bool was;
+  TracePause();
+  ~TracePause();
+};
 // Names the GEMM launches issued while it is alive (for the per-phase split).
 struct TraceTag {
   std::string prev;

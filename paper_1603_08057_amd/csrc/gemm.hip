@@ -522,6 +522,8 @@ struct GemmTrace {
 void trace_enable(bool on) { g_trace.on = on; }
 
 std::string trace_current() { return g_trace.tag; }
+TracePause::TracePause() : was(g_trace.on) { g_trace.on = false; }
+TracePause::~TracePause() { g_trace.on = was; }
 
 TraceLaunch::TraceLaunch(hipStream_t st, double fl, double by) : s(st), flops(fl), bytes(by) {
   if (!g_trace.on) return;

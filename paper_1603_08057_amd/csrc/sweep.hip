@@ -3,6 +3,11 @@
 // operator.  Vectors are row-major panels in tree order (row = DOF), so each
 // box's S and R rows are gathered / scattered through index maps inside one
 // batched matrix-core GEMM per step and level.
+#include <functional>
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "rsf.h"
 
 namespace rsf {
@@ -71,7 +76,7 @@ static void scatter_rows(const int* rows, long long nrows, const double* Tmp, in
 // LDS, applies the level's steps there with matrix-core products (the box's
 // dense blocks are read from global memory / L2) and scatters the rows back,
 // so the panel is read and written once per level instead of once per step.
-constexpr int BS_AMAX = 128;
+constexpr int BS_AMAX = 256;  // boxes up to 128 DOFs take 2 row blocks per wave, up to 256 take 4
 constexpr int BS_NCT = 32;
 constexpr int BS_KC = 8;  // k-steps per batch of operand loads
 enum BoxOp { BS_SOLVE_UP = 0, BS_SOLVE_DOWN = 1, BS_MULT_UP = 2, BS_MULT_DOWN = 3 };
@@ -82,53 +87,55 @@ enum BoxOp { BS_SOLVE_UP = 0, BS_SOLVE_DOWN = 1, BS_MULT_UP = 2, BS_MULT_DOWN = 
 __device__ __forceinline__ int bsi(int row, int col) { return row * BS_NCT + (col ^ ((row & 1) << 4)); }
 
 // acc[p][q] += sum_kk A(16 (wave + 4 p) + row, kk) B(row0 + kk, 16 q + col) for
-// the row blocks of this wave (M <= 128 rows in 8 blocks over 4 waves) and the
-// two 16-column blocks.  B must hold finite values in rows [row0 + K, row0 + K + 4).
-template <class AF>
-__device__ __forceinline__ void box_mm(int M, int K, AF A, const double* Bl, int row0, v4d (&acc)[2][2],
+// the RB row blocks of this wave (M <= 64 RB rows over 4 waves) and the two
+// 16-column blocks.  B must hold finite values in rows [row0 + K, row0 + K + 4).
+template <int RB, class AF>
+__device__ __forceinline__ void box_mm(int M, int K, AF A, const double* Bl, int row0, v4d (&acc)[RB][2],
                                        int wave, int lane) {
   if (16 * wave >= M) return;
-  const int i0 = 16 * wave + (lane & 15), i1 = i0 + 64;
-  const bool two = 16 * (wave + 4) < M;
   const int kl = lane >> 4, cl = lane & 15;
   // the A fragments of BS_KC k-steps are loaded together (one wait for the
   // global / L2 latency), then fed to the matrix cores
   for (int c0 = 0; c0 < K; c0 += 4 * BS_KC) {
-    double a0[BS_KC], a1[BS_KC];
+    double af[RB][BS_KC];
 #pragma unroll
-    for (int t = 0; t < BS_KC; ++t) {
-      const int kk = c0 + 4 * t + kl;
-      a0[t] = (kk < K && i0 < M) ? A(i0, kk) : 0.0;
-      a1[t] = (two && kk < K && i1 < M) ? A(i1, kk) : 0.0;
+    for (int p = 0; p < RB; ++p) {
+      const int i = 16 * (wave + 4 * p) + cl;
+#pragma unroll
+      for (int t = 0; t < BS_KC; ++t) {
+        const int kk = c0 + 4 * t + kl;
+        af[p][t] = (kk < K && i < M) ? A(i, kk) : 0.0;
+      }
     }
 #pragma unroll
     for (int t = 0; t < BS_KC; ++t) {
       if (c0 + 4 * t < K) {
         const int kk = c0 + 4 * t + kl;
         const double b0 = Bl[bsi(row0 + kk, cl)], b1 = Bl[bsi(row0 + kk, 16 + cl)];
-        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[t], b0, acc[0][0], 0, 0, 0);
-        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[t], b1, acc[0][1], 0, 0, 0);
-        if (two) {
-          acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[t], b1, acc[1][1], 0, 0, 0);
-        }
+#pragma unroll
+        for (int p = 0; p < RB; ++p)
+          if (16 * (wave + 4 * p) < M) {
+            acc[p][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[p][t], b0, acc[p][0], 0, 0, 0);
+            acc[p][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[p][t], b1, acc[p][1], 0, 0, 0);
+          }
       }
     }
   }
 }
 
-__device__ __forceinline__ void zero_acc(v4d (&acc)[2][2]) {
+template <int RB>
+__device__ __forceinline__ void zero_acc(v4d (&acc)[RB][2]) {
 #pragma unroll
-  for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < RB; ++p)
 #pragma unroll
     for (int q = 0; q < 2; ++q) acc[p][q] = v4d{0.0, 0.0, 0.0, 0.0};
 }
 
 // Calls f(row, col, value) for every accumulator entry with row < M.
-template <class EF>
-__device__ __forceinline__ void box_epilogue(int M, const v4d (&acc)[2][2], int wave, int lane, EF f) {
+template <int RB, class EF>
+__device__ __forceinline__ void box_epilogue(int M, const v4d (&acc)[RB][2], int wave, int lane, EF f) {
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
+  for (int p = 0; p < RB; ++p) {
     const int rb = 16 * (wave + 4 * p);
     if (rb >= M) continue;
 #pragma unroll
@@ -141,7 +148,7 @@ __device__ __forceinline__ void box_epilogue(int M, const v4d (&acc)[2][2], int 
   }
 }
 
-template <int OP>
+template <int OP, int RB>
 __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict__ boxes, int nbox,
                                                         const int* __restrict__ tile_off,
                                                         const int* __restrict__ box_cols,
@@ -198,7 +205,7 @@ __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict
     for (int e = tid; e < 4 * BS_NCT; e += 256) Tl[bsi(r + e / BS_NCT, e % BS_NCT)] = 0.0;
   }
   __syncthreads();
-  v4d acc[2][2];
+  v4d acc[RB][2];
   if (OP == BS_SOLVE_UP) {
     // X_R -= T^T X_S
     zero_acc(acc);
@@ -312,22 +319,33 @@ static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int o
   const long long grid = ((long long)toff[L.nb] + 7) / 8 * 8;
   const dim3 g((unsigned)grid), blk(256);
   TraceLaunch tl(s, fl, by);
-  // the largest box needs more than the default dynamic LDS limit of 64 KiB
-  static bool lds_set[4] = {false, false, false, false};
+  // the largest boxes need more than the default dynamic LDS limit of 64 KiB
+  static bool lds_set[4][2] = {{false, false}, {false, false}, {false, false}, {false, false}};
   const int max_lds = 2 * (BS_AMAX + 4) * BS_NCT * (int)sizeof(double);
-#define RSF_BOX(OPV)                                                                                          \
-  if (!lds_set[OPV]) {                                                                                        \
-    RSF_HIP(hipFuncSetAttribute((const void*)box_sweep_kernel<OPV>,                                          \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));                        \
-    lds_set[OPV] = true;                                                                                      \
-  }                                                                                                           \
-  hipLaunchKernelGGL(box_sweep_kernel<OPV>, g, blk, lds, s, L.box, L.nb, dtoff, dcols, L.S, L.R, L.T, L.W, L.Lm, X, \
-                     Y, nc, ld, amax)
-  switch (op) {
-    case BS_SOLVE_UP: RSF_BOX(BS_SOLVE_UP); break;
-    case BS_SOLVE_DOWN: RSF_BOX(BS_SOLVE_DOWN); break;
-    case BS_MULT_UP: RSF_BOX(BS_MULT_UP); break;
-    default: RSF_BOX(BS_MULT_DOWN); break;
+#define RSF_BOX(OPV, RBV)                                                                                     \
+  {                                                                                                           \
+    if (!lds_set[OPV][RBV / 4]) {                                                                             \
+      RSF_HIP(hipFuncSetAttribute((const void*)box_sweep_kernel<OPV, RBV>,                                   \
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, max_lds));                      \
+      lds_set[OPV][RBV / 4] = true;                                                                           \
+    }                                                                                                         \
+    hipLaunchKernelGGL((box_sweep_kernel<OPV, RBV>), g, blk, lds, s, L.box, L.nb, dtoff, dcols, L.S, L.R, L.T, \
+                       L.W, L.Lm, X, Y, nc, ld, amax);                                                        \
+  }
+  if (amax <= 128) {
+    switch (op) {
+      case BS_SOLVE_UP: RSF_BOX(BS_SOLVE_UP, 2); break;
+      case BS_SOLVE_DOWN: RSF_BOX(BS_SOLVE_DOWN, 2); break;
+      case BS_MULT_UP: RSF_BOX(BS_MULT_UP, 2); break;
+      default: RSF_BOX(BS_MULT_DOWN, 2); break;
+    }
+  } else {
+    switch (op) {
+      case BS_SOLVE_UP: RSF_BOX(BS_SOLVE_UP, 4); break;
+      case BS_SOLVE_DOWN: RSF_BOX(BS_SOLVE_DOWN, 4); break;
+      case BS_MULT_UP: RSF_BOX(BS_MULT_UP, 4); break;
+      default: RSF_BOX(BS_MULT_DOWN, 4); break;
+    }
   }
 #undef RSF_BOX
   RSF_HIP(hipGetLastError());
@@ -384,6 +402,131 @@ static void level_gemm(const LevelFactor& L, const std::vector<int>& bc, int nc,
   gemm_batched(g, scr, s);
 }
 
+// The GEMM form of one level step of the solve and multiply sweeps (all
+// boxes of the level in one batched launch per product).
+static void gemm_step(const LevelFactor& L, const std::vector<int>& bc, int op, double* X, double* Y, int nc,
+                      long long ld, double* tmp, Scratch& scr, hipStream_t s) {
+  if (op == BS_SOLVE_UP) {
+    // X_R -= T^T X_S
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
+               RS, X, ld, 1.0, RR, X, ld, scr, s);
+    // tmp = L^-1 X_R
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
+               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
+    // X_S -= W tmp
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
+               RTMP, tmp, nc, 1.0, RS, X, ld, scr, s);
+    scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
+  } else if (op == BS_SOLVE_DOWN) {
+    // X_R -= W^T X_S
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
+               RS, X, ld, 1.0, RR, X, ld, scr, s);
+    // tmp = L^-T X_R
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lm + L.l_off[i], r); },
+               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
+    scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
+    // X_S -= T tmp
+    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
+               RTMP, tmp, nc, 1.0, RS, X, ld, scr, s);
+  } else if (op == BS_MULT_UP) {
+    // X_S += T X_R
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
+               RR, X, ld, 1.0, RS, X, ld, scr, s);
+    // Y_R += X_rr X_R + X_sr^T X_S
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
+               RR, X, ld, 1.0, RR, Y, ld, scr, s);
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
+               RS, X, ld, 1.0, RR, Y, ld, scr, s);
+  } else {
+    // Y_S += X_sr X_R  (after the coarser levels' L operators)
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
+               RR, X, ld, 1.0, RS, Y, ld, scr, s);
+    // Y_R += T^T Y_S
+    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
+               RS, Y, ld, 1.0, RR, Y, ld, scr, s);
+  }
+}
+
+// ---- autotuning of the level steps
+// Where both forms apply (every box of the level has at most BS_AMAX active
+// DOFs), the first step of a given shape (operation, boxes, largest box,
+// redundant DOFs, panel width rounded up to a power of two) runs both forms
+// on copies of the panels, timed with HIP events, and the faster one is kept
+// for every later step of that shape in the process.  The real step always
+// runs the chosen form, so repeated calls give bitwise equal results.
+namespace {
+struct TuneKey {
+  int op, nb, amax, ncb;
+  long long sr;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(op, nb, amax, ncb, sr) < std::tie(o.op, o.nb, o.amax, o.ncb, o.sr);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;  // 1: fused per-box kernel, 0: GEMM form
+
+float time_on(hipStream_t s, const std::function<void()>& fn) {
+  hipEvent_t e0, e1;
+  RSF_HIP(hipEventCreate(&e0));
+  RSF_HIP(hipEventCreate(&e1));
+  RSF_HIP(hipEventRecord(e0, s));
+  fn();
+  RSF_HIP(hipEventRecord(e1, s));
+  RSF_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  RSF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+}  // namespace
+
+static void level_step(const rsf_factor_s* h, const LevelFactor& L, const std::vector<int>& bc, int op, double* X,
+                       double* Y, int nc, long long ld, double* tmp, Scratch& scr, hipStream_t s) {
+  int amax = 0;
+  long long sr = 0;
+  for (int i = 0; i < L.nb; ++i) {
+    amax = std::max(amax, L.a[i]);
+    sr += L.a[i] - L.k[i];
+  }
+  if (L.nb == 0 || nc <= 0) return;
+  if (amax > BS_AMAX) {
+    gemm_step(L, bc, op, X, Y, nc, ld, tmp, scr, s);
+    return;
+  }
+  int ncb = 1;
+  while (ncb < nc) ncb <<= 1;
+  const TuneKey key{op, L.nb, amax, ncb, sr};
+  int path = -1;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) path = it->second;
+  }
+  if (path < 0) {
+    TracePause tp;
+    const long long sz = h->tree.n * ld;
+    Scratch ts(s);
+    double* Xc = ts.make<double>(sz);
+    double* Yc = Y ? ts.make<double>(sz) : nullptr;
+    auto reset = [&] {
+      copy_dev(Xc, X, sz, s);
+      if (Y) copy_dev(Yc, Y, sz, s);
+    };
+    reset();
+    const float tg = time_on(s, [&] { gemm_step(L, bc, op, Xc, Yc, nc, ld, tmp, ts, s); });
+    reset();
+    const float tf = time_on(s, [&] { box_sweep(L, bc, op, Xc, Yc, nc, ld, ts, s); });
+    path = tf < tg ? 1 : 0;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = path;
+  }
+  if (path == 1)
+    box_sweep(L, bc, op, X, Y, nc, ld, scr, s);
+  else
+    gemm_step(L, bc, op, X, Y, nc, ld, tmp, scr, s);
+}
+
 void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
                  hipStream_t s, const int* inst_cols) {
   TraceTag tag("sweep_solve");
@@ -396,17 +539,7 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "up");
     const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
-    if (box_sweep(L, bc, BS_SOLVE_UP, X, nullptr, nc, ld, scr, s)) continue;
-    // X_R -= T^T X_S
-    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
-               RS, X, ld, 1.0, RR, X, ld, scr, s);
-    // tmp = L^-1 X_R
-    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
-               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
-    // X_S -= W tmp
-    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
-               RTMP, tmp, nc, 1.0, RS, X, ld, scr, s);
-    scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
+    level_step(h, L, bc, BS_SOLVE_UP, X, nullptr, nc, ld, tmp, scr, s);
   }
   if (F.nroot > 0) {
     std::vector<GemmDesc> g1, g2;
@@ -426,17 +559,7 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "down");
     const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
-    if (box_sweep(L, bc, BS_SOLVE_DOWN, X, nullptr, nc, ld, scr, s)) continue;
-    // X_R -= W^T X_S
-    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
-               RS, X, ld, 1.0, RR, X, ld, scr, s);
-    // tmp = L^-T X_R
-    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lm + L.l_off[i], r); },
-               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
-    scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
-    // X_S -= T tmp
-    level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
-               RTMP, tmp, nc, 1.0, RS, X, ld, scr, s);
+    level_step(h, L, bc, BS_SOLVE_DOWN, X, nullptr, nc, ld, tmp, scr, s);
   }
 }
 
@@ -510,15 +633,7 @@ void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, dou
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "up");
     const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
-    if (box_sweep(L, bc, BS_MULT_UP, X, Y, nc, ld, scr, s)) continue;
-    // X_S += T X_R
-    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
-               RR, X, ld, 1.0, RS, X, ld, scr, s);
-    // Y_R += X_rr X_R + X_sr^T X_S
-    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
-               RR, X, ld, 1.0, RR, Y, ld, scr, s);
-    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
-               RS, X, ld, 1.0, RR, Y, ld, scr, s);
+    level_step(h, L, bc, BS_MULT_UP, X, Y, nc, ld, nullptr, scr, s);
   }
   if (F.nroot > 0) {
     std::vector<GemmDesc> g;
@@ -535,13 +650,7 @@ void sweep_apply_mult(const rsf_factor_s* h, const FactorData& F, double* X, dou
     const LevelFactor& L = F.levels[d];
     LevelTag lt(d, "down");
     const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
-    if (box_sweep(L, bc, BS_MULT_DOWN, X, Y, nc, ld, scr, s)) continue;
-    // Y_S += X_sr X_R  (after the coarser levels' L operators)
-    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
-               RR, X, ld, 1.0, RS, Y, ld, scr, s);
-    // Y_R += T^T Y_S
-    level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
-               RS, Y, ld, 1.0, RR, Y, ld, scr, s);
+    level_step(h, L, bc, BS_MULT_DOWN, X, Y, nc, ld, nullptr, scr, s);
   }
 }
 
