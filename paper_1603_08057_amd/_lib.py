@@ -74,6 +74,7 @@ def load():
         "rsf_logdet_batched": ([vp, dp], C.c_int),
         "rsf_loglik_batched": ([vp, C.POINTER(vp), dp, vp], C.c_int),
         "rsf_grad_batched": ([vp, C.POINTER(vp), C.c_double, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
+        "rsf_graph_state": ([vp, C.POINTER(C.c_int)], C.c_int),
         "rsf_trace_enable": ([C.c_int], C.c_int),
         "rsf_trace_read": ([dp, dp, dp, C.POINTER(C.c_int64), C.c_int], C.c_int),
         "rsf_trace_phases": ([C.c_char_p, C.c_size_t], C.c_int),
@@ -224,6 +225,14 @@ class Factor:
         _check(load().rsf_grad(self._h, C.c_void_p(z.data_ptr()), eps_peel, int(seed), g, C.byref(info),
                                _stream()))
         return [g[0], g[1], g[2]], info
+
+    @property
+    def graph_state(self):
+        """0: the log-likelihood graph is not recorded yet, 1: recorded (later
+        loglik calls replay it), -1: eager only."""
+        st = C.c_int()
+        _check(load().rsf_graph_state(self._h, C.byref(st)))
+        return st.value
 
     def tree_info(self, want_perm=False):
         info = TreeInfo()

@@ -2,6 +2,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 #include "rsf.h"
@@ -268,14 +270,109 @@ rsf_status rsf_apply_sqrt(rsf_factor f, const double* d_w, double* d_z, int64_t 
   });
 }
 
+namespace rsf {
+LoglikGraph::~LoglikGraph() {
+  if (exec) (void)hipGraphExecDestroy(exec);
+  mem.reset();
+  for (void* p : pinned) (void)hipHostFree(p);
+  if (cap) (void)hipStreamDestroy(cap);
+}
+}  // namespace rsf
+
+// The tree-order solve and dot products of loglik_all, recorded on stream s
+// into f->lgraph (after an eager call has tuned every level step of this
+// shape).  On any failure the capture is abandoned and the factor stays eager.
+static void capture_loglik(rsf_factor f, hipStream_t s) {
+  if (std::getenv("RSFGP_NO_GRAPH")) {
+    f->lgraph_state = -1;
+    return;
+  }
+  const Tree& t = f->tree;
+  const long long n = t.n;
+  std::unique_ptr<LoglikGraph> g(new LoglikGraph());
+  g->stream = s;
+  // recorded on a stream of its own (the legacy default stream cannot be
+  // captured); replays go to the caller's stream
+  RSF_HIP(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking));
+  const hipStream_t cs = g->cap;
+  // the graph's buffers are released in the caller's stream order (the
+  // recording stream is destroyed with the graph)
+  g->mem.reset(new Scratch(s));
+  Scratch& m = *g->mem;
+  g->zin = m.make<double>(n);
+  g->alpha = m.make<double>(n);
+  g->dots = m.make<double>(t.ninst);
+  double* Z = m.make<double>(n);
+  double* A = m.make<double>(n);
+  TracePause tp;
+  // every earlier use of the pool's memory has finished: allocations made
+  // while recording need no stream synchronisation
+  RSF_HIP(hipDeviceSynchronize());
+  std::string why;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (!ok) why = "begin capture";
+  if (ok) {
+    upload_capture_begin(&g->pinned);
+    pool_sync_free(true);
+    try {
+      to_panel(f, g->zin, n, Z, 1, 1, cs);
+      copy_dev(A, Z, n, cs);
+      sweep_solve(f, f->F, A, 1, 1, m, cs);
+      for (int i = 0; i < t.ninst; ++i)
+        device_dot(Z + t.ioff[i], A + t.ioff[i], t.ioff[i + 1] - t.ioff[i], g->dots + i, m, cs);
+      from_panel(f, A, 1, 1, g->alpha, n, cs);
+    } catch (const std::exception& e) {
+      ok = false;
+      why = e.what();
+    } catch (...) {
+      ok = false;
+      why = "exception";
+    }
+    pool_sync_free(false);
+    upload_capture_end();
+    hipGraph_t graph = nullptr;
+    const hipError_t ee = hipStreamEndCapture(cs, &graph);
+    if (ok && (ee != hipSuccess || !graph)) {
+      ok = false;
+      why = std::string("end capture: ") + hipGetErrorString(ee);
+    }
+    if (ok && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+      ok = false;
+      why = "instantiate";
+    }
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+  (void)hipGetLastError();
+  if (!ok && std::getenv("RSFGP_GRAPH_DEBUG")) fprintf(stderr, "[graph] not recorded: %s\n", why.c_str());
+  if (ok) {
+    f->lgraph = std::move(g);
+    f->lgraph_state = 1;
+  } else {
+    f->lgraph_state = -1;
+  }
+}
+
 // l_i = -1/2 z_i^T alpha_i - 1/2 log|F_i| - (n_i / 2) log 2 pi for every
 // instance, alpha = F^-1 z (eq. loglikelihood); d_z in caller order (all
 // instances concatenated).
 static void loglik_all(rsf_factor f, const double* d_z, double* out, double* d_alpha, hipStream_t s) {
-  Scratch scr(s);
   const Tree& t = f->tree;
   const long long n = t.n;
   const int ni = t.ninst;
+  const double log2pi = 1.8378770664093454835606594728112;
+  if (f->lgraph && f->lgraph->stream == s) {
+    LoglikGraph& g = *f->lgraph;
+    RSF_HIP(hipMemcpyAsync(g.zin, d_z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    RSF_HIP(hipGraphLaunch(g.exec, s));
+    std::vector<double> zt(ni);
+    RSF_HIP(hipMemcpyAsync(zt.data(), g.dots, ni * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (d_alpha) RSF_HIP(hipMemcpyAsync(d_alpha, g.alpha, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    RSF_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < ni; ++i)
+      out[i] = -0.5 * zt[i] - 0.5 * f->F.logdet[i] - 0.5 * (double)(t.ioff[i + 1] - t.ioff[i]) * log2pi;
+    return;
+  }
+  Scratch scr(s);
   double* Z = scr.make<double>(n);
   double* A = scr.make<double>(n);
   double* dot = scr.make<double>(ni);
@@ -289,9 +386,18 @@ static void loglik_all(rsf_factor f, const double* d_z, double* out, double* d_a
   RSF_HIP(hipMemcpyAsync(zt.data(), dot, ni * sizeof(double), hipMemcpyDeviceToHost, s));
   RSF_HIP(hipStreamSynchronize(s));
   if (d_alpha) from_panel(f, A, 1, 1, d_alpha, n, s);
-  const double log2pi = 1.8378770664093454835606594728112;
   for (int i = 0; i < ni; ++i)
     out[i] = -0.5 * zt[i] - 0.5 * f->F.logdet[i] - 0.5 * (double)(t.ioff[i + 1] - t.ioff[i]) * log2pi;
+  // later calls on this stream replay a recorded graph of the same work
+  if (f->lgraph_state == 0) capture_loglik(f, s);
+}
+
+rsf_status rsf_graph_state(rsf_factor f, int* state) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(state != nullptr, RSF_E_INVALID, "null output");
+    *state = f->lgraph_state;
+  });
 }
 
 // The caller's per-instance vectors, concatenated in caller order.

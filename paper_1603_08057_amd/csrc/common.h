@@ -37,6 +37,10 @@ struct Error : std::runtime_error {
 void* pool_alloc(size_t nbytes, hipStream_t s);
 void pool_free(void* p, size_t nbytes, hipStream_t s);
 void pool_trim();
+// true: the caller has synchronised the device, so reusing memory released
+// on another stream needs no stream synchronisation (used while recording a
+// graph, where such a synchronisation is not allowed)
+void pool_sync_free(bool on);
 
 struct Arena {
   std::vector<void*> blocks;
@@ -84,6 +88,10 @@ struct Scratch {
 // Host-to-device copy of launch descriptors and index lists, staged through a
 // pinned ring buffer so that the copy is asynchronous on stream s.
 void upload_bytes(void* dst, const void* src, size_t nbytes, hipStream_t s);
+// While a stream capture records a graph, uploads go through pinned blocks
+// that the graph keeps (appended to *pins) instead of the reusable ring.
+void upload_capture_begin(std::vector<void*>* pins);
+void upload_capture_end();
 
 template <class T>
 inline void upload(T* dst, const std::vector<T>& src, hipStream_t s) {

@@ -77,6 +77,9 @@ size_t pool_release_empty() {
 }
 }  // namespace
 
+static thread_local bool g_pool_no_sync = false;
+void pool_sync_free(bool on) { g_pool_no_sync = on; }
+
 void* pool_alloc(size_t nbytes, hipStream_t s) {
   const size_t n = (std::max<size_t>(nbytes, 1) + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
   std::lock_guard<std::mutex> lk(g_pool.mu);
@@ -116,7 +119,7 @@ void* pool_alloc(size_t nbytes, hipStream_t s) {
   Region& g = g_pool.regions[ri];
   g.free.erase(off);
   if (ex.size > n) g.free[off + n] = Extent{ex.size - n, ex.s};
-  if (ex.s != s) RSF_HIP(hipStreamSynchronize(ex.s));
+  if (ex.s != s && !g_pool_no_sync) RSF_HIP(hipStreamSynchronize(ex.s));
   g.used += n;
   void* p = g.base + off;
   g_pool.live[p] = std::make_pair(ri, n);
@@ -176,8 +179,20 @@ struct Ring {
 constexpr size_t RING_BYTES = size_t(512) << 20;
 }  // namespace
 
+static thread_local std::vector<void*>* g_capture_pins = nullptr;
+void upload_capture_begin(std::vector<void*>* pins) { g_capture_pins = pins; }
+void upload_capture_end() { g_capture_pins = nullptr; }
+
 void upload_bytes(void* dst, const void* src, size_t nbytes, hipStream_t s) {
   if (nbytes == 0) return;
+  if (g_capture_pins) {
+    void* p = nullptr;
+    RSF_HIP(hipHostMalloc(&p, nbytes, hipHostMallocDefault));
+    g_capture_pins->push_back(p);
+    std::memcpy(p, src, nbytes);
+    RSF_HIP(hipMemcpyAsync(dst, p, nbytes, hipMemcpyHostToDevice, s));
+    return;
+  }
   std::lock_guard<std::mutex> lk(g_ring.mu);
   if (!g_ring.buf) {
     void* p = nullptr;

@@ -91,6 +91,25 @@ struct Options {
 
 }  // namespace rsf
 
+namespace rsf {
+// The single-vector log-likelihood of a factor recorded once as a HIP graph
+// (gather into tree order, the solve sweep, the per-instance dot products,
+// the scatter of alpha) and replayed for later calls.  The graph owns the
+// device buffers and the pinned host copies of the launch descriptors it
+// reads.
+struct LoglikGraph {
+  hipGraphExec_t exec = nullptr;
+  hipStream_t stream = nullptr;  // the caller's stream the graph is replayed on
+  hipStream_t cap = nullptr;     // the stream it was recorded on
+  std::unique_ptr<Scratch> mem;
+  std::vector<void*> pinned;
+  double* zin = nullptr;    // caller order
+  double* alpha = nullptr;  // caller order
+  double* dots = nullptr;   // one per instance
+  ~LoglikGraph();
+};
+}  // namespace rsf
+
 struct rsf_factor_s {
   rsf::Tree tree;
   rsf::Options opt;
@@ -106,6 +125,8 @@ struct rsf_factor_s {
   double* prox_u = nullptr;  // device unit offsets of the proxy points (x then y)
   rsf::FactorData F;
   std::unique_ptr<rsf::FactorData> Frho;
+  std::unique_ptr<rsf::LoglikGraph> lgraph;
+  int lgraph_state = 0;  // 0: not yet, 1: captured, -1: capture failed (eager from then on)
 };
 
 namespace rsf {
