@@ -408,6 +408,74 @@ __global__ __launch_bounds__(256) void cpqr_big_update_tall_kernel(const CpqrJob
   reflect_columns(J.A, J.ld, m, s, j0, j1, J.v, J.scal[0], J.norms);
 }
 
+// T = R_11^-1 R_12 for the multi-workgroup path: one workgroup per eight
+// columns of R_12, held in registers (thread t owns rows t, t + 256, ...),
+// solved right-looking from the last row up.  Column i of R_11 is contiguous,
+// so each step reads it coalesced; it is fetched one step ahead.
+constexpr int TRSM_C = 8;
+
+template <int KQ>
+__global__ __launch_bounds__(256) void cpqr_trsm_kernel(const CpqrJob* __restrict__ jobs) {
+  __shared__ double xs[2][TRSM_C];
+  const CpqrJob J = jobs[blockIdx.x];
+  const int k = *J.kout, a = J.a, tid = threadIdx.x;
+  const int c0 = k + (int)blockIdx.y * TRSM_C;
+  if (k == 0 || c0 >= a) return;
+  const int nc = std::min(TRSM_C, a - c0);
+  const long long ld = J.ld;
+  double* A = J.A;
+  double b[KQ][TRSM_C], rc[KQ];
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int r = q * 256 + tid;
+#pragma unroll
+    for (int c = 0; c < TRSM_C; ++c) b[q][c] = (r < k && c < nc) ? A[(long long)(c0 + c) * ld + r] : 0.0;
+    rc[q] = (r < k) ? A[(long long)(k - 1) * ld + r] : 0.0;
+  }
+  int buf = 0;
+#pragma unroll
+  for (int q = KQ - 1; q >= 0; --q) {
+    const int ihi = std::min(k, (q + 1) * 256) - 1;
+    for (int i = ihi; i >= q * 256; --i) {
+      double rn[KQ];
+#pragma unroll
+      for (int qq = 0; qq < KQ; ++qq) {
+        const int r = qq * 256 + tid;
+        rn[qq] = (qq <= q && i > 0 && r < i) ? A[(long long)(i - 1) * ld + r] : 0.0;
+      }
+      if (tid == (i & 255)) {
+        const double d = rc[q];
+#pragma unroll
+        for (int c = 0; c < TRSM_C; ++c) {
+          b[q][c] = b[q][c] / d;
+          xs[buf][c] = b[q][c];
+        }
+      }
+      __syncthreads();
+      double x[TRSM_C];
+#pragma unroll
+      for (int c = 0; c < TRSM_C; ++c) x[c] = xs[buf][c];
+#pragma unroll
+      for (int qq = 0; qq <= q; ++qq) {
+        if (qq * 256 + tid < i) {
+#pragma unroll
+          for (int c = 0; c < TRSM_C; ++c) b[qq][c] -= x[c] * rc[qq];
+        }
+      }
+#pragma unroll
+      for (int qq = 0; qq < KQ; ++qq) rc[qq] = rn[qq];
+      buf ^= 1;
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KQ; ++q) {
+    const int r = q * 256 + tid;
+#pragma unroll
+    for (int c = 0; c < TRSM_C; ++c)
+      if (r < k && c < nc) A[(long long)(c0 + c) * ld + r] = b[q][c];
+  }
+}
+
 __global__ __launch_bounds__(256) void cpqr_backsub_kernel(const CpqrJob* __restrict__ jobs) {
   const CpqrJob J = jobs[blockIdx.x];
   const int k = *J.kout;
@@ -627,6 +695,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
   std::vector<int> ld_inst;
   int* fail = keep.make<int>(1);
   RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
+  const bool stats = std::getenv("RSFGP_FACTOR_STATS") != nullptr;
 
   for (int d = D; d >= 1; --d) {
     Scratch scr(s);
@@ -756,6 +825,12 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       RSF_HIP(hipGetLastError());
     }
     // interpolative decompositions
+    hipEvent_t ev_id[2] = {nullptr, nullptr};
+    if (stats) {
+      RSF_HIP(hipEventCreate(&ev_id[0]));
+      RSF_HIP(hipEventCreate(&ev_id[1]));
+      RSF_HIP(hipEventRecord(ev_id[0], s));
+    }
     int* piv = scr.make<int>(std::max<long long>(aoff[nb], 1));
     int* kout = scr.make<int>(nb);
     {
@@ -805,17 +880,48 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
             if (nd >= nb) break;
           }
         }
-        const int bchunks = std::max(1, std::min(16, ceil_div(maxa, 256)));
-        hipLaunchKernelGGL(cpqr_backsub_kernel, dim3(nb, bchunks), dim3(256), 0, s, dj);
+        // ranks are on the device: size the solve by the largest possible one
+        int kmax = 0;
+        for (int i = 0; i < nb; ++i) kmax = std::max<int>(kmax, (int)std::min<long long>(mub[i], L.a[i]));
+        const int tchunks = std::max(1, ceil_div(maxa, TRSM_C));
+        if (kmax <= 256)
+          hipLaunchKernelGGL(cpqr_trsm_kernel<1>, dim3(nb, tchunks), dim3(256), 0, s, dj);
+        else if (kmax <= 512)
+          hipLaunchKernelGGL(cpqr_trsm_kernel<2>, dim3(nb, tchunks), dim3(256), 0, s, dj);
+        else if (kmax <= 1024)
+          hipLaunchKernelGGL(cpqr_trsm_kernel<4>, dim3(nb, tchunks), dim3(256), 0, s, dj);
+        else if (kmax <= 2048)
+          hipLaunchKernelGGL(cpqr_trsm_kernel<8>, dim3(nb, tchunks), dim3(256), 0, s, dj);
+        else
+          hipLaunchKernelGGL(cpqr_backsub_kernel, dim3(nb, std::max(1, std::min(16, ceil_div(maxa, 256)))),
+                             dim3(256), 0, s, dj);
         RSF_HIP(hipGetLastError());
       }
     }
+    if (stats) RSF_HIP(hipEventRecord(ev_id[1], s));
     std::vector<int> kh(nb);
     RSF_HIP(hipMemcpyAsync(kh.data(), kout, nb * sizeof(int), hipMemcpyDeviceToHost, s));
     int fh = 0;
     RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
     RSF_HIP(hipStreamSynchronize(s));
     RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "redundant block not positive definite at depth " + std::to_string(d + 1));
+    if (stats) {
+      float ms = 0.f;
+      RSF_HIP(hipEventElapsedTime(&ms, ev_id[0], ev_id[1]));
+      RSF_HIP(hipEventDestroy(ev_id[0]));
+      RSF_HIP(hipEventDestroy(ev_id[1]));
+      long long sa = 0, sm = 0, sk = 0, ma = 0, mm = 0, mk = 0;
+      for (int i = 0; i < nb; ++i) {
+        sa += L.a[i];
+        sm += mub[i];
+        sk += kh[i];
+        ma = std::max<long long>(ma, L.a[i]);
+        mm = std::max<long long>(mm, mub[i]);
+        mk = std::max<long long>(mk, kh[i]);
+      }
+      fprintf(stderr, "[factor%s] depth %d boxes %d a mean %.0f max %lld  m<= mean %.0f max %lld  k mean %.0f max %lld  ID %.2f ms\n",
+              mult ? "_rho" : "", d, nb, (double)sa / nb, ma, (double)sm / nb, mm, (double)sk / nb, mk, ms);
+    }
     // factor storage
     L.k = kh;
     L.s_off.assign(nb + 1, 0);
