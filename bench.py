@@ -4,7 +4,8 @@ One step = one evaluation of Algorithm 1 for a parameter vector theta on fixed
 observation sites: build F ~= Sigma(theta) (quadtree, near fields, IDs,
 elimination, root), l(theta) from one solve and log|F|, then the score:
 F_rho (multiply-only skeletonization of dSigma/drho), the quadratic terms and
-the peeled traces of F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1).  Inputs are
+the peeled traces of B B^T = Tr F^-1 and B F_rho B^T = Tr F^-1 F_rho
+(F^-1 = B^T B).  Inputs are
 resident on the device before the timed region.
 
 Workload (default): n = 65536 sites uniform in [0,1]^2 (seed 31), Matern 3/2,

@@ -150,9 +150,10 @@ typedef struct {
  *   g_i = q_i - t_i / 2,  q_i = 1/2 alpha^T Sigma_i alpha,  t_i = Tr(F^-1 Sigma_i),
  * with Sigma_rho represented by its own skeletonization (multiply-only form),
  * Sigma_sigma2 = (Sigma - nugget I) / sigma2 and Sigma_nugget = I, and the
- * traces taken by matrix peeling (Section 3.2) of F^-1 and of
- * 1/2 (F^-1 F_rho + F_rho F^-1) (Algorithm 1, the symmetrized operator) to
- * relative tolerance eps_peel, with Gaussian probes from Philox4x32-10 keyed by
+ * traces taken by matrix peeling (Section 3.2) of symmetric operators with the
+ * traces of F^-1 and F^-1 F_rho (Section 3 allows any such symmetrized form):
+ * B B^T and B F_rho B^T for F^-1 = B^T B (B: the up half of the solve sweep),
+ * to relative tolerance eps_peel, with Gaussian probes from Philox4x32-10 keyed by
  * seed.
  *   d_z       device, n observations (caller's order).
  *   g         host, 3 values.

@@ -24,8 +24,8 @@ factorization (boxes are contiguous ranges of tree order):
   H = (G - sum_m G^(m)) E, and Tr G ~= sum over leaves of Tr H(I_i, 1:n_i).
 
 Several operators can be peeled together from the same probes (``applies``
-returns one product per operator), which is how F^-1 and
-1/2 (F^-1 F_rho + F_rho F^-1) share their products with F^-1.
+returns one product per operator), which is how B B^T and B F_rho B^T
+(F^-1 = B^T B) share the product B^T W.
 """
 import numpy as np
 import scipy.linalg as sla
@@ -56,17 +56,22 @@ def round8(c):
 
 def first_cols(n):
     """Probe count at the first peeled level: the top-level sibling blocks have
-    ranks that grow like sqrt(n) (Section 3.3), so 4.5 sqrt(n), at least
+    ranks that grow like sqrt(n) (Section 3.3), so 3 sqrt(n), at least
     FIRST_COLS, rounded up to a multiple of 8."""
     import math
-    return round8(max(FIRST_COLS, 9 * math.isqrt(n) // 2))
+    return round8(max(FIRST_COLS, 3 * math.isqrt(n)))
 
 
-def next_cols(prev_rank):
-    """Initial probe count per quadrant block at the next level: the largest
-    rank found above scaled by 0.85, plus the oversampling, at least MIN_COLS,
-    rounded up to a multiple of 8."""
-    c = (17 * prev_rank + 19) // 20 + OVERSAMPLE
+def next_cols(prev_rank, peeled):
+    """Initial probe count per quadrant block at the next level from the
+    largest rank found at the level above (peeled = levels peeled so far):
+    1.5x after the first peeled level (the second level's sibling blocks of
+    B F_rho B^T and B B^T have the larger ranks), 0.7x below it, plus the
+    oversampling, at least MIN_COLS, rounded up to a multiple of 8."""
+    if peeled == 1:
+        c = (3 * prev_rank + 1) // 2 + OVERSAMPLE
+    else:
+        c = (7 * prev_rank + 9) // 10 + OVERSAMPLE
     return round8(max(MIN_COLS, c))
 
 
@@ -113,6 +118,7 @@ class Peeler:
         t = self.t
         n = t.n
         prev = None
+        peeled = 0
         for lev in range(1, t.max_depth + 1):
             boxes = [int(b) for b in t.levels[lev]]
             pairs = []
@@ -125,7 +131,7 @@ class Peeler:
                 for op in range(self.nop):
                     self.blocks[op].append({})
                 continue
-            c = first_cols(n) if prev is None else next_cols(prev)
+            c = first_cols(n) if prev is None else next_cols(prev, peeled)
             total = 0
             Om = {b: np.zeros((t.count[b], 0)) for b in boxes}
             Y = [{b: np.zeros((t.count[b], 0)) for b in boxes} for _ in range(self.nop)]
@@ -162,6 +168,7 @@ class Peeler:
                     break
                 c = grow_cols(total, maxrank)
             prev = maxrank
+            peeled += 1
             self.cols[lev] = total
             self.ranks[lev] = maxrank
             for op in range(self.nop):

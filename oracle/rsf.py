@@ -346,6 +346,41 @@ class Factor:
             x[S] = x[S] - self.T[b] @ xr
         return x
 
+    def half_up(self, bvec):
+        """B b for F^-1 = B^T B: the up sweep of solve() followed by
+        L_root^-1 (the first half of the solve, Section 2.4).  B^T B = F^-1
+        because each box's down step is the transpose of its up step."""
+        assert self.mode == "chol"
+        x = np.array(bvec, dtype=np.float64, copy=True)
+        for b in self._boxes_up():
+            S, R = self.S[b], self.R[b]
+            if R.shape[0] == 0:
+                continue
+            xr = x[R] - self.T[b].T @ x[S]
+            cr = sla.solve_triangular(self.L[b], xr, lower=True)
+            x[S] = x[S] - self.W[b] @ cr
+            x[R] = cr
+        I = self.Iroot
+        if I.shape[0] > 0:
+            x[I] = sla.solve_triangular(self.Lroot, x[I], lower=True)
+        return x
+
+    def half_down(self, xvec):
+        """B^T x: L_root^-T, then the down sweep of solve()."""
+        assert self.mode == "chol"
+        x = np.array(xvec, dtype=np.float64, copy=True)
+        I = self.Iroot
+        if I.shape[0] > 0:
+            x[I] = sla.solve_triangular(self.Lroot, x[I], lower=True, trans="T")
+        for b in self._boxes_down():
+            S, R = self.S[b], self.R[b]
+            if R.shape[0] == 0:
+                continue
+            xr = sla.solve_triangular(self.L[b], x[R] - self.W[b].T @ x[S], lower=True, trans="T")
+            x[R] = xr
+            x[S] = x[S] - self.T[b] @ xr
+        return x
+
     def sqrt_t(self, xvec):
         """(F^(1/2))^T x."""
         x = np.array(xvec, dtype=np.float64, copy=True)
@@ -430,8 +465,11 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
       q_rho = 1/2 a^T F_rho a,  q_sigma2 = 1/2 (z^T a - nugget a^T a) / sigma2,
       q_nug = 1/2 a^T a            (a = F^-1 z, Sigma_sigma2 = (Sigma - nugget I) / sigma2)
       t_nug = Tr F^-1,  t_sigma2 = (n - nugget t_nug) / sigma2,
-      t_rho = Tr 1/2 (F^-1 F_rho + F_rho F^-1)   (both traces by peeling)
-      g_i = q_i - t_i / 2.
+      t_rho = Tr F^-1 F_rho,  g_i = q_i - t_i / 2.
+    Both traces are peeled from symmetric operators with the same traces
+    (Section 3 allows any symmetrized form with the trace of F^-1 F_rho): with
+    F^-1 = B^T B, Tr F^-1 = Tr B B^T and Tr F^-1 F_rho = Tr B F_rho B^T, and the
+    two operators share the product B^T W.
     Returns a dict (user order for vectors)."""
     from . import peel
     eps_peel = eps if eps_peel is None else eps_peel
@@ -452,9 +490,8 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
     q = np.array([0.5 * float(a @ Fr.apply(a)), 0.5 * (za - nug * aa) / s2, 0.5 * aa])
 
     def applies(Wm):
-        X = F.solve(Wm)
-        V = Fr.apply(Wm)
-        return [X, 0.5 * (F.solve(V) + Fr.apply(X))]
+        H = F.half_down(Wm)
+        return [F.half_up(H), F.half_up(Fr.apply(H))]
 
     pl = peel.Peeler(F.tree, applies, 2, eps_peel, seed)
     t_inv, t_rho = pl.run()

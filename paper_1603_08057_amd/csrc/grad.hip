@@ -6,8 +6,11 @@
 //   coarser levels' low-rank blocks subtracted, and a randomized low-rank
 //   approximation (eq. lowrankapprox) of every sibling block; at the leaves the
 //   diagonal blocks are extracted and their traces summed (Section 3.2.4).
-// The operators F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1) are peeled together from
-// the same probes and share their products with F^-1.
+// Section 3 allows any symmetric operator with the trace of F^-1 F_rho: with
+// F^-1 = B^T B (the two halves of the solve sweep), B B^T (trace Tr F^-1) and
+// B F_rho B^T (trace Tr F^-1 F_rho) are peeled together from the same probes
+// and share the product B^T W, so one probe block costs one and a half solve
+// sweeps and one multiply sweep.
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -97,11 +100,6 @@ __global__ void regrid_kernel(long long n, int nq, int cols, const double* __res
     const int q = c / cols, t = c - q * cols;
     dst[d * (long long)nq * Cd + (long long)q * Cd + t] = src[d * (long long)nq * Cs + (long long)q * Cs + t];
   }
-}
-
-__global__ void axpby_kernel(long long n, double a, const double* __restrict__ x, double b,
-                             const double* __restrict__ y, double* __restrict__ out) {
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) out[i] = a * x[i] + b * y[i];
 }
 
 __global__ void eye_blocks_kernel(const int* __restrict__ lbeg, const int* __restrict__ lcnt, int nleaf,
@@ -346,15 +344,17 @@ long long isqrt(long long n) {
 }
 
 // Probe columns at the first peeled level: sibling blocks of the top level
-// have ranks that grow like sqrt(n) (Section 3.3), so start at 4.5 sqrt(n),
-// at least FIRST_COLS.
-int first_cols(long long n) { return round8((int)std::max<long long>(FIRST_COLS, 9 * isqrt(n) / 2)); }
+// have ranks that grow like sqrt(n) (Section 3.3), so start at 3 sqrt(n), at
+// least FIRST_COLS.
+int first_cols(long long n) { return round8((int)std::max<long long>(FIRST_COLS, 3 * isqrt(n))); }
 
-// Probe columns at the next level: the largest rank found at this level
-// scaled by 0.85 (ranks shrink slowly from level to level) plus the
-// oversampling, at least MIN_COLS, rounded up to a multiple of 8.
-int next_cols(int prev_rank) {
-  int c = (17 * prev_rank + 19) / 20 + OVERSAMPLE;
+// Probe columns at the next level from the largest rank found at the level
+// above, plus the oversampling, at least MIN_COLS, rounded up to a multiple
+// of 8: the second peeled level's sibling blocks of B F_rho B^T and B B^T
+// have larger ranks than the first level's (1.5x), below that the ranks
+// shrink by less than half per level (0.7x).
+int next_cols(int prev_rank, int peeled) {
+  const int c = peeled == 1 ? (3 * prev_rank + 1) / 2 + OVERSAMPLE : (7 * prev_rank + 9) / 10 + OVERSAMPLE;
   return round8(std::max(MIN_COLS, c));
 }
 
@@ -399,18 +399,13 @@ struct Peeler {
   // rows take part in.
   void apply_ops(const double* X, int nc, double* out0, double* out1, Scratch& scr, const int* cols) {
     const long long n = t.n, sz = n * nc;
-    double* A = scr.make<double>(sz);
-    double* V = scr.make<double>(sz);
-    double* Z = scr.make<double>(sz);
-    copy_dev(out0, X, sz, s);
-    sweep_solve(h, h->F, out0, nc, nc, scr, s, cols);  // F^-1 X
-    copy_dev(A, X, sz, s);
-    sweep_apply_mult(h, *h->Frho, A, V, nc, nc, scr, s, cols);  // F_rho X
-    sweep_solve(h, h->F, V, nc, nc, scr, s, cols);               // F^-1 F_rho X
-    copy_dev(A, out0, sz, s);
-    sweep_apply_mult(h, *h->Frho, A, Z, nc, nc, scr, s, cols);  // F_rho F^-1 X
-    hipLaunchKernelGGL(axpby_kernel, dim3(grid_of(sz)), dim3(256), 0, s, sz, 0.5, V, 0.5, Z, out1);
-    RSF_HIP(hipGetLastError());
+    double* H = scr.make<double>(sz);
+    copy_dev(H, X, sz, s);
+    sweep_half_down(h, h->F, H, nc, nc, scr, s, cols);          // B^T X
+    copy_dev(out0, H, sz, s);
+    sweep_half_up(h, h->F, out0, nc, nc, scr, s, cols);         // B B^T X
+    sweep_apply_mult(h, *h->Frho, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
+    sweep_half_up(h, h->F, out1, nc, nc, scr, s, cols);         // B F_rho B^T X
   }
 
   int cols_of(const int* cols, int box, int nc) const { return cols ? std::min(nc, cols[t.inst[box]]) : nc; }
@@ -670,7 +665,7 @@ struct Peeler {
     // (the Gram squares the singular values), so the threshold is floored there
     const double tol2 = std::max(eps_peel * eps_peel, 1e-13);
     // per instance: the largest sibling-block rank of the previous level (-1: none yet)
-    std::vector<int> prev(ni, -1);
+    std::vector<int> prev(ni, -1), peeled(ni, 0);
     std::vector<int> qd(n), rinst(n);
     for (int i = 0; i < ni; ++i)
       for (long long d = t.ioff[i]; d < t.ioff[i + 1]; ++d) rinst[d] = i;
@@ -715,7 +710,7 @@ struct Peeler {
       std::vector<int> has(ni, 0), cc(ni, 0), tot(ni, 0);
       for (auto& pr : pairs) has[t.inst[pr.first]] = 1;
       for (int i = 0; i < ni; ++i)
-        if (has[i]) cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i]);
+        if (has[i]) cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i], peeled[i]);
       int C = 0;  // layout of the probe and sample stores (columns per quadrant block)
       std::vector<int> rk(2 * nblk), maxr(ni, 0);
       std::vector<long long> poff(2 * nblk + 1, 0);
@@ -748,11 +743,11 @@ struct Peeler {
         }
         tm[6] += std::chrono::duration<double>(std::chrono::steady_clock::now() - cg0).count();
         // the new probe columns of every instance go through the operators
-        // together, in chunks that keep the six n x 4 cw work panels within
+        // together, in chunks that keep the four n x 4 cw work panels within
         // PEEL_CHUNK_BYTES
         int newmax = 0;
         for (int i = 0; i < ni; ++i) newmax = std::max(newmax, cc[i] - tot[i]);
-        const long long per_col = 6LL * n * 4 * (long long)sizeof(double);
+        const long long per_col = 4LL * n * 4 * (long long)sizeof(double);
         const int cw = std::min(newmax, (int)std::max<long long>(8, PEEL_CHUNK_BYTES / per_col / 8 * 8));
         int* dact = scr.make<int>(ni);
         int* dj0 = scr.make<int>(ni);
@@ -857,6 +852,7 @@ struct Peeler {
       for (int i = 0; i < ni; ++i)
         if (has[i]) {
           prev[i] = maxr[i];
+          ++peeled[i];
           colmax = std::max(colmax, tot[i]);
           rankmax = std::max(rankmax, maxr[i]);
         }

@@ -141,6 +141,11 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s);
 // undefined.
 void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld,
                  Scratch& scr, hipStream_t s, const int* inst_cols = nullptr);
+// X = B X and X = B^T X for F^-1 = B^T B (B: the up sweep, then L_root^-1)
+void sweep_half_up(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
+                   hipStream_t s, const int* inst_cols = nullptr);
+void sweep_half_down(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
+                     hipStream_t s, const int* inst_cols = nullptr);
 void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, double* V, int nc,
                 long long ld, Scratch& scr, hipStream_t s);
 void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double* Out, int nc,
@@ -154,8 +159,8 @@ void to_panel(const rsf_factor_s* h, const double* src, long long ld, double* P,
 void from_panel(const rsf_factor_s* h, const double* P, int nc, long long ldp, double* dst,
                 long long ld, hipStream_t s);
 
-// Peeled traces of F^-1 and 1/2 (F^-1 F_rho + F_rho F^-1) (Section 3.2), one
-// value per instance in tr_inv and tr_rho.
+// Peeled traces of B B^T = Tr F^-1 and B F_rho B^T = Tr F^-1 F_rho, with
+// F^-1 = B^T B (Section 3.2), one value per instance in tr_inv and tr_rho.
 struct PeelStats {
   int levels = 0;
   int cols[32] = {0};

@@ -563,6 +563,61 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
   }
 }
 
+// The two halves of the solve: F^-1 = B^T B with B = L_root^-1 U_1 ... U_D
+// (U_d: the up step of depth d).  The down step of depth d is U_d^T, so
+// B^T = D_D ... D_1 L_root^-T, and B F_rho B^T is a symmetric operator with
+// the trace of F^-1 F_rho.
+static double* root_tmp(const FactorData& F, int nc, Scratch& scr) {
+  long long maxr = 1;
+  for (size_t d = 1; d < F.levels.size(); ++d) maxr = std::max(maxr, F.levels[d].total_r);
+  maxr = std::max<long long>(maxr, F.nroot);
+  return scr.make<double>((size_t)maxr * nc);
+}
+
+// X_root = L_root^-1 X_root (trans = false) or L_root^-T X_root (trans = true)
+static void root_half(const FactorData& F, bool trans, double* X, int nc, long long ld, double* tmp, Scratch& scr,
+                      hipStream_t s, const int* inst_cols) {
+  if (F.nroot <= 0) return;
+  std::vector<GemmDesc> g;
+  for (size_t i = 0; i < F.roots.size(); ++i) {
+    const RootBlock& rb = F.roots[i];
+    const int N = rb.N, cols = root_cols(inst_cols, (int)i, nc);
+    if (N == 0 || cols == 0) continue;
+    g.push_back(gemm_desc(N, cols, N, 1.0, trans ? colmajT(rb.Linv, N) : colmaj(rb.Linv, N),
+                          panel(X, ld, F.root_idx + rb.off), 0.0, panel(tmp + (long long)rb.off * nc, nc)));
+  }
+  gemm_batched(g, scr, s);
+  scatter_rows(F.root_idx, F.nroot, tmp, nc, X, ld, s);
+}
+
+void sweep_half_up(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
+                   hipStream_t s, const int* inst_cols) {
+  TraceTag tag("sweep_solve");
+  const int D = h->tree.maxdepth;
+  double* tmp = root_tmp(F, nc, scr);
+  for (int d = D; d >= 1; --d) {
+    const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "up");
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
+    level_step(h, L, bc, BS_SOLVE_UP, X, nullptr, nc, ld, tmp, scr, s);
+  }
+  root_half(F, false, X, nc, ld, tmp, scr, s, inst_cols);
+}
+
+void sweep_half_down(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
+                     hipStream_t s, const int* inst_cols) {
+  TraceTag tag("sweep_solve");
+  const int D = h->tree.maxdepth;
+  double* tmp = root_tmp(F, nc, scr);
+  root_half(F, true, X, nc, ld, tmp, scr, s, inst_cols);
+  for (int d = 1; d <= D; ++d) {
+    const LevelFactor& L = F.levels[d];
+    LevelTag lt(d, "down");
+    const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
+    level_step(h, L, bc, BS_SOLVE_DOWN, X, nullptr, nc, ld, tmp, scr, s);
+  }
+}
+
 void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double* Out, int nc, long long ld,
                   Scratch& scr, hipStream_t s) {
   TraceTag tag("sweep_sqrt");

@@ -150,6 +150,12 @@ def test_sweep_identities(f1024):
     w = W.gaussian(1024, 7)
     assert u @ F.apply(w) == pytest.approx(w @ F.apply(u), rel=1e-12)
     assert u @ Fr.apply(w) == pytest.approx(w @ Fr.apply(u), rel=1e-10)
+    # the solve's halves: B is the inverse of the separately written F^(1/2),
+    # B^T is its transpose, and B^T B is the solve
+    np.testing.assert_allclose(F.half_up(F.sqrt(v)), v, rtol=0, atol=1e-11 * np.abs(v).max())
+    assert u @ F.half_up(w) == pytest.approx(F.half_down(u) @ w, rel=1e-12)
+    x = F.solve(v)
+    np.testing.assert_allclose(F.half_down(F.half_up(v)), x, rtol=0, atol=1e-12 * np.abs(x).max())
 
 
 def test_factor_approximates_sigma(f1024):
@@ -162,6 +168,9 @@ def test_factor_approximates_sigma(f1024):
     assert err < 1e-8
     err_r = np.linalg.norm(Fr.from_tree(Fr.apply(Vt)) - Sr @ V) / np.linalg.norm(Sr @ V)
     assert err_r < 1e-8
+    # B Sigma B^T = I to the factorization accuracy (F^-1 = B^T B)
+    SVt = F.to_tree(S @ F.from_tree(F.half_down(Vt)))
+    assert np.linalg.norm(F.half_up(SVt) - Vt) <= 1e-6 * np.linalg.norm(Vt)
     ld = dense.loglik(P, V[:, 0], theta, K.MATERN32)[1]
     assert abs(F.logdet - ld) <= 10 * 1e-9 * abs(ld)
 
