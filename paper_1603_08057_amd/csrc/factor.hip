@@ -284,6 +284,7 @@ __device__ void backsub_columns(double* A, long long ld, int k, int j0, int j1, 
 constexpr int CPQR_MAXA = 512;
 constexpr int SCHUR_FUSED_MAXA = 128;
 constexpr int CPQR_MAXM = 4096;
+constexpr int CPQR_BOX_MAXA = 64;
 
 __global__ __launch_bounds__(256) void cpqr_box_kernel(const CpqrJob* __restrict__ jobs,
                                                         double eps, int nprox) {
@@ -383,12 +384,16 @@ __global__ __launch_bounds__(256) void cpqr_big_pivot_kernel(const CpqrJob* __re
 
 constexpr int BIG_MAXM = 12288;
 
+// One workgroup per cw columns of a box (cw = 4, 8 or 16: levels with few
+// boxes take narrow chunks so that one step still spreads over the CUs).
+// The reflector is staged in dynamic LDS sized by the level's longest
+// compression matrix (so short ones leave room for many workgroups per CU).
 __global__ __launch_bounds__(256) void cpqr_big_update_kernel(const CpqrJob* __restrict__ jobs,
-                                                               int s, int nprox) {
-  __shared__ double v[BIG_MAXM];
+                                                               int s, int nprox, int cw) {
+  extern __shared__ double v[];
   const CpqrJob J = jobs[blockIdx.x];
   if (*J.done) return;
-  const int j0 = std::max(s + 1, (int)blockIdx.y * 16), j1 = std::min(J.a, (int)blockIdx.y * 16 + 16);
+  const int j0 = std::max(s + 1, (int)blockIdx.y * cw), j1 = std::min(J.a, (int)blockIdx.y * cw + cw);
   if (j0 >= j1) return;
   const long long m = (long long)*J.ncnt + nprox;
   for (long long i = s + threadIdx.x; i < m; i += blockDim.x) v[i - s] = J.v[i - s];
@@ -399,10 +404,10 @@ __global__ __launch_bounds__(256) void cpqr_big_update_kernel(const CpqrJob* __r
 // The same for compression matrices taller than BIG_MAXM rows: the reflector
 // is read from global memory (it stays in L2 across the columns).
 __global__ __launch_bounds__(256) void cpqr_big_update_tall_kernel(const CpqrJob* __restrict__ jobs,
-                                                                    int s, int nprox) {
+                                                                    int s, int nprox, int cw) {
   const CpqrJob J = jobs[blockIdx.x];
   if (*J.done) return;
-  const int j0 = std::max(s + 1, (int)blockIdx.y * 16), j1 = std::min(J.a, (int)blockIdx.y * 16 + 16);
+  const int j0 = std::max(s + 1, (int)blockIdx.y * cw), j1 = std::min(J.a, (int)blockIdx.y * cw + cw);
   if (j0 >= j1) return;
   const long long m = (long long)*J.ncnt + nprox;
   reflect_columns(J.A, J.ld, m, s, j0, j1, J.v, J.scal[0], J.norms);
@@ -841,7 +846,9 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         maxm = std::max(maxm, mub[i]);
       }
       std::vector<CpqrJob> cj(nb);
-      const bool big = (maxa > CPQR_MAXA || maxm > CPQR_MAXM || nb < 128);
+      // one workgroup per box only for the smallest boxes; larger ones (or
+      // few boxes) spread every pivoting step over many workgroups
+      const bool big = (maxa > CPQR_BOX_MAXA || maxm > CPQR_MAXM || nb < 128);
       double* norms = big ? scr.make<double>(std::max<long long>(aoff[nb], 1)) : nullptr;
       double* vb = big ? scr.make<double>(std::max<long long>(noff[nb] + (long long)nb * nprox, 1)) : nullptr;
       double* scal = big ? scr.make<double>(2 * nb) : nullptr;
@@ -859,19 +866,40 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       } else {
         int* ndone = done + nb;
         RSF_HIP(hipMemsetAsync(ndone, 0, sizeof(int), s));
+        // exact row counts (the near field is compacted on the device)
+        std::vector<int> nh(nb);
+        RSF_HIP(hipMemcpyAsync(nh.data(), ncnt, nb * sizeof(int), hipMemcpyDeviceToHost, s));
+        RSF_HIP(hipStreamSynchronize(s));
+        maxm = 0;
+        for (int i = 0; i < nb; ++i) maxm = std::max<long long>(maxm, (long long)nh[i] + nprox);
+        static bool upd_lds = false;
+        if (!upd_lds) {
+          RSF_HIP(hipFuncSetAttribute((const void*)cpqr_big_update_kernel,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, BIG_MAXM * (int)sizeof(double)));
+          upd_lds = true;
+        }
+        if (stats) {
+          long long sm = 0;
+          for (int i = 0; i < nb; ++i) sm += nh[i] + nprox;
+          fprintf(stderr, "[factor%s] depth %d rows mean %.0f max %lld\n", mult ? "_rho" : "", d, (double)sm / nb, maxm);
+        }
         const int chunks = std::max(1, ceil_div(maxa, 16));
         hipLaunchKernelGGL(cpqr_big_init_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, nprox);
         RSF_HIP(hipGetLastError());
+        int cw = 16;
+        while (cw > 4 && (long long)nb * ceil_div(maxa, cw) < 2048) cw /= 2;
+        const int ucols = ceil_div(maxa, cw);
         long long steps = 0;
-        for (int i = 0; i < nb; ++i) steps = std::max<long long>(steps, std::min<long long>(mub[i], L.a[i]));
+        for (int i = 0; i < nb; ++i) steps = std::max<long long>(steps, std::min<long long>((long long)nh[i] + nprox, L.a[i]));
         for (int st = 0; st <= steps; ++st) {
           hipLaunchKernelGGL(cpqr_big_pivot_kernel, dim3(nb), dim3(256), 0, s, dj, st, h->eps, nprox, ndone);
           RSF_HIP(hipGetLastError());
           if (st == steps) break;
           if (maxm <= BIG_MAXM)
-            hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, st, nprox);
+            hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, ucols), dim3(256), (size_t)maxm * sizeof(double), s,
+                               dj, st, nprox, cw);
           else
-            hipLaunchKernelGGL(cpqr_big_update_tall_kernel, dim3(nb, chunks), dim3(256), 0, s, dj, st, nprox);
+            hipLaunchKernelGGL(cpqr_big_update_tall_kernel, dim3(nb, ucols), dim3(256), 0, s, dj, st, nprox, cw);
           RSF_HIP(hipGetLastError());
           if ((st & 15) == 15) {
             int nd = 0;
@@ -882,7 +910,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         }
         // ranks are on the device: size the solve by the largest possible one
         int kmax = 0;
-        for (int i = 0; i < nb; ++i) kmax = std::max<int>(kmax, (int)std::min<long long>(mub[i], L.a[i]));
+        for (int i = 0; i < nb; ++i) kmax = std::max<int>(kmax, (int)std::min<long long>((long long)nh[i] + nprox, L.a[i]));
         const int tchunks = std::max(1, ceil_div(maxa, TRSM_C));
         if (kmax <= 256)
           hipLaunchKernelGGL(cpqr_trsm_kernel<1>, dim3(nb, tchunks), dim3(256), 0, s, dj);
