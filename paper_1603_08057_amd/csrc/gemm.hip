@@ -369,45 +369,58 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
   v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
   const bool a_icontig = (d.ars == 1 && d.aidx == nullptr);
   const bool b_jcontig = (d.bcs == 1);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
-    __syncthreads();
+  // this thread's four A and four B elements of every K chunk: fixed tile
+  // positions, the K index advancing by 16 per chunk; A's row map is read once
+  int ia[4], ka[4], jb[4], kb[4];
+  long long arow[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (a_icontig) {
+      ia[r] = tid & 63;
+      ka[r] = (tid >> 6) + 4 * r;
+    } else {
+      ka[r] = tid & 15;
+      ia[r] = (tid >> 4) + 16 * r;
+    }
+    const int gi = i0 + ia[r];
+    arow[r] = gi < d.M ? (d.aidx ? (long long)d.aidx[gi] : (long long)gi) * d.ars : -1;
+    if (b_jcontig) {
+      jb[r] = tid & 63;
+      kb[r] = (tid >> 6) + 4 * r;
+    } else {
+      kb[r] = tid & 15;
+      jb[r] = (tid >> 4) + 16 * r;
+    }
+  }
+  double ra[4], rbv[4];
+  // the next chunk is fetched into registers while the current one is multiplied
+  auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int i, kk;
-      if (a_icontig) {
-        i = tid & 63;
-        kk = (tid >> 6) + 4 * r;
-      } else {
-        kk = tid & 15;
-        i = (tid >> 4) + 16 * r;
-      }
-      const int gi = i0 + i, gk = k0 + kk;
-      double v = 0.0;
-      if (gi < d.M && gk < d.K) {
-        const long long row = d.aidx ? (long long)d.aidx[gi] : (long long)gi;
-        v = d.A[row * d.ars + (long long)gk * d.acs];
-      }
-      As[kk][i] = v;
+      const int gk = k0 + ka[r];
+      ra[r] = (arow[r] >= 0 && gk < d.K) ? d.A[arow[r] + (long long)gk * d.acs] : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      int j, kk;
-      if (b_jcontig) {
-        j = tid & 63;
-        kk = (tid >> 6) + 4 * r;
-      } else {
-        kk = tid & 15;
-        j = (tid >> 4) + 16 * r;
-      }
-      const int gj = j0 + j, gk = k0 + kk;
+      const int gj = j0 + jb[r], gk = k0 + kb[r];
       double v = 0.0;
       if (gj < d.N && gk < d.K) {
         const long long row = d.bidx ? (long long)d.bidx[gk] : (long long)gk;
         v = d.B[row * d.brs + (long long)gj * d.bcs];
       }
-      Bs[kk][j] = v;
+      rbv[r] = v;
+    }
+  };
+  fetch(0);
+  for (int k0 = 0; k0 < d.K; k0 += 16) {
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      As[ka[r]][ia[r]] = ra[r];
+      Bs[kb[r]][jb[r]] = rbv[r];
     }
     __syncthreads();
+    if (k0 + 16 < d.K) fetch(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
@@ -766,6 +779,24 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     toff[g].push_back(toff[g].back() + (int)nt);
   }
   if (live.empty()) return;
+  static const bool gstats = std::getenv("RSFGP_GEMM_STATS") != nullptr;
+  if (gstats) {
+    // per launch group: problems, tiles, GFLOP and mean shape
+    for (int g = 0; g < NG; ++g) {
+      if (probs[g].empty()) continue;
+      double fl = 0.0, sm = 0.0, sn = 0.0, sk = 0.0;
+      for (int p : probs[g]) {
+        const GemmDesc& d = live[p];
+        fl += 2.0 * d.M * d.N * d.K;
+        sm += d.M;
+        sn += d.N;
+        sk += d.K;
+      }
+      const double np = (double)probs[g].size();
+      fprintf(stderr, "[gemm] %s g%d probs %zu tiles %d gflop %.3f M %.0f N %.0f K %.0f\n", g_trace.tag.c_str(), g,
+              probs[g].size(), toff[g].back(), fl * 1e-9, sm / np, sn / np, sk / np);
+    }
+  }
   GemmDesc* dd = scr.make<GemmDesc>(live.size());
   upload(dd, live, s);
   std::vector<int> cat;
