@@ -113,6 +113,7 @@ struct GemmDesc {
   const int* aidx;
   const int* bidx;
   const int* cidx;
+  const int* kidx;  // A(i, k) reads column kidx[k] of A (64 x 64 tile kernel only)
   long long ars, acs, brs, bcs, crs, ccs;
   int M, N, K;
   double alpha, beta;
@@ -143,6 +144,7 @@ inline GemmDesc gemm_desc(int M, int N, int K, double alpha, Mat A, Mat B, doubl
   d.aidx = A.idx;
   d.bidx = B.idx;
   d.cidx = C.idx;
+  d.kidx = nullptr;
   d.ars = A.rs;
   d.acs = A.cs;
   d.brs = B.rs;

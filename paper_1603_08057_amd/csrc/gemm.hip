@@ -398,7 +398,7 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gk = k0 + ka[r];
-      ra[r] = (arow[r] >= 0 && gk < d.K) ? d.A[arow[r] + (long long)gk * d.acs] : 0.0;
+      ra[r] = (arow[r] >= 0 && gk < d.K) ? d.A[arow[r] + (long long)(d.kidx ? d.kidx[gk] : gk) * d.acs] : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -738,6 +738,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
 // contiguous), bit 0 = B has a row map (only with contiguous columns);
 // -1 = no fitting layout, use the 64 x 64 kernel
 static int big_class(const GemmDesc& d) {
+  if (d.kidx) return -1;
   const bool ai = (d.ars == 1 && d.aidx == nullptr), ak = (d.acs == 1 && d.aidx == nullptr);
   const bool bj = (d.bcs == 1), bk = (d.brs == 1 && d.bidx == nullptr);
   if (!(ai || ak) || !(bj || bk)) return -1;
@@ -756,6 +757,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   for (const GemmDesc& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
     RSF_CHECK(!d.lower || d.M == d.N, RSF_E_INVALID, "lower-triangle GEMM needs a square C");
+    RSF_CHECK(!(d.kidx && d.f32), RSF_E_INVALID, "column-mapped A needs the FP64 tile kernel");
     flops += (d.lower ? 1.0 : 2.0) * d.M * d.N * d.K;
     bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     const int p = (int)live.size();

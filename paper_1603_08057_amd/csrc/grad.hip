@@ -410,8 +410,21 @@ struct Peeler {
 
   int cols_of(const int* cols, int box, int nc) const { return cols ? std::min(nc, cols[t.inst[box]]) : nc; }
 
-  // out -= sum_{m < upto} G^(m) X  for operator op (same column rule as apply_ops)
-  void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr, const int* cols) {
+  // Probes of one chunk in compact form: row d holds its own quadrant's
+  // columns, Om[d * ldo + j0[instance] + t] = X[d, 4 t + qd[d]] (qd: the
+  // quadrant of d's box at the level being peeled, -1 for rows without one).
+  struct CompactProbes {
+    const double* Om;
+    long long ldo;
+    const std::vector<int>* j0;
+    const std::vector<int>* qd;
+  };
+
+  // out -= sum_{m < upto} G^(m) X  for operator op (same column rule as apply_ops).
+  // With cp, X is a probe chunk and U_b^T X[I_b] is formed per quadrant from
+  // the rows of that quadrant only (the other rows are zero in its columns).
+  void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr, const int* cols,
+                        const CompactProbes* cp = nullptr) {
     TraceTag tag("peel_subtract");
     for (int m = 1; m < upto && m < (int)lr[op].size(); ++m) {
       const LevelLR& L = lr[op][m];
@@ -424,10 +437,47 @@ struct Peeler {
       // a pair with one empty basis contributes nothing: its Q segment stays zero
       fill_zero(Q, poff[nbx], s);
       std::vector<GemmDesc> g1;
-      for (int b = 0; b < nbx; ++b) {
-        const int box = L.boxes[b];
-        g1.push_back(gemm_desc(L.K[b], cols_of(cols, box, nc), t.count[box], 1.0, colmajT(L.U[b], t.count[box]),
-                               panel(X + (long long)t.begin[box] * nc, nc), 0.0, panel(P + poff[b], nc)));
+      if (!cp) {
+        for (int b = 0; b < nbx; ++b) {
+          const int box = L.boxes[b];
+          g1.push_back(gemm_desc(L.K[b], cols_of(cols, box, nc), t.count[box], 1.0, colmajT(L.U[b], t.count[box]),
+                                 panel(X + (long long)t.begin[box] * nc, nc), 0.0, panel(P + poff[b], nc)));
+        }
+      } else {
+        // rows of each box by quadrant (box-relative); a quadrant whose rows
+        // form one run is passed as a contiguous block
+        const std::vector<int>& qd = *cp->qd;
+        std::vector<int> rows;
+        std::vector<long long> lo(4 * nbx + 1, 0);
+        for (int b = 0; b < nbx; ++b) {
+          const int box = L.boxes[b], b0 = t.begin[box], cnt = t.count[box];
+          for (int q = 0; q < 4; ++q) {
+            for (int u = 0; u < cnt; ++u)
+              if (qd[b0 + u] == q) rows.push_back(u);
+            lo[4 * b + q + 1] = (long long)rows.size();
+          }
+        }
+        int* drows = scr.make<int>(std::max<size_t>(rows.size(), 1));
+        upload(drows, rows, s);
+        for (int b = 0; b < nbx; ++b) {
+          const int box = L.boxes[b], cnt = t.count[box];
+          const int N = cols_of(cols, box, nc) / 4;
+          const double* Ob = cp->Om + (long long)t.begin[box] * cp->ldo + (*cp->j0)[t.inst[box]];
+          for (int q = 0; q < 4; ++q) {
+            const long long a = lo[4 * b + q], e = lo[4 * b + q + 1];
+            const int K = (int)(e - a);
+            const Mat C{P + poff[b] + q, nc, 4, nullptr};
+            if (K > 0 && rows[e - 1] - rows[a] == K - 1) {
+              const int r0 = rows[a];
+              g1.push_back(gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b] + r0, cnt), panel(Ob + (long long)r0 * cp->ldo, cp->ldo),
+                                     0.0, C));
+            } else {
+              GemmDesc d = gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b], cnt), Mat{Ob, cp->ldo, 1, drows + a}, 0.0, C);
+              d.kidx = drows + a;
+              g1.push_back(d);
+            }
+          }
+        }
       }
       gemm_batched(g1, scr, s);
       std::vector<GemmDesc> g2;
@@ -774,8 +824,9 @@ struct Peeler {
           auto c0 = std::chrono::steady_clock::now();
           apply_ops(Wm, 4 * ncw, B0, B1, rs, pc);
           auto c1 = std::chrono::steady_clock::now();
-          subtract_lowrank(0, lev, Wm, 4 * ncw, B0, rs, pc);
-          subtract_lowrank(1, lev, Wm, 4 * ncw, B1, rs, pc);
+          const CompactProbes cpr{Om, (long long)C, &j0, &qd};
+          subtract_lowrank(0, lev, Wm, 4 * ncw, B0, rs, pc, &cpr);
+          subtract_lowrank(1, lev, Wm, 4 * ncw, B1, rs, pc, &cpr);
           auto c2 = std::chrono::steady_clock::now();
           tm[0] += std::chrono::duration<double>(c1 - c0).count();
           tm[1] += std::chrono::duration<double>(c2 - c1).count();
