@@ -737,6 +737,31 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
 // contiguous (else k contiguous), bit 1 = B columns contiguous (else k
 // contiguous), bit 0 = B has a row map (only with contiguous columns);
 // -1 = no fitting layout, use the 64 x 64 kernel
+// Split-K: partial products of K slices land in a workspace (column-major,
+// one M x N block per slice) and are summed in slice order into C.
+struct SplitRed {
+  const double* W;
+  long long M, N;
+  int s;
+  double alpha, beta;
+  double* C;
+  const int* cidx;
+  long long crs, ccs;
+};
+
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(const SplitRed* __restrict__ jobs) {
+  const SplitRed J = jobs[blockIdx.y];
+  const long long tot = J.M * J.N, blk = tot;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    double v = 0.0;
+    for (int p = 0; p < J.s; ++p) v += J.W[p * blk + e];
+    const long long i = e % J.M, j = e / J.M;
+    const long long row = J.cidx ? (long long)J.cidx[i] : i;
+    double* c = J.C + row * J.crs + j * J.ccs;
+    *c = (J.beta == 0.0) ? J.alpha * v : J.alpha * v + J.beta * *c;
+  }
+}
+
 static int big_class(const GemmDesc& d) {
   if (d.kidx) return -1;
   const bool ai = (d.ars == 1 && d.aidx == nullptr), ak = (d.acs == 1 && d.aidx == nullptr);
@@ -781,6 +806,63 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     toff[g].push_back(toff[g].back() + (int)nt);
   }
   if (live.empty()) return;
+  // Split-K for launch groups with fewer tiles than two per CU: problems with
+  // a long K are cut into slices of at least 512 that run as separate
+  // problems of the same launch, then summed (fixed order: deterministic).
+  constexpr int SPLIT_TILES = 512, SPLIT_MIN_K = 512, SPLIT_MAX = 8;
+  std::vector<SplitRed> reds;
+  for (int g = 0; g < 9; ++g) {
+    const int T = toff[g].back();
+    if (T == 0 || T >= SPLIT_TILES) continue;
+    const int want = std::min(SPLIT_MAX, SPLIT_TILES / T);
+    if (want < 2) continue;
+    const int ts = g == 0 ? 64 : BT;
+    const size_t np0 = probs[g].size();
+    for (size_t u = 0; u < np0; ++u) {
+      const int p = probs[g][u];
+      const GemmDesc d = live[p];
+      const int sp = std::min(want, d.K / SPLIT_MIN_K);
+      if (d.lower || sp < 2) continue;
+      const int kpart = (d.K + sp - 1) / sp / 16 * 16 + 16;
+      const int nparts = (d.K + kpart - 1) / kpart;
+      if (nparts < 2) continue;
+      double* W = scr.make<double>((size_t)nparts * d.M * d.N);
+      reds.push_back(SplitRed{W, d.M, d.N, nparts, d.alpha, d.beta, d.C, d.cidx, d.crs, d.ccs});
+      for (int q = 0; q < nparts; ++q) {
+        const int k0 = q * kpart;
+        GemmDesc e = d;
+        e.K = std::min(kpart, d.K - k0);
+        if (d.kidx)
+          e.kidx = d.kidx + k0;
+        else
+          e.A = d.A + (long long)k0 * d.acs;
+        if (d.bidx)
+          e.bidx = d.bidx + k0;
+        else
+          e.B = d.B + (long long)k0 * d.brs;
+        e.C = W + (size_t)q * d.M * d.N;
+        e.cidx = nullptr;
+        e.crs = 1;
+        e.ccs = d.M;
+        e.alpha = 1.0;
+        e.beta = 0.0;
+        if (q == 0) {
+          live[p] = e;
+        } else {
+          probs[g].push_back((int)live.size());
+          live.push_back(e);
+        }
+      }
+    }
+    toff[g].assign(1, 0);
+    for (int p : probs[g]) {
+      const GemmDesc& d = live[p];
+      const long long tm = (d.M + ts - 1) / ts, tn = (d.N + ts - 1) / ts;
+      const long long nt = d.lower ? tm * (tm + 1) / 2 : tm * tn;
+      RSF_CHECK(toff[g].back() + nt < (1LL << 31), RSF_E_INVALID, "too many GEMM tiles in one launch");
+      toff[g].push_back(toff[g].back() + (int)nt);
+    }
+  }
   static const bool gstats = std::getenv("RSFGP_GEMM_STATS") != nullptr;
   if (gstats) {
     // per launch group: problems, tiles, GFLOP and mean shape
@@ -834,6 +916,15 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   RSF_LAUNCH(gemm_tiles_f32_kernel, 9)
 #undef RSF_LAUNCH
   RSF_HIP(hipGetLastError());
+  if (!reds.empty()) {
+    SplitRed* dr = scr.make<SplitRed>(reds.size());
+    upload(dr, reds, s);
+    long long mx = 1;
+    for (const SplitRed& r : reds) mx = std::max(mx, r.M * r.N);
+    const unsigned gx = (unsigned)std::min<long long>(1024, (mx + 255) / 256);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gx, (unsigned)reds.size()), dim3(256), 0, s, dr);
+    RSF_HIP(hipGetLastError());
+  }
   if (g_trace.on) {
     RSF_HIP(hipEventRecord(e1, s));
     // launches with FP32 products are booked under "<phase>/f32"
