@@ -976,12 +976,13 @@ struct DiagJob {
 __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* __restrict__ jobs, int* fail) {
   __shared__ double B[64][65];
   __shared__ double I[64][65];
+  __shared__ double dg[64];
   const DiagJob J = jobs[blockIdx.x];
   const int nb = J.nb, tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e % nb, j = e / nb;
-    B[i][j] = J.A[(long long)j * J.lda + i];
-  }
+  // thread (row ti, column group tg): rows are lanes, the four waves split the columns
+  const int ti = tid & 63, tg = tid >> 6;
+  for (int c = tg; c < nb; c += 4)
+    if (ti < nb) B[ti][c] = J.A[(long long)c * J.lda + ti];
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
     const double d = B[j][j];
@@ -990,16 +991,18 @@ __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* _
       return;
     }
     const double sq = sqrt(d);
+    // column j below the diagonal (the diagonal itself is written at the end)
+    if (tg == 0 && ti > j && ti < nb) B[ti][j] /= sq;
+    if (tid == 0) dg[j] = sq;
     __syncthreads();
-    if (tid == 0) B[j][j] = sq;
-    for (int i = j + 1 + tid; i < nb; i += 256) B[i][j] /= sq;
-    __syncthreads();
-    for (int e = tid; e < nb * nb; e += 256) {
-      const int i = e % nb, l = e / nb;
-      if (l > j && i >= l) B[i][l] -= B[i][j] * B[l][j];
+    if (ti > j && ti < nb) {
+      const double bij = B[ti][j];
+      for (int l = j + 1 + tg; l <= ti; l += 4) B[ti][l] -= bij * B[l][j];
     }
     __syncthreads();
   }
+  if (tid < nb) B[tid][tid] = dg[tid];
+  __syncthreads();
   if (tid == 0 && J.logd) {
     double sm = 0.0;
     for (int j = 0; j < nb; ++j) sm += log(B[j][j]);
@@ -1015,11 +1018,11 @@ __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* _
     }
   }
   __syncthreads();
-  for (int e = tid; e < nb * nb; e += 256) {
-    const int i = e % nb, j = e / nb;
-    J.A[(long long)j * J.lda + i] = (i >= j) ? B[i][j] : 0.0;
-    J.Dinv[(long long)j * 64 + i] = I[i][j];
-  }
+  for (int c = tg; c < nb; c += 4)
+    if (ti < nb) {
+      J.A[(long long)c * J.lda + ti] = (ti >= c) ? B[ti][c] : 0.0;
+      J.Dinv[(long long)c * 64 + ti] = I[ti][c];
+    }
 }
 
 void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr, hipStream_t s) {
