@@ -881,8 +881,6 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
               probs[g].size(), toff[g].back(), fl * 1e-9, sm / np, sn / np, sk / np);
     }
   }
-  GemmDesc* dd = scr.make<GemmDesc>(live.size());
-  upload(dd, live, s);
   std::vector<int> cat;
   size_t po[NG], to[NG];
   for (int g = 0; g < NG; ++g) {
@@ -891,8 +889,18 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     to[g] = cat.size();
     cat.insert(cat.end(), toff[g].begin(), toff[g].end());
   }
-  int* dc = scr.make<int>(cat.size());
-  upload(dc, cat, s);
+  // descriptors, problem / tile tables and split-K jobs go up in one copy
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t b_desc = al(live.size() * sizeof(GemmDesc)), b_cat = al(cat.size() * sizeof(int));
+  const size_t b_red = reds.size() * sizeof(SplitRed);
+  std::vector<char> stage(b_desc + b_cat + b_red);
+  std::memcpy(stage.data(), live.data(), live.size() * sizeof(GemmDesc));
+  std::memcpy(stage.data() + b_desc, cat.data(), cat.size() * sizeof(int));
+  if (b_red) std::memcpy(stage.data() + b_desc + b_cat, reds.data(), b_red);
+  char* dblk = scr.make<char>(stage.size());
+  upload_bytes(dblk, stage.data(), stage.size(), s);
+  GemmDesc* dd = reinterpret_cast<GemmDesc*>(dblk);
+  int* dc = reinterpret_cast<int*>(dblk + b_desc);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (g_trace.on) {
     RSF_HIP(hipEventCreate(&e0));
@@ -917,8 +925,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
 #undef RSF_LAUNCH
   RSF_HIP(hipGetLastError());
   if (!reds.empty()) {
-    SplitRed* dr = scr.make<SplitRed>(reds.size());
-    upload(dr, reds, s);
+    SplitRed* dr = reinterpret_cast<SplitRed*>(dblk + b_desc + b_cat);
     long long mx = 1;
     for (const SplitRed& r : reds) mx = std::max(mx, r.M * r.N);
     const unsigned gx = (unsigned)std::min<long long>(1024, (mx + 255) / 256);

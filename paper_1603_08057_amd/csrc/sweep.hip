@@ -312,10 +312,12 @@ static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int o
     if (r > 0) by += 8.0 * c * (op == BS_SOLVE_UP || op == BS_SOLVE_DOWN ? 2.0 * (k + r) : 2.0 * k + 3.0 * r);
   }
   if (toff[L.nb] == 0) return true;
-  int* dtoff = scr.make<int>(L.nb + 1);
-  int* dcols = scr.make<int>(L.nb);
-  upload(dtoff, toff, s);
-  upload(dcols, cols, s);
+  // tile offsets and column counts in one upload
+  std::vector<int> tc(toff);
+  tc.insert(tc.end(), cols.begin(), cols.end());
+  int* dtoff = scr.make<int>(tc.size());
+  upload(dtoff, tc, s);
+  int* dcols = dtoff + (L.nb + 1);
   const long long grid = ((long long)toff[L.nb] + 7) / 8 * 8;
   const dim3 g((unsigned)grid), blk(256);
   TraceLaunch tl(s, fl, by);
