@@ -158,10 +158,12 @@ __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict
                                                         const double* __restrict__ Lm, double* __restrict__ X,
                                                         double* __restrict__ Y, int nc, long long ld,
                                                         int amax) {
-  // LDS: Xl and Tl, (amax + 4) rows of BS_NCT each (amax = the level's largest box)
+  // LDS: one (amax + 4)-row buffer of BS_NCT columns (amax = the level's
+  // largest box): rows [0, k) hold the S rows, [k, a) the R rows.  Every step
+  // works in place: a product that overwrites its own operand rows keeps its
+  // result in registers until all waves have read them.
   extern __shared__ double bs_smem[];
   double* Xl = bs_smem;
-  double* Tl = bs_smem + (amax + 4) * BS_NCT;
   // tiles of one box stay on one XCD (consecutive workgroup ids alternate XCDs);
   // box bx owns the tiles [tile_off[bx], tile_off[bx + 1]) of its box_cols[bx] columns
   const int total = tile_off[nbox];
@@ -187,55 +189,42 @@ __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict
   const double* W = Wm + b.t_off;  // k x r
   const double* L = Lm + b.l_off;  // r x r
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // gather [X_S; X_R] (and Y_S for the multiply down-sweep), zero rows up to a + 4
+  // gather [X_S; X_R] (Y_S in place of X_S for the multiply down-sweep), zero rows up to a + 4
   for (int e = tid; e < (a + 4) * BS_NCT; e += 256) {
     const int row = e / BS_NCT, col = e - row * BS_NCT;
-    double v = 0.0, w = 0.0;
+    double v = 0.0;
     if (row < a && col < ncol) {
       const long long g = row < k ? Sb[row] : Rb[row - k];
-      if (OP == BS_MULT_DOWN && row < k)
-        w = Y[g * ld + j0 + col];  // X_S is not used by this step
-      else
-        v = X[g * ld + j0 + col];
+      v = (OP == BS_MULT_DOWN && row < k) ? Y[g * ld + j0 + col] : X[g * ld + j0 + col];
     }
     Xl[bsi(row, col)] = v;
-    if (OP == BS_MULT_DOWN) Tl[bsi(row, col)] = w;
-  }
-  if (OP == BS_SOLVE_UP || OP == BS_SOLVE_DOWN) {
-    for (int e = tid; e < 4 * BS_NCT; e += 256) Tl[bsi(r + e / BS_NCT, e % BS_NCT)] = 0.0;
   }
   __syncthreads();
   v4d acc[RB][2];
-  if (OP == BS_SOLVE_UP) {
-    // X_R -= T^T X_S
+  if (OP == BS_SOLVE_UP || OP == BS_SOLVE_DOWN) {
+    // X_R -= T^T X_S (up) or W^T X_S (down)
     zero_acc(acc);
-    box_mm(r, k, [&](int i, int q) { return T[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
+    if (OP == BS_SOLVE_UP)
+      box_mm(r, k, [&](int i, int q) { return T[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
+    else
+      box_mm(r, k, [&](int i, int q) { return W[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
     box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(k + i, c)] -= v; });
     __syncthreads();
-    // tmp = L^-1 X_R
+    // X_R = L^-1 X_R (up) or L^-T X_R (down), in place
     zero_acc(acc);
-    box_mm(r, r, [&](int i, int q) { return L[i + (long long)q * r]; }, Xl, k, acc, wave, lane);
-    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Tl[bsi(i, c)] = v; });
+    if (OP == BS_SOLVE_UP)
+      box_mm(r, r, [&](int i, int q) { return L[i + (long long)q * r]; }, Xl, k, acc, wave, lane);
+    else
+      box_mm(r, r, [&](int i, int q) { return L[q + (long long)i * r]; }, Xl, k, acc, wave, lane);
     __syncthreads();
-    // X_S -= W tmp
-    zero_acc(acc);
-    box_mm(k, r, [&](int i, int q) { return W[i + (long long)q * k]; }, Tl, 0, acc, wave, lane);
-    box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(i, c)] -= v; });
+    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(k + i, c)] = v; });
     __syncthreads();
-  } else if (OP == BS_SOLVE_DOWN) {
-    // X_R -= W^T X_S
+    // X_S -= W X_R (up) or T X_R (down)
     zero_acc(acc);
-    box_mm(r, k, [&](int i, int q) { return W[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
-    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(k + i, c)] -= v; });
-    __syncthreads();
-    // tmp = L^-T X_R
-    zero_acc(acc);
-    box_mm(r, r, [&](int i, int q) { return L[q + (long long)i * r]; }, Xl, k, acc, wave, lane);
-    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) { Tl[bsi(i, c)] = v; });
-    __syncthreads();
-    // X_S -= T tmp
-    zero_acc(acc);
-    box_mm(k, r, [&](int i, int q) { return T[i + (long long)q * k]; }, Tl, 0, acc, wave, lane);
+    if (OP == BS_SOLVE_UP)
+      box_mm(k, r, [&](int i, int q) { return W[i + (long long)q * k]; }, Xl, k, acc, wave, lane);
+    else
+      box_mm(k, r, [&](int i, int q) { return T[i + (long long)q * k]; }, Xl, k, acc, wave, lane);
     box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(i, c)] -= v; });
     __syncthreads();
   } else if (OP == BS_MULT_UP) {
@@ -252,14 +241,14 @@ __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict
       if (c < ncol) Y[(long long)Rb[i] * ld + j0 + c] += v;
     });
   } else {
-    // Y_S += X_sr X_R
+    // Y_S += X_sr X_R  (Y_S in the S rows)
     zero_acc(acc);
     box_mm(k, r, [&](int i, int q) { return W[i + (long long)q * k]; }, Xl, k, acc, wave, lane);
-    box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Tl[bsi(i, c)] += v; });
+    box_epilogue(k, acc, wave, lane, [&](int i, int c, double v) { Xl[bsi(i, c)] += v; });
     __syncthreads();
     // Y_R += T^T Y_S
     zero_acc(acc);
-    box_mm(r, k, [&](int i, int q) { return T[q + (long long)i * k]; }, Tl, 0, acc, wave, lane);
+    box_mm(r, k, [&](int i, int q) { return T[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
     box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) {
       if (c < ncol) Y[(long long)Rb[i] * ld + j0 + c] += v;
     });
@@ -269,20 +258,13 @@ __global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict
     for (int e = tid; e < a * BS_NCT; e += 256) {
       const int row = e / BS_NCT, col = e - row * BS_NCT;
       if (col >= ncol) continue;
-      if (row < k)
-        X[(long long)Sb[row] * ld + j0 + col] = Xl[bsi(row, col)];
-      else
-        X[(long long)Rb[row - k] * ld + j0 + col] = Tl[bsi(row - k, col)];
-    }
-  } else if (OP == BS_MULT_UP) {
-    for (int e = tid; e < k * BS_NCT; e += 256) {
-      const int row = e / BS_NCT, col = e - row * BS_NCT;
-      if (col < ncol) X[(long long)Sb[row] * ld + j0 + col] = Xl[bsi(row, col)];
+      X[(long long)(row < k ? Sb[row] : Rb[row - k]) * ld + j0 + col] = Xl[bsi(row, col)];
     }
   } else {
+    double* dst = OP == BS_MULT_UP ? X : Y;
     for (int e = tid; e < k * BS_NCT; e += 256) {
       const int row = e / BS_NCT, col = e - row * BS_NCT;
-      if (col < ncol) Y[(long long)Sb[row] * ld + j0 + col] = Tl[bsi(row, col)];
+      if (col < ncol) dst[(long long)Sb[row] * ld + j0 + col] = Xl[bsi(row, col)];
     }
   }
 }
@@ -298,7 +280,7 @@ static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int o
   int amax = 0;
   for (int i = 0; i < L.nb; ++i) amax = std::max(amax, L.a[i]);
   amax = (amax + 3) / 4 * 4;
-  const size_t lds = (size_t)(op == BS_MULT_UP ? 1 : 2) * (amax + 4) * BS_NCT * sizeof(double);
+  const size_t lds = (size_t)(amax + 4) * BS_NCT * sizeof(double);
   std::vector<int> toff(L.nb + 1, 0), cols(L.nb);
   double fl = 0.0, by = 0.0;
   for (int i = 0; i < L.nb; ++i) {
@@ -323,7 +305,7 @@ static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int o
   TraceLaunch tl(s, fl, by);
   // the largest boxes need more than the default dynamic LDS limit of 64 KiB
   static bool lds_set[4][2] = {{false, false}, {false, false}, {false, false}, {false, false}};
-  const int max_lds = 2 * (BS_AMAX + 4) * BS_NCT * (int)sizeof(double);
+  const int max_lds = (BS_AMAX + 4) * BS_NCT * (int)sizeof(double);
 #define RSF_BOX(OPV, RBV)                                                                                     \
   {                                                                                                           \
     if (!lds_set[OPV][RBV / 4]) {                                                                             \
