@@ -149,7 +149,7 @@ __device__ __forceinline__ void box_epilogue(int M, const v4d (&acc)[RB][2], int
 }
 
 template <int OP, int RB>
-__global__ __launch_bounds__(256) void box_sweep_kernel(const BoxRec* __restrict__ boxes, int nbox,
+__global__ __launch_bounds__(256, RB == 2 ? 4 : 2) void box_sweep_kernel(const BoxRec* __restrict__ boxes, int nbox,
                                                         const int* __restrict__ tile_off,
                                                         const int* __restrict__ box_cols,
                                                         const int* __restrict__ S, const int* __restrict__ R,
