@@ -66,13 +66,16 @@ def next_cols(prev_rank, peeled):
     """Initial probe count per quadrant block at the next level from the
     largest rank found at the level above (peeled = levels peeled so far):
     1.5x after the first peeled level (the second level's sibling blocks of
-    B F_rho B^T and B B^T have the larger ranks), 0.7x below it, plus the
-    oversampling, at least MIN_COLS, rounded up to a multiple of 8."""
+    B F_rho B^T and B B^T have the larger ranks), 0.7x after the second,
+    0.6x below that (the ranks shrink by at most half per level there), plus
+    the oversampling, at least MIN_COLS, rounded up to a multiple of 8."""
     if peeled == 1:
-        c = (3 * prev_rank + 1) // 2 + OVERSAMPLE
+        c = (3 * prev_rank + 1) // 2
+    elif peeled == 2:
+        c = (7 * prev_rank + 9) // 10
     else:
-        c = (7 * prev_rank + 9) // 10 + OVERSAMPLE
-    return round8(max(MIN_COLS, c))
+        c = (3 * prev_rank + 4) // 5
+    return round8(max(MIN_COLS, c + OVERSAMPLE))
 
 
 def grow_cols(total, maxrank):

@@ -351,11 +351,17 @@ int first_cols(long long n) { return round8((int)std::max<long long>(FIRST_COLS,
 // Probe columns at the next level from the largest rank found at the level
 // above, plus the oversampling, at least MIN_COLS, rounded up to a multiple
 // of 8: the second peeled level's sibling blocks of B F_rho B^T and B B^T
-// have larger ranks than the first level's (1.5x), below that the ranks
-// shrink by less than half per level (0.7x).
+// have larger ranks than the first level's (1.5x); the third level's shrink
+// by up to 0.65x (0.7x), later levels' by at most 0.5x (0.6x).
 int next_cols(int prev_rank, int peeled) {
-  const int c = peeled == 1 ? (3 * prev_rank + 1) / 2 + OVERSAMPLE : (7 * prev_rank + 9) / 10 + OVERSAMPLE;
-  return round8(std::max(MIN_COLS, c));
+  int c;
+  if (peeled == 1)
+    c = (3 * prev_rank + 1) / 2;
+  else if (peeled == 2)
+    c = (7 * prev_rank + 9) / 10;
+  else
+    c = (3 * prev_rank + 4) / 5;
+  return round8(std::max(MIN_COLS, c + OVERSAMPLE));
 }
 
 // Growth when some block's rank is not resolved: 1.5x, at least the rank
