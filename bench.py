@@ -107,7 +107,7 @@ def bench_batch(args):
     print("setup done: %d instances, %d points" % (len(pts), ntot), file=sys.stderr, flush=True)
 
     def step_batched():
-        B = R.BatchedFactor(pts, thetas, **kw)
+        B = R.BatchedFactor(pts, thetas, with_score=True, **kw)
         ls = B.loglik(zs)
         gs, info = B.grad(zs, spec["eps"], spec["peel_seed"])
         B.close()
@@ -190,7 +190,8 @@ def main():
     print("setup done: n=%d" % n, file=sys.stderr, flush=True)
 
     def step():
-        F = R.Factor(P, theta, **kw)
+        # Sigma_rho is factored beside Sigma (second stream), as the score needs it
+        F = R.Factor(P, theta, with_score=True, **kw)
         ell = F.loglik(z)
         g, info = F.grad(z, spec["eps"], spec.get("peel_seed", 0))
         F.close()

@@ -74,12 +74,16 @@ typedef struct {
                            (X_sr, X_rr, W, X_ss) on FP32 matrix cores with FP32
                            accumulation; the IDs, the Cholesky factors of the redundant
                            blocks and of the root, log|F| and every sweep stay FP64 */
+  int with_score;       /* 1: rsf_factor_create also factors the derivative matrix
+                           Sigma_rho that rsf_grad needs (Algorithm 1), on a second
+                           stream while Sigma is factored; rsf_grad then reuses it.
+                           0 (default): rsf_grad factors Sigma_rho itself */
 } rsf_opts;
 
 enum { RSF_FP64 = 0, RSF_MIXED = 1 };
 
 /* Fills *opts with the defaults above (n_prox 256, 4 rings, 1.8, 1.75, 2.45,
- * alpha 1, no cap, FP64).  Errors: RSF_E_INVALID if opts is NULL. */
+ * alpha 1, no cap, FP64, with_score 0).  Errors: RSF_E_INVALID if opts is NULL. */
 rsf_status rsf_opts_default(rsf_opts* opts);
 
 /* Builds F ~= Sigma(theta) (Section 2, eq. rskelf; Algorithm 1, step "factor").

@@ -5,6 +5,10 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
+#include <map>
+#include <mutex>
+#include <thread>
 
 #include "rsf.h"
 
@@ -34,6 +38,23 @@ int guarded(F&& f) {
 }
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// A second stream per device for work that runs beside the caller's stream
+// (created on first use, default priority, kept until the process ends: the
+// device pool may hold extents released on it).
+static hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  RSF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  RSF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  streams[dev] = s;
+  return s;
+}
 
 void check_handle(rsf_factor f) { RSF_CHECK(f != nullptr, RSF_E_INVALID, "null factor handle"); }
 
@@ -69,6 +90,7 @@ rsf_status rsf_opts_default(rsf_opts* o) {
   o->rq_alpha = 1.0;
   o->mem_cap_bytes = 0;
   o->precision = RSF_FP64;
+  o->with_score = 0;
   return RSF_OK;
 }
 
@@ -104,6 +126,7 @@ static rsf_factor_s* create_handle(const std::vector<std::vector<double>>& xy, c
   RSF_CHECK(o.r_near > 0 && o.prox_r_in > 0 && o.prox_r_out >= o.prox_r_in && o.rq_alpha > 0, RSF_E_INVALID,
             "bad proxy geometry or rq_alpha");
   RSF_CHECK(o.precision == RSF_FP64 || o.precision == RSF_MIXED, RSF_E_INVALID, "unknown precision");
+  RSF_CHECK(o.with_score == 0 || o.with_score == 1, RSF_E_INVALID, "with_score must be 0 or 1");
   std::unique_ptr<rsf_factor_s> h(new rsf_factor_s());
   h->opt.n_prox = o.n_prox;
   h->opt.prox_rings = o.prox_rings;
@@ -139,7 +162,33 @@ static rsf_factor_s* create_handle(const std::vector<std::vector<double>>& xy, c
   RSF_HIP(hipMemcpy(h->py, py.data(), n * sizeof(double), hipMemcpyHostToDevice));
   RSF_HIP(hipMemcpy(h->perm, h->tree.perm.data(), n * sizeof(int), hipMemcpyHostToDevice));
   make_proxy_table(h.get());
-  build_factor(h.get(), h->F, 0, s);
+  if (o.with_score) {
+    // Sigma and Sigma_rho are independent factorizations whose level loops
+    // are mostly latency-bound: Sigma_rho is built by a second host thread on
+    // the library's side stream while this thread builds Sigma on s
+    RSF_HIP(hipStreamSynchronize(s));
+    hipStream_t s2 = side_stream();
+    h->Frho.reset(new FactorData());
+    std::exception_ptr err;
+    std::thread th([&] {
+      try {
+        build_factor(h.get(), *h->Frho, 1, s2);
+        RSF_HIP(hipStreamSynchronize(s2));
+      } catch (...) {
+        err = std::current_exception();
+      }
+    });
+    try {
+      build_factor(h.get(), h->F, 0, s);
+    } catch (...) {
+      th.join();
+      throw;
+    }
+    th.join();
+    if (err) std::rethrow_exception(err);
+  } else {
+    build_factor(h.get(), h->F, 0, s);
+  }
   RSF_HIP(hipStreamSynchronize(s));
   return h.release();
 }

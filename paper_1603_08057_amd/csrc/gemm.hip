@@ -5,6 +5,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <atomic>
 #include <mutex>
 #include <tuple>
 
@@ -40,17 +41,23 @@ struct Pool {
   std::map<const void*, std::pair<int, size_t>> live;  // block -> (region, size)
 } g_pool;
 
-// best-fitting free extent over all regions; false if none
-bool pool_find(size_t n, int& ri, size_t& off, Extent& ex) {
-  bool found = false;
+// best-fitting free extent over all regions, preferring extents released on
+// stream s (reusing another stream's extent costs a synchronisation of that
+// stream); false if none
+bool pool_find(size_t n, hipStream_t s, int& ri, size_t& off, Extent& ex) {
+  bool found = false, same = false;
   for (int r = 0; r < (int)g_pool.regions.size(); ++r)
-    for (const auto& kv : g_pool.regions[r].free)
-      if (kv.second.size >= n && (!found || kv.second.size < ex.size)) {
+    for (const auto& kv : g_pool.regions[r].free) {
+      if (kv.second.size < n) continue;
+      const bool sm = kv.second.s == s;
+      if (!found || (sm && !same) || (sm == same && kv.second.size < ex.size)) {
         found = true;
+        same = sm;
         ri = r;
         off = kv.first;
         ex = kv.second;
       }
+    }
   return found;
 }
 
@@ -86,7 +93,7 @@ void* pool_alloc(size_t nbytes, hipStream_t s) {
   int ri = -1;
   size_t off = 0;
   Extent ex{0, nullptr};
-  if (!pool_find(n, ri, off, ex)) {
+  if (!pool_find(n, s, ri, off, ex)) {
     // a new region: at least REGION_MIN, or the request rounded to 2 MiB
     const size_t rs = std::max(REGION_MIN, (n + (size_t(2) << 20) - 1) / (size_t(2) << 20) * (size_t(2) << 20));
     void* base = nullptr;
@@ -114,7 +121,7 @@ void* pool_alloc(size_t nbytes, hipStream_t s) {
       g_pool.regions.push_back(std::move(g));
     }
     RSF_HIP(e);
-    RSF_CHECK(pool_find(n, ri, off, ex), RSF_E_OOM, "device pool: no extent after growth");
+    RSF_CHECK(pool_find(n, s, ri, off, ex), RSF_E_OOM, "device pool: no extent after growth");
   }
   Region& g = g_pool.regions[ri];
   g.free.erase(off);
@@ -537,24 +544,38 @@ struct TraceEv {
   hipEvent_t a, b;
   std::string tag;
 };
+// One record for the process; launches may come from several host threads
+// (the two factorizations built side by side), so the record is locked and
+// the call-site tag and the pause flag are per thread.
 struct GemmTrace {
-  bool on = false;
+  std::atomic<bool> on{false};
+  std::mutex mu;
   std::vector<TraceEv> ev;
   double ms = 0.0, flops = 0.0, bytes = 0.0;
   long long launches = 0;
-  std::string tag = "other";
   std::map<std::string, double> tag_ms, tag_flops;
 } g_trace;
+thread_local std::string t_tag = "other";
+thread_local bool t_paused = false;
+bool tracing() { return g_trace.on.load() && !t_paused; }
+void trace_push(hipEvent_t e0, hipEvent_t e1, const std::string& tag, double flops, double bytes) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  g_trace.ev.push_back(TraceEv{e0, e1, tag});
+  g_trace.flops += flops;
+  g_trace.bytes += bytes;
+  g_trace.launches += 1;
+  g_trace.tag_flops[tag] += flops;
+}
 }  // namespace
 
 void trace_enable(bool on) { g_trace.on = on; }
 
-std::string trace_current() { return g_trace.tag; }
-TracePause::TracePause() : was(g_trace.on) { g_trace.on = false; }
-TracePause::~TracePause() { g_trace.on = was; }
+std::string trace_current() { return t_tag; }
+TracePause::TracePause() : was(t_paused) { t_paused = true; }
+TracePause::~TracePause() { t_paused = was; }
 
 TraceLaunch::TraceLaunch(hipStream_t st, double fl, double by) : s(st), flops(fl), bytes(by) {
-  if (!g_trace.on) return;
+  if (!tracing()) return;
   RSF_HIP(hipEventCreate(&e0));
   RSF_HIP(hipEventCreate(&e1));
   RSF_HIP(hipEventRecord(e0, s));
@@ -562,16 +583,13 @@ TraceLaunch::TraceLaunch(hipStream_t st, double fl, double by) : s(st), flops(fl
 TraceLaunch::~TraceLaunch() {
   if (!e0) return;
   (void)hipEventRecord(e1, s);
-  g_trace.ev.push_back(TraceEv{e0, e1, g_trace.tag});
-  g_trace.flops += flops;
-  g_trace.bytes += bytes;
-  g_trace.launches += 1;
-  g_trace.tag_flops[g_trace.tag] += flops;
+  trace_push(e0, e1, t_tag, flops, bytes);
 }
-TraceTag::TraceTag(const char* t) : prev(g_trace.tag) { g_trace.tag = t; }
-TraceTag::~TraceTag() { g_trace.tag = prev; }
+TraceTag::TraceTag(const char* t) : prev(t_tag) { t_tag = t; }
+TraceTag::~TraceTag() { t_tag = prev; }
 
 void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset) {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
   for (auto& e : g_trace.ev) {
     float t = 0.f;
     RSF_HIP(hipEventSynchronize(e.b));
@@ -595,6 +613,7 @@ void trace_read(double* ms, double* flops, double* bytes, long long* launches, b
 }
 
 std::string trace_tags() {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
   std::string out;
   for (auto& kv : g_trace.tag_ms) {
     char buf[160];
@@ -877,7 +896,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
         sk += d.K;
       }
       const double np = (double)probs[g].size();
-      fprintf(stderr, "[gemm] %s g%d probs %zu tiles %d gflop %.3f M %.0f N %.0f K %.0f\n", g_trace.tag.c_str(), g,
+      fprintf(stderr, "[gemm] %s g%d probs %zu tiles %d gflop %.3f M %.0f N %.0f K %.0f\n", t_tag.c_str(), g,
               probs[g].size(), toff[g].back(), fl * 1e-9, sm / np, sn / np, sk / np);
     }
   }
@@ -902,7 +921,8 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   GemmDesc* dd = reinterpret_cast<GemmDesc*>(dblk);
   int* dc = reinterpret_cast<int*>(dblk + b_desc);
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (g_trace.on) {
+  const bool traced = tracing();
+  if (traced) {
     RSF_HIP(hipEventCreate(&e0));
     RSF_HIP(hipEventCreate(&e1));
     RSF_HIP(hipEventRecord(e0, s));
@@ -932,15 +952,10 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gx, (unsigned)reds.size()), dim3(256), 0, s, dr);
     RSF_HIP(hipGetLastError());
   }
-  if (g_trace.on) {
+  if (traced) {
     RSF_HIP(hipEventRecord(e1, s));
     // launches with FP32 products are booked under "<phase>/f32"
-    const std::string tag = probs[9].empty() ? g_trace.tag : g_trace.tag + "/f32";
-    g_trace.ev.push_back(TraceEv{e0, e1, tag});
-    g_trace.flops += flops;
-    g_trace.bytes += bytes;
-    g_trace.launches += 1;
-    g_trace.tag_flops[tag] += flops;
+    trace_push(e0, e1, probs[9].empty() ? t_tag : t_tag + "/f32", flops, bytes);
   }
 }
 

@@ -103,3 +103,33 @@ def test_grad_matches_central_difference_of_frozen_loglik():
         tm[i] -= h
         fd = (dense.loglik(P, z, tp, K.MATERN32)[0] - dense.loglik(P, z, tm, K.MATERN32)[0]) / (2 * h)
         assert g[i] == pytest.approx(fd, rel=1e-4, abs=1e-3)
+
+
+def test_with_score_builds_sigma_rho_alongside():
+    """with_score: Sigma_rho factored on the side stream during the create
+    call gives the same score, bitwise, as factoring it inside the grad call;
+    the batched handle too."""
+    print("with_score n=4096", flush=True)
+    n, theta = 4096, (0.05, 1.0, 1e-4)
+    P = W.uniform_points(n, 11)
+    z = _t(W.gaussian(n, 12))
+    kw = dict(kernel=K.MATERN32, eps=1e-6, leaf=64)
+    F = R.Factor(_t(P), theta, **kw)
+    g0, i0 = F.grad(z, 1e-6, 33)
+    l0 = F.loglik(z)
+    F.close()
+    G = R.Factor(_t(P), theta, with_score=True, **kw)
+    g1, i1 = G.grad(z, 1e-6, 33)
+    l1 = G.loglik(z)
+    G.close()
+    assert l1 == l0
+    assert list(g1) == list(g0)
+    assert list(i1.peel_cols) == list(i0.peel_cols)
+    pts = [_t(W.uniform_points(m, 20 + m)) for m in (700, 1500)]
+    zs = [_t(W.gaussian(m, 30 + m)) for m in (700, 1500)]
+    th = [theta, (0.08, 1.5, 1e-3)]
+    B0 = R.BatchedFactor(pts, th, **kw)
+    B1 = R.BatchedFactor(pts, th, with_score=True, **kw)
+    a0, _ = B0.grad(zs, 1e-6, 7)
+    a1, _ = B1.grad(zs, 1e-6, 7)
+    assert np.array_equal(np.asarray(a0), np.asarray(a1))
