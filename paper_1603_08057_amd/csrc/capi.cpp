@@ -39,23 +39,6 @@ int guarded(F&& f) {
 
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
-// A second stream per device for work that runs beside the caller's stream
-// (created on first use, default priority, kept until the process ends: the
-// device pool may hold extents released on it).
-static hipStream_t side_stream() {
-  static std::mutex mu;
-  static std::map<int, hipStream_t> streams;
-  int dev = 0;
-  RSF_HIP(hipGetDevice(&dev));
-  std::lock_guard<std::mutex> lk(mu);
-  auto it = streams.find(dev);
-  if (it != streams.end()) return it->second;
-  hipStream_t s = nullptr;
-  RSF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-  streams[dev] = s;
-  return s;
-}
-
 void check_handle(rsf_factor f) { RSF_CHECK(f != nullptr, RSF_E_INVALID, "null factor handle"); }
 
 void make_proxy_table(rsf_factor_s* h) {

@@ -7,12 +7,31 @@
 // and the remaining DOFs of the root get a blocked dense Cholesky.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <mutex>
 
 #include "rsf.h"
 
 namespace rsf {
 
 // ------------------------------------------------------------------ small helpers
+// A second stream per device for work that runs beside the caller's stream
+// (created on first use, default priority, kept until the process ends: the
+// device pool may hold extents released on it).
+hipStream_t side_stream() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  RSF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t s = nullptr;
+  RSF_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+  streams[dev] = s;
+  return s;
+}
+
 __global__ void fill_kernel(double* p, long long n, double v) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x)

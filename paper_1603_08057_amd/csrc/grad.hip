@@ -12,6 +12,8 @@
 // and share the product B^T W, so one probe block costs one and a half solve
 // sweeps and one multiply sweep.
 #include <chrono>
+#include <exception>
+#include <thread>
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -407,11 +409,39 @@ struct Peeler {
     const long long n = t.n, sz = n * nc;
     double* H = scr.make<double>(sz);
     copy_dev(H, X, sz, s);
-    sweep_half_down(h, h->F, H, nc, nc, scr, s, cols);          // B^T X
+    sweep_half_down(h, h->F, H, nc, nc, scr, s, cols);  // B^T X
     copy_dev(out0, H, sz, s);
-    sweep_half_up(h, h->F, out0, nc, nc, scr, s, cols);         // B B^T X
-    sweep_apply_mult(h, *h->Frho, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
-    sweep_half_up(h, h->F, out1, nc, nc, scr, s, cols);         // B F_rho B^T X
+    // B B^T X runs on the side stream (second host thread) beside
+    // F_rho B^T X and B F_rho B^T X here: the two sweeps are independent and
+    // each leaves part of the GPU idle
+    hipStream_t s2 = side_stream();
+    hipEvent_t fork = nullptr, done = nullptr;
+    RSF_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+    RSF_HIP(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+    RSF_HIP(hipEventRecord(fork, s));
+    RSF_HIP(hipStreamWaitEvent(s2, fork, 0));
+    std::exception_ptr err;
+    std::thread th([&] {
+      try {
+        Scratch sc2(s2);
+        sweep_half_up(h, h->F, out0, nc, nc, sc2, s2, cols);  // B B^T X
+        RSF_HIP(hipEventRecord(done, s2));
+      } catch (...) {
+        err = std::current_exception();
+      }
+    });
+    try {
+      sweep_apply_mult(h, *h->Frho, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
+      sweep_half_up(h, h->F, out1, nc, nc, scr, s, cols);            // B F_rho B^T X
+    } catch (...) {
+      th.join();
+      throw;
+    }
+    th.join();
+    if (err) std::rethrow_exception(err);
+    RSF_HIP(hipStreamWaitEvent(s, done, 0));
+    (void)hipEventDestroy(fork);
+    (void)hipEventDestroy(done);
   }
 
   int cols_of(const int* cols, int box, int nc) const { return cols ? std::min(nc, cols[t.inst[box]]) : nc; }

@@ -141,6 +141,10 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s);
 // undefined.
 void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld,
                  Scratch& scr, hipStream_t s, const int* inst_cols = nullptr);
+// The library's second stream on the current device (for work that runs
+// beside the caller's stream; never destroyed).
+hipStream_t side_stream();
+
 // X = B X and X = B^T X for F^-1 = B^T B (B: the up sweep, then L_root^-1)
 void sweep_half_up(const rsf_factor_s* h, const FactorData& F, double* X, int nc, long long ld, Scratch& scr,
                    hipStream_t s, const int* inst_cols = nullptr);
