@@ -212,7 +212,9 @@ def main():
     torch.cuda.synchronize()
     elapsed = time.time() - t0
     R.trace_enable(False)
-    ms, flops, nbytes, launches, phases = R.trace_read(reset=True, phases=True)
+    ms, flops, nbytes, launches, phases = R.trace_read(reset=False, phases=True)
+    busy = R.trace_busy_ms()
+    R.trace_read(reset=True)
     ms_per_step = 1000.0 * elapsed / args.steps
     # phases are "<phase>" or "<phase>/<sweep direction><depth>": the JSON line
     # carries the phase totals, stderr the per-level split
@@ -254,6 +256,10 @@ def main():
                      "launches": launches, "kernel_ms_per_step": ms / args.steps,
                      "flops_per_launch": flops / max(launches, 1),
                      "avg_launch_us": 1000.0 * ms / max(launches, 1),
+                     # launches on the two streams overlap: the family's busy time
+                     # (union of the launch intervals) and the rate over it
+                     "busy_ms_per_step": busy / args.steps,
+                     "achieved_over_busy_time": (flops / (busy * 1e-3) / 1e12) if busy > 0 else 0.0,
                      "phases": {k: {"ms_per_step": v[0] / args.steps,
                                     "tflops": (v[1] / (v[0] * 1e-3) / 1e12) if v[0] > 0 else 0.0}
                                 for k, v in sorted(phases.items())}},

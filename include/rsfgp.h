@@ -226,10 +226,15 @@ rsf_status rsf_skeleton_export(rsf_factor f, int level, int32_t* offsets, int32_
  * 8 (M K + K N + M N [+ M N when C is read]) bytes per problem.
  * rsf_trace_read synchronises on the recorded events and returns the summed
  * kernel time (ms), flops, bytes and launch count (any output may be NULL);
- * reset != 0 clears the counters.  Not thread-safe: one tracing client at a time. */
+ * reset != 0 clears the counters.  Launches from the library's own helper
+ * threads are recorded too; one tracing client (caller) at a time. */
 rsf_status rsf_trace_enable(int on);
 rsf_status rsf_trace_read(double* gemm_ms, double* gemm_flops, double* gemm_bytes, int64_t* gemm_launches,
                           int reset);
+/* The traced launches' busy time: the length (ms) of the union of their
+ * intervals, which is below the summed time when launches on the library's
+ * two streams overlap; as of the last rsf_trace_read (before its reset). */
+rsf_status rsf_trace_busy(double* busy_ms);
 /* The same GEMM time split by phase, as "phase:ms:flops;..." (NUL-terminated,
  * truncated to len - 1 characters); call after rsf_trace_read without reset.
  * Phases: factor, factor_rho, chol, sweep_solve, sweep_mult, sweep_sqrt,

@@ -78,6 +78,7 @@ def load():
         "rsf_trace_enable": ([C.c_int], C.c_int),
         "rsf_trace_read": ([dp, dp, dp, C.POINTER(C.c_int64), C.c_int], C.c_int),
         "rsf_trace_phases": ([C.c_char_p, C.c_size_t], C.c_int),
+        "rsf_trace_busy": ([dp], C.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -123,6 +124,13 @@ def _colmajor(b, n):
 def trace_enable(on=True):
     """Starts / stops event tracing of the batched matrix-core GEMM launches."""
     _check(load().rsf_trace_enable(1 if on else 0))
+
+
+def trace_busy_ms():
+    """Union of the traced launches' intervals (ms) as of the last trace_read."""
+    out = C.c_double()
+    _check(load().rsf_trace_busy(C.byref(out)))
+    return out.value
 
 
 def trace_read(reset=False, phases=False):

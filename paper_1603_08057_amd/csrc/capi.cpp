@@ -510,6 +510,13 @@ rsf_status rsf_trace_read(double* gemm_ms, double* gemm_flops, double* gemm_byte
   });
 }
 
+rsf_status rsf_trace_busy(double* busy_ms) {
+  return guarded([&] {
+    RSF_CHECK(busy_ms != nullptr, RSF_E_INVALID, "null output");
+    *busy_ms = trace_busy();
+  });
+}
+
 rsf_status rsf_trace_phases(char* buf, size_t len) {
   return guarded([&] {
     RSF_CHECK(buf != nullptr && len > 0, RSF_E_INVALID, "null buffer");

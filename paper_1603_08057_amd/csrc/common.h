@@ -196,6 +196,8 @@ void copy_blocks(const std::vector<CopyBlock>& jobs, Scratch& scr, hipStream_t s
 // its stream, with the algorithmic flops (2 M N K) and operand bytes counted.
 void trace_enable(bool on);
 void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset);
+// union of the traced launches' intervals (ms) as of the last trace_read
+double trace_busy();
 // "tag:ms:flops;..." per call-site tag (read after trace_read)
 std::string trace_tags();
 // The current phase name.

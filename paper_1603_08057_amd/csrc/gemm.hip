@@ -552,6 +552,7 @@ struct GemmTrace {
   std::mutex mu;
   std::vector<TraceEv> ev;
   double ms = 0.0, flops = 0.0, bytes = 0.0;
+  double busy = 0.0, last_busy = 0.0;  // union of the launch intervals (ms)
   long long launches = 0;
   std::map<std::string, double> tag_ms, tag_flops;
 } g_trace;
@@ -590,26 +591,54 @@ TraceTag::~TraceTag() { t_tag = prev; }
 
 void trace_read(double* ms, double* flops, double* bytes, long long* launches, bool reset) {
   std::lock_guard<std::mutex> lk(g_trace.mu);
+  // launches on different streams may overlap: besides the summed durations,
+  // the length of the union of the intervals (timestamps relative to the
+  // first launch's start event)
+  std::vector<std::pair<double, double>> iv;
   for (auto& e : g_trace.ev) {
-    float t = 0.f;
+    float t = 0.f, a = 0.f;
     RSF_HIP(hipEventSynchronize(e.b));
     RSF_HIP(hipEventElapsedTime(&t, e.a, e.b));
+    RSF_HIP(hipEventElapsedTime(&a, g_trace.ev.front().a, e.a));
+    iv.emplace_back((double)a, (double)a + t);
     g_trace.ms += t;
     g_trace.tag_ms[e.tag] += t;
+  }
+  std::sort(iv.begin(), iv.end());
+  double cur0 = 0.0, cur1 = 0.0;
+  bool open = false;
+  for (const auto& x : iv) {
+    if (open && x.first <= cur1) {
+      cur1 = std::max(cur1, x.second);
+    } else {
+      if (open) g_trace.busy += cur1 - cur0;
+      cur0 = x.first;
+      cur1 = x.second;
+      open = true;
+    }
+  }
+  if (open) g_trace.busy += cur1 - cur0;
+  for (auto& e : g_trace.ev) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
   }
   g_trace.ev.clear();
+  g_trace.last_busy = g_trace.busy;
   if (ms) *ms = g_trace.ms;
   if (flops) *flops = g_trace.flops;
   if (bytes) *bytes = g_trace.bytes;
   if (launches) *launches = g_trace.launches;
   if (reset) {
-    g_trace.ms = g_trace.flops = g_trace.bytes = 0.0;
+    g_trace.ms = g_trace.flops = g_trace.bytes = g_trace.busy = 0.0;
     g_trace.launches = 0;
     g_trace.tag_ms.clear();
     g_trace.tag_flops.clear();
   }
+}
+
+double trace_busy() {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  return g_trace.last_busy;
 }
 
 std::string trace_tags() {

@@ -411,9 +411,24 @@ struct Peeler {
     copy_dev(H, X, sz, s);
     sweep_half_down(h, h->F, H, nc, nc, scr, s, cols);  // B^T X
     copy_dev(out0, H, sz, s);
-    // B B^T X runs on the side stream (second host thread) beside
-    // F_rho B^T X and B F_rho B^T X here: the two sweeps are independent and
-    // each leaves part of the GPU idle
+    // B B^T X beside F_rho B^T X and B F_rho B^T X: the two sweeps are
+    // independent and each leaves part of the GPU idle
+    beside(
+        [&](hipStream_t s2) {
+          Scratch sc2(s2);
+          sweep_half_up(h, h->F, out0, nc, nc, sc2, s2, cols);  // B B^T X
+        },
+        [&] {
+          sweep_apply_mult(h, *h->Frho, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
+          sweep_half_up(h, h->F, out1, nc, nc, scr, s, cols);            // B F_rho B^T X
+        });
+  }
+
+  // Runs side(s2) on the library's side stream from a second host thread
+  // while here() runs on s; the side work starts after everything already
+  // enqueued on s, and s waits for it before this returns.
+  template <class SideFn, class HereFn>
+  void beside(SideFn side, HereFn here) {
     hipStream_t s2 = side_stream();
     hipEvent_t fork = nullptr, done = nullptr;
     RSF_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
@@ -423,22 +438,28 @@ struct Peeler {
     std::exception_ptr err;
     std::thread th([&] {
       try {
-        Scratch sc2(s2);
-        sweep_half_up(h, h->F, out0, nc, nc, sc2, s2, cols);  // B B^T X
+        side(s2);
         RSF_HIP(hipEventRecord(done, s2));
       } catch (...) {
         err = std::current_exception();
       }
     });
     try {
-      sweep_apply_mult(h, *h->Frho, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
-      sweep_half_up(h, h->F, out1, nc, nc, scr, s, cols);            // B F_rho B^T X
+      here();
     } catch (...) {
       th.join();
+      (void)hipStreamSynchronize(s2);
+      (void)hipEventDestroy(fork);
+      (void)hipEventDestroy(done);
       throw;
     }
     th.join();
-    if (err) std::rethrow_exception(err);
+    if (err) {
+      (void)hipStreamSynchronize(s2);
+      (void)hipEventDestroy(fork);
+      (void)hipEventDestroy(done);
+      std::rethrow_exception(err);
+    }
     RSF_HIP(hipStreamWaitEvent(s, done, 0));
     (void)hipEventDestroy(fork);
     (void)hipEventDestroy(done);
@@ -460,7 +481,8 @@ struct Peeler {
   // With cp, X is a probe chunk and U_b^T X[I_b] is formed per quadrant from
   // the rows of that quadrant only (the other rows are zero in its columns).
   void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr, const int* cols,
-                        const CompactProbes* cp = nullptr) {
+                        const CompactProbes* cp = nullptr, hipStream_t st = nullptr) {
+    if (!st) st = s;
     TraceTag tag("peel_subtract");
     for (int m = 1; m < upto && m < (int)lr[op].size(); ++m) {
       const LevelLR& L = lr[op][m];
@@ -471,7 +493,7 @@ struct Peeler {
       double* P = scr.make<double>(std::max<long long>(poff[nbx], 1));
       double* Q = scr.make<double>(std::max<long long>(poff[nbx], 1));
       // a pair with one empty basis contributes nothing: its Q segment stays zero
-      fill_zero(Q, poff[nbx], s);
+      fill_zero(Q, poff[nbx], st);
       std::vector<GemmDesc> g1;
       if (!cp) {
         for (int b = 0; b < nbx; ++b) {
@@ -494,7 +516,7 @@ struct Peeler {
           }
         }
         int* drows = scr.make<int>(std::max<size_t>(rows.size(), 1));
-        upload(drows, rows, s);
+        upload(drows, rows, st);
         for (int b = 0; b < nbx; ++b) {
           const int box = L.boxes[b], cnt = t.count[box];
           const int N = cols_of(cols, box, nc) / 4;
@@ -515,7 +537,7 @@ struct Peeler {
           }
         }
       }
-      gemm_batched(g1, scr, s);
+      gemm_batched(g1, scr, st);
       std::vector<GemmDesc> g2;
       for (size_t p = 0; p < L.pairs.size(); ++p) {
         const PairLR& pr = L.pairs[p];
@@ -529,14 +551,14 @@ struct Peeler {
                                panel(P + poff[L.pos_i[p]] + (long long)L.off_i[p] * nc, nc), 0.0,
                                panel(Q + poff[L.pos_j[p]] + (long long)L.off_j[p] * nc, nc)));
       }
-      gemm_batched(g2, scr, s);
+      gemm_batched(g2, scr, st);
       std::vector<GemmDesc> g3;
       for (int b = 0; b < nbx; ++b) {
         const int box = L.boxes[b];
         g3.push_back(gemm_desc(t.count[box], cols_of(cols, box, nc), L.K[b], -1.0, colmaj(L.U[b], t.count[box]),
                                panel(Q + poff[b], nc), 1.0, panel(out + (long long)t.begin[box] * nc, nc)));
       }
-      gemm_batched(g3, scr, s);
+      gemm_batched(g3, scr, st);
     }
   }
 
@@ -619,9 +641,35 @@ struct Peeler {
   //     equations, with (Om_i^T U1)^T (Om_i^T Y_ij) formed as (Om_i A1)^T Y_ij.
   // Y: samples, row d holds quadrant block q at columns [q C, q C + tot); Om:
   // probes (ld C); pivots of block e at dpiv + poff[e].
+  // Every sibling pair of one level and operator, in chunks that bound the
+  // work memory.
+  void lowrank_level(LevelLR& L, const std::vector<int>& tot, int C, const double* Yop, const double* Om,
+                     const int* dpiv, const std::vector<long long>& poff, int blk0, hipStream_t st) {
+    TraceTag tg("peel_lowrank");
+    const int np = (int)L.pairs.size();
+    int p0 = 0;
+    while (p0 < np) {
+      long long bytes = 0;
+      int p1 = p0;
+      while (p1 < np) {
+        const PairLR& pr = L.pairs[p1];
+        const long long ci = t.count[pr.i], cj = t.count[pr.j], k1 = pr.k1, k2 = pr.k2;
+        const long long total = tot[t.inst[pr.i]];
+        const long long est = 8 * (2 * (ci * k1 + cj * k2) + 4 * (k1 * k1 + k2 * k2) + 2 * total * (k1 + k2) +
+                                   total * k1 + 3 * k1 * k2 + 64);
+        if (p1 > p0 && bytes + est > LOWRANK_CHUNK_BYTES) break;
+        bytes += est;
+        ++p1;
+      }
+      lowrank_chunk(L, p0, p1, tot, C, Yop, Om, dpiv, poff, blk0, st);
+      p0 = p1;
+    }
+  }
+
   void lowrank_chunk(LevelLR& L, int p0, int p1, const std::vector<int>& tot, int C, const double* Yop,
-                     const double* Om, const int* dpiv, const std::vector<long long>& poff, int blk0) {
-    Scratch ms(s);
+                     const double* Om, const int* dpiv, const std::vector<long long>& poff, int blk0,
+                     hipStream_t st) {
+    Scratch ms(st);
     const long long ld = 4LL * C;
     // every per-pair buffer is carved from one block (one allocation per chunk)
     long long need = 0;
@@ -640,7 +688,7 @@ struct Peeler {
       return q;
     };
     int* fail = ms.make<int>(1);
-    RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
+    RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), st));
     struct Blk {
       int e, k, cnt;
       const double* Yb;
@@ -678,12 +726,12 @@ struct Peeler {
         g2.push_back(gemm_desc(b.cnt, b.k, b.k, 1.0, colmaj(b.Yg, b.cnt), colmajT(b.Li, b.k), 0.0, colmaj(b.U, b.cnt)));
       }
       GatherColsJob* dg = ms.make<GatherColsJob>(gj.size());
-      upload(dg, gj, s);
-      hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_of(maxe), (unsigned)gj.size()), dim3(256), 0, s, dg);
+      upload(dg, gj, st);
+      hipLaunchKernelGGL(gather_cols_kernel, dim3(grid_of(maxe), (unsigned)gj.size()), dim3(256), 0, st, dg);
       RSF_HIP(hipGetLastError());
-      gemm_batched(g1, ms, s);
-      batched_chol_inv(cp, fail, ms, s);
-      gemm_batched(g2, ms, s);
+      gemm_batched(g1, ms, st);
+      batched_chol_inv(cp, fail, ms, st);
+      gemm_batched(g2, ms, st);
     }
     std::vector<GemmDesc> ga, gb, gc, gd, ge, gf, gg, gh;
     std::vector<CholProblem> cn;
@@ -728,18 +776,18 @@ struct Peeler {
       gh.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(X, k1), colmaj(N2i, k2), 0.0, colmaj(pr.M, k1)));
     }
     RSF_CHECK(used <= need, RSF_E_HIP, "peeling work buffer overrun");
-    gemm_batched(ga, ms, s);
-    gemm_batched(gb, ms, s);
-    batched_chol_inv(cn, fail, ms, s);
-    gemm_batched(gc, ms, s);
-    gemm_batched(gd, ms, s);
-    gemm_batched(ge, ms, s);
-    gemm_batched(gf, ms, s);
-    gemm_batched(gg, ms, s);
-    gemm_batched(gh, ms, s);
+    gemm_batched(ga, ms, st);
+    gemm_batched(gb, ms, st);
+    batched_chol_inv(cn, fail, ms, st);
+    gemm_batched(gc, ms, st);
+    gemm_batched(gd, ms, st);
+    gemm_batched(ge, ms, st);
+    gemm_batched(gf, ms, st);
+    gemm_batched(gg, ms, st);
+    gemm_batched(gh, ms, st);
     int fh = 0;
-    RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
-    RSF_HIP(hipStreamSynchronize(s));
+    RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, st));
+    RSF_HIP(hipStreamSynchronize(st));
     RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: singular normal equations of a basis or core matrix");
   }
 
@@ -861,16 +909,24 @@ struct Peeler {
           apply_ops(Wm, 4 * ncw, B0, B1, rs, pc);
           auto c1 = std::chrono::steady_clock::now();
           const CompactProbes cpr{Om, (long long)C, &j0, &qd};
-          subtract_lowrank(0, lev, Wm, 4 * ncw, B0, rs, pc, &cpr);
-          subtract_lowrank(1, lev, Wm, 4 * ncw, B1, rs, pc, &cpr);
+          // the two operators' subtractions and sample stores side by side
+          beside(
+              [&](hipStream_t s2) {
+                Scratch r2(s2);
+                subtract_lowrank(1, lev, Wm, 4 * ncw, B1, r2, pc, &cpr, s2);
+                hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s2, dqd, drinst, dact, dj0,
+                                   n, ncw, C, B1, Y[1]);
+                RSF_HIP(hipGetLastError());
+              },
+              [&] {
+                subtract_lowrank(0, lev, Wm, 4 * ncw, B0, rs, pc, &cpr);
+                hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0,
+                                   n, ncw, C, B0, Y[0]);
+                RSF_HIP(hipGetLastError());
+              });
           auto c2 = std::chrono::steady_clock::now();
           tm[0] += std::chrono::duration<double>(c1 - c0).count();
           tm[1] += std::chrono::duration<double>(c2 - c1).count();
-          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, C,
-                             B0, Y[0]);
-          hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, C,
-                             B1, Y[1]);
-          RSF_HIP(hipGetLastError());
         }
         for (int i = 0; i < ni; ++i) tot[i] = cc[i];
         // ranks of every sample block (both operators) by pivoted Cholesky of
@@ -1002,27 +1058,12 @@ struct Peeler {
           }
         }
         RSF_CHECK(lused <= std::max<long long>(lvl, 1), RSF_E_HIP, "low-rank store overrun");
-        // the pairs in chunks that bound the work memory
-        int p0 = 0;
-        while (p0 < np) {
-          long long bytes = 0;
-          int p1 = p0;
-          while (p1 < np) {
-            const PairLR& pr = L.pairs[p1];
-            const long long ci = t.count[pr.i], cj = t.count[pr.j], k1 = pr.k1, k2 = pr.k2;
-            const long long total = tot[t.inst[pr.i]];
-            const long long est = 8 * (2 * (ci * k1 + cj * k2) + 4 * (k1 * k1 + k2 * k2) + 2 * total * (k1 + k2) +
-                                       total * k1 + 3 * k1 * k2 + 64);
-            if (p1 > p0 && bytes + est > LOWRANK_CHUNK_BYTES) break;
-            bytes += est;
-            ++p1;
-          }
-          auto c0 = std::chrono::steady_clock::now();
-          lowrank_chunk(L, p0, p1, tot, C, Y[op], Om, dpiv, poff, op * nblk);
-          tm[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
-          p0 = p1;
-        }
       }
+      // bases and core matrices: operator 1 on the side stream beside operator 0
+      auto c0 = std::chrono::steady_clock::now();
+      beside([&](hipStream_t s2) { lowrank_level(lr[1][lev], tot, C, Y[1], Om, dpiv, poff, nblk, s2); },
+             [&] { lowrank_level(lr[0][lev], tot, C, Y[0], Om, dpiv, poff, 0, s); });
+      tm[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
     }
     // extraction at the leaves: traces of every instance over its own leaves
     const auto cx0 = std::chrono::steady_clock::now();
