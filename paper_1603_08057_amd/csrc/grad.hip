@@ -566,9 +566,10 @@ struct Peeler {
   // by blocked pivoted Cholesky; pivots of matrix e go to dpiv + poff[e].
   // G is preserved.
   void pivot_ranks(const double* G, const std::vector<long long>& goff, const std::vector<int>& c,
-                   const std::vector<long long>& poff, double tol2, int* dpiv, std::vector<int>& rk) {
+                   const std::vector<long long>& poff, double tol2, int* dpiv, std::vector<int>& rk,
+                   hipStream_t st) {
     TraceTag tag("peel_pivot");
-    Scratch ws(s);  // work buffers live only through this call
+    Scratch ws(st);  // work buffers live only through this call
     const int nj = (int)c.size();
     const int cmax = *std::max_element(c.begin(), c.end());
     RSF_CHECK(cmax <= PCHOL_MAXN, RSF_E_INVALID,
@@ -577,7 +578,7 @@ struct Peeler {
     std::vector<long long> doff(nj + 1, 0);
     for (int e = 0; e < nj; ++e) doff[e + 1] = doff[e] + c[e];
     double* Gw = ws.make<double>(std::max<long long>(goff[nj], 1));
-    copy_dev(Gw, G, goff[nj], s);
+    copy_dev(Gw, G, goff[nj], st);
     double* d = ws.make<double>(std::max<long long>(doff[nj], 1));
     double* Lp = ws.make<double>(std::max<long long>(doff[nj] * NB, 1));
     double* d1 = ws.make<double>(nj);
@@ -587,8 +588,8 @@ struct Peeler {
       all[e] = PpanelJob{Gw + goff[e], d + doff[e], Lp + doff[e] * NB, dpiv + poff[e], state + 2 * e, d1 + e, c[e]};
     {
       PpanelJob* dj = ws.make<PpanelJob>(nj);
-      upload(dj, all, s);
-      hipLaunchKernelGGL(ppanel_init_kernel, dim3(nj), dim3(256), 0, s, dj);
+      upload(dj, all, st);
+      hipLaunchKernelGGL(ppanel_init_kernel, dim3(nj), dim3(256), 0, st, dj);
       RSF_HIP(hipGetLastError());
     }
     std::vector<int> active(nj);
@@ -599,22 +600,22 @@ struct Peeler {
       std::vector<PpanelJob> jobs;
       for (int e : active) jobs.push_back(all[e]);
       PpanelJob* dj = ws.make<PpanelJob>(jobs.size());
-      upload(dj, jobs, s);
+      upload(dj, jobs, st);
       const dim3 grid((unsigned)jobs.size()), blk(PCHOL_WG);
       // one row per thread and panel column: small Gram matrices take small workgroups
       if (cmax <= 256)
-        hipLaunchKernelGGL((ppanel_kernel<1, 32, 256>), grid, dim3(256), 0, s, dj, tol2);
+        hipLaunchKernelGGL((ppanel_kernel<1, 32, 256>), grid, dim3(256), 0, st, dj, tol2);
       else if (cmax <= 1024)
-        hipLaunchKernelGGL((ppanel_kernel<1, 32, 1024>), grid, blk, 0, s, dj, tol2);
+        hipLaunchKernelGGL((ppanel_kernel<1, 32, 1024>), grid, blk, 0, st, dj, tol2);
       else if (cmax <= 2048)
-        hipLaunchKernelGGL((ppanel_kernel<2, 16, 1024>), grid, blk, 0, s, dj, tol2);
+        hipLaunchKernelGGL((ppanel_kernel<2, 16, 1024>), grid, blk, 0, st, dj, tol2);
       else
-        hipLaunchKernelGGL((ppanel_kernel<4, 8, 1024>), grid, blk, 0, s, dj, tol2);
+        hipLaunchKernelGGL((ppanel_kernel<4, 8, 1024>), grid, blk, 0, st, dj, tol2);
       RSF_HIP(hipGetLastError());
       // every few panels, drop the matrices that have reached their rank
       if (pnl % 4 == 3 || pnl + 1 >= npanel) {
-        RSF_HIP(hipMemcpyAsync(hs.data(), state, hs.size() * sizeof(int), hipMemcpyDeviceToHost, s));
-        RSF_HIP(hipStreamSynchronize(s));
+        RSF_HIP(hipMemcpyAsync(hs.data(), state, hs.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        RSF_HIP(hipStreamSynchronize(st));
         std::vector<int> still;
         for (int e : active)
           if (!hs[2 * e + 1]) still.push_back(e);
@@ -625,7 +626,7 @@ struct Peeler {
       for (int e : active)
         tg.push_back(gemm_desc(c[e], c[e], NB, -1.0, colmaj(all[e].Lp, c[e]), colmajT(all[e].Lp, c[e]), 1.0,
                                colmaj(Gw + goff[e], c[e])));
-      gemm_batched(tg, ws, s);
+      gemm_batched(tg, ws, st);
     }
     RSF_CHECK(active.empty(), RSF_E_INVALID, "pivoted Cholesky did not terminate");
     rk.assign(nj, 0);
@@ -938,40 +939,45 @@ struct Peeler {
         }
         scr.release(dpiv);
         dpiv = scr.make<int>(std::max<long long>(poff[2 * nblk], 1));
-        for (int e0 = 0; e0 < 2 * nblk;) {
-          std::vector<long long> goff(1, 0);
-          std::vector<int> cs;
-          int e1 = e0;
-          while (e1 < 2 * nblk) {
-            const long long add = (long long)bc[e1] * bc[e1];
-            if (e1 > e0 && 8 * 2 * (goff.back() + add) > GRAM_CHUNK_BYTES) break;
-            goff.push_back(goff.back() + add);
-            cs.push_back(bc[e1]);
-            ++e1;
+        // the sample blocks of the two operators side by side (operator 1 on
+        // the side stream), each in chunks that bound the Gram storage
+        auto gram_ranks = [&](int ebeg, int eend, hipStream_t st) {
+          for (int e0 = ebeg; e0 < eend;) {
+            std::vector<long long> goff(1, 0);
+            std::vector<int> cs;
+            int e1 = e0;
+            while (e1 < eend) {
+              const long long add = (long long)bc[e1] * bc[e1];
+              if (e1 > e0 && 8 * 2 * (goff.back() + add) > GRAM_CHUNK_BYTES) break;
+              goff.push_back(goff.back() + add);
+              cs.push_back(bc[e1]);
+              ++e1;
+            }
+            Scratch gs(st);
+            double* Gram = gs.make<double>(std::max<long long>(goff.back(), GRAM_CHUNK_BYTES / 16));
+            std::vector<GemmDesc> g;
+            for (int idx = e0; idx < e1; ++idx) {
+              const int op = idx / nblk, e = idx % nblk;
+              const int rb = blocks[e].first, cbx = blocks[e].second, c = bc[idx];
+              const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * C + (long long)t.quad[cbx] * C;
+              g.push_back(gemm_desc(c, c, t.count[rb], 1.0, Mat{Yb, 1, 4LL * C, nullptr}, panel(Yb, 4LL * C), 0.0,
+                                    colmaj(Gram + goff[idx - e0], c)));
+            }
+            {
+              TraceTag tg("peel_gram");
+              gemm_batched(g, gs, st);
+            }
+            std::vector<long long> pv(poff.begin() + e0, poff.begin() + e1);
+            std::vector<int> rq;
+            pivot_ranks(Gram, goff, cs, pv, tol2, dpiv, rq, st);
+            for (int q = 0; q < e1 - e0; ++q) rk[e0 + q] = rq[q];
+            e0 = e1;
           }
-          Scratch gs(s);
-          double* Gram = gs.make<double>(std::max<long long>(goff.back(), GRAM_CHUNK_BYTES / 16));
-          std::vector<GemmDesc> g;
-          for (int idx = e0; idx < e1; ++idx) {
-            const int op = idx / nblk, e = idx % nblk;
-            const int rb = blocks[e].first, cbx = blocks[e].second, c = bc[idx];
-            const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * C + (long long)t.quad[cbx] * C;
-            g.push_back(gemm_desc(c, c, t.count[rb], 1.0, Mat{Yb, 1, 4LL * C, nullptr}, panel(Yb, 4LL * C), 0.0,
-                                  colmaj(Gram + goff[idx - e0], c)));
-          }
-          {
-            TraceTag tg("peel_gram");
-            auto c0 = std::chrono::steady_clock::now();
-            gemm_batched(g, gs, s);
-            tm[4] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
-          }
-          std::vector<long long> pv(poff.begin() + e0, poff.begin() + e1);
-          std::vector<int> rq;
+        };
+        {
           auto c0 = std::chrono::steady_clock::now();
-          pivot_ranks(Gram, goff, cs, pv, tol2, dpiv, rq);
+          beside([&](hipStream_t s2) { gram_ranks(nblk, 2 * nblk, s2); }, [&] { gram_ranks(0, nblk, s); });
           tm[2] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
-          for (int q = 0; q < e1 - e0; ++q) rk[e0 + q] = rq[q];
-          e0 = e1;
         }
         // an instance needs more columns while a block's rank is not
         // resolved (rank + oversampling above its columns, which are fewer
