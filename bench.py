@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--workload", default=DEFAULT)
     ap.add_argument("--n", type=int, default=None, help="override n (same recipe)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--hutch", type=int, default=0,
+                    help="score traces by Hutchinson's estimator with this many probes instead of peeling")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -193,7 +195,10 @@ def main():
         # Sigma_rho is factored beside Sigma (second stream), as the score needs it
         F = R.Factor(P, theta, with_score=True, **kw)
         ell = F.loglik(z)
-        g, info = F.grad(z, spec["eps"], spec.get("peel_seed", 0))
+        if args.hutch > 0:
+            g, info = F.grad_hutch(z, args.hutch, spec.get("peel_seed", 0))
+        else:
+            g, info = F.grad(z, spec["eps"], spec.get("peel_seed", 0))
         F.close()
         return ell, g, info
 
@@ -230,7 +235,8 @@ def main():
     phases = totals
     achieved = (flops / (ms * 1e-3)) / 1e12 if ms > 0 else 0.0
     out = {
-        "metric": "loglik+grad evals/sec at n=%d (eps=%g)" % (n, spec["eps"]),
+        "metric": ("loglik+grad evals/sec at n=%d (eps=%g)" % (n, spec["eps"]) if args.hutch <= 0 else
+                   "loglik+grad (Hutchinson traces, %d probes) evals/sec at n=%d (eps=%g)" % (args.hutch, n, spec["eps"])),
         "value": args.steps / elapsed,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -251,7 +257,8 @@ def main():
                                "box_sweep_kernel)",
                      "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
-                     "traffic": measured_traffic(launches / args.steps) if not args.n and name == DEFAULT else None,
+                     "traffic": (measured_traffic(launches / args.steps)
+                                 if not args.n and name == DEFAULT and args.hutch <= 0 else None),
                      "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
                      "launches": launches, "kernel_ms_per_step": ms / args.steps,
                      "flops_per_launch": flops / max(launches, 1),

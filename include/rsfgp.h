@@ -200,6 +200,22 @@ rsf_status rsf_loglik_batched(rsf_factor f, const double* const* d_z, double* ou
 rsf_status rsf_grad_batched(rsf_factor f, const double* const* d_z, double eps_peel, uint64_t seed,
                             double* g_nb_p, rsf_grad_info* info_or_null, void* stream);
 
+/* The score with the traces by Hutchinson's estimator (eq. hutch) instead of
+ * peeling: nprobe Rademacher vectors u_j (Philox4x32-10 keyed by seed, counter
+ * (the DOF's tree-order index within its instance, j, 0, 1), sign from the
+ * lowest bit of the first word; a batch draws what each instance draws alone),
+ * w_j = B^T u_j for F^-1 = B^T B, Tr F^-1 ~= mean |w_j|^2 and
+ * Tr F^-1 F_rho ~= mean w_j^T F_rho w_j (unbiased; the symmetric forms of
+ * Section 3 in place of the unsymmetric Sigma^-1 Sigma_rho of Section 5.2).
+ * Cheap and of statistical accuracy (the cross-check of peeling and the
+ * early-iteration gradient of Section 5.2).  Arguments as rsf_grad /
+ * rsf_grad_batched; info's peeling statistics are zero.  Errors:
+ * RSF_E_INVALID for nprobe < 1, a null argument or the wrong handle kind. */
+rsf_status rsf_grad_hutch(rsf_factor f, const double* d_z, int nprobe, uint64_t seed, double* g,
+                          rsf_grad_info* info_or_null, void* stream);
+rsf_status rsf_grad_hutch_batched(rsf_factor f, const double* const* d_z, int nprobe, uint64_t seed,
+                                  double* g_nb_p, rsf_grad_info* info_or_null, void* stream);
+
 typedef struct {
   int64_t n;
   int depth;            /* deepest level L */

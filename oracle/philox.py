@@ -19,6 +19,8 @@ sqrt(-2 log u1) cos(2 pi u2).
 
 Counter layout of one probe entry (peeling level l, probe column j, DOF d in
 tree order, operator stream s): c = (d, j, l, s), k = (seed mod 2^32, seed >> 32).
+Rademacher entries of the Hutchinson estimator use c = (d, j, 0, 1) and the
+lowest bit of the first output word: +1 when it is 0, -1 when it is 1.
 """
 import numpy as np
 
@@ -63,3 +65,10 @@ def normal(d, j, level, stream, seed):
     u1 = _uniform53(x0, x1)
     u2 = _uniform53(x2, x3)
     return np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+
+
+def rademacher(d, j, seed):
+    """+1 / -1 for counter (d, j, 0, 1) under key seed (lowest bit of word 0)."""
+    seed = int(seed)
+    x0, _, _, _ = philox4x32_10(d, j, 0, 1, seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    return np.where((x0 & np.uint32(1)) == 0, 1.0, -1.0)

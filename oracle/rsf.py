@@ -456,8 +456,25 @@ class Factor:
 LOG2PI = float(np.log(2.0 * np.pi))
 
 
+def hutchinson_traces(F, Fr, nprobe, seed):
+    """Hutchinson's estimator (eq. hutch) of Tr F^-1 and Tr F^-1 F_rho from
+    nprobe Rademacher vectors u_j (oracle.philox.rademacher over the tree
+    order): with w_j = B^T u_j (F^-1 = B^T B), u^T F^-1 u = |w|^2 and
+    u^T B F_rho B^T u = w^T F_rho w, whose expectations are the two traces.
+    Returns (t_inv, t_rho)."""
+    from . import philox
+    n = F.tree.n
+    d = np.arange(n)[:, None]
+    j = np.arange(nprobe)[None, :]
+    U = philox.rademacher(d, j, seed)
+    Wt = F.half_down(U)
+    t_inv = float(np.sum(Wt * Wt)) / nprobe
+    t_rho = float(np.sum(Wt * Fr.apply(Wt))) / nprobe
+    return t_inv, t_rho
+
+
 def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0,
-                n_prox=256, prox_rings=4, want_grad=True):
+                n_prox=256, prox_rings=4, want_grad=True, hutch_probes=0):
     """The paper's Algorithm 1 with the readings used throughout this package.
 
     l_hat = -1/2 z^T F^-1 z - 1/2 log|F| - (n/2) log 2 pi; for theta =
@@ -488,6 +505,12 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
                 mode="mult", tree=F.tree)
     aa = float(a @ a)
     q = np.array([0.5 * float(a @ Fr.apply(a)), 0.5 * (za - nug * aa) / s2, 0.5 * aa])
+
+    if hutch_probes > 0:
+        t_inv, t_rho = hutchinson_traces(F, Fr, hutch_probes, seed)
+        t = np.array([t_rho, (n - nug * t_inv) / s2, t_inv])
+        out.update(q=q, t=t, g=q - 0.5 * t, factor_rho=Fr)
+        return out
 
     def applies(Wm):
         H = F.half_down(Wm)

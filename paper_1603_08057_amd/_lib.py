@@ -74,6 +74,8 @@ def load():
         "rsf_logdet_batched": ([vp, dp], C.c_int),
         "rsf_loglik_batched": ([vp, C.POINTER(vp), dp, vp], C.c_int),
         "rsf_grad_batched": ([vp, C.POINTER(vp), C.c_double, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
+        "rsf_grad_hutch": ([vp, vp, C.c_int, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
+        "rsf_grad_hutch_batched": ([vp, C.POINTER(vp), C.c_int, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
         "rsf_graph_state": ([vp, C.POINTER(C.c_int)], C.c_int),
         "rsf_trace_enable": ([C.c_int], C.c_int),
         "rsf_trace_read": ([dp, dp, dp, C.POINTER(C.c_int64), C.c_int], C.c_int),
@@ -235,6 +237,15 @@ class Factor:
                                _stream()))
         return [g[0], g[1], g[2]], info
 
+    def grad_hutch(self, z, nprobe, seed=0):
+        """The score with Hutchinson trace estimates from nprobe Rademacher probes."""
+        z = _dev_f64(z, (self.n,))
+        g = (C.c_double * 3)()
+        info = GradInfo()
+        _check(load().rsf_grad_hutch(self._h, C.c_void_p(z.data_ptr()), int(nprobe), int(seed), g,
+                                     C.byref(info), _stream()))
+        return [g[0], g[1], g[2]], info
+
     @property
     def graph_state(self):
         """0: the log-likelihood graph is not recorded yet, 1: recorded (later
@@ -345,6 +356,14 @@ class BatchedFactor:
         g = (C.c_double * (3 * self.nb))()
         info = GradInfo()
         _check(load().rsf_grad_batched(self._h, ptrs, float(eps_peel), int(seed), g, C.byref(info), _stream()))
+        return [tuple(g[3 * i:3 * i + 3]) for i in range(self.nb)], info
+
+    def grad_hutch(self, zs, nprobe, seed=0):
+        """Scores of every instance with Hutchinson trace estimates."""
+        zs, ptrs = self._ptrs(zs)
+        g = (C.c_double * (3 * self.nb))()
+        info = GradInfo()
+        _check(load().rsf_grad_hutch_batched(self._h, ptrs, int(nprobe), int(seed), g, C.byref(info), _stream()))
         return [tuple(g[3 * i:3 * i + 3]) for i in range(self.nb)], info
 
     def tree_info(self):

@@ -535,6 +535,30 @@ rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t s
   });
 }
 
+rsf_status rsf_grad_hutch(rsf_factor f, const double* d_z, int nprobe, uint64_t seed, double* g,
+                          rsf_grad_info* info, void* stream) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(f->tree.ninst == 1, RSF_E_INVALID, "a batched handle takes rsf_grad_hutch_batched");
+    RSF_CHECK(d_z != nullptr && g != nullptr, RSF_E_INVALID, "null argument");
+    RSF_CHECK(nprobe >= 1, RSF_E_INVALID, "nprobe must be >= 1");
+    grad_eval(f, d_z, 0.0, seed, g, info, stream, nprobe);
+  });
+}
+
+rsf_status rsf_grad_hutch_batched(rsf_factor f, const double* const* d_z, int nprobe, uint64_t seed, double* g_nb_p,
+                                  rsf_grad_info* info_or_null, void* stream) {
+  return guarded([&] {
+    check_handle(f);
+    RSF_CHECK(d_z != nullptr && g_nb_p != nullptr, RSF_E_INVALID, "null argument");
+    RSF_CHECK(nprobe >= 1, RSF_E_INVALID, "nprobe must be >= 1");
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const double* Z = gather_instances(f, d_z, scr, s);
+    grad_eval(f, Z, 0.0, seed, g_nb_p, info_or_null, stream, nprobe);
+  });
+}
+
 rsf_status rsf_grad_batched(rsf_factor f, const double* const* d_z, double eps_peel, uint64_t seed,
                             double* g_nb_p, rsf_grad_info* info_or_null, void* stream) {
   return guarded([&] {

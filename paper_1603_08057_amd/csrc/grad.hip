@@ -1138,8 +1138,70 @@ void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* 
 
 namespace rsf {
 
+// Rademacher probes of Hutchinson's estimator (eq. hutch): U[d, j] = +1 or
+// -1 from the lowest bit of the first Philox4x32-10 word for counter
+// (d_local, j, 0, 1), d_local = d's tree-order index inside its instance
+// (ioff: the instances' first rows), so a batch draws the probes each
+// instance would draw alone; stream 1 keeps them apart from the peeling's
+// Gaussian probes.
+__global__ void rademacher_kernel(long long n, int q, const long long* __restrict__ ioff, int ni, uint64_t seed,
+                                  double* __restrict__ U) {
+  const long long tot = n * q;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const long long d = e / q;
+    const int j = (int)(e - d * q);
+    int lo = 0, hi = ni;  // last instance with ioff <= d
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (ioff[mid] <= d)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    uint32_t c[4] = {(uint32_t)(d - ioff[lo]), (uint32_t)j, 0u, 1u};
+    philox(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    U[e] = (c[0] & 1u) ? -1.0 : 1.0;
+  }
+}
+
+// Hutchinson estimates of Tr F^-1 and Tr F^-1 F_rho per instance: with
+// w_j = B^T u_j (F^-1 = B^T B), |w_j|^2 and w_j^T F_rho w_j have expectations
+// Tr B B^T = Tr F^-1 and Tr B F_rho B^T = Tr F^-1 F_rho; one half solve sweep
+// and one multiply sweep over the q probe columns.
+static void hutch_traces(rsf_factor_s* f, int q, uint64_t seed, double* tinv, double* trho, hipStream_t s) {
+  TraceTag tag("hutch");
+  const Tree& t = f->tree;
+  const long long n = t.n;
+  const int ni = t.ninst;
+  Scratch scr(s);
+  double* W = scr.make<double>(n * q);
+  double* X = scr.make<double>(n * q);
+  double* V = scr.make<double>(n * q);
+  double* dots = scr.make<double>(2 * ni);
+  std::vector<long long> io(t.ioff.begin(), t.ioff.end());
+  long long* dio = scr.make<long long>(io.size());
+  upload(dio, io, s);
+  hipLaunchKernelGGL(rademacher_kernel, dim3(grid_of(n * q)), dim3(256), 0, s, n, q, dio, ni, seed, W);
+  RSF_HIP(hipGetLastError());
+  sweep_half_down(f, f->F, W, q, q, scr, s);  // W = B^T U
+  copy_dev(X, W, n * q, s);
+  sweep_apply_mult(f, *f->Frho, X, V, q, q, scr, s);  // V = F_rho W
+  for (int i = 0; i < ni; ++i) {
+    const long long o = t.ioff[i] * (long long)q, m = (t.ioff[i + 1] - t.ioff[i]) * (long long)q;
+    device_dot(W + o, W + o, m, dots + 2 * i, scr, s);
+    device_dot(W + o, V + o, m, dots + 2 * i + 1, scr, s);
+  }
+  std::vector<double> hd(2 * ni);
+  RSF_HIP(hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSF_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < ni; ++i) {
+    tinv[i] = hd[2 * i] / q;
+    trho[i] = hd[2 * i + 1] / q;
+  }
+}
+
 void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g, rsf_grad_info* info,
-               void* stream) {
+               void* stream, int hutch_probes) {
   using clk = std::chrono::steady_clock;
   RSF_CHECK(f != nullptr, RSF_E_INVALID, "null factor handle");
   RSF_CHECK(d_z != nullptr && g != nullptr, RSF_E_INVALID, "null argument");
@@ -1179,7 +1241,10 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   const auto t2 = clk::now();
   std::vector<double> trinv(ni), trrho(ni);
   PeelStats ps;
-  peel_traces(f, eps_peel, seed, trinv.data(), trrho.data(), &ps, s);
+  if (hutch_probes > 0)
+    hutch_traces(f, hutch_probes, seed, trinv.data(), trrho.data(), s);
+  else
+    peel_traces(f, eps_peel, seed, trinv.data(), trrho.data(), &ps, s);
   const auto t3 = clk::now();
   double q0[3] = {0, 0, 0}, tt0[3] = {0, 0, 0};
   for (int i = 0; i < ni; ++i) {

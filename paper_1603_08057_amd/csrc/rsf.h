@@ -177,8 +177,10 @@ void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* 
 // Score equations of every instance: g (3 values per instance, host); d_z in
 // caller order (instances concatenated).  info (may be null) gets instance 0's
 // split terms and the peeling statistics.
+// hutch_probes > 0: the traces by Hutchinson's estimator with that many
+// Rademacher probes instead of peeling (eps_peel unused).
 void grad_eval(rsf_factor_s* f, const double* d_z, double eps_peel, uint64_t seed, double* g,
-               rsf_grad_info* info, void* stream);
+               rsf_grad_info* info, void* stream, int hutch_probes = 0);
 
 void fill_zero(double* p, long long n, hipStream_t s);
 void copy_dev(double* dst, const double* src, long long n, hipStream_t s);

@@ -133,3 +133,43 @@ def test_with_score_builds_sigma_rho_alongside():
     a0, _ = B0.grad(zs, 1e-6, 7)
     a1, _ = B1.grad(zs, 1e-6, 7)
     assert np.array_equal(np.asarray(a0), np.asarray(a1))
+
+
+@pytest.mark.parametrize("n,q", [(2500, 16), (4096, 8)])
+def test_hutchinson_matches_oracle(n, q):
+    """Hutchinson traces (eq. hutch) from the same Rademacher probes through
+    B^T and F_rho: equal to the oracle's to rounding."""
+    print("hutchinson n=%d q=%d" % (n, q), flush=True)
+    theta = (0.06, 1.2, 1e-3)
+    P = W.uniform_points(n, 11)
+    z = dense.sample(P, W.gaussian(n, 12), theta, K.MATERN52)
+    F = R.Factor(_t(P), theta, kernel=K.MATERN52, eps=1e-7, leaf=64)
+    g, info = F.grad_hutch(_t(z), q, 5)
+    o = rsf.loglik_grad(P, z, theta, K.MATERN52, 1e-7, 64, seed=5, hutch_probes=q)
+    np.testing.assert_allclose(list(info.t), o["t"], rtol=1e-9)
+    np.testing.assert_allclose(list(info.q), o["q"], rtol=1e-9)
+    scale = np.abs(o["q"]) + 0.5 * np.abs(o["t"])
+    assert np.all(np.abs(np.array(g) - o["g"]) <= 1e-9 * scale)
+    # unbiased estimate of the peeled trace: within a generous statistical band
+    gp, ip = F.grad(_t(z), 1e-6, 33)
+    assert abs(info.t[2] - ip.t[2]) < 0.2 * abs(ip.t[2])
+
+
+def test_hutchinson_exact_on_diagonal_and_batched():
+    """A diagonal covariance makes every Rademacher probe exact; a batch draws
+    the probes each instance draws alone."""
+    P = W.uniform_points(700, 4) * 1e3
+    theta = (1e-3, 2.0, 0.5)
+    F = R.Factor(_t(P), theta, kernel=K.MATERN32, eps=1e-9, leaf=32)
+    z = _t(W.gaussian(700, 3))
+    g, info = F.grad_hutch(z, 3, 9)
+    assert info.t[2] == pytest.approx(700 / 2.5, rel=1e-12)
+    pts = [W.uniform_points(m, 40 + m) for m in (900, 1700)]
+    zs = [W.gaussian(m, 50 + m) for m in (900, 1700)]
+    th = [(0.05, 1.0, 1e-4), (0.08, 1.5, 1e-3)]
+    B = R.BatchedFactor([_t(p) for p in pts], th, kernel=K.MATERN32, eps=1e-6, leaf=64)
+    gb, _ = B.grad_hutch([_t(x) for x in zs], 12, 4)
+    for i in range(2):
+        Fi = R.Factor(_t(pts[i]), th[i], kernel=K.MATERN32, eps=1e-6, leaf=64)
+        gi, _ = Fi.grad_hutch(_t(zs[i]), 12, 4)
+        np.testing.assert_allclose(gb[i], gi, rtol=1e-9, atol=1e-9 * np.max(np.abs(gi)))

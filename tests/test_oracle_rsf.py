@@ -252,3 +252,54 @@ def test_method_gradient_close_to_dense():
     assert o["logdet"] == pytest.approx(d["logdet"], rel=1e-10)
     np.testing.assert_allclose(o["t"], d["t"], rtol=1e-8)
     assert np.linalg.norm(o["g"] - d["g"]) <= 1e-5 * np.linalg.norm(d["g"])
+
+
+def test_rademacher_draws():
+    """+1/-1 from the lowest bit of Philox word 0 (counter (d, j, 0, 1)):
+    balanced and uncorrelated across DOFs and columns."""
+    d = np.arange(4096)[:, None]
+    j = np.arange(64)[None, :]
+    U = philox.rademacher(d, j, 77)
+    assert set(np.unique(U)) == {-1.0, 1.0}
+    assert abs(U.mean()) < 4.0 / np.sqrt(U.size)
+    C = U.T @ U / U.shape[0]
+    off = C[~np.eye(64, dtype=bool)]
+    assert np.abs(off).max() < 5.0 / np.sqrt(U.shape[0])
+    # the draw is the published generator's word, not a reseeded stream
+    x0 = philox.philox4x32_10(d[:5, 0], 3, 0, 1, 77, 0)[0]
+    assert np.array_equal(philox.rademacher(d[:5, 0], 3, 77), np.where(x0 % 2 == 0, 1.0, -1.0))
+
+
+def test_hutchinson_exact_on_diagonal_and_unbiased():
+    """Hutchinson (eq. hutch) on a diagonal covariance is exact for every
+    probe; on a correlated one its mean over many probes lies within the
+    Rademacher standard error sqrt(2 sum_{i != j} G_ij^2 / q) of the dense
+    traces of B B^T and B F_rho B^T."""
+    # far-apart sites: Sigma = (sigma2 + nugget) I to rounding
+    P = W.uniform_points(300, 4) * 1e3
+    theta = (1e-3, 2.0, 0.5)
+    F = rsf.Factor(P, theta, K.MATERN32, 1e-9, 32, n_prox=64, prox_rings=1)
+    Fr = rsf.Factor(P, theta, K.MATERN32, 1e-9, 32, n_prox=64, prox_rings=1, mode="mult", tree=F.tree)
+    ti, tr = rsf.hutchinson_traces(F, Fr, 3, 5)
+    assert ti == pytest.approx(300 / 2.5, rel=1e-12)
+    assert abs(tr) < 1e-12
+    # correlated: exact traces of the two symmetric operators from dense matrices
+    n = 512
+    P = W.uniform_points(n, 21)
+    theta = (0.1, 1.0, 1e-2)
+    F = rsf.Factor(P, theta, K.MATERN32, 1e-10, 64, n_prox=64, prox_rings=1)
+    Fr = rsf.Factor(P, theta, K.MATERN32, 1e-10, 64, n_prox=64, prox_rings=1, mode="mult", tree=F.tree)
+    Bt = F.half_down(np.eye(n))          # B^T
+    G0 = Bt.T @ Bt                        # B B^T
+    G1 = Bt.T @ Fr.apply(Bt)              # B F_rho B^T
+    q = 4000
+    ti, tr = rsf.hutchinson_traces(F, Fr, q, 9)
+    for est, G in ((ti, G0), (tr, 0.5 * (G1 + G1.T))):
+        se = np.sqrt(2.0 * (np.sum(G * G) - np.sum(np.diag(G) ** 2)) / q)
+        assert abs(est - np.trace(G)) < 4.0 * se
+    # and the traces are those of Sigma^-1 and Sigma^-1 Sigma_rho
+    S = dense.cov_matrix(P, theta, K.MATERN32)
+    Si = np.linalg.inv(S)
+    Sr = dense.dcov_matrix(P, 0, theta, K.MATERN32)
+    assert np.trace(G0) == pytest.approx(np.trace(Si), rel=1e-8)
+    assert np.trace(G1) == pytest.approx(np.sum(Si * Sr.T), rel=1e-7)
