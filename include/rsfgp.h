@@ -200,6 +200,37 @@ rsf_status rsf_loglik_batched(rsf_factor f, const double* const* d_z, double* ou
 rsf_status rsf_grad_batched(rsf_factor f, const double* const* d_z, double eps_peel, uint64_t seed,
                             double* g_nb_p, rsf_grad_info* info_or_null, void* stream);
 
+/* Log profile likelihood (eq. prof: the mean and the variance profiled out)
+ *   l~ = -1/2 log|F| - n/2 log(z^T (F + 1 1^T)^-1 z) + n/2 (log n - 1 - log 2 pi)
+ * and, when g_or_null is not NULL, its gradient (3 values, host)
+ *   g~_i = -1/2 Tr(F^-1 Sigma_i) + n/2 beta^T Sigma_i beta / z^T beta,
+ * beta = (F + 1 1^T)^-1 z by Sherman-Morrison from F^-1 z and F^-1 1, the
+ * traces peeled as in rsf_grad (the paper's model fixes sigma2 = 1; the
+ * derivative for sigma2 is returned all the same).  info_or_null gets
+ * beta^T Sigma_i beta in q and the traces in t.  Single handles only.
+ * Errors: RSF_E_INVALID, RSF_E_NOT_SPD if z^T (F + 1 1^T)^-1 z <= 0. */
+rsf_status rsf_profile_loglik(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* ell,
+                              double* g_or_null, rsf_grad_info* info_or_null, void* stream);
+
+/* Conditional distribution of z' given z (the remark after Algorithm 1).
+ * f: the handle factored on the joint sites [x'; x] (the n1 prediction sites
+ * first, then the n2 observed sites, in that order in its points array);
+ * f22: the handle on the observed sites x alone; both single-instance with
+ * the same kernel and theta (else RSF_E_INVALID).  With
+ * Sigma_12 v = the first block of F [0; v] and Sigma_22^-1 b = F22^-1 b:
+ *   rsf_cond_mean:   d_mean (n1 x nrhs, column-major, ld n1) =
+ *                    Sigma_12 Sigma_22^-1 d_z (d_z: n2 x nrhs, ld n2);
+ *   rsf_cond_sample: d_dev (n1 x nrhs, ld n1) = S d_xi with
+ *                    S S^T = Sigma_11 - Sigma_12 Sigma_22^-1 Sigma_12^T,
+ *                    S = [I, -Sigma_12 Sigma_22^-1] F^(1/2); d_xi (n x nrhs,
+ *                    ld n = n1 + n2) holds the caller's standard normal draws;
+ *                    a conditional sample is the mean plus this deviation.
+ * All arrays are device memory in the caller's site order. */
+rsf_status rsf_cond_mean(rsf_factor f, rsf_factor f22, const double* d_z, double* d_mean, int64_t nrhs,
+                         void* stream);
+rsf_status rsf_cond_sample(rsf_factor f, rsf_factor f22, const double* d_xi, double* d_dev, int64_t nrhs,
+                           void* stream);
+
 /* The score with the traces by Hutchinson's estimator (eq. hutch) instead of
  * peeling: nprobe Rademacher vectors u_j (Philox4x32-10 keyed by seed, counter
  * (the DOF's tree-order index within its instance, j, 0, 1), sign from the

@@ -118,6 +118,32 @@ def loglik_and_grad(P, z, theta, kernel, alpha=1.0, block=2048, want_terms=False
     return out
 
 
+def profile_loglik(P, z, theta, kernel, alpha=1.0, want_grad=False):
+    """The log profile likelihood of eq. prof and its gradient, dense:
+      l~ = -1/2 log|Sigma| - n/2 log(z^T (Sigma + 1 1^T)^-1 z) + n/2 (log n - 1 - log 2 pi),
+      g~_i = -1/2 Tr(Sigma^-1 Sigma_i) + n/2 (beta^T Sigma_i beta) / (z^T beta),
+    beta = (Sigma + 1 1^T)^-1 z, for theta = (rho, sigma2, nugget).
+    Returns l~ or (l~, g~)."""
+    P = np.asarray(P, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    n = P.shape[0]
+    S = cov_matrix(P, theta, kernel, alpha)
+    one = np.ones(n)
+    A = S + np.outer(one, one)
+    beta = np.linalg.solve(A, z)
+    zb = float(z @ beta)
+    ld = np.linalg.slogdet(S)[1]
+    ell = -0.5 * ld - 0.5 * n * np.log(zb) + 0.5 * n * (np.log(n) - 1.0 - np.log(2.0 * np.pi))
+    if not want_grad:
+        return ell
+    Si = np.linalg.inv(S)
+    g = np.zeros(3)
+    for i in range(3):
+        Di = dcov_matrix(P, i, theta, kernel, alpha)
+        g[i] = -0.5 * np.sum(Si * Di.T) + 0.5 * n * float(beta @ (Di @ beta)) / zb
+    return ell, g
+
+
 def trace_inverse(P, theta, kernel, alpha=1.0):
     """Tr(Sigma^-1) (small n)."""
     S = cov_matrix(P, theta, kernel, alpha)

@@ -456,6 +456,51 @@ class Factor:
 LOG2PI = float(np.log(2.0 * np.pi))
 
 
+def profile_loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0, n_prox=256,
+                        prox_rings=4):
+    """The log profile likelihood of eq. prof and its gradient with the RSF:
+    a = F^-1 z, b = F^-1 1, beta = (Sigma + 1 1^T)^-1 z = a - b (1^T a) / (1 + 1^T b)
+    (Sherman-Morrison), z^T beta, and for the gradient beta^T Sigma_i beta with
+    Sigma beta = z - 1 (1^T beta) and F_rho beta, the traces as in loglik_grad."""
+    o = loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=eps_peel, seed=seed, alpha=alpha, n_prox=n_prox,
+                    prox_rings=prox_rings)
+    F, Fr = o["factor"], o["factor_rho"]
+    n = F.tree.n
+    rho, s2, nug = (float(v) for v in theta)
+    zt = F.to_tree(np.asarray(z, dtype=np.float64))
+    a = F.solve(zt)
+    b = F.solve(np.ones(n))
+    beta = a - b * (float(np.sum(a)) / (1.0 + float(np.sum(b))))
+    zb = float(zt @ beta)
+    ell = -0.5 * F.logdet - 0.5 * n * np.log(zb) + 0.5 * n * (np.log(n) - 1.0 - LOG2PI)
+    sb = float(beta @ zt) - float(np.sum(beta)) ** 2       # beta^T Sigma beta
+    bb = float(beta @ beta)
+    quad = np.array([float(beta @ Fr.apply(beta)), (sb - nug * bb) / s2, bb])
+    g = -0.5 * o["t"] + 0.5 * n * quad / zb
+    return {"ell": ell, "g": g, "t": o["t"], "quad": quad, "zbeta": zb}
+
+
+def conditional_mean(F, F22, z):
+    """E[z' | z] = Sigma_12 Sigma_22^-1 z as in the remark after Algorithm 1:
+    F factors the joint sites [x'; x] (the n1 prediction sites first), F22 the
+    observed sites; Sigma_12 v is the first block of F [0; v] and
+    Sigma_22^-1 b is F22^-1 b.  Vectors in caller order, (n2,) or (n2, k)."""
+    n1 = F.tree.n - F22.tree.n
+    z = np.asarray(z, dtype=np.float64)
+    a = F22.from_tree(F22.solve(F22.to_tree(z)))
+    v = np.concatenate([np.zeros((n1,) + a.shape[1:]), a])
+    return F.from_tree(F.apply(F.to_tree(v)))[:n1]
+
+
+def conditional_deviation(F, F22, xi):
+    """S xi with S = [I, -Sigma_12 Sigma_22^-1] F^(1/2), so that S S^T is the
+    conditional covariance Sigma_11 - Sigma_12 Sigma_22^-1 Sigma_12^T (the same
+    remark); xi: (n,) or (n, k) standard normal draws, n = n1 + n2."""
+    n1 = F.tree.n - F22.tree.n
+    y = F.from_tree(F.sqrt(F.to_tree(np.asarray(xi, dtype=np.float64))))
+    return y[:n1] - conditional_mean(F, F22, y[n1:])
+
+
 def hutchinson_traces(F, Fr, nprobe, seed):
     """Hutchinson's estimator (eq. hutch) of Tr F^-1 and Tr F^-1 F_rho from
     nprobe Rademacher vectors u_j (oracle.philox.rademacher over the tree

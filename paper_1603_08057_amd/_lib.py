@@ -75,6 +75,9 @@ def load():
         "rsf_loglik_batched": ([vp, C.POINTER(vp), dp, vp], C.c_int),
         "rsf_grad_batched": ([vp, C.POINTER(vp), C.c_double, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
         "rsf_grad_hutch": ([vp, vp, C.c_int, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
+        "rsf_cond_mean": ([vp, vp, vp, vp, C.c_int64, vp], C.c_int),
+        "rsf_profile_loglik": ([vp, vp, C.c_double, C.c_uint64, dp, dp, C.POINTER(GradInfo), vp], C.c_int),
+        "rsf_cond_sample": ([vp, vp, vp, vp, C.c_int64, vp], C.c_int),
         "rsf_grad_hutch_batched": ([vp, C.POINTER(vp), C.c_int, C.c_uint64, dp, C.POINTER(GradInfo), vp], C.c_int),
         "rsf_graph_state": ([vp, C.POINTER(C.c_int)], C.c_int),
         "rsf_trace_enable": ([C.c_int], C.c_int),
@@ -121,6 +124,31 @@ def _colmajor(b, n):
     if b.dim() == 1:
         return b.reshape(1, n).contiguous(), 1, True
     return b.t().contiguous(), b.shape[1], False
+
+
+def cond_mean(F, F22, z):
+    """E[z' | z] = Sigma_12 Sigma_22^-1 z: F factors the joint sites [x'; x]
+    (prediction sites first), F22 the observed sites x; z is (n2,) or
+    (n2, k); returns (n1,) or (n1, k) on the device."""
+    torch = _torch()
+    n2, n1 = F22.n, F.n - F22.n
+    cm, k, sq = _colmajor(z, n2)
+    out = torch.empty((k, max(n1, 1)), dtype=torch.float64, device=cm.device)  # the library checks n1 >= 1
+    _check(load().rsf_cond_mean(F._h, F22._h, C.c_void_p(cm.data_ptr()), C.c_void_p(out.data_ptr()), k, _stream()))
+    return out.reshape(-1) if sq else out.t()
+
+
+def cond_sample(F, F22, xi):
+    """The conditional deviation S xi (S S^T = Sigma_11 - Sigma_12 Sigma_22^-1
+    Sigma_21) for standard normal draws xi of size (n,) or (n, k), n = n1 + n2;
+    a conditional sample is cond_mean(...) + this."""
+    torch = _torch()
+    n1 = F.n - F22.n
+    cm, k, sq = _colmajor(xi, F.n)
+    out = torch.empty((k, max(n1, 1)), dtype=torch.float64, device=cm.device)
+    _check(load().rsf_cond_sample(F._h, F22._h, C.c_void_p(cm.data_ptr()), C.c_void_p(out.data_ptr()), k,
+                                  _stream()))
+    return out.reshape(-1) if sq else out.t()
 
 
 def trace_enable(on=True):
@@ -236,6 +264,17 @@ class Factor:
         _check(load().rsf_grad(self._h, C.c_void_p(z.data_ptr()), eps_peel, int(seed), g, C.byref(info),
                                _stream()))
         return [g[0], g[1], g[2]], info
+
+    def profile_loglik(self, z, eps_peel=None, seed=0, grad=True):
+        """Log profile likelihood (eq. prof) and, with grad, its gradient and info."""
+        z = _dev_f64(z, (self.n,))
+        ell = C.c_double()
+        g = (C.c_double * 3)()
+        info = GradInfo()
+        eps_peel = float(eps_peel) if eps_peel is not None else -1.0
+        _check(load().rsf_profile_loglik(self._h, C.c_void_p(z.data_ptr()), eps_peel, int(seed), C.byref(ell),
+                                         g if grad else None, C.byref(info), _stream()))
+        return (ell.value, [g[0], g[1], g[2]], info) if grad else ell.value
 
     def grad_hutch(self, z, nprobe, seed=0):
         """The score with Hutchinson trace estimates from nprobe Rademacher probes."""

@@ -302,6 +302,51 @@ rsf_status rsf_apply_sqrt(rsf_factor f, const double* d_w, double* d_z, int64_t 
   });
 }
 
+// ---- conditional distribution (the remark after Algorithm 1)
+// F factors the joint covariance of [x'; x] (the n1 prediction sites first),
+// F22 that of the observed sites x.  Sigma_12 v is the first block of
+// F [0; v]; Sigma_22^-1 b is F22^-1 b.
+static void check_pair(rsf_factor f, rsf_factor f22) {
+  check_handle(f);
+  check_handle(f22);
+  RSF_CHECK(f->tree.ninst == 1 && f22->tree.ninst == 1, RSF_E_INVALID, "conditional sampling takes single handles");
+  RSF_CHECK(f->tree.n > f22->tree.n, RSF_E_INVALID, "the joint handle must hold more sites than the observed one");
+  RSF_CHECK(f->kernel == f22->kernel && f->theta[0] == f22->theta[0] && f->theta[1] == f22->theta[1] &&
+                f->theta[2] == f22->theta[2],
+            RSF_E_INVALID, "the joint and observed handles must share kernel and theta");
+}
+
+// out(i, c) = Y(i, c) - U(i, c) for the first n1 rows (Y: leading dimension ldy)
+__global__ void cond_dev_kernel(const double* __restrict__ Y, long long ldy, const double* __restrict__ U, long long n1,
+                                int nc, double* __restrict__ out) {
+  const long long tot = n1 * nc;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const long long c = e / n1, i = e - c * n1;
+    out[e] = Y[c * ldy + i] - U[e];
+  }
+}
+
+// Y (n1 x nc, leading dimension ld1) = first n1 rows of F [0; F22^-1 B],
+// B: n2 x nc with leading dimension ldb (device, caller order)
+static void sigma12_sigma22inv(rsf_factor f, rsf_factor f22, const double* B, long long ldb, double* Y, long long ld1,
+                               int nc, Scratch& scr, hipStream_t s) {
+  const long long n = f->tree.n, n2 = f22->tree.n, n1 = n - n2;
+  double* V = scr.make<double>((size_t)n * nc);
+  double* P2 = scr.make<double>((size_t)n2 * nc);
+  double* P = scr.make<double>((size_t)n * nc);
+  double* Q = scr.make<double>((size_t)n * nc);
+  fill_zero(V, n * nc, s);
+  to_panel(f22, B, ldb, P2, nc, nc, s);
+  sweep_solve(f22, f22->F, P2, nc, nc, scr, s);
+  from_panel(f22, P2, nc, nc, V + n1, n, s);  // rows n1 .. n - 1 of V
+  to_panel(f, V, n, P, nc, nc, s);
+  sweep_sqrt_t(f, f->F, P, Q, nc, nc, scr, s);
+  sweep_sqrt(f, f->F, Q, P, nc, nc, scr, s);
+  from_panel(f, P, nc, nc, V, n, s);
+  RSF_HIP(hipMemcpy2DAsync(Y, ld1 * sizeof(double), V, n * sizeof(double), n1 * sizeof(double), nc,
+                           hipMemcpyDeviceToDevice, s));
+}
+
 namespace rsf {
 LoglikGraph::~LoglikGraph() {
   if (exec) (void)hipGraphExecDestroy(exec);
@@ -532,6 +577,55 @@ rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t s
     check_handle(f);
     RSF_CHECK(f->tree.ninst == 1, RSF_E_INVALID, "a batched handle takes rsf_grad_batched");
     grad_eval(f, d_z, eps_peel, seed, g, info, stream);
+  });
+}
+
+rsf_status rsf_profile_loglik(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* ell,
+                              double* g_or_null, rsf_grad_info* info_or_null, void* stream) {
+  return guarded([&] {
+    check_handle(f);
+    profile_eval(f, d_z, eps_peel, seed, ell, g_or_null, info_or_null, stream);
+  });
+}
+
+rsf_status rsf_cond_mean(rsf_factor f, rsf_factor f22, const double* d_z, double* d_mean, int64_t nrhs,
+                         void* stream) {
+  return guarded([&] {
+    check_pair(f, f22);
+    RSF_CHECK(d_z != nullptr && d_mean != nullptr, RSF_E_INVALID, "null vector");
+    RSF_CHECK(nrhs >= 0 && nrhs < (int64_t(1) << 24), RSF_E_INVALID, "bad nrhs");
+    if (nrhs == 0) return;
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const long long n1 = f->tree.n - f22->tree.n;
+    sigma12_sigma22inv(f, f22, d_z, f22->tree.n, d_mean, n1, (int)nrhs, scr, s);
+  });
+}
+
+rsf_status rsf_cond_sample(rsf_factor f, rsf_factor f22, const double* d_xi, double* d_dev, int64_t nrhs,
+                           void* stream) {
+  return guarded([&] {
+    check_pair(f, f22);
+    RSF_CHECK(d_xi != nullptr && d_dev != nullptr, RSF_E_INVALID, "null vector");
+    RSF_CHECK(nrhs >= 0 && nrhs < (int64_t(1) << 24), RSF_E_INVALID, "bad nrhs");
+    if (nrhs == 0) return;
+    hipStream_t s = as_stream(stream);
+    Scratch scr(s);
+    const long long n = f->tree.n, n1 = n - f22->tree.n;
+    const int nc = (int)nrhs;
+    // y = F^(1/2) xi; deviation = y_1 - Sigma_12 Sigma_22^-1 y_2
+    double* P = scr.make<double>((size_t)n * nc);
+    double* Q = scr.make<double>((size_t)n * nc);
+    double* Yc = scr.make<double>((size_t)n * nc);
+    double* U = scr.make<double>((size_t)n1 * nc);
+    to_panel(f, d_xi, n, P, nc, nc, s);
+    sweep_sqrt(f, f->F, P, Q, nc, nc, scr, s);
+    from_panel(f, Q, nc, nc, Yc, n, s);
+    sigma12_sigma22inv(f, f22, Yc + n1, n, U, n1, nc, scr, s);
+    const long long tot = n1 * nc;
+    hipLaunchKernelGGL(cond_dev_kernel, dim3((unsigned)std::min<long long>(4096, (tot + 255) / 256)), dim3(256), 0, s,
+                       Yc, n, U, n1, nc, d_dev);
+    RSF_HIP(hipGetLastError());
   });
 }
 

@@ -1278,4 +1278,91 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   }
 }
 
+__global__ void set_kernel(long long n, double v, double* __restrict__ out) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) out[i] = v;
+}
+
+// beta = a - c b (device)
+__global__ void axmy_kernel(long long n, const double* __restrict__ a, double c, const double* __restrict__ b,
+                            double* __restrict__ out) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) out[i] = a[i] - c * b[i];
+}
+
+void profile_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* ell, double* g,
+                  rsf_grad_info* info, void* stream) {
+  RSF_CHECK(f != nullptr, RSF_E_INVALID, "null factor handle");
+  RSF_CHECK(d_z != nullptr && ell != nullptr, RSF_E_INVALID, "null argument");
+  RSF_CHECK(f->tree.ninst == 1, RSF_E_INVALID, "the profile likelihood takes a single handle");
+  if (!(eps_peel > 0.0)) eps_peel = f->eps;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const long long n = f->tree.n;
+  Scratch scr(s);
+  double* Z = scr.make<double>(n);
+  double* A = scr.make<double>(n);
+  double* Bv = scr.make<double>(n);
+  double* dots = scr.make<double>(8);
+  to_panel(f, d_z, n, Z, 1, 1, s);
+  copy_dev(A, Z, n, s);
+  hipLaunchKernelGGL(set_kernel, dim3(grid_of(n)), dim3(256), 0, s, n, 1.0, Bv);
+  RSF_HIP(hipGetLastError());
+  double* ones = scr.make<double>(n);
+  copy_dev(ones, Bv, n, s);
+  sweep_solve(f, f->F, A, 1, 1, scr, s);   // a = F^-1 z
+  sweep_solve(f, f->F, Bv, 1, 1, scr, s);  // b = F^-1 1
+  device_dot(ones, A, n, dots + 0, scr, s);  // 1^T a
+  device_dot(ones, Bv, n, dots + 1, scr, s); // 1^T b
+  device_dot(Z, A, n, dots + 2, scr, s);     // z^T a
+  double hd[8];
+  RSF_HIP(hipMemcpyAsync(hd, dots, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSF_HIP(hipStreamSynchronize(s));
+  double logdet = 0.0;
+  for (double v : f->F.logdet) logdet += v;
+  const double sa = hd[0], sb = hd[1], za = hd[2];
+  // z^T beta with beta = (Sigma + 1 1^T)^-1 z = a - b (1^T a) / (1 + 1^T b)
+  const double c = sa / (1.0 + sb), zb = za - c * sa;
+  RSF_CHECK(zb > 0.0, RSF_E_NOT_SPD, "z^T (Sigma + 1 1^T)^-1 z is not positive");
+  const double dn = (double)n;
+  *ell = -0.5 * logdet - 0.5 * dn * std::log(zb) + 0.5 * dn * (std::log(dn) - 1.0 - std::log(2.0 * M_PI));
+  if (!g) return;
+  if (!f->Frho) {
+    f->Frho.reset(new FactorData());
+    build_factor(f, *f->Frho, 1, s);
+  }
+  double* beta = scr.make<double>(n);
+  double* X = scr.make<double>(n);
+  double* Y = scr.make<double>(n);
+  hipLaunchKernelGGL(axmy_kernel, dim3(grid_of(n)), dim3(256), 0, s, n, A, c, Bv, beta);
+  RSF_HIP(hipGetLastError());
+  copy_dev(X, beta, n, s);
+  sweep_apply_mult(f, *f->Frho, X, Y, 1, 1, scr, s);  // F_rho beta
+  device_dot(beta, Y, n, dots + 3, scr, s);   // beta^T F_rho beta
+  device_dot(beta, Z, n, dots + 4, scr, s);   // beta^T z
+  device_dot(ones, beta, n, dots + 5, scr, s);  // 1^T beta
+  device_dot(beta, beta, n, dots + 6, scr, s);  // beta^T beta
+  RSF_HIP(hipMemcpyAsync(hd, dots, 7 * sizeof(double), hipMemcpyDeviceToHost, s));
+  RSF_HIP(hipStreamSynchronize(s));
+  double trinv = 0.0, trrho = 0.0;
+  PeelStats ps;
+  peel_traces(f, eps_peel, seed, &trinv, &trrho, &ps, s);
+  const double s2 = f->thetas[1], nug = f->thetas[2];
+  // beta^T Sigma beta = beta^T z - (1^T beta)^2 since (Sigma + 1 1^T) beta = z
+  const double sbeta = hd[4] - hd[5] * hd[5];
+  const double quad[3] = {hd[3], (sbeta - nug * hd[6]) / s2, hd[6]};
+  const double t[3] = {trrho, (dn - nug * trinv) / s2, trinv};
+  for (int i = 0; i < 3; ++i) g[i] = -0.5 * t[i] + 0.5 * dn * quad[i] / zb;
+  if (info) {
+    for (int i = 0; i < 3; ++i) {
+      info->q[i] = quad[i];
+      info->t[i] = t[i];
+    }
+    info->trace_inv = trinv;
+    info->peel_levels = ps.levels;
+    for (int i = 0; i < 32; ++i) {
+      info->peel_cols[i] = ps.cols[i];
+      info->peel_rank[i] = ps.rank[i];
+    }
+    info->leaf_cols = ps.leaf_cols;
+  }
+}
+
 }  // namespace rsf

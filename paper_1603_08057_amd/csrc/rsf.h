@@ -177,6 +177,11 @@ void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* 
 // Score equations of every instance: g (3 values per instance, host); d_z in
 // caller order (instances concatenated).  info (may be null) gets instance 0's
 // split terms and the peeling statistics.
+// Log profile likelihood of eq. prof (*ell) and, when g is not null, its
+// gradient (3 values); info gets beta^T Sigma_i beta in q and the traces in t.
+void profile_eval(rsf_factor_s* f, const double* d_z, double eps_peel, uint64_t seed, double* ell, double* g,
+                  rsf_grad_info* info, void* stream);
+
 // hutch_probes > 0: the traces by Hutchinson's estimator with that many
 // Rademacher probes instead of peeling (eps_peel unused).
 void grad_eval(rsf_factor_s* f, const double* d_z, double eps_peel, uint64_t seed, double* g,

@@ -173,3 +173,29 @@ def test_hutchinson_exact_on_diagonal_and_batched():
         Fi = R.Factor(_t(pts[i]), th[i], kernel=K.MATERN32, eps=1e-6, leaf=64)
         gi, _ = Fi.grad_hutch(_t(zs[i]), 12, 4)
         np.testing.assert_allclose(gb[i], gi, rtol=1e-9, atol=1e-9 * np.max(np.abs(gi)))
+
+
+def test_profile_likelihood_matches_oracle_and_dense():
+    """eq. prof on the GPU: l~ and its gradient against the oracle's RSF
+    version (same peeling, rounding level) and the dense definition."""
+    print("profile likelihood n=1024 and 4096", flush=True)
+    theta = (0.12, 1.0, 2e-3)
+    P = W.uniform_points(1024, 17)
+    z = dense.sample(P, W.gaussian(1024, 18), theta, K.MATERN32) + 0.3
+    F = R.Factor(_t(P), theta, kernel=K.MATERN32, eps=1e-10, leaf=64, n_prox=64, prox_rings=1)
+    ell, g, info = F.profile_loglik(_t(z), 1e-9, 3)
+    assert F.profile_loglik(_t(z), grad=False) == ell
+    ld, gd = dense.profile_loglik(P, z, theta, K.MATERN32, want_grad=True)
+    assert ell == pytest.approx(ld, rel=1e-8)
+    assert np.linalg.norm(np.array(g) - gd) <= 1e-6 * np.linalg.norm(gd)
+    P = W.uniform_points(4096, 19)
+    theta = (0.05, 1.0, 1e-4)
+    z = W.gaussian(4096, 20) + 1.0
+    F = R.Factor(_t(P), theta, kernel=K.MATERN32, eps=1e-6, leaf=64)
+    ell, g, info = F.profile_loglik(_t(z), 1e-6, 33)
+    o = rsf.profile_loglik_grad(P, z, theta, K.MATERN32, 1e-6, 64, eps_peel=1e-6, seed=33)
+    assert ell == pytest.approx(o["ell"], rel=1e-10)
+    np.testing.assert_allclose(list(info.t), o["t"], rtol=1e-8)
+    np.testing.assert_allclose(list(info.q), o["quad"], rtol=1e-8)
+    scale = 0.5 * np.abs(o["t"]) + 0.5 * 4096 * np.abs(o["quad"]) / o["zbeta"]
+    assert np.all(np.abs(np.array(g) - o["g"]) <= 1e-8 * scale)

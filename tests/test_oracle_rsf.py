@@ -303,3 +303,46 @@ def test_hutchinson_exact_on_diagonal_and_unbiased():
     Sr = dense.dcov_matrix(P, 0, theta, K.MATERN32)
     assert np.trace(G0) == pytest.approx(np.trace(Si), rel=1e-8)
     assert np.trace(G1) == pytest.approx(np.sum(Si * Sr.T), rel=1e-7)
+
+
+def test_conditional_mean_and_covariance():
+    """The remark after Algorithm 1: with F on [x'; x] and F22 on x, the
+    conditional mean matches Sigma_12 Sigma_22^-1 z and the square root S of
+    the deviation satisfies S S^T = Sigma_11 - Sigma_12 Sigma_22^-1 Sigma_21,
+    both from the dense covariance, to the factorization accuracy."""
+    n1, n2 = 60, 700
+    Pall = W.uniform_points(n1 + n2, 31)
+    theta = (0.1, 1.0, 1e-3)
+    F = rsf.Factor(Pall, theta, K.MATERN32, 1e-10, 32, n_prox=64, prox_rings=1)
+    F22 = rsf.Factor(Pall[n1:], theta, K.MATERN32, 1e-10, 32, n_prox=64, prox_rings=1)
+    S = dense.cov_matrix(Pall, theta, K.MATERN32)
+    S11, S12, S22 = S[:n1, :n1], S[:n1, n1:], S[n1:, n1:]
+    z = W.gaussian((n2, 2), 33)
+    mu = rsf.conditional_mean(F, F22, z)
+    mu_d = S12 @ np.linalg.solve(S22, z)
+    assert np.linalg.norm(mu - mu_d) <= 1e-6 * np.linalg.norm(mu_d)
+    Sq = rsf.conditional_deviation(F, F22, np.eye(n1 + n2))  # the n1 x n operator S
+    C = Sq @ Sq.T
+    C_d = S11 - S12 @ np.linalg.solve(S22, S12.T)
+    assert np.linalg.norm(C - C_d) <= 1e-6 * np.linalg.norm(C_d)
+
+
+def test_profile_likelihood_gradient_and_rsf():
+    """eq. prof: the dense gradient formula agrees with central differences of
+    the dense profile likelihood, and the RSF version (Sherman-Morrison, peeled
+    traces) agrees with the dense one to the factorization / peeling accuracy."""
+    P = W.uniform_points(400, 17)
+    theta = np.array([0.12, 1.0, 2e-3])
+    z = dense.sample(P, W.gaussian(400, 18), tuple(theta), K.MATERN32) + 0.3
+    ell, g = dense.profile_loglik(P, z, tuple(theta), K.MATERN32, want_grad=True)
+    for i in range(3):
+        h = 1e-5 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (dense.profile_loglik(P, z, tuple(tp), K.MATERN32) - dense.profile_loglik(P, z, tuple(tm), K.MATERN32)) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-6 * np.abs(g).max())
+    o = rsf.profile_loglik_grad(P, z, tuple(theta), K.MATERN32, 1e-10, 64, eps_peel=1e-9, seed=3, n_prox=64,
+                                prox_rings=1)
+    assert o["ell"] == pytest.approx(ell, rel=1e-9)
+    assert np.linalg.norm(o["g"] - g) <= 1e-6 * np.linalg.norm(g)
