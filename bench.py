@@ -50,6 +50,9 @@ def measured_traffic(launches_per_step):
     return rec["family_hbm_bytes"] / (launches_per_step + rec["setup_launches_estimate"])
 
 
+KERNEL_NAMES = {0: "matern12", 1: "matern32", 2: "matern52", 3: "rq", 4: "matern32_aniso", 5: "rq_aniso"}
+
+
 def cpu_baseline(spec, name, budget_s=35.0):
     """The dense oracle (l and g by FP64 Cholesky) timed on the host on a
     sample n of the same recipe: a 4096-point calibration run, then the
@@ -183,6 +186,7 @@ def main():
     P = torch.tensor(W.workload_points(name, n), dtype=torch.float64, device=dev)
     w = torch.tensor(W.gaussian(n, spec["w_seed"]), dtype=torch.float64, device=dev)
     theta = spec["theta"]
+    eps_peel = spec.get("eps_peel", spec["eps"])
     kw = dict(kernel=spec["kernel"], eps=spec["eps"], leaf=spec["leaf"], n_prox=spec["n_prox"],
               prox_rings=spec["prox_rings"], rq_alpha=spec["alpha"])
     F0 = R.Factor(P, theta, **kw)
@@ -198,7 +202,7 @@ def main():
         if args.hutch > 0:
             g, info = F.grad_hutch(z, args.hutch, spec.get("peel_seed", 0))
         else:
-            g, info = F.grad(z, spec["eps"], spec.get("peel_seed", 0))
+            g, info = F.grad(z, eps_peel, spec.get("peel_seed", 0))
         F.close()
         return ell, g, info
 
@@ -249,8 +253,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": name if not args.n else "%s_recipe_n%d" % (name, n), "n": n,
-                   "kernel": "matern32" if spec["kernel"] == 1 else spec["kernel"], "theta": list(theta),
-                   "eps": spec["eps"], "eps_peel": spec["eps"], "leaf": spec["leaf"], "n_prox": spec["n_prox"],
+                   "kernel": KERNEL_NAMES.get(spec["kernel"], spec["kernel"]), "theta": list(theta),
+                   "eps": spec["eps"], "eps_peel": eps_peel, "leaf": spec["leaf"], "n_prox": spec["n_prox"],
                    "parallelism": "single GPU"},
         "roofline": {"bound": "mfma",
                      "kernel": "batched FP64 matrix-core products (gemm_big_kernel, gemm_tiles_kernel, "

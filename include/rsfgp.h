@@ -58,8 +58,13 @@ enum {
 };
 
 /* Covariance families.  Matern nu = 1/2, 3/2, 5/2 closed forms (eq. diffkernels)
- * and the rational quadratic kernel with fixed shape alpha (opts.rq_alpha). */
-enum { RSF_MATERN12 = 0, RSF_MATERN32 = 1, RSF_MATERN52 = 2, RSF_RQ = 3 };
+ * and the rational quadratic kernel with fixed shape alpha (opts.rq_alpha),
+ * with theta = (rho, sigma2, nugget); and the anisotropic kernels of the
+ * runtime experiments (eq. specmatern, eq. specrq: Matern 3/2 and RQ(alpha)
+ * of the scaled distance dx^2 / theta_1^2 + dy^2 / theta_2^2, no variance
+ * factor) with theta = (theta_1, theta_2, nugget); their score is with respect
+ * to theta_1, theta_2 and the nugget. */
+enum { RSF_MATERN12 = 0, RSF_MATERN32 = 1, RSF_MATERN52 = 2, RSF_RQ = 3, RSF_MATERN32_ANISO = 4, RSF_RQ_ANISO = 5 };
 
 typedef struct {
   int n_prox;           /* proxy points per box (Section 2.3.1; Section 5 uses 256) */

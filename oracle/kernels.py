@@ -29,11 +29,26 @@ Derivatives with respect to rho (Sigma_i = dSigma/dtheta_i in eq. gradient):
 
 and they vanish on the diagonal.  d/dsigma2 gives k(r/rho) (1 on the diagonal),
 d/dnugget gives the identity.
+
+Anisotropic kernels of the runtime experiments (eq. specmatern, eq. specrq),
+theta = (theta_1, theta_2, nugget), no variance factor:
+
+    Sigma_ij = k(s),  s^2 = dx^2 / theta_1^2 + dy^2 / theta_2^2,   Sigma_ii = 1 + nugget,
+
+with k the Matern 3/2 or RQ(alpha) form above.  Writing h = -dk/d(s^2)
+(Matern 3/2: 3/2 exp(-sqrt3 s); RQ: 1/2 (1 + s^2/(2 alpha))^(-alpha-1)),
+dSigma_ij/dtheta_1 = h 2 dx^2 / theta_1^3 and dSigma_ij/dtheta_2 = h 2 dy^2 / theta_2^3
+(zero on the diagonal), and d/dnugget gives the identity.
 """
 import numpy as np
 
-MATERN12, MATERN32, MATERN52, RQ = 0, 1, 2, 3
-KERNEL_NAMES = {MATERN12: "matern12", MATERN32: "matern32", MATERN52: "matern52", RQ: "rq"}
+MATERN12, MATERN32, MATERN52, RQ, MATERN32_ANISO, RQ_ANISO = 0, 1, 2, 3, 4, 5
+KERNEL_NAMES = {MATERN12: "matern12", MATERN32: "matern32", MATERN52: "matern52", RQ: "rq",
+                MATERN32_ANISO: "matern32_aniso", RQ_ANISO: "rq_aniso"}
+
+
+def is_aniso(kernel):
+    return kernel in (MATERN32_ANISO, RQ_ANISO)
 SQRT3 = np.sqrt(3.0)
 SQRT5 = np.sqrt(5.0)
 
@@ -79,16 +94,45 @@ def distances(X, Y):
     return np.sqrt(dx * dx + dy * dy)
 
 
+def _aniso_parts(X, Y, theta):
+    X = np.asarray(X, dtype=np.float64)
+    Y = np.asarray(Y, dtype=np.float64)
+    dx = X[:, 0][:, None] - Y[:, 0][None, :]
+    dy = X[:, 1][:, None] - Y[:, 1][None, :]
+    ux, uy = dx / float(theta[0]), dy / float(theta[1])
+    return dx, dy, ux * ux + uy * uy
+
+
 def cross_cov(X, Y, theta, kernel, alpha=1.0):
-    """sigma2 * k(|x - y| / rho) for every pair (no nugget: distinct observations)."""
+    """Kernel entries for every pair (no nugget: distinct observations):
+    sigma2 k(|x - y| / rho), or k(s) of the scaled distance for the
+    anisotropic kernels."""
+    if is_aniso(kernel):
+        _, _, s2 = _aniso_parts(X, Y, theta)
+        return corr(np.sqrt(s2), MATERN32 if kernel == MATERN32_ANISO else RQ, alpha)
     rho, sigma2 = float(theta[0]), float(theta[1])
     return sigma2 * corr(distances(X, Y) / rho, kernel, alpha)
 
 
-def cross_dcov_drho(X, Y, theta, kernel, alpha=1.0):
-    """d/drho of sigma2 * k(|x - y| / rho) for every pair."""
+def cross_dcov(X, Y, which, theta, kernel, alpha=1.0):
+    """d/dtheta_which of the kernel entries for every pair (which = 0: rho or
+    theta_1; 1: theta_2 of the anisotropic kernels)."""
+    if is_aniso(kernel):
+        dx, dy, s2 = _aniso_parts(X, Y, theta)
+        if kernel == MATERN32_ANISO:
+            h = 1.5 * np.exp(-SQRT3 * np.sqrt(s2))
+        else:
+            h = 0.5 * (1.0 + s2 / (2.0 * alpha)) ** (-alpha - 1.0)
+        d, th = (dx, float(theta[0])) if which == 0 else (dy, float(theta[1]))
+        return h * 2.0 * d * d / th ** 3
+    assert which == 0
     rho, sigma2 = float(theta[0]), float(theta[1])
     return sigma2 * dcorr_drho(distances(X, Y), rho, kernel, alpha)
+
+
+def cross_dcov_drho(X, Y, theta, kernel, alpha=1.0):
+    """d/drho (d/dtheta_1) of the kernel entries for every pair."""
+    return cross_dcov(X, Y, 0, theta, kernel, alpha)
 
 
 def cov_block(P, rows, cols, theta, kernel, alpha=1.0):
@@ -102,7 +146,7 @@ def cov_block(P, rows, cols, theta, kernel, alpha=1.0):
     same = rows[:, None] == cols[None, :]
     if np.any(same):
         # k(0) = 1 exactly; rebuild the diagonal entries without rounding noise.
-        B[same] = float(theta[1]) + float(theta[2])
+        B[same] = (1.0 if is_aniso(kernel) else float(theta[1])) + float(theta[2])
     return B
 
 
@@ -111,8 +155,8 @@ def dcov_block(P, rows, cols, which, theta, kernel, alpha=1.0):
     rows = np.asarray(rows)
     cols = np.asarray(cols)
     same = rows[:, None] == cols[None, :]
-    if which == 0:
-        B = cross_dcov_drho(P[rows], P[cols], theta, kernel, alpha)
+    if which == 0 or (which == 1 and is_aniso(kernel)):
+        B = cross_dcov(P[rows], P[cols], which, theta, kernel, alpha)
         B[same] = 0.0
         return B
     if which == 1:

@@ -189,13 +189,14 @@ class Factor:
     multiply-only representation of Sigma_rho (mode 'mult')."""
 
     def __init__(self, P, theta, kernel, eps, leaf, alpha=1.0, n_prox=256, prox_rings=4,
-                 mode="chol", r_near=NEAR_RADIUS, r_in=PROXY_R_IN, r_out=PROXY_R_OUT, tree=None):
+                 mode="chol", r_near=NEAR_RADIUS, r_in=PROXY_R_IN, r_out=PROXY_R_OUT, tree=None, deriv=0):
         self.P = np.asarray(P, dtype=np.float64)
         self.tree = Tree(self.P, leaf) if tree is None else tree
         self.Pt = self.P[self.tree.perm]
         self.theta = tuple(float(t) for t in theta)
         self.kernel, self.alpha, self.eps = kernel, alpha, eps
         self.mode = mode
+        self.deriv = deriv  # mode "mult": the parameter index of the derivative (0 = rho / theta_1, 1 = theta_2)
         self.n = self.P.shape[0]
         self._run(n_prox, prox_rings, r_near, r_in, r_out)
 
@@ -203,12 +204,12 @@ class Factor:
     def _entries(self, rows, cols):
         if self.mode == "chol":
             return K.cov_block(self.Pt, rows, cols, self.theta, self.kernel, self.alpha)
-        return K.dcov_block(self.Pt, rows, cols, 0, self.theta, self.kernel, self.alpha)
+        return K.dcov_block(self.Pt, rows, cols, self.deriv, self.theta, self.kernel, self.alpha)
 
     def _proxy_entries(self, G, cols):
         if self.mode == "chol":
             return K.cross_cov(G, self.Pt[cols], self.theta, self.kernel, self.alpha)
-        return K.cross_dcov_drho(G, self.Pt[cols], self.theta, self.kernel, self.alpha)
+        return K.cross_dcov(G, self.Pt[cols], self.deriv, self.theta, self.kernel, self.alpha)
 
     def _diag_block(self, b, I):
         """Current diagonal block of box b in the order of its active list I."""
@@ -532,6 +533,12 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
     (Section 3 allows any symmetrized form with the trace of F^-1 F_rho): with
     F^-1 = B^T B, Tr F^-1 = Tr B B^T and Tr F^-1 F_rho = Tr B F_rho B^T, and the
     two operators share the product B^T W.
+
+    Anisotropic kernels (theta = (theta_1, theta_2, nugget)): q_i = 1/2 a^T F_i a
+    and t_i = Tr F^-1 F_i for the derivative factorizations F_1, F_2 of
+    Sigma_theta1, Sigma_theta2 (each trace peeled beside Tr F^-1 with the same
+    seed, as for rho above); q_nug = 1/2 a^T a, t_nug = Tr F^-1 from the first
+    peel.
     Returns a dict (user order for vectors)."""
     from . import peel
     eps_peel = eps if eps_peel is None else eps_peel
@@ -545,6 +552,9 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
     out = {"ell": ell, "logdet": F.logdet, "alpha": F.from_tree(a), "factor": F}
     if not want_grad:
         return out
+    if K.is_aniso(kernel):
+        return _loglik_grad_aniso(out, F, P, a, theta, kernel, eps, leaf, eps_peel, seed, alpha,
+                                  n_prox, prox_rings, hutch_probes)
     rho, s2, nug = (float(v) for v in theta)
     Fr = Factor(P, theta, kernel, eps, leaf, alpha=alpha, n_prox=n_prox, prox_rings=prox_rings,
                 mode="mult", tree=F.tree)
@@ -566,3 +576,33 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
     t = np.array([t_rho, (n - nug * t_inv) / s2, t_inv])
     out.update(q=q, t=t, g=q - 0.5 * t, factor_rho=Fr, peel_cols=pl.cols, peel_ranks=pl.ranks)
     return out
+
+
+def _loglik_grad_aniso(out, F, P, a, theta, kernel, eps, leaf, eps_peel, seed, alpha,
+                       n_prox, prox_rings, hutch_probes):
+    from . import peel
+    Fs = [Factor(P, theta, kernel, eps, leaf, alpha=alpha, n_prox=n_prox, prox_rings=prox_rings,
+                 mode="mult", tree=F.tree, deriv=w) for w in (0, 1)]
+    aa = float(a @ a)
+    q = np.array([0.5 * float(a @ Fs[0].apply(a)), 0.5 * float(a @ Fs[1].apply(a)), 0.5 * aa])
+    tinv, tr, stats = [], [], []
+    for Fd in Fs:
+        if hutch_probes > 0:
+            ti, td = hutchinson_traces(F, Fd, hutch_probes, seed)
+        else:
+            def applies(Wm, Fd=Fd):
+                H = F.half_down(Wm)
+                return [F.half_up(H), F.half_up(Fd.apply(H))]
+
+            pl = peel.Peeler(F.tree, applies, 2, eps_peel, seed)
+            ti, td = pl.run()
+            stats.append((pl.cols, pl.ranks))
+        tinv.append(ti)
+        tr.append(td)
+    t = np.array([tr[0], tr[1], tinv[0]])
+    out.update(q=q, t=t, g=q - 0.5 * t, factor_rho=Fs[0], factor_theta2=Fs[1])
+    if stats:
+        out.update(peel_cols=stats[0][0], peel_ranks=stats[0][1], peel_cols2=stats[1][0],
+                   peel_ranks2=stats[1][1])
+    return out
+

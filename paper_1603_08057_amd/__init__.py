@@ -10,7 +10,8 @@ device memory and the current stream.  There is no CPU fallback: without the
 built library, or without a HIP device, the calls raise.
 """
 from ._lib import (  # noqa: F401
-    MATERN12, MATERN32, MATERN52, RQ, PRECISIONS, RsfError, Factor, BatchedFactor, Options, GradInfo, library_path, load,
+    MATERN12, MATERN32, MATERN52, RQ, MATERN32_ANISO, RQ_ANISO, PRECISIONS, RsfError, Factor, BatchedFactor, Options, GradInfo, library_path, load,
     trace_enable, trace_read, trace_busy_ms, cond_mean, cond_sample,
 )
 from .autograd import loglik_fn  # noqa: F401
+from .mle import fit, FitResult  # noqa: F401

@@ -3,7 +3,7 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-MATERN12, MATERN32, MATERN52, RQ = 0, 1, 2, 3
+MATERN12, MATERN32, MATERN52, RQ, MATERN32_ANISO, RQ_ANISO = 0, 1, 2, 3, 4, 5
 
 _ERRORS = {-1: "RSF_E_INVALID", -2: "RSF_E_NOT_SPD", -3: "RSF_E_OOM", -4: "RSF_E_HIP",
            -5: "RSF_E_DUPLICATE", -6: "RSF_E_NONFINITE"}

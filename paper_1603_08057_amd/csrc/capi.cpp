@@ -79,8 +79,8 @@ rsf_status rsf_opts_default(rsf_opts* o) {
 
 static void check_theta(const double* theta) {
   for (int i = 0; i < 3; ++i) RSF_CHECK(std::isfinite(theta[i]), RSF_E_NONFINITE, "non-finite theta");
-  RSF_CHECK(theta[0] > 0.0, RSF_E_INVALID, "rho must be > 0");
-  RSF_CHECK(theta[1] > 0.0, RSF_E_INVALID, "sigma2 must be > 0");
+  RSF_CHECK(theta[0] > 0.0, RSF_E_INVALID, "rho (theta_1) must be > 0");
+  RSF_CHECK(theta[1] > 0.0, RSF_E_INVALID, "sigma2 (theta_2) must be > 0");
 }
 
 // Shared by the single and the batched constructor: host copies of every
@@ -88,7 +88,7 @@ static void check_theta(const double* theta) {
 // Argument checks that need no device access (run before any copy).
 static void check_args(const double* thetas, int ni, int kernel, double eps, int leaf) {
   RSF_CHECK(leaf >= 1, RSF_E_INVALID, "leaf must be >= 1");
-  RSF_CHECK(kernel >= RSF_MATERN12 && kernel <= RSF_RQ, RSF_E_INVALID, "unknown kernel");
+  RSF_CHECK(kernel >= RSF_MATERN12 && kernel <= RSF_RQ_ANISO, RSF_E_INVALID, "unknown kernel");
   RSF_CHECK(std::isfinite(eps), RSF_E_NONFINITE, "non-finite eps");
   RSF_CHECK(eps > 0.0, RSF_E_INVALID, "eps must be > 0");
   for (int i = 0; i < ni; ++i) check_theta(thetas + 3 * i);
@@ -110,6 +110,8 @@ static rsf_factor_s* create_handle(const std::vector<std::vector<double>>& xy, c
             "bad proxy geometry or rq_alpha");
   RSF_CHECK(o.precision == RSF_FP64 || o.precision == RSF_MIXED, RSF_E_INVALID, "unknown precision");
   RSF_CHECK(o.with_score == 0 || o.with_score == 1, RSF_E_INVALID, "with_score must be 0 or 1");
+  RSF_CHECK(!(o.precision == RSF_MIXED && kernel >= RSF_MATERN32_ANISO), RSF_E_INVALID,
+            "mixed precision takes the isotropic kernels only");
   std::unique_ptr<rsf_factor_s> h(new rsf_factor_s());
   h->opt.n_prox = o.n_prox;
   h->opt.prox_rings = o.prox_rings;
@@ -156,6 +158,10 @@ static rsf_factor_s* create_handle(const std::vector<std::vector<double>>& xy, c
     std::thread th([&] {
       try {
         build_factor(h.get(), *h->Frho, 1, s2);
+        if (kernel >= RSF_MATERN32_ANISO) {
+          h->Frho2.reset(new FactorData());
+          build_factor(h.get(), *h->Frho2, 2, s2);
+        }
         RSF_HIP(hipStreamSynchronize(s2));
       } catch (...) {
         err = std::current_exception();

@@ -232,12 +232,13 @@ void device_dot(const double* x, const double* y, long long n, double* out, Scra
                 hipStream_t s);
 
 // ---------------------------------------------------------------- kernel functions
-enum { K_MATERN12 = 0, K_MATERN32 = 1, K_MATERN52 = 2, K_RQ = 3 };
+enum { K_MATERN12 = 0, K_MATERN32 = 1, K_MATERN52 = 2, K_RQ = 3, K_MATERN32_ANISO = 4, K_RQ_ANISO = 5 };
 
 struct KernelParams {
   int kernel;
   double rho, sigma2, nugget, alpha;
-  int deriv;  // 0: Sigma entries, 1: d/drho entries
+  double rho2;  // anisotropic kernels: rho = theta_1 (x), rho2 = theta_2 (y), sigma2 = 1
+  int deriv;  // 0: Sigma entries, 1: d/drho (d/dtheta_1) entries, 2: d/dtheta_2 entries
   int f32;    // 1: entries evaluated in FP32 arithmetic (mixed precision)
 };
 
@@ -296,11 +297,26 @@ __device__ __forceinline__ float dcorr_drho_dev32(float r, float rho, int kernel
   return c * powf(1.0f + s * s / (2.0f * alpha), -alpha - 1.0f);
 }
 
+// Anisotropic kernels of the runtime experiments (eq. specmatern, eq. specrq):
+// k(s) with the scaled distance s^2 = dx^2 / theta_1^2 + dy^2 / theta_2^2,
+// no variance factor.  With h = -dk/d(s^2) (Matern 3/2: 3/2 exp(-sqrt3 s);
+// RQ(alpha): 1/2 (1 + s^2 / (2 alpha))^(-alpha-1)),
+// dk/dtheta_i = h * 2 d_i^2 / theta_i^3.
+__device__ __forceinline__ double kentry_aniso(double dx, double dy, const KernelParams& kp) {
+  const double ux = dx / kp.rho, uy = dy / kp.rho2, s2 = ux * ux + uy * uy;
+  const bool m32 = kp.kernel == K_MATERN32_ANISO;
+  if (!kp.deriv) return corr_dev(sqrt(s2), m32 ? K_MATERN32 : K_RQ, kp.alpha);
+  const double h = m32 ? 1.5 * exp(-1.7320508075688772 * sqrt(s2)) : 0.5 * pow(1.0 + s2 / (2.0 * kp.alpha), -kp.alpha - 1.0);
+  const double d = kp.deriv == 1 ? dx : dy, th = kp.deriv == 1 ? kp.rho : kp.rho2;
+  return h * 2.0 * d * d / (th * th * th);
+}
+
 // Kernel entry between two distinct sites at distance components (dx, dy).
 // The components are differences of FP64 coordinates (exact for nearby
 // sites); in mixed precision the distance and the kernel are then evaluated
 // in FP32.
 __device__ __forceinline__ double kentry(double dx, double dy, const KernelParams& kp) {
+  if (kp.kernel >= K_MATERN32_ANISO) return kentry_aniso(dx, dy, kp);
   if (kp.f32) {
     const float fx = (float)dx, fy = (float)dy;
     const float r = sqrtf(fx * fx + fy * fy);

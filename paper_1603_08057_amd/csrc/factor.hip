@@ -698,8 +698,15 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
   for (int i = 0; i < ni; ++i) {
     KernelParams& kp = F.kp[i];
     kp.kernel = h->kernel;
-    kp.rho = h->thetas[3 * i];
-    kp.sigma2 = h->thetas[3 * i + 1];
+    if (h->kernel >= K_MATERN32_ANISO) {
+      kp.rho = h->thetas[3 * i];
+      kp.rho2 = h->thetas[3 * i + 1];
+      kp.sigma2 = 1.0;
+    } else {
+      kp.rho = h->thetas[3 * i];
+      kp.rho2 = 0.0;
+      kp.sigma2 = h->thetas[3 * i + 1];
+    }
     kp.nugget = h->thetas[3 * i + 2];
     kp.alpha = o.rq_alpha;
     kp.deriv = mult;

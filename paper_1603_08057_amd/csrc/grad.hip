@@ -400,7 +400,8 @@ struct Peeler {
   hipStream_t s;
   Arena store;  // low-rank blocks of every level
   std::vector<LevelLR> lr[2];
-  Peeler(const rsf_factor_s* hh, hipStream_t ss) : h(hh), t(hh->tree), s(ss) {}
+  const FactorData* Fd;  // the derivative factorization of the second operator
+  Peeler(const rsf_factor_s* hh, const FactorData* fd, hipStream_t ss) : h(hh), t(hh->tree), s(ss), Fd(fd) {}
 
   // out_op = G_op X for both operators (X row-major n x nc); X is preserved.
   // cols (host, per instance, or null): the leading columns each instance's
@@ -419,7 +420,7 @@ struct Peeler {
           sweep_half_up(h, h->F, out0, nc, nc, sc2, s2, cols);  // B B^T X
         },
         [&] {
-          sweep_apply_mult(h, *h->Frho, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
+          sweep_apply_mult(h, *Fd, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
           sweep_half_up(h, h->F, out1, nc, nc, scr, s, cols);            // B F_rho B^T X
         });
   }
@@ -1129,8 +1130,8 @@ struct Peeler {
 }  // namespace
 
 void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv, double* tr_rho,
-                 PeelStats* st, hipStream_t s) {
-  Peeler p(h, s);
+                 PeelStats* st, hipStream_t s, const FactorData* Fd) {
+  Peeler p(h, Fd ? Fd : h->Frho.get(), s);
   p.run(eps_peel, seed, tr_inv, tr_rho, st);
 }
 
@@ -1168,7 +1169,9 @@ __global__ void rademacher_kernel(long long n, int q, const long long* __restric
 // w_j = B^T u_j (F^-1 = B^T B), |w_j|^2 and w_j^T F_rho w_j have expectations
 // Tr B B^T = Tr F^-1 and Tr B F_rho B^T = Tr F^-1 F_rho; one half solve sweep
 // and one multiply sweep over the q probe columns.
-static void hutch_traces(rsf_factor_s* f, int q, uint64_t seed, double* tinv, double* trho, hipStream_t s) {
+static void hutch_traces(rsf_factor_s* f, int q, uint64_t seed, double* tinv, double* trho, hipStream_t s,
+                         const FactorData* Fd = nullptr) {
+  if (!Fd) Fd = f->Frho.get();
   TraceTag tag("hutch");
   const Tree& t = f->tree;
   const long long n = t.n;
@@ -1185,7 +1188,7 @@ static void hutch_traces(rsf_factor_s* f, int q, uint64_t seed, double* tinv, do
   RSF_HIP(hipGetLastError());
   sweep_half_down(f, f->F, W, q, q, scr, s);  // W = B^T U
   copy_dev(X, W, n * q, s);
-  sweep_apply_mult(f, *f->Frho, X, V, q, q, scr, s);  // V = F_rho W
+  sweep_apply_mult(f, *Fd, X, V, q, q, scr, s);  // V = F_rho W
   for (int i = 0; i < ni; ++i) {
     const long long o = t.ioff[i] * (long long)q, m = (t.ioff[i + 1] - t.ioff[i]) * (long long)q;
     device_dot(W + o, W + o, m, dots + 2 * i, scr, s);
@@ -1210,9 +1213,16 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   const Tree& tr = f->tree;
   const int ni = tr.ninst;
   const auto t0 = clk::now();
+  // anisotropic kernels: derivatives with respect to theta_1 and theta_2
+  // (two multiply-only factorizations) and the nugget
+  const bool aniso = f->kernel >= K_MATERN32_ANISO;
   if (!f->Frho) {
     f->Frho.reset(new FactorData());
     build_factor(f, *f->Frho, 1, s);
+  }
+  if (aniso && !f->Frho2) {
+    f->Frho2.reset(new FactorData());
+    build_factor(f, *f->Frho2, 2, s);
   }
   RSF_HIP(hipStreamSynchronize(s));
   const auto t1 = clk::now();
@@ -1222,36 +1232,50 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   double* A = scr.make<double>(n);
   double* X = scr.make<double>(n);
   double* Y = scr.make<double>(n);
-  double* dots = scr.make<double>(3 * ni);
+  double* Y2 = aniso ? scr.make<double>(n) : nullptr;
+  double* dots = scr.make<double>(4 * ni);
   to_panel(f, d_z, n, Z, 1, 1, s);
   copy_dev(A, Z, n, s);
   sweep_solve(f, f->F, A, 1, 1, scr, s);
   copy_dev(X, A, n, s);
   sweep_apply_mult(f, *f->Frho, X, Y, 1, 1, scr, s);
-  // per instance (tree-order range [ioff[i], ioff[i + 1])): a^T F_rho a, z^T a, a^T a
+  if (aniso) {
+    copy_dev(X, A, n, s);
+    sweep_apply_mult(f, *f->Frho2, X, Y2, 1, 1, scr, s);
+  }
+  // per instance (tree-order range [ioff[i], ioff[i + 1])): a^T F_rho a, z^T a,
+  // a^T a (and a^T F_theta2 a)
   for (int i = 0; i < ni; ++i) {
     const long long o = tr.ioff[i], m = tr.ioff[i + 1] - tr.ioff[i];
-    device_dot(A + o, Y + o, m, dots + 3 * i, scr, s);
-    device_dot(Z + o, A + o, m, dots + 3 * i + 1, scr, s);
-    device_dot(A + o, A + o, m, dots + 3 * i + 2, scr, s);
+    device_dot(A + o, Y + o, m, dots + 4 * i, scr, s);
+    device_dot(Z + o, A + o, m, dots + 4 * i + 1, scr, s);
+    device_dot(A + o, A + o, m, dots + 4 * i + 2, scr, s);
+    if (aniso) device_dot(A + o, Y2 + o, m, dots + 4 * i + 3, scr, s);
   }
-  std::vector<double> hd(3 * ni);
+  std::vector<double> hd(4 * ni, 0.0);
   RSF_HIP(hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   RSF_HIP(hipStreamSynchronize(s));
   const auto t2 = clk::now();
-  std::vector<double> trinv(ni), trrho(ni);
-  PeelStats ps;
-  if (hutch_probes > 0)
+  std::vector<double> trinv(ni), trrho(ni), trinv2(ni), trrho2(ni);
+  PeelStats ps, ps2;
+  if (hutch_probes > 0) {
     hutch_traces(f, hutch_probes, seed, trinv.data(), trrho.data(), s);
-  else
+    if (aniso) hutch_traces(f, hutch_probes, seed, trinv2.data(), trrho2.data(), s, f->Frho2.get());
+  } else {
     peel_traces(f, eps_peel, seed, trinv.data(), trrho.data(), &ps, s);
+    if (aniso) peel_traces(f, eps_peel, seed, trinv2.data(), trrho2.data(), &ps2, s, f->Frho2.get());
+  }
   const auto t3 = clk::now();
   double q0[3] = {0, 0, 0}, tt0[3] = {0, 0, 0};
   for (int i = 0; i < ni; ++i) {
     const double s2 = f->thetas[3 * i + 1], nug = f->thetas[3 * i + 2];
     const double m = (double)(tr.ioff[i + 1] - tr.ioff[i]);
-    const double q[3] = {0.5 * hd[3 * i], 0.5 * (hd[3 * i + 1] - nug * hd[3 * i + 2]) / s2, 0.5 * hd[3 * i + 2]};
-    const double tt[3] = {trrho[i], (m - nug * trinv[i]) / s2, trinv[i]};
+    double q[3] = {0.5 * hd[4 * i], 0.5 * (hd[4 * i + 1] - nug * hd[4 * i + 2]) / s2, 0.5 * hd[4 * i + 2]};
+    double tt[3] = {trrho[i], (m - nug * trinv[i]) / s2, trinv[i]};
+    if (aniso) {
+      q[1] = 0.5 * hd[4 * i + 3];
+      tt[1] = trrho2[i];
+    }
     for (int j = 0; j < 3; ++j) g[3 * i + j] = q[j] - 0.5 * tt[j];
     if (i == 0)
       for (int j = 0; j < 3; ++j) {
@@ -1293,6 +1317,7 @@ void profile_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t see
   RSF_CHECK(f != nullptr, RSF_E_INVALID, "null factor handle");
   RSF_CHECK(d_z != nullptr && ell != nullptr, RSF_E_INVALID, "null argument");
   RSF_CHECK(f->tree.ninst == 1, RSF_E_INVALID, "the profile likelihood takes a single handle");
+  RSF_CHECK(f->kernel < K_MATERN32_ANISO, RSF_E_INVALID, "the profile likelihood takes the isotropic kernels");
   if (!(eps_peel > 0.0)) eps_peel = f->eps;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const long long n = f->tree.n;

@@ -124,7 +124,8 @@ struct rsf_factor_s {
   rsf::Arena arena;      // points, permutation, proxy table
   double* prox_u = nullptr;  // device unit offsets of the proxy points (x then y)
   rsf::FactorData F;
-  std::unique_ptr<rsf::FactorData> Frho;
+  std::unique_ptr<rsf::FactorData> Frho;   // d/drho (d/dtheta_1 for anisotropic kernels)
+  std::unique_ptr<rsf::FactorData> Frho2;  // d/dtheta_2 (anisotropic kernels only)
   std::unique_ptr<rsf::LoglikGraph> lgraph;
   int lgraph_state = 0;  // 0: not yet, 1: captured, -1: capture failed (eager from then on)
 };
@@ -171,8 +172,9 @@ struct PeelStats {
   int rank[32] = {0};
   int leaf_cols = 0;
 };
+// Fd: the derivative factorization of the second operator (default: Frho).
 void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv,
-                 double* tr_rho, PeelStats* st, hipStream_t s);
+                 double* tr_rho, PeelStats* st, hipStream_t s, const FactorData* Fd = nullptr);
 
 // Score equations of every instance: g (3 values per instance, host); d_z in
 // caller order (instances concatenated).  info (may be null) gets instance 0's

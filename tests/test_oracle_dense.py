@@ -170,3 +170,65 @@ def test_not_spd_is_reported():
     P = W.uniform_points(50, 13)
     with pytest.raises(dense.NotSPD):
         dense.loglik(P, W.gaussian(50, 1), (0.3, 1.0, -0.5), K.MATERN32)
+
+
+ANISO = [(K.MATERN32_ANISO, K.MATERN32), (K.RQ_ANISO, K.RQ)]
+
+
+@pytest.mark.parametrize("kernel,iso", ANISO)
+def test_aniso_isotropic_limit(kernel, iso):
+    """theta_1 = theta_2 = rho gives the isotropic kernel with sigma2 = 1, and
+    the two derivatives add up to d/drho of it (dx^2 + dy^2 = r^2)."""
+    P = W.uniform_points(60, 21)
+    rho = 0.17
+    A = K.cross_cov(P, P[:40], (rho, rho, 0.0), kernel, 0.7)
+    np.testing.assert_allclose(A, K.cross_cov(P, P[:40], (rho, 1.0, 0.0), iso, 0.7), rtol=1e-14, atol=1e-300)
+    D = K.cross_dcov(P, P[:40], 0, (rho, rho, 0.0), kernel, 0.7) + K.cross_dcov(P, P[:40], 1, (rho, rho, 0.0), kernel, 0.7)
+    np.testing.assert_allclose(D, K.cross_dcov_drho(P, P[:40], (rho, 1.0, 0.0), iso, 0.7), rtol=1e-12, atol=1e-14)
+    S = dense.cov_matrix(P, (rho, rho, 0.03), kernel, 0.7)
+    np.testing.assert_allclose(S, dense.cov_matrix(P, (rho, 1.0, 0.03), iso, 0.7), rtol=1e-14, atol=1e-300)
+
+
+@pytest.mark.parametrize("kernel,iso", ANISO)
+def test_aniso_axis_stretch(kernel, iso):
+    """Scaling the y coordinates by theta_1 / theta_2 turns the anisotropic
+    kernel into the isotropic one of range theta_1; a separation along one
+    axis sees only that axis' range."""
+    P = W.uniform_points(50, 22)
+    th = (0.2, 0.05, 0.0)
+    Q = P.copy()
+    Q[:, 1] *= th[0] / th[1]
+    np.testing.assert_allclose(K.cross_cov(P, P, th, kernel, 0.7), K.cross_cov(Q, Q, (th[0], 1.0, 0.0), iso, 0.7),
+                               rtol=1e-12, atol=1e-300)
+    x = np.array([[0.3, 0.3]])
+    y = np.array([[0.3, 0.34]])
+    assert K.cross_cov(x, y, th, kernel, 0.7)[0, 0] == pytest.approx(float(K.corr(np.array([0.04 / th[1]]), iso, 0.7)[0]), rel=1e-13)
+    assert K.cross_dcov(x, y, 0, th, kernel, 0.7)[0, 0] == 0.0
+
+
+@pytest.mark.parametrize("kernel,iso", ANISO)
+def test_aniso_derivatives_match_central_difference(kernel, iso):
+    P = W.uniform_points(40, 23)
+    th = np.array([0.13, 0.07, 0.0])
+    for which in (0, 1):
+        h = 1e-6 * th[which]
+        tp, tm = th.copy(), th.copy()
+        tp[which] += h
+        tm[which] -= h
+        fd = (K.cross_cov(P, P, tp, kernel, 0.7) - K.cross_cov(P, P, tm, kernel, 0.7)) / (2 * h)
+        np.testing.assert_allclose(K.cross_dcov(P, P, which, th, kernel, 0.7), fd, rtol=1e-6, atol=1e-7)
+
+
+@pytest.mark.parametrize("kernel,iso", ANISO)
+def test_aniso_gradient_matches_central_difference_of_loglik(kernel, iso):
+    P = W.uniform_points(80, 24)
+    theta = np.array([0.15, 0.06, 0.02])
+    z = dense.sample(P, W.gaussian(80, 25), theta, kernel, 0.7)
+    o = dense.loglik_and_grad(P, z, theta, kernel, 0.7, block=32)
+    for i in range(3):
+        h = 1e-5 * theta[i]
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (dense.loglik(P, z, tp, kernel, 0.7)[0] - dense.loglik(P, z, tm, kernel, 0.7)[0]) / (2 * h)
+        assert o["g"][i] == pytest.approx(fd, rel=1e-6, abs=1e-6)

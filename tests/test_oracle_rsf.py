@@ -346,3 +346,21 @@ def test_profile_likelihood_gradient_and_rsf():
                                 prox_rings=1)
     assert o["ell"] == pytest.approx(ell, rel=1e-9)
     assert np.linalg.norm(o["g"] - g) <= 1e-6 * np.linalg.norm(g)
+
+
+@pytest.mark.parametrize("kernel", [K.MATERN32_ANISO, K.RQ_ANISO])
+def test_aniso_method_gradient_close_to_dense(kernel):
+    """Anisotropic kernels: the factorization's l and log|F| and the peeled
+    traces Tr F^-1 F_theta1, Tr F^-1 F_theta2, Tr F^-1 against the dense
+    definitions."""
+    P = W.uniform_points(1024, 13)
+    theta = (0.12, 0.05, 1e-4)
+    z = dense.sample(P, W.gaussian(1024, 14), theta, kernel)
+    o = rsf.loglik_grad(P, z, theta, kernel, 1e-9, 64, seed=35, n_prox=64, prox_rings=1)
+    d = dense.loglik_and_grad(P, z, theta, kernel, want_terms=True)
+    # l is a small difference of terms of size n (z^T Sigma^-1 z ~ n): compare on that scale
+    assert o["ell"] == pytest.approx(d["ell"], rel=1e-7, abs=1e-8 * 1024)
+    assert o["logdet"] == pytest.approx(d["logdet"], rel=1e-9)
+    np.testing.assert_allclose(o["q"], d["q"], rtol=1e-6)
+    np.testing.assert_allclose(o["t"], d["t"], rtol=1e-7)
+    assert np.linalg.norm(o["g"] - d["g"]) <= 1e-5 * np.linalg.norm(d["g"])

@@ -8,7 +8,7 @@ All draws use numpy's PCG64 ``default_rng(seed)``.
 """
 import numpy as np
 
-MATERN12, MATERN32, MATERN52, RQ = 0, 1, 2, 3
+MATERN12, MATERN32, MATERN52, RQ, MATERN32_ANISO, RQ_ANISO = 0, 1, 2, 3, 4, 5
 
 
 def uniform_points(n, seed):
@@ -41,7 +41,8 @@ def gaussian(shape, seed):
     return np.random.default_rng(seed).standard_normal(shape)
 
 
-# The named workloads.  theta = (length scale rho, variance sigma2, nugget).
+# The named workloads.  theta = (length scale rho, variance sigma2, nugget), or
+# (theta_1, theta_2, nugget) for the anisotropic kernels.
 WORKLOADS = {
     # small case: Matern 3/2, single 64-point proxy ring, tight tolerance
     "c1_matern32_n1024": dict(n=1024, points=("uniform", 11), w_seed=12, kernel=MATERN32,
@@ -59,6 +60,12 @@ WORKLOADS = {
     "c5_matern52_n262144": dict(n=262144, points=("mixed", 51, 52), w_seed=53, peel_seed=54,
                                 kernel=MATERN52, theta=(0.03, 1.0, 1e-4), alpha=1.0, eps=1e-6,
                                 leaf=128, n_prox=256, prox_rings=4, nrhs=1),
+    # the paper's MLE profiling setup (Section 5): a 256 x 256 grid on
+    # [0, 100]^2, anisotropic Matern 3/2 with theta = (10, 7), noise 1e-4,
+    # eps_peel 1e-6 and eps_fact = eps_peel / 1000
+    "g1_matern32aniso_grid256": dict(n=65536, points=("grid", 100.0), w_seed=62, peel_seed=63,
+                                     kernel=MATERN32_ANISO, theta=(10.0, 7.0, 1e-4), alpha=1.0,
+                                     eps=1e-9, eps_peel=1e-6, leaf=64, n_prox=256, prox_rings=4, nrhs=1),
 }
 
 
@@ -101,4 +108,8 @@ def workload_points(name, n=None):
         return uniform_points(n, kind[1])
     if kind[0] == "mixed":
         return mixed_points(n, 16, 0.02, kind[1], kind[2])
+    if kind[0] == "grid":
+        side = int(round(np.sqrt(n)))
+        assert side * side == n, "grid workloads take square n"
+        return grid_points(side, kind[1])
     raise ValueError(kind)
