@@ -536,9 +536,9 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
 
     Anisotropic kernels (theta = (theta_1, theta_2, nugget)): q_i = 1/2 a^T F_i a
     and t_i = Tr F^-1 F_i for the derivative factorizations F_1, F_2 of
-    Sigma_theta1, Sigma_theta2 (each trace peeled beside Tr F^-1 with the same
-    seed, as for rho above); q_nug = 1/2 a^T a, t_nug = Tr F^-1 from the first
-    peel.
+    Sigma_theta1, Sigma_theta2; the three operators B B^T, B F_1 B^T and
+    B F_2 B^T are peeled jointly from one set of probes (as the two are for
+    rho above); q_nug = 1/2 a^T a, t_nug = Tr F^-1.
     Returns a dict (user order for vectors)."""
     from . import peel
     eps_peel = eps if eps_peel is None else eps_peel
@@ -585,24 +585,17 @@ def _loglik_grad_aniso(out, F, P, a, theta, kernel, eps, leaf, eps_peel, seed, a
                  mode="mult", tree=F.tree, deriv=w) for w in (0, 1)]
     aa = float(a @ a)
     q = np.array([0.5 * float(a @ Fs[0].apply(a)), 0.5 * float(a @ Fs[1].apply(a)), 0.5 * aa])
-    tinv, tr, stats = [], [], []
-    for Fd in Fs:
-        if hutch_probes > 0:
-            ti, td = hutchinson_traces(F, Fd, hutch_probes, seed)
-        else:
-            def applies(Wm, Fd=Fd):
-                H = F.half_down(Wm)
-                return [F.half_up(H), F.half_up(Fd.apply(H))]
+    if hutch_probes > 0:
+        t_inv, t1 = hutchinson_traces(F, Fs[0], hutch_probes, seed)
+        _, t2 = hutchinson_traces(F, Fs[1], hutch_probes, seed)
+    else:
+        def applies(Wm):
+            H = F.half_down(Wm)
+            return [F.half_up(H), F.half_up(Fs[0].apply(H)), F.half_up(Fs[1].apply(H))]
 
-            pl = peel.Peeler(F.tree, applies, 2, eps_peel, seed)
-            ti, td = pl.run()
-            stats.append((pl.cols, pl.ranks))
-        tinv.append(ti)
-        tr.append(td)
-    t = np.array([tr[0], tr[1], tinv[0]])
+        pl = peel.Peeler(F.tree, applies, 3, eps_peel, seed)
+        t_inv, t1, t2 = pl.run()
+        out.update(peel_cols=pl.cols, peel_ranks=pl.ranks)
+    t = np.array([t1, t2, t_inv])
     out.update(q=q, t=t, g=q - 0.5 * t, factor_rho=Fs[0], factor_theta2=Fs[1])
-    if stats:
-        out.update(peel_cols=stats[0][0], peel_ranks=stats[0][1], peel_cols2=stats[1][0],
-                   peel_ranks2=stats[1][1])
     return out
-

@@ -399,29 +399,45 @@ struct Peeler {
   const Tree& t;
   hipStream_t s;
   Arena store;  // low-rank blocks of every level
-  std::vector<LevelLR> lr[2];
-  const FactorData* Fd;  // the derivative factorization of the second operator
-  Peeler(const rsf_factor_s* hh, const FactorData* fd, hipStream_t ss) : h(hh), t(hh->tree), s(ss), Fd(fd) {}
+  // operator 0 is B B^T; operator k >= 1 is B F_k B^T with F_k = Fd[k - 1]
+  static constexpr int MAXOP = 3;
+  std::vector<LevelLR> lr[MAXOP];
+  const FactorData* Fd[MAXOP - 1];  // the derivative factorizations
+  int nop;
+  Peeler(const rsf_factor_s* hh, const FactorData* const* fd, int nd, hipStream_t ss)
+      : h(hh), t(hh->tree), s(ss), nop(1 + nd) {
+    RSF_CHECK(nd >= 1 && nd <= MAXOP - 1, RSF_E_INVALID, "peeling takes one or two derivative factorizations");
+    for (int k = 0; k < nd; ++k) Fd[k] = fd[k];
+  }
 
-  // out_op = G_op X for both operators (X row-major n x nc); X is preserved.
+  // out[op] = G_op X for every operator (X row-major n x nc); X is preserved.
   // cols (host, per instance, or null): the leading columns each instance's
   // rows take part in.
-  void apply_ops(const double* X, int nc, double* out0, double* out1, Scratch& scr, const int* cols) {
+  void apply_ops(const double* X, int nc, double* const* out, Scratch& scr, const int* cols) {
     const long long n = t.n, sz = n * nc;
     double* H = scr.make<double>(sz);
     copy_dev(H, X, sz, s);
     sweep_half_down(h, h->F, H, nc, nc, scr, s, cols);  // B^T X
-    copy_dev(out0, H, sz, s);
-    // B B^T X beside F_rho B^T X and B F_rho B^T X: the two sweeps are
-    // independent and each leaves part of the GPU idle
+    copy_dev(out[0], H, sz, s);
+    double* H2 = nullptr;
+    if (nop == 3) {
+      H2 = scr.make<double>(sz);
+      copy_dev(H2, H, sz, s);
+    }
+    // B B^T X (and B F_2 B^T X) beside F_1 B^T X and B F_1 B^T X: the sweeps
+    // are independent and each leaves part of the GPU idle
     beside(
         [&](hipStream_t s2) {
           Scratch sc2(s2);
-          sweep_half_up(h, h->F, out0, nc, nc, sc2, s2, cols);  // B B^T X
+          sweep_half_up(h, h->F, out[0], nc, nc, sc2, s2, cols);  // B B^T X
+          if (nop == 3) {
+            sweep_apply_mult(h, *Fd[1], H2, out[2], nc, nc, sc2, s2, cols);  // F_2 B^T X (H2 is consumed)
+            sweep_half_up(h, h->F, out[2], nc, nc, sc2, s2, cols);           // B F_2 B^T X
+          }
         },
         [&] {
-          sweep_apply_mult(h, *Fd, H, out1, nc, nc, scr, s, cols);  // F_rho B^T X (H is consumed)
-          sweep_half_up(h, h->F, out1, nc, nc, scr, s, cols);            // B F_rho B^T X
+          sweep_apply_mult(h, *Fd[0], H, out[1], nc, nc, scr, s, cols);  // F_1 B^T X (H is consumed)
+          sweep_half_up(h, h->F, out[1], nc, nc, scr, s, cols);          // B F_1 B^T X
         });
   }
 
@@ -793,10 +809,11 @@ struct Peeler {
     RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "peeling: singular normal equations of a basis or core matrix");
   }
 
-  void run(double eps_peel, uint64_t seed, double* tr_inv, double* tr_rho, PeelStats* st) {
+  // traces[op][i]: the trace of operator op for instance i
+  void run(double eps_peel, uint64_t seed, double* const* traces, PeelStats* st) {
     const long long n = t.n;
     const int D = t.maxdepth, ni = t.ninst;
-    for (int op = 0; op < 2; ++op) lr[op].assign(D + 1, LevelLR());
+    for (int op = 0; op < nop; ++op) lr[op].assign(D + 1, LevelLR());
     // relative pivots below ~1e-13 of the Gram diagonal are rounding noise
     // (the Gram squares the singular values), so the threshold is floored there
     const double tol2 = std::max(eps_peel * eps_peel, 1e-13);
@@ -810,7 +827,7 @@ struct Peeler {
     upload(drinst, rinst, s);
     // probe and sample stores, kept across levels (capacity Ccap columns per quadrant block)
     double* Om = nullptr;
-    double* Y[2] = {nullptr, nullptr};
+    double* Y[MAXOP] = {nullptr, nullptr, nullptr};
     int Ccap = 0;
     for (int lev = 1; lev <= D; ++lev) {
       const auto cl0 = std::chrono::steady_clock::now();
@@ -848,8 +865,9 @@ struct Peeler {
       for (int i = 0; i < ni; ++i)
         if (has[i]) cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i], peeled[i]);
       int C = 0;  // layout of the probe and sample stores (columns per quadrant block)
-      std::vector<int> rk(2 * nblk), maxr(ni, 0);
-      std::vector<long long> poff(2 * nblk + 1, 0);
+      const int nsb = nop * nblk;  // sample blocks of every operator
+      std::vector<int> rk(nsb), maxr(ni, 0);
+      std::vector<long long> poff(nsb + 1, 0);
       int* dpiv = nullptr;
       while (true) {
         const int cnew = *std::max_element(cc.begin(), cc.end());
@@ -860,30 +878,31 @@ struct Peeler {
           // grow the probe and sample stores: a new layout, the samples taken so far copied over
           const int cap = std::max(cnew, Ccap);
           double* Om2 = keep.make<double>((size_t)n * cap);
-          double* Y2[2] = {keep.make<double>((size_t)n * 4 * cap), keep.make<double>((size_t)n * 4 * cap)};
+          double* Y2[MAXOP] = {nullptr, nullptr, nullptr};
+          for (int op = 0; op < nop; ++op) Y2[op] = keep.make<double>((size_t)n * 4 * cap);
           if (C > 0) {
             hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * C)), dim3(256), 0, s, n, 1, C, Om, C, Om2, cnew);
-            for (int op = 0; op < 2; ++op)
+            for (int op = 0; op < nop; ++op)
               hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * 4 * C)), dim3(256), 0, s, n, 4, C, Y[op], C, Y2[op],
                                  cnew);
             RSF_HIP(hipGetLastError());
           }
           keep.release(Om);
-          keep.release(Y[0]);
-          keep.release(Y[1]);
+          for (int op = 0; op < nop; ++op) {
+            keep.release(Y[op]);
+            Y[op] = Y2[op];
+          }
           Om = Om2;
-          Y[0] = Y2[0];
-          Y[1] = Y2[1];
           Ccap = cap;
           C = cnew;
         }
         tm[6] += std::chrono::duration<double>(std::chrono::steady_clock::now() - cg0).count();
         // the new probe columns of every instance go through the operators
-        // together, in chunks that keep the four n x 4 cw work panels within
+        // together, in chunks that keep the 2 nop n x 4 cw work panels within
         // PEEL_CHUNK_BYTES
         int newmax = 0;
         for (int i = 0; i < ni; ++i) newmax = std::max(newmax, cc[i] - tot[i]);
-        const long long per_col = 4LL * n * 4 * (long long)sizeof(double);
+        const long long per_col = 2LL * nop * n * 4 * (long long)sizeof(double);
         const int cw = std::min(newmax, (int)std::max<long long>(8, PEEL_CHUNK_BYTES / per_col / 8 * 8));
         int* dact = scr.make<int>(ni);
         int* dj0 = scr.make<int>(ni);
@@ -904,27 +923,29 @@ struct Peeler {
           hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * ncw)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, lev,
                              seed, Wm, Om, (long long)C);
           RSF_HIP(hipGetLastError());
-          double* B0 = rs.make<double>(n * 4LL * cw);
-          double* B1 = rs.make<double>(n * 4LL * cw);
+          double* Bo[MAXOP] = {nullptr, nullptr, nullptr};
+          for (int op = 0; op < nop; ++op) Bo[op] = rs.make<double>(n * 4LL * cw);
           const int* pc = ni > 1 ? pcols.data() : nullptr;
           auto c0 = std::chrono::steady_clock::now();
-          apply_ops(Wm, 4 * ncw, B0, B1, rs, pc);
+          apply_ops(Wm, 4 * ncw, Bo, rs, pc);
           auto c1 = std::chrono::steady_clock::now();
           const CompactProbes cpr{Om, (long long)C, &j0, &qd};
-          // the two operators' subtractions and sample stores side by side
+          auto sub_store = [&](int op, Scratch& r, hipStream_t st) {
+            subtract_lowrank(op, lev, Wm, 4 * ncw, Bo[op], r, pc, &cpr, st);
+            hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, st, dqd, drinst, dact, dj0, n,
+                               ncw, C, Bo[op], Y[op]);
+            RSF_HIP(hipGetLastError());
+          };
+          // the operators' subtractions and sample stores side by side
+          // (operator 1 on the side stream)
           beside(
               [&](hipStream_t s2) {
                 Scratch r2(s2);
-                subtract_lowrank(1, lev, Wm, 4 * ncw, B1, r2, pc, &cpr, s2);
-                hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s2, dqd, drinst, dact, dj0,
-                                   n, ncw, C, B1, Y[1]);
-                RSF_HIP(hipGetLastError());
+                sub_store(1, r2, s2);
               },
               [&] {
-                subtract_lowrank(0, lev, Wm, 4 * ncw, B0, rs, pc, &cpr);
-                hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, s, dqd, drinst, dact, dj0,
-                                   n, ncw, C, B0, Y[0]);
-                RSF_HIP(hipGetLastError());
+                for (int op = 0; op < nop; ++op)
+                  if (op != 1) sub_store(op, rs, s);
               });
           auto c2 = std::chrono::steady_clock::now();
           tm[0] += std::chrono::duration<double>(c1 - c0).count();
@@ -933,15 +954,15 @@ struct Peeler {
         for (int i = 0; i < ni; ++i) tot[i] = cc[i];
         // ranks of every sample block (both operators) by pivoted Cholesky of
         // its Gram matrix, in chunks that bound the Gram storage
-        std::vector<int> bc(2 * nblk);
-        for (int idx = 0; idx < 2 * nblk; ++idx) {
+        std::vector<int> bc(nsb);
+        for (int idx = 0; idx < nsb; ++idx) {
           bc[idx] = tot[t.inst[blocks[idx % nblk].first]];
           poff[idx + 1] = poff[idx] + bc[idx];
         }
         scr.release(dpiv);
-        dpiv = scr.make<int>(std::max<long long>(poff[2 * nblk], 1));
-        // the sample blocks of the two operators side by side (operator 1 on
-        // the side stream), each in chunks that bound the Gram storage
+        dpiv = scr.make<int>(std::max<long long>(poff[nsb], 1));
+        // the sample blocks of the operators side by side (operator 1 on the
+        // side stream), each in chunks that bound the Gram storage
         auto gram_ranks = [&](int ebeg, int eend, hipStream_t st) {
           for (int e0 = ebeg; e0 < eend;) {
             std::vector<long long> goff(1, 0);
@@ -977,7 +998,11 @@ struct Peeler {
         };
         {
           auto c0 = std::chrono::steady_clock::now();
-          beside([&](hipStream_t s2) { gram_ranks(nblk, 2 * nblk, s2); }, [&] { gram_ranks(0, nblk, s); });
+          beside([&](hipStream_t s2) { gram_ranks(nblk, 2 * nblk, s2); },
+                 [&] {
+                   gram_ranks(0, nblk, s);
+                   if (nop > 2) gram_ranks(2 * nblk, nsb, s);
+                 });
           tm[2] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
         }
         // an instance needs more columns while a block's rank is not
@@ -985,7 +1010,7 @@ struct Peeler {
         // than the block's own)
         std::vector<int> need(ni, 0);
         std::fill(maxr.begin(), maxr.end(), 0);
-        for (int idx = 0; idx < 2 * nblk; ++idx) {
+        for (int idx = 0; idx < nsb; ++idx) {
           const int e = idx % nblk, i = t.inst[blocks[e].first], k = rk[idx];
           maxr[i] = std::max(maxr[i], k);
           if (k + OVERSAMPLE > tot[i] && tot[i] < t.count[blocks[e].second]) need[i] = 1;
@@ -1012,7 +1037,7 @@ struct Peeler {
       }
       TraceTag tg("peel_lowrank");
       const int np = (int)pairs.size();
-      for (int op = 0; op < 2; ++op) {
+      for (int op = 0; op < nop; ++op) {
         LevelLR& L = lr[op][lev];
         L.any = true;
         std::vector<int> pos(t.nbox(), -1);
@@ -1069,7 +1094,10 @@ struct Peeler {
       // bases and core matrices: operator 1 on the side stream beside operator 0
       auto c0 = std::chrono::steady_clock::now();
       beside([&](hipStream_t s2) { lowrank_level(lr[1][lev], tot, C, Y[1], Om, dpiv, poff, nblk, s2); },
-             [&] { lowrank_level(lr[0][lev], tot, C, Y[0], Om, dpiv, poff, 0, s); });
+             [&] {
+               for (int op = 0; op < nop; ++op)
+                 if (op != 1) lowrank_level(lr[op][lev], tot, C, Y[op], Om, dpiv, poff, op * nblk, s);
+             });
       tm[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
     }
     // extraction at the leaves: traces of every instance over its own leaves
@@ -1096,25 +1124,23 @@ struct Peeler {
     fill_zero(E, sz, s);
     hipLaunchKernelGGL(eye_blocks_kernel, dim3(nleaf), dim3(256), 0, s, dlb, dlc, nleaf, E, nL);
     RSF_HIP(hipGetLastError());
-    double* H0 = scr.make<double>(sz);
-    double* H1 = scr.make<double>(sz);
-    apply_ops(E, nL, H0, H1, scr, nullptr);
-    subtract_lowrank(0, D + 1, E, nL, H0, scr, nullptr);
-    subtract_lowrank(1, D + 1, E, nL, H1, scr, nullptr);
-    double* tr = scr.make<double>(2 * ni);
+    double* Ho[MAXOP] = {nullptr, nullptr, nullptr};
+    for (int op = 0; op < nop; ++op) Ho[op] = scr.make<double>(sz);
+    apply_ops(E, nL, Ho, scr, nullptr);
+    for (int op = 0; op < nop; ++op) subtract_lowrank(op, D + 1, E, nL, Ho[op], scr, nullptr);
+    double* tr = scr.make<double>(nop * ni);
     for (int i = 0; i < ni; ++i) {
       const int l0 = lfirst[i], nl = lfirst[i + 1] - lfirst[i];
-      hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb + l0, dlc + l0, nl, H0, nL, tr + i);
-      hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb + l0, dlc + l0, nl, H1, nL, tr + ni + i);
+      for (int op = 0; op < nop; ++op)
+        hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb + l0, dlc + l0, nl, Ho[op], nL,
+                           tr + op * ni + i);
     }
     RSF_HIP(hipGetLastError());
-    std::vector<double> th(2 * ni);
+    std::vector<double> th(nop * ni);
     RSF_HIP(hipMemcpyAsync(th.data(), tr, th.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     RSF_HIP(hipStreamSynchronize(s));
-    for (int i = 0; i < ni; ++i) {
-      tr_inv[i] = th[i];
-      tr_rho[i] = th[ni + i];
-    }
+    for (int op = 0; op < nop; ++op)
+      for (int i = 0; i < ni; ++i) traces[op][i] = th[op * ni + i];
     if (st) {
       st->levels = D;
       st->leaf_cols = nL;
@@ -1130,9 +1156,11 @@ struct Peeler {
 }  // namespace
 
 void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv, double* tr_rho,
-                 PeelStats* st, hipStream_t s, const FactorData* Fd) {
-  Peeler p(h, Fd ? Fd : h->Frho.get(), s);
-  p.run(eps_peel, seed, tr_inv, tr_rho, st);
+                 PeelStats* st, hipStream_t s, const FactorData* Fd2, double* tr_rho2) {
+  const FactorData* fd[2] = {h->Frho.get(), Fd2};
+  double* traces[3] = {tr_inv, tr_rho, tr_rho2};
+  Peeler p(h, fd, Fd2 ? 2 : 1, s);
+  p.run(eps_peel, seed, traces, st);
 }
 
 }  // namespace rsf
@@ -1257,13 +1285,14 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   RSF_HIP(hipStreamSynchronize(s));
   const auto t2 = clk::now();
   std::vector<double> trinv(ni), trrho(ni), trinv2(ni), trrho2(ni);
-  PeelStats ps, ps2;
+  PeelStats ps;
   if (hutch_probes > 0) {
     hutch_traces(f, hutch_probes, seed, trinv.data(), trrho.data(), s);
     if (aniso) hutch_traces(f, hutch_probes, seed, trinv2.data(), trrho2.data(), s, f->Frho2.get());
   } else {
-    peel_traces(f, eps_peel, seed, trinv.data(), trrho.data(), &ps, s);
-    if (aniso) peel_traces(f, eps_peel, seed, trinv2.data(), trrho2.data(), &ps2, s, f->Frho2.get());
+    // anisotropic kernels: B B^T, B F_theta1 B^T and B F_theta2 B^T from one set of probes
+    peel_traces(f, eps_peel, seed, trinv.data(), trrho.data(), &ps, s, aniso ? f->Frho2.get() : nullptr,
+                aniso ? trrho2.data() : nullptr);
   }
   const auto t3 = clk::now();
   double q0[3] = {0, 0, 0}, tt0[3] = {0, 0, 0};

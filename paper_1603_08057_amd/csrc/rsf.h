@@ -172,9 +172,11 @@ struct PeelStats {
   int rank[32] = {0};
   int leaf_cols = 0;
 };
-// Fd: the derivative factorization of the second operator (default: Frho).
+// Traces per instance of B B^T (tr_inv) and B Frho B^T (tr_rho), and with Fd2
+// also of B Fd2 B^T (tr_rho2), peeled jointly from one set of probes.
 void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* tr_inv,
-                 double* tr_rho, PeelStats* st, hipStream_t s, const FactorData* Fd = nullptr);
+                 double* tr_rho, PeelStats* st, hipStream_t s, const FactorData* Fd2 = nullptr,
+                 double* tr_rho2 = nullptr);
 
 // Score equations of every instance: g (3 values per instance, host); d_z in
 // caller order (instances concatenated).  info (may be null) gets instance 0's
