@@ -161,9 +161,15 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default=DEFAULT)
     ap.add_argument("--n", type=int, default=None, help="override n (same recipe)")
+    ap.add_argument("--eps", type=float, default=None, help="override the factorization tolerance")
+    ap.add_argument("--eps-peel", type=float, default=None, help="override the peeling tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hutch", type=int, default=0,
                     help="score traces by Hutchinson's estimator with this many probes instead of peeling")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only copy 1 GiB device to device (the known-size run that scales the HBM counters)")
+    ap.add_argument("--setup-launches", action="store_true",
+                    help="only count the traced launches of the setup (factorization and z = F^(1/2) w)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -175,12 +181,24 @@ def main():
     import paper_1603_08057_amd as R
     import workloads as W
 
+    if args.copy_calibration:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print("copied %d bytes" % (8 * a.numel()))
+        return
     if args.workload in W.BATCHES:
         return bench_batch(args)
     spec = dict(W.WORKLOADS[args.workload])
     name = args.workload
     if args.n:
         spec["n"] = args.n
+    if args.eps:
+        spec["eps"] = args.eps
+    if args.eps_peel:
+        spec["eps_peel"] = args.eps_peel
     n = spec["n"]
     dev = torch.device("cuda:0")
     P = torch.tensor(W.workload_points(name, n), dtype=torch.float64, device=dev)
@@ -189,9 +207,17 @@ def main():
     eps_peel = spec.get("eps_peel", spec["eps"])
     kw = dict(kernel=spec["kernel"], eps=spec["eps"], leaf=spec["leaf"], n_prox=spec["n_prox"],
               prox_rings=spec["prox_rings"], rq_alpha=spec["alpha"])
+    if args.setup_launches:
+        R.trace_enable(True)
     F0 = R.Factor(P, theta, **kw)
     z = F0.apply_sqrt(w)
     F0.close()
+    if args.setup_launches:
+        torch.cuda.synchronize()
+        R.trace_enable(False)
+        ms, _, _, launches = R.trace_read(reset=True)[:4]
+        print("setup traced launches %d ms %.1f" % (launches, ms))
+        return
     torch.cuda.synchronize()
     print("setup done: n=%d" % n, file=sys.stderr, flush=True)
 
@@ -216,8 +242,10 @@ def main():
     R.trace_enable(True)
     t0 = time.time()
     for i in range(args.steps):
+        t1 = time.time()
         ell, g, info = step()
-        print("step %d done" % i, file=sys.stderr, flush=True)
+        print("step %d done: %.3f s  peel %.3f s" % (i, time.time() - t1, info.seconds[2]), file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     elapsed = time.time() - t0
     R.trace_enable(False)
@@ -252,7 +280,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": name if not args.n else "%s_recipe_n%d" % (name, n), "n": n,
+        "config": {"workload": name if not (args.n or args.eps or args.eps_peel) else
+                   "%s_recipe_n%d_eps%g_peel%g" % (name, n, spec["eps"], eps_peel), "n": n,
                    "kernel": KERNEL_NAMES.get(spec["kernel"], spec["kernel"]), "theta": list(theta),
                    "eps": spec["eps"], "eps_peel": eps_peel, "leaf": spec["leaf"], "n_prox": spec["n_prox"],
                    "parallelism": "single GPU"},
@@ -262,7 +291,8 @@ def main():
                      "achieved": achieved, "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / FP64_MFMA_PEAK_TFLOPS,
                      "traffic": (measured_traffic(launches / args.steps)
-                                 if not args.n and name == DEFAULT and args.hutch <= 0 else None),
+                                 if not (args.n or args.eps or args.eps_peel) and name == DEFAULT and args.hutch <= 0
+                                 else None),
                      "algorithmic_bytes_per_launch": nbytes / max(launches, 1),
                      "launches": launches, "kernel_ms_per_step": ms / args.steps,
                      "flops_per_launch": flops / max(launches, 1),

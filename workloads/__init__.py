@@ -66,6 +66,10 @@ WORKLOADS = {
     "g1_matern32aniso_grid256": dict(n=65536, points=("grid", 100.0), w_seed=62, peel_seed=63,
                                      kernel=MATERN32_ANISO, theta=(10.0, 7.0, 1e-4), alpha=1.0,
                                      eps=1e-9, eps_peel=1e-6, leaf=64, n_prox=256, prox_rings=4, nrhs=1),
+    # the same grid with the rational quadratic kernel of eq. specrq (alpha = 1/2)
+    "g2_rqaniso_grid256": dict(n=65536, points=("grid", 100.0), w_seed=64, peel_seed=65,
+                               kernel=RQ_ANISO, theta=(10.0, 7.0, 1e-4), alpha=0.5,
+                               eps=1e-9, eps_peel=1e-6, leaf=64, n_prox=256, prox_rings=4, nrhs=1),
 }
 
 
