@@ -44,10 +44,11 @@ def measured_traffic(launches_per_step):
     for f in FAMILY_SOURCES:
         with open(os.path.join(HERE, f), "rb") as fh:
             h.update(fh.read())
-    if h.hexdigest() != rec.get("sources_sha256"):
+    if h.hexdigest() != rec.get("sources_sha256") or "family_hbm_bytes_per_step" not in rec:
         return None
-    # the counted run holds the setup factorization and one step
-    return rec["family_hbm_bytes"] / (launches_per_step + rec["setup_launches_estimate"])
+    # two counted runs of one and of two steps: their difference is one
+    # steady-state step (the setup and the first step's autotuning cancel)
+    return rec["family_hbm_bytes_per_step"] / launches_per_step
 
 
 KERNEL_NAMES = {0: "matern12", 1: "matern32", 2: "matern52", 3: "rq", 4: "matern32_aniso", 5: "rq_aniso"}
@@ -168,8 +169,6 @@ def main():
                     help="score traces by Hutchinson's estimator with this many probes instead of peeling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (the known-size run that scales the HBM counters)")
-    ap.add_argument("--setup-launches", action="store_true",
-                    help="only count the traced launches of the setup (factorization and z = F^(1/2) w)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
@@ -207,17 +206,9 @@ def main():
     eps_peel = spec.get("eps_peel", spec["eps"])
     kw = dict(kernel=spec["kernel"], eps=spec["eps"], leaf=spec["leaf"], n_prox=spec["n_prox"],
               prox_rings=spec["prox_rings"], rq_alpha=spec["alpha"])
-    if args.setup_launches:
-        R.trace_enable(True)
     F0 = R.Factor(P, theta, **kw)
     z = F0.apply_sqrt(w)
     F0.close()
-    if args.setup_launches:
-        torch.cuda.synchronize()
-        R.trace_enable(False)
-        ms, _, _, launches = R.trace_read(reset=True)[:4]
-        print("setup traced launches %d ms %.1f" % (launches, ms))
-        return
     torch.cuda.synchronize()
     print("setup done: n=%d" % n, file=sys.stderr, flush=True)
 
