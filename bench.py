@@ -51,6 +51,28 @@ def measured_traffic(launches_per_step):
     return rec["family_hbm_bytes_per_step"] / launches_per_step
 
 
+def bench_mle(args, spec, name, P, z, kw, eps_peel):
+    """The MLE loop: L-BFGS-B over log theta (the nugget held fixed) from the
+    workload's theta0, every l and g from the library."""
+    import torch
+    import paper_1603_08057_amd as R
+    kw = dict(kw)
+    kernel, eps = kw.pop("kernel"), kw.pop("eps")
+    leaf = kw.pop("leaf")
+    t0 = time.time()
+    r = R.fit(P, z, spec["theta0"], kernel, eps=eps, eps_peel=eps_peel, leaf=leaf, seed=spec.get("peel_seed", 0),
+              log=sys.stderr, **kw)
+    torch.cuda.synchronize()
+    el = time.time() - t0
+    print(json.dumps({
+        "metric": "MLE fit (L-BFGS-B over log theta, nugget fixed)", "seconds": el, "unit": "s",
+        "objective_calls": r.nfev, "iterations": r.nit, "success": r.success, "message": r.message,
+        "theta_true": list(spec["theta"]), "theta0": list(spec["theta0"]), "theta_hat": [float(v) for v in r.theta],
+        "ell_hat": r.ell, "grad_hat": [float(v) for v in r.grad],
+        "seconds_per_call": el / max(r.nfev, 1), "n": int(P.shape[0]), "dtype": "f64", "data": "synthetic",
+        "config": {"workload": name, "eps": eps, "eps_peel": eps_peel, "leaf": leaf}}))
+
+
 KERNEL_NAMES = {0: "matern12", 1: "matern32", 2: "matern52", 3: "rq", 4: "matern32_aniso", 5: "rq_aniso"}
 
 
@@ -167,6 +189,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hutch", type=int, default=0,
                     help="score traces by Hutchinson's estimator with this many probes instead of peeling")
+    ap.add_argument("--mle", action="store_true",
+                    help="fit theta by the MLE driver from the workload's theta0 (data drawn at its theta) "
+                         "and print one JSON line with the fit")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (the known-size run that scales the HBM counters)")
     args = ap.parse_args()
@@ -211,6 +236,8 @@ def main():
     F0.close()
     torch.cuda.synchronize()
     print("setup done: n=%d" % n, file=sys.stderr, flush=True)
+    if args.mle:
+        return bench_mle(args, spec, name, P, z, kw, eps_peel)
 
     def step():
         # Sigma_rho is factored beside Sigma (second stream), as the score needs it

@@ -163,7 +163,10 @@ typedef struct {
  * traces of F^-1 and F^-1 F_rho (Section 3 allows any such symmetrized form):
  * B B^T and B F_rho B^T for F^-1 = B^T B (B: the up half of the solve sweep),
  * to relative tolerance eps_peel, with Gaussian probes from Philox4x32-10 keyed by
- * seed.
+ * seed.  For the anisotropic kernels theta = (theta_1, theta_2, nugget): q and
+ * t of theta_1 and theta_2 come from two derivative skeletonizations, and the
+ * three operators B B^T, B F_theta1 B^T and B F_theta2 B^T are peeled from one
+ * set of probes.
  *   d_z       device, n observations (caller's order).
  *   g         host, 3 values.
  *   info_or_null  host; receives the split terms and peeling statistics. */

@@ -34,11 +34,12 @@ class FitResult:
 
 
 def fit(points, z, theta0, kernel, eps=1e-9, eps_peel=1e-6, leaf=64, seed=0, fixed=(False, False, True),
-        maxiter=50, gtol=1e-5, ftol=1e-12, **opts):
+        maxiter=50, gtol=1e-5, ftol=1e-12, log=None, **opts):
     """Maximise l(theta) from theta0 (a 3-vector in the kernel's order).
 
     points: (n, 2) float64 device tensor; z: (n,) float64 device tensor.
     fixed: which entries of theta stay at theta0 (default: the nugget).
+    log: a writable text stream that gets one line per objective call, or None.
     Returns a FitResult with theta, l(theta), the score g(theta), and the
     (theta, l, g) history of every objective call."""
     from scipy.optimize import minimize
@@ -65,6 +66,9 @@ def fit(points, z, theta0, kernel, eps=1e-9, eps_peel=1e-6, leaf=64, seed=0, fix
             F.close()
         g = np.asarray(g, dtype=np.float64)
         history.append((th.copy(), ell, g.copy()))
+        if log is not None:
+            log.write("fit call %d: theta %s l %.10e g %s\n" % (len(history), list(th), ell, list(g)))
+            log.flush()
         # d(-l)/d(log theta_i) = -g_i theta_i
         return -ell, -(g * th)[free]
 

@@ -66,6 +66,13 @@ WORKLOADS = {
     "g1_matern32aniso_grid256": dict(n=65536, points=("grid", 100.0), w_seed=62, peel_seed=63,
                                      kernel=MATERN32_ANISO, theta=(10.0, 7.0, 1e-4), alpha=1.0,
                                      eps=1e-9, eps_peel=1e-6, leaf=64, n_prox=256, prox_rings=4, nrhs=1),
+    # the paper's MLE example (Section 5): 2^16 scattered sites (here uniform
+    # in [0, 100]^2), anisotropic Matern 3/2, theta* = (10, 7), noise 1e-4 held
+    # fixed, eps_fact 1e-9, eps_peel 1e-6, the fit starting from (3, 30)
+    "m1_matern32aniso_scattered65536": dict(n=65536, points=("uniform", 71, 100.0), w_seed=72, peel_seed=73,
+                                            kernel=MATERN32_ANISO, theta=(10.0, 7.0, 1e-4),
+                                            theta0=(3.0, 30.0, 1e-4), alpha=1.0, eps=1e-9, eps_peel=1e-6,
+                                            leaf=64, n_prox=256, prox_rings=4, nrhs=1),
     # the same grid with the rational quadratic kernel of eq. specrq (alpha = 1/2)
     "g2_rqaniso_grid256": dict(n=65536, points=("grid", 100.0), w_seed=64, peel_seed=65,
                                kernel=RQ_ANISO, theta=(10.0, 7.0, 1e-4), alpha=0.5,
@@ -109,7 +116,7 @@ def workload_points(name, n=None):
     n = w["n"] if n is None else n
     kind = w["points"]
     if kind[0] == "uniform":
-        return uniform_points(n, kind[1])
+        return uniform_points(n, kind[1]) * (kind[2] if len(kind) > 2 else 1.0)
     if kind[0] == "mixed":
         return mixed_points(n, 16, 0.02, kind[1], kind[2])
     if kind[0] == "grid":
