@@ -67,7 +67,7 @@ def fit(points, z, theta0, kernel, eps=1e-9, eps_peel=1e-6, leaf=64, seed=0, fix
         g = np.asarray(g, dtype=np.float64)
         history.append((th.copy(), ell, g.copy()))
         if log is not None:
-            log.write("fit call %d: theta %s l %.10e g %s\n" % (len(history), list(th), ell, list(g)))
+            log.write("fit call %d: theta %s l %.10e g %s\n" % (len(history), th.tolist(), ell, g.tolist()))
             log.flush()
         # d(-l)/d(log theta_i) = -g_i theta_i
         return -ell, -(g * th)[free]

@@ -1,7 +1,8 @@
 """Anisotropic kernels (eq. specmatern, eq. specrq) on the HIP path against the
 oracle and the dense definitions: skeletons, log|F|, solves, l, the score
-(three factorizations: Sigma, Sigma_theta1, Sigma_theta2; two peeled traces
-beside Tr F^-1), Hutchinson traces, and the MLE driver against a dense MLE.
+(three factorizations: Sigma, Sigma_theta1, Sigma_theta2; B B^T, B F_theta1 B^T
+and B F_theta2 B^T peeled from one set of probes), Hutchinson traces, batches,
+and the MLE driver against a dense MLE.
 """
 import math
 
@@ -136,3 +137,25 @@ def test_mle_matches_dense_mle():
     # the score at the estimate is small against its value at the start
     g0 = r.history[0][2]
     assert np.max(np.abs(r.grad[:2] * r.theta[:2])) <= 1e-2 * np.max(np.abs(g0[:2] * r.history[0][0][:2]))
+
+
+def test_aniso_batched_scores_against_dense():
+    """A batch of anisotropic instances (own theta_1, theta_2 each): every
+    instance's score within the dense bound, and its log-det equal to a
+    single-instance handle's."""
+    print("aniso batch", flush=True)
+    inst = [(W.uniform_points(700, 81), (0.15, 0.06, 1e-3)), (W.uniform_points(1500, 82), (0.05, 0.12, 1e-3)),
+            (W.uniform_points(1100, 83), (0.1, 0.1, 1e-3))]
+    B = R.BatchedFactor([_t(p) for p, _ in inst], [th for _, th in inst], kernel=K.MATERN32_ANISO, eps=1e-8,
+                        leaf=64)
+    zs = [dense.sample(p, W.gaussian(len(p), 90 + i), th, K.MATERN32_ANISO) for i, (p, th) in enumerate(inst)]
+    eps_peel = 1e-6
+    gs, _ = B.grad([_t(z) for z in zs], eps_peel, 19)
+    for i, ((P, th), z) in enumerate(zip(inst, zs)):
+        F = R.Factor(_t(P), th, kernel=K.MATERN32_ANISO, eps=1e-8, leaf=64)
+        assert B.logdets[i] == pytest.approx(F.logdet, rel=1e-12)
+        d = dense.loglik_and_grad(P, z, th, K.MATERN32_ANISO, want_terms=True)
+        scale = np.abs(d["q"]) + 0.5 * np.abs(d["t"])
+        err = np.abs(np.array(gs[i]) - d["g"]) / scale
+        print("instance %d: g %s dense %s err/scale %s" % (i, np.array(gs[i]), d["g"], err), flush=True)
+        assert np.all(err <= 1e3 * 1e-8 + 50 * eps_peel)
