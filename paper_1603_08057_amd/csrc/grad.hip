@@ -1197,9 +1197,12 @@ __global__ void rademacher_kernel(long long n, int q, const long long* __restric
 // w_j = B^T u_j (F^-1 = B^T B), |w_j|^2 and w_j^T F_rho w_j have expectations
 // Tr B B^T = Tr F^-1 and Tr B F_rho B^T = Tr F^-1 F_rho; one half solve sweep
 // and one multiply sweep over the q probe columns.
+// With Fd2 (the anisotropic kernels' second derivative factorization), also
+// trho2 = mean w^T F_2 w from the same w.
 static void hutch_traces(rsf_factor_s* f, int q, uint64_t seed, double* tinv, double* trho, hipStream_t s,
-                         const FactorData* Fd = nullptr) {
-  if (!Fd) Fd = f->Frho.get();
+                         const FactorData* Fd2 = nullptr, double* trho2 = nullptr) {
+  const FactorData* Fd = f->Frho.get();
+  const int nd = Fd2 ? 3 : 2;  // dot products per instance
   TraceTag tag("hutch");
   const Tree& t = f->tree;
   const long long n = t.n;
@@ -1208,7 +1211,8 @@ static void hutch_traces(rsf_factor_s* f, int q, uint64_t seed, double* tinv, do
   double* W = scr.make<double>(n * q);
   double* X = scr.make<double>(n * q);
   double* V = scr.make<double>(n * q);
-  double* dots = scr.make<double>(2 * ni);
+  double* V2 = Fd2 ? scr.make<double>(n * q) : nullptr;
+  double* dots = scr.make<double>(nd * ni);
   std::vector<long long> io(t.ioff.begin(), t.ioff.end());
   long long* dio = scr.make<long long>(io.size());
   upload(dio, io, s);
@@ -1216,18 +1220,24 @@ static void hutch_traces(rsf_factor_s* f, int q, uint64_t seed, double* tinv, do
   RSF_HIP(hipGetLastError());
   sweep_half_down(f, f->F, W, q, q, scr, s);  // W = B^T U
   copy_dev(X, W, n * q, s);
-  sweep_apply_mult(f, *Fd, X, V, q, q, scr, s);  // V = F_rho W
+  sweep_apply_mult(f, *Fd, X, V, q, q, scr, s);  // V = F_rho W (X is consumed)
+  if (Fd2) {
+    copy_dev(X, W, n * q, s);
+    sweep_apply_mult(f, *Fd2, X, V2, q, q, scr, s);  // V2 = F_2 W
+  }
   for (int i = 0; i < ni; ++i) {
     const long long o = t.ioff[i] * (long long)q, m = (t.ioff[i + 1] - t.ioff[i]) * (long long)q;
-    device_dot(W + o, W + o, m, dots + 2 * i, scr, s);
-    device_dot(W + o, V + o, m, dots + 2 * i + 1, scr, s);
+    device_dot(W + o, W + o, m, dots + nd * i, scr, s);
+    device_dot(W + o, V + o, m, dots + nd * i + 1, scr, s);
+    if (Fd2) device_dot(W + o, V2 + o, m, dots + nd * i + 2, scr, s);
   }
-  std::vector<double> hd(2 * ni);
+  std::vector<double> hd(nd * ni);
   RSF_HIP(hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   RSF_HIP(hipStreamSynchronize(s));
   for (int i = 0; i < ni; ++i) {
-    tinv[i] = hd[2 * i] / q;
-    trho[i] = hd[2 * i + 1] / q;
+    tinv[i] = hd[nd * i] / q;
+    trho[i] = hd[nd * i + 1] / q;
+    if (Fd2) trho2[i] = hd[nd * i + 2] / q;
   }
 }
 
@@ -1284,11 +1294,11 @@ void grad_eval(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, 
   RSF_HIP(hipMemcpyAsync(hd.data(), dots, hd.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   RSF_HIP(hipStreamSynchronize(s));
   const auto t2 = clk::now();
-  std::vector<double> trinv(ni), trrho(ni), trinv2(ni), trrho2(ni);
+  std::vector<double> trinv(ni), trrho(ni), trrho2(ni);
   PeelStats ps;
   if (hutch_probes > 0) {
-    hutch_traces(f, hutch_probes, seed, trinv.data(), trrho.data(), s);
-    if (aniso) hutch_traces(f, hutch_probes, seed, trinv2.data(), trrho2.data(), s, f->Frho2.get());
+    hutch_traces(f, hutch_probes, seed, trinv.data(), trrho.data(), s, aniso ? f->Frho2.get() : nullptr,
+                 aniso ? trrho2.data() : nullptr);
   } else {
     // anisotropic kernels: B B^T, B F_theta1 B^T and B F_theta2 B^T from one set of probes
     peel_traces(f, eps_peel, seed, trinv.data(), trrho.data(), &ps, s, aniso ? f->Frho2.get() : nullptr,
