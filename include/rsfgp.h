@@ -80,9 +80,11 @@ typedef struct {
                            accumulation; the IDs, the Cholesky factors of the redundant
                            blocks and of the root, log|F| and every sweep stay FP64 */
   int with_score;       /* 1: rsf_factor_create also factors the derivative matrix
-                           Sigma_rho that rsf_grad needs (Algorithm 1), on a second
-                           stream while Sigma is factored; rsf_grad then reuses it.
-                           0 (default): rsf_grad factors Sigma_rho itself */
+                           Sigma_rho that rsf_grad needs (Algorithm 1; both
+                           Sigma_theta1 and Sigma_theta2 for the anisotropic
+                           kernels), on a second stream while Sigma is factored;
+                           rsf_grad then reuses them.  0 (default): rsf_grad
+                           factors them itself */
 } rsf_opts;
 
 enum { RSF_FP64 = 0, RSF_MIXED = 1 };
