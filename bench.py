@@ -133,7 +133,7 @@ def bench_batch(args):
     print("setup done: %d instances, %d points" % (len(pts), ntot), file=sys.stderr, flush=True)
 
     def step_batched():
-        B = R.BatchedFactor(pts, thetas, with_score=True, **kw)
+        B = R.BatchedFactor(pts, thetas, with_score=True, precision=args.precision, **kw)
         ls = B.loglik(zs)
         gs, info = B.grad(zs, spec["eps"], spec["peel_seed"])
         B.close()
@@ -142,7 +142,7 @@ def bench_batch(args):
     def step_single():
         out = []
         for P, th, z in zip(pts, thetas, zs):
-            F = R.Factor(P, th, **kw)
+            F = R.Factor(P, th, precision=args.precision, **kw)
             ell = F.loglik(z)
             g, _ = F.grad(z, spec["eps"], spec["peel_seed"])
             F.close()
@@ -168,8 +168,8 @@ def bench_batch(args):
         "metric": "loglik+grad evals/sec of a %d-instance batch (eps=%g)" % (len(pts), spec["eps"]),
         "value": 1.0 / tb, "unit": "batch evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * tb, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": args.workload, "instances": len(pts), "points": ntot,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
+        "config": {"precision": args.precision, "workload": args.workload, "instances": len(pts), "points": ntot,
                    "n_range": [min(len(p) for p in pts), max(len(p) for p in pts)], "eps": spec["eps"],
                    "leaf": spec["leaf"], "parallelism": "single GPU"},
         "one_by_one": {"seconds": ts, "speedup_of_batching": ts / tb, "max_rel_diff_loglik": rel_l},
@@ -189,6 +189,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hutch", type=int, default=0,
                     help="score traces by Hutchinson's estimator with this many probes instead of peeling")
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
+                    help="arithmetic of the timed factorizations (mixed: FP32 kernel entries and Schur products; "
+                         "the data z is drawn in FP64 either way)")
     ap.add_argument("--mle", action="store_true",
                     help="fit theta by the MLE driver from the workload's theta0 (data drawn at its theta) "
                          "and print one JSON line with the fit")
@@ -239,9 +242,9 @@ def main():
     if args.mle:
         return bench_mle(args, spec, name, P, z, kw, eps_peel)
 
-    def step():
+    def step(precision=args.precision):
         # Sigma_rho is factored beside Sigma (second stream), as the score needs it
-        F = R.Factor(P, theta, with_score=True, **kw)
+        F = R.Factor(P, theta, with_score=True, precision=precision, **kw)
         ell = F.loglik(z)
         if args.hutch > 0:
             g, info = F.grad_hutch(z, args.hutch, spec.get("peel_seed", 0))
@@ -296,9 +299,10 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": name if not (args.n or args.eps or args.eps_peel) else
+        "config": {"precision": args.precision,
+                   "workload": name if not (args.n or args.eps or args.eps_peel) else
                    "%s_recipe_n%d_eps%g_peel%g" % (name, n, spec["eps"], eps_peel), "n": n,
                    "kernel": KERNEL_NAMES.get(spec["kernel"], spec["kernel"]), "theta": list(theta),
                    "eps": spec["eps"], "eps_peel": eps_peel, "leaf": spec["leaf"], "n_prox": spec["n_prox"],
@@ -325,6 +329,13 @@ def main():
         "result": {"loglik": ell, "grad": g, "peel_cols": list(info.peel_cols)[:12],
                    "peel_rank": list(info.peel_rank)[:12]},
     }
+    if args.precision != "fp64":
+        # the same evaluation in FP64, untimed: the mixed form's error against it
+        ell64, g64, info64 = step("fp64")
+        scale = [abs(a) + 0.5 * abs(b) for a, b in zip(info64.q, info64.t)]
+        out["vs_fp64"] = {"rel_err_loglik": abs(ell - ell64) / abs(ell64),
+                          "grad_err_over_scale": [abs(a - b) / s for a, b, s in zip(g, g64, scale)],
+                          "fp64_grad": list(g64)}
     if not args.no_cpu_baseline:
         print("timing the CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(spec, name)
