@@ -56,10 +56,10 @@ def round8(c):
 
 def first_cols(n):
     """Probe count at the first peeled level: the top-level sibling blocks have
-    ranks that grow like sqrt(n) (Section 3.3), so 3 sqrt(n), at least
-    FIRST_COLS, rounded up to a multiple of 8."""
+    ranks that grow like sqrt(n) (Section 3.3), so 9/4 sqrt(n) (integer
+    arithmetic), at least FIRST_COLS, rounded up to a multiple of 8."""
     import math
-    return round8(max(FIRST_COLS, 3 * math.isqrt(n)))
+    return round8(max(FIRST_COLS, 9 * math.isqrt(n) // 4))
 
 
 def next_cols(prev_rank, peeled):

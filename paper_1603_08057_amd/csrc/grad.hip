@@ -346,9 +346,9 @@ long long isqrt(long long n) {
 }
 
 // Probe columns at the first peeled level: sibling blocks of the top level
-// have ranks that grow like sqrt(n) (Section 3.3), so start at 3 sqrt(n), at
+// have ranks that grow like sqrt(n) (Section 3.3), so start at 9/4 sqrt(n), at
 // least FIRST_COLS.
-int first_cols(long long n) { return round8((int)std::max<long long>(FIRST_COLS, 3 * isqrt(n))); }
+int first_cols(long long n) { return round8((int)std::max<long long>(FIRST_COLS, 9 * isqrt(n) / 4)); }
 
 // Probe columns at the next level from the largest rank found at the level
 // above, plus the oversampling, at least MIN_COLS, rounded up to a multiple
