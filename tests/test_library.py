@@ -85,3 +85,16 @@ def test_binding_fails_loudly_without_a_device(monkeypatch):
     import paper_1603_08057_amd as R
     with pytest.raises(RuntimeError):
         R.Factor([[0.0, 0.0], [1.0, 1.0]], (0.1, 1.0, 1e-4))
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU: --gpus 2 exits with status 2 and says why,
+    before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
