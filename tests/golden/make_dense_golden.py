@@ -1,17 +1,19 @@
 """Writes dense-oracle reference values for the named workloads into
 tests/golden/<workload>_dense.json.  Calls only oracle.dense (dense FP64
-Cholesky; for n > 20000 the blocked in-place factorization, which gives l,
-log|Sigma| and Sigma^-1 z but not the score).  The n = 65536 workload needs
-about 35 GB of host memory and tens of minutes on 8 cores.
+Cholesky; for n > 20000 the blocked in-place route of one n x n buffer:
+factor, triangular inverse and Sigma^-1 in place, then the score terms).  The
+n = 65536 workload needs about 36 GB of host memory and most of an hour on 8
+cores.
 
   python tests/golden/make_dense_golden.py c3_matern32_n65536
   python tests/golden/make_dense_golden.py c2_rq_n16384
   python tests/golden/make_dense_golden.py c3_matern32_n65536 model
 
 With "model", z is a draw from the model itself, z = L w with the dense
-Cholesky factor L of Sigma and w = workloads.gaussian(n, w_seed); z is written
-next to the reference as <workload>_model_z.npy (the log-likelihood is then
-exact for that z: z^T Sigma^-1 z = w^T w).
+Cholesky factor L of Sigma and w = workloads.gaussian(n, w_seed); z and
+Sigma^-1 z are written next to the reference as <workload>_model_z.npy and
+<workload>_model_alpha.npy (the log-likelihood is then exact for that z:
+z^T Sigma^-1 z = w^T w), with the score terms q, t and g.
 
 Observations z are N(0, I) draws (workloads.gaussian(n, w_seed)); the
 log-likelihood and its score are defined for any z.
@@ -44,10 +46,8 @@ def main():
     if n <= 20000:
         o = dense.loglik_and_grad(P, z, spec["theta"], spec["kernel"], spec["alpha"], block=2048, want_terms=True)
     else:
-        # the score needs Sigma^-1 (a second n x n buffer): beyond this host's
-        # memory at n = 65536, so only l, log|Sigma| and Sigma^-1 z are written
-        ell, logdet, a = dense.loglik_large(P, z, spec["theta"], spec["kernel"], spec["alpha"])
-        o = {"ell": ell, "logdet": logdet, "alpha": a}
+        o = dense.score_large(P, spec["theta"], spec["kernel"], spec["alpha"], bs=8192, z=z,
+                              log=lambda m: print(m, flush=True))
     secs = time.time() - t0
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(n, size=min(n, 64), replace=False))
@@ -70,19 +70,27 @@ def main():
 
 
 def model(name, spec):
+    """z = L w (a draw from the model, Sigma = L L^T by the blocked dense
+    Cholesky) and, for that z, the exact l, log|Sigma|, Sigma^-1 z = L^-T w and
+    the score terms q, t, g from Sigma^-1 = L^-T L^-1 formed in place."""
     n = spec["n"]
     P = W.workload_points(name, n)
     w = W.gaussian(n, spec["w_seed"])
     t0 = time.time()
-    z, ell, logdet, a = dense.sample_loglik_large(P, w, spec["theta"], spec["kernel"], spec["alpha"])
+    o = dense.score_large(P, spec["theta"], spec["kernel"], spec["alpha"], bs=8192, w=w,
+                          log=lambda m: print(m, flush=True))
     secs = time.time() - t0
+    z, a = o["z"], o["alpha"]
     rng = np.random.default_rng(7)
     sample = np.sort(rng.choice(n, size=min(n, 64), replace=False))
     np.save(os.path.join(HERE, "%s_model_z.npy" % name), z)
+    np.save(os.path.join(HERE, "%s_model_alpha.npy" % name), a)
     out = {
         "workload": name, "n": n, "kernel": spec["kernel"], "theta": list(spec["theta"]),
         "z": "%s_model_z.npy: z = L w, Sigma = L L^T (dense), w = workloads.gaussian(n, %d)" % (name, spec["w_seed"]),
-        "ell": ell, "logdet": logdet, "ztSinvz": float(w @ w),
+        "alpha": "%s_model_alpha.npy: Sigma^-1 z = L^-T w" % name,
+        "ell": o["ell"], "logdet": o["logdet"], "ztSinvz": float(w @ w),
+        "q": list(map(float, o["q"])), "t": list(map(float, o["t"])), "g": list(map(float, o["g"])),
         "alpha_index": sample.tolist(), "alpha_value": [float(a[i]) for i in sample],
         "oracle_seconds": secs,
         "generator": "tests/golden/make_dense_golden.py %s model (oracle.dense only)" % name,
