@@ -138,11 +138,13 @@ rsf_status rsf_apply_sqrt(rsf_factor f, const double* d_w, double* d_z, int64_t 
 rsf_status rsf_loglik(rsf_factor f, const double* d_z, double* out, double* d_alpha_or_null,
                       void* stream);
 
-/* The first rsf_loglik call on a handle runs eagerly and then records the
- * same work (the solve sweep and the dot products) as a HIP graph on that
- * stream; later calls on the same stream replay it (one graph launch instead
- * of the sweep's launches).  *state: 0 = not recorded yet, 1 = recorded,
- * -1 = recording failed or disabled (RSFGP_NO_GRAPH set): calls stay eager. */
+/* The first rsf_loglik call on a handle runs eagerly (and tunes the sweep's
+ * level steps); the second records the same work (the solve sweep and the
+ * dot products) as a HIP graph and replays it on the caller's stream, and
+ * later calls on that stream replay it too (one graph launch instead of the
+ * sweep's launches).  A handle used for one call records nothing.
+ * *state: 0 = not recorded yet, 1 = recorded, -1 = recording failed or
+ * disabled (RSFGP_NO_GRAPH set): calls stay eager. */
 rsf_status rsf_graph_state(rsf_factor f, int* state);
 
 typedef struct {

@@ -443,6 +443,11 @@ static void loglik_all(rsf_factor f, const double* d_z, double* out, double* d_a
   const long long n = t.n;
   const int ni = t.ninst;
   const double log2pi = 1.8378770664093454835606594728112;
+  // the graph is recorded on a handle's second call (the first one runs
+  // eagerly and tunes every level step of this shape), so a handle used once
+  // never pays for a recording it would not replay
+  if (f->lgraph_state == 0 && f->loglik_calls >= 1) capture_loglik(f, s);
+  ++f->loglik_calls;
   if (f->lgraph && f->lgraph->stream == s) {
     LoglikGraph& g = *f->lgraph;
     RSF_HIP(hipMemcpyAsync(g.zin, d_z, n * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -471,8 +476,6 @@ static void loglik_all(rsf_factor f, const double* d_z, double* out, double* d_a
   if (d_alpha) from_panel(f, A, 1, 1, d_alpha, n, s);
   for (int i = 0; i < ni; ++i)
     out[i] = -0.5 * zt[i] - 0.5 * f->F.logdet[i] - 0.5 * (double)(t.ioff[i + 1] - t.ioff[i]) * log2pi;
-  // later calls on this stream replay a recorded graph of the same work
-  if (f->lgraph_state == 0) capture_loglik(f, s);
 }
 
 rsf_status rsf_graph_state(rsf_factor f, int* state) {

@@ -432,28 +432,44 @@ __global__ __launch_bounds__(256) void cpqr_big_update_tall_kernel(const CpqrJob
   reflect_columns(J.A, J.ld, m, s, j0, j1, J.v, J.scal[0], J.norms);
 }
 
-// T = R_11^-1 R_12 for the multi-workgroup path: one workgroup per eight
-// columns of R_12, held in registers (thread t owns rows t, t + 256, ...),
-// solved right-looking from the last row up.  Column i of R_11 is contiguous,
-// so each step reads it coalesced; it is fetched one step ahead.
+// T = R_11^-1 R_12 for the multi-workgroup path, by row blocks of at most
+// TRSM_ROWS rows solved from the last block up: each diagonal block by
+// trsm_upper_kernel, then the rows above it updated by one batched GEMM.
+// trsm_upper_kernel solves R X = B in place for an upper triangular kb x kb
+// block R (kb <= 256 KQ): one workgroup per eight columns of B, held in
+// registers (thread t owns rows t, t + 256, ...), solved right-looking from
+// the last row up.  Column i of R is contiguous, so each step reads it
+// coalesced; it is fetched one step ahead.
 constexpr int TRSM_C = 8;
+constexpr int TRSM_ROWS = 2048;
+static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+struct TrsmJob {
+  const double* R;  // kb x kb upper triangular, column-major, leading dimension ldr
+  long long ldr;
+  int kb;
+  double* B;  // kb x nc, column-major, leading dimension ldb; overwritten by R^-1 B
+  long long ldb;
+  int nc;
+};
 
 template <int KQ>
-__global__ __launch_bounds__(256) void cpqr_trsm_kernel(const CpqrJob* __restrict__ jobs) {
+__global__ __launch_bounds__(256) void trsm_upper_kernel(const TrsmJob* __restrict__ jobs) {
   __shared__ double xs[2][TRSM_C];
-  const CpqrJob J = jobs[blockIdx.x];
-  const int k = *J.kout, a = J.a, tid = threadIdx.x;
-  const int c0 = k + (int)blockIdx.y * TRSM_C;
-  if (k == 0 || c0 >= a) return;
-  const int nc = std::min(TRSM_C, a - c0);
-  const long long ld = J.ld;
-  double* A = J.A;
+  const TrsmJob J = jobs[blockIdx.x];
+  const int k = J.kb, tid = threadIdx.x;
+  const int c0 = (int)blockIdx.y * TRSM_C;
+  if (k == 0 || c0 >= J.nc) return;
+  const int nc = std::min(TRSM_C, J.nc - c0);
+  const long long ld = J.ldr;
+  const double* A = J.R;
+  double* Bc = J.B + (long long)c0 * J.ldb;
   double b[KQ][TRSM_C], rc[KQ];
 #pragma unroll
   for (int q = 0; q < KQ; ++q) {
     const int r = q * 256 + tid;
 #pragma unroll
-    for (int c = 0; c < TRSM_C; ++c) b[q][c] = (r < k && c < nc) ? A[(long long)(c0 + c) * ld + r] : 0.0;
+    for (int c = 0; c < TRSM_C; ++c) b[q][c] = (r < k && c < nc) ? Bc[(long long)c * J.ldb + r] : 0.0;
     rc[q] = (r < k) ? A[(long long)(k - 1) * ld + r] : 0.0;
   }
   int buf = 0;
@@ -496,15 +512,56 @@ __global__ __launch_bounds__(256) void cpqr_trsm_kernel(const CpqrJob* __restric
     const int r = q * 256 + tid;
 #pragma unroll
     for (int c = 0; c < TRSM_C; ++c)
-      if (r < k && c < nc) A[(long long)(c0 + c) * ld + r] = b[q][c];
+      if (r < k && c < nc) Bc[(long long)c * J.ldb + r] = b[q][c];
   }
 }
 
-__global__ __launch_bounds__(256) void cpqr_backsub_kernel(const CpqrJob* __restrict__ jobs) {
-  const CpqrJob J = jobs[blockIdx.x];
-  const int k = *J.kout;
-  const int j0 = k + blockIdx.y * 256 + threadIdx.x;
-  backsub_columns(J.A, J.ld, k, j0, J.a, 256 * gridDim.y);
+// T = R_11^-1 R_12 in place for the boxes of a level whose ranks k[i] are
+// known on the host: A_i is the box's compression matrix after the pivoted QR
+// (leading dimension ld[i], a[i] columns).  Row blocks of rows_per_block rows
+// (TRSM_ROWS, or less when a test asks for it) from the last one up.
+static void blocked_back_substitution(const std::vector<double*>& A, const std::vector<long long>& ld,
+                                      const std::vector<int>& a, const std::vector<int>& k, int rows_per_block,
+                                      Scratch& scr, hipStream_t s) {
+  const int nb = (int)A.size();
+  int rounds = 0;
+  for (int i = 0; i < nb; ++i)
+    if (k[i] > 0 && a[i] > k[i]) rounds = std::max(rounds, (k[i] + rows_per_block - 1) / rows_per_block);
+  for (int step = 0; step < rounds; ++step) {
+    std::vector<TrsmJob> jobs;
+    std::vector<GemmDesc> upd;
+    int kbmax = 0, ncmax = 0;
+    for (int i = 0; i < nb; ++i) {
+      const int nr = a[i] - k[i];
+      if (k[i] == 0 || nr == 0) continue;
+      const int nblk = (k[i] + rows_per_block - 1) / rows_per_block;
+      if (step >= nblk) continue;
+      const int bi = nblk - 1 - step;
+      const int r0 = bi * rows_per_block, r1 = std::min(k[i], r0 + rows_per_block);
+      double* R12 = A[i] + (long long)k[i] * ld[i];
+      jobs.push_back(TrsmJob{A[i] + r0 + (long long)r0 * ld[i], ld[i], r1 - r0, R12 + r0, ld[i], nr});
+      kbmax = std::max(kbmax, r1 - r0);
+      ncmax = std::max(ncmax, nr);
+      // the rows above: R12[0, r0) -= R11[0, r0; r0, r1) X[r0, r1)
+      if (r0 > 0)
+        upd.push_back(gemm_desc(r0, nr, r1 - r0, -1.0, colmaj(A[i] + (long long)r0 * ld[i], ld[i]),
+                                colmaj(R12 + r0, ld[i]), 1.0, colmaj(R12, ld[i])));
+    }
+    if (jobs.empty()) continue;
+    TrsmJob* dj = scr.make<TrsmJob>(jobs.size());
+    upload(dj, jobs, s);
+    const dim3 g((unsigned)jobs.size(), (unsigned)std::max(1, ceil_div(ncmax, TRSM_C)));
+    if (kbmax <= 256)
+      hipLaunchKernelGGL(trsm_upper_kernel<1>, g, dim3(256), 0, s, dj);
+    else if (kbmax <= 512)
+      hipLaunchKernelGGL(trsm_upper_kernel<2>, g, dim3(256), 0, s, dj);
+    else if (kbmax <= 1024)
+      hipLaunchKernelGGL(trsm_upper_kernel<4>, g, dim3(256), 0, s, dj);
+    else
+      hipLaunchKernelGGL(trsm_upper_kernel<8>, g, dim3(256), 0, s, dj);
+    RSF_HIP(hipGetLastError());
+    gemm_batched(upd, scr, s);
+  }
 }
 
 // ------------------------------------------------------------------ elimination
@@ -683,8 +740,6 @@ __global__ void triu_zero_kernel(double* A, int N) {
 }
 
 // ------------------------------------------------------------------ host driver
-static inline int ceil_div(long long a, long long b) { return (int)((a + b - 1) / b); }
-
 void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
   TraceTag tag(mult ? "factor_rho" : "factor");
   const Tree& t = h->tree;
@@ -727,6 +782,13 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
   int* fail = keep.make<int>(1);
   RSF_HIP(hipMemsetAsync(fail, 0, sizeof(int), s));
   const bool stats = std::getenv("RSFGP_FACTOR_STATS") != nullptr;
+  // Test-only overrides that send small problems down the paths large ones
+  // take: the row-block size of the back-substitution T = R_11^-1 R_12 and
+  // the height above which a pivoting step reads its reflector from global
+  // memory instead of LDS.
+  int trsm_rows = TRSM_ROWS, big_maxm = BIG_MAXM;
+  if (const char* e = std::getenv("RSFGP_TEST_TRSM_ROWS")) trsm_rows = std::max(1, std::min(TRSM_ROWS, atoi(e)));
+  if (const char* e = std::getenv("RSFGP_TEST_BIG_MAXM")) big_maxm = std::max(1, std::min(BIG_MAXM, atoi(e)));
 
   for (int d = D; d >= 1; --d) {
     Scratch scr(s);
@@ -864,6 +926,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
     }
     int* piv = scr.make<int>(std::max<long long>(aoff[nb], 1));
     int* kout = scr.make<int>(nb);
+    bool id_big = false;
     {
       int maxa = 0;
       long long maxm = 0;
@@ -875,6 +938,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
       // one workgroup per box only for the smallest boxes; larger ones (or
       // few boxes) spread every pivoting step over many workgroups
       const bool big = (maxa > CPQR_BOX_MAXA || maxm > CPQR_MAXM || nb < 128);
+      id_big = big;
       double* norms = big ? scr.make<double>(std::max<long long>(aoff[nb], 1)) : nullptr;
       double* vb = big ? scr.make<double>(std::max<long long>(noff[nb] + (long long)nb * nprox, 1)) : nullptr;
       double* scal = big ? scr.make<double>(2 * nb) : nullptr;
@@ -921,7 +985,7 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
           hipLaunchKernelGGL(cpqr_big_pivot_kernel, dim3(nb), dim3(256), 0, s, dj, st, h->eps, nprox, ndone);
           RSF_HIP(hipGetLastError());
           if (st == steps) break;
-          if (maxm <= BIG_MAXM)
+          if (maxm <= big_maxm)
             hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, ucols), dim3(256), (size_t)maxm * sizeof(double), s,
                                dj, st, nprox, cw);
           else
@@ -934,32 +998,23 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
             if (nd >= nb) break;
           }
         }
-        // ranks are on the device: size the solve by the largest possible one
-        int kmax = 0;
-        for (int i = 0; i < nb; ++i) kmax = std::max<int>(kmax, (int)std::min<long long>((long long)nh[i] + nprox, L.a[i]));
-        const int tchunks = std::max(1, ceil_div(maxa, TRSM_C));
-        if (kmax <= 256)
-          hipLaunchKernelGGL(cpqr_trsm_kernel<1>, dim3(nb, tchunks), dim3(256), 0, s, dj);
-        else if (kmax <= 512)
-          hipLaunchKernelGGL(cpqr_trsm_kernel<2>, dim3(nb, tchunks), dim3(256), 0, s, dj);
-        else if (kmax <= 1024)
-          hipLaunchKernelGGL(cpqr_trsm_kernel<4>, dim3(nb, tchunks), dim3(256), 0, s, dj);
-        else if (kmax <= 2048)
-          hipLaunchKernelGGL(cpqr_trsm_kernel<8>, dim3(nb, tchunks), dim3(256), 0, s, dj);
-        else
-          hipLaunchKernelGGL(cpqr_backsub_kernel, dim3(nb, std::max(1, std::min(16, ceil_div(maxa, 256)))),
-                             dim3(256), 0, s, dj);
-        RSF_HIP(hipGetLastError());
       }
     }
-    if (stats) RSF_HIP(hipEventRecord(ev_id[1], s));
     std::vector<int> kh(nb);
     RSF_HIP(hipMemcpyAsync(kh.data(), kout, nb * sizeof(int), hipMemcpyDeviceToHost, s));
     int fh = 0;
     RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
     RSF_HIP(hipStreamSynchronize(s));
     RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "redundant block not positive definite at depth " + std::to_string(d + 1));
+    if (id_big) {
+      // T = R_11^-1 R_12 with the ranks now on the host
+      std::vector<double*> Ab(nb);
+      for (int i = 0; i < nb; ++i) Ab[i] = Kaux + kaoff[i];
+      blocked_back_substitution(Ab, mub, L.a, kh, trsm_rows, scr, s);
+    }
     if (stats) {
+      RSF_HIP(hipEventRecord(ev_id[1], s));
+      RSF_HIP(hipEventSynchronize(ev_id[1]));
       float ms = 0.f;
       RSF_HIP(hipEventElapsedTime(&ms, ev_id[0], ev_id[1]));
       RSF_HIP(hipEventDestroy(ev_id[0]));

@@ -182,6 +182,7 @@ struct Ring {
     hipEvent_t ev;
   };
   std::deque<Use> inflight;
+  std::vector<hipEvent_t> spare;  // events of retired stretches, reused
 } g_ring;
 constexpr size_t RING_BYTES = size_t(512) << 20;
 }  // namespace
@@ -221,7 +222,7 @@ void upload_bytes(void* dst, const void* src, size_t nbytes, hipStream_t s) {
     // wrap around: every stretch of the lap that ends here must have been sent
     for (const auto& u : g_ring.inflight) {
       RSF_HIP(hipEventSynchronize(u.ev));
-      (void)hipEventDestroy(u.ev);
+      g_ring.spare.push_back(u.ev);
     }
     g_ring.inflight.clear();
     a = 0;
@@ -229,13 +230,18 @@ void upload_bytes(void* dst, const void* src, size_t nbytes, hipStream_t s) {
   std::memcpy(g_ring.buf + a, src, nbytes);
   RSF_HIP(hipMemcpyAsync(dst, g_ring.buf + a, nbytes, hipMemcpyHostToDevice, s));
   hipEvent_t ev;
-  RSF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  if (!g_ring.spare.empty()) {
+    ev = g_ring.spare.back();
+    g_ring.spare.pop_back();
+  } else {
+    RSF_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  }
   RSF_HIP(hipEventRecord(ev, s));
   g_ring.inflight.push_back(Ring::Use{a, a + n, ev});
   g_ring.head = a + n;
   // retire finished stretches from the front
   while (!g_ring.inflight.empty() && hipEventQuery(g_ring.inflight.front().ev) == hipSuccess) {
-    (void)hipEventDestroy(g_ring.inflight.front().ev);
+    g_ring.spare.push_back(g_ring.inflight.front().ev);
     g_ring.inflight.pop_front();
   }
 }

@@ -822,6 +822,19 @@ struct Peeler {
     std::vector<int> qd(n), rinst(n);
     for (int i = 0; i < ni; ++i)
       for (long long d = t.ioff[i]; d < t.ioff[i + 1]; ++d) rinst[d] = i;
+    // Test-only: RSFGP_TEST_PEEL_COLS = "c1,c2,..." starts level l at c_l
+    // probe columns per quadrant block (every instance), so that a parity test
+    // can run the probe schedule of a reference run; growth still applies.
+    std::vector<int> forced;
+    if (const char* e = std::getenv("RSFGP_TEST_PEEL_COLS")) {
+      for (const char* q = e; *q;) {
+        char* end = nullptr;
+        const long v = strtol(q, &end, 10);
+        if (end == q) break;
+        forced.push_back((int)std::max(1L, std::min(v, 1L << 20)));
+        q = *end == ',' ? end + 1 : end;
+      }
+    }
     Scratch keep(s);
     int* drinst = keep.make<int>(n);
     upload(drinst, rinst, s);
@@ -863,7 +876,10 @@ struct Peeler {
       std::vector<int> has(ni, 0), cc(ni, 0), tot(ni, 0);
       for (auto& pr : pairs) has[t.inst[pr.first]] = 1;
       for (int i = 0; i < ni; ++i)
-        if (has[i]) cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i], peeled[i]);
+        if (has[i]) {
+          cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i], peeled[i]);
+          if (lev <= (int)forced.size()) cc[i] = forced[lev - 1];
+        }
       int C = 0;  // layout of the probe and sample stores (columns per quadrant block)
       const int nsb = nop * nblk;  // sample blocks of every operator
       std::vector<int> rk(nsb), maxr(ni, 0);

@@ -128,6 +128,7 @@ struct rsf_factor_s {
   std::unique_ptr<rsf::FactorData> Frho2;  // d/dtheta_2 (anisotropic kernels only)
   std::unique_ptr<rsf::LoglikGraph> lgraph;
   int lgraph_state = 0;  // 0: not yet, 1: captured, -1: capture failed (eager from then on)
+  int loglik_calls = 0;  // single-vector log-likelihood calls so far (the graph is recorded on the second)
 };
 
 namespace rsf {

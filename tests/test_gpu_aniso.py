@@ -22,6 +22,14 @@ def _t(x):
     return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
 
 
+def _entrywise(got, ref, rtol, what):
+    """Every entry within rtol of the reference's largest entry (a few wrong
+    rows cannot hide under the norm of the whole block)."""
+    err = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(ref)))
+    print("  %s: max entry error %.2e of max |ref| (bar %.0e)" % (what, err, rtol), flush=True)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=rtol * float(np.max(np.abs(ref))))
+
+
 @pytest.mark.parametrize("kernel,pts,theta,eps,leaf", [
     (K.MATERN32_ANISO, ("grid", 48), (10.0, 7.0, 1e-4), 1e-9, 64),
     (K.RQ_ANISO, ("uniform", 3001), (0.12, 0.05, 1e-3), 1e-7, 50),
@@ -42,10 +50,10 @@ def test_aniso_factor_matches_oracle(kernel, pts, theta, eps, leaf):
     B = W.gaussian((n, 2), 5)
     X = F.solve(_t(B)).cpu().numpy()
     Xo = O.from_tree(O.solve(O.to_tree(B)))
-    assert np.linalg.norm(X - Xo) <= 1e-9 * np.linalg.norm(Xo)
+    _entrywise(X, Xo, 1e-9, "F^-1 B")
     Y = F.apply(_t(B)).cpu().numpy()
     Yo = O.from_tree(O.apply(O.to_tree(B)))
-    assert np.linalg.norm(Y - Yo) <= 1e-12 * np.linalg.norm(Yo)
+    _entrywise(Y, Yo, 1e-12, "F B")
     z = B[:, 0]
     ello = -0.5 * float(z @ Xo[:, 0]) - 0.5 * O.logdet - 0.5 * n * math.log(2 * math.pi)
     assert F.loglik(_t(z)) == pytest.approx(ello, rel=1e-9)
@@ -58,7 +66,7 @@ def test_aniso_factor_matches_oracle(kernel, pts, theta, eps, leaf):
     (K.MATERN32_ANISO, ("grid", 32), (10.0, 7.0, 1e-4), 1e-9, 64, 1),
     (K.RQ_ANISO, ("uniform", 2500), (0.12, 0.05, 1e-3), 1e-7, 256, 4),
 ])
-def test_aniso_grad_matches_oracle_and_dense(kernel, pts, theta, eps, n_prox, rings):
+def test_aniso_grad_matches_oracle_and_dense(kernel, pts, theta, eps, n_prox, rings, monkeypatch):
     print("aniso grad kernel=%d %s" % (kernel, pts), flush=True)
     P = W.grid_points(pts[1]) if pts[0] == "grid" else W.uniform_points(pts[1], 42)
     n = P.shape[0]
@@ -68,14 +76,20 @@ def test_aniso_grad_matches_oracle_and_dense(kernel, pts, theta, eps, n_prox, ri
     g, info = F.grad(_t(z), eps_peel, 33)
     o = rsf.loglik_grad(P, z, theta, kernel, eps, 64, eps_peel=eps_peel, seed=33, n_prox=n_prox,
                         prox_rings=rings)
-    same_cols = True
+    same = all(info.peel_cols[lev] == c for lev, c in o["peel_cols"].items())
+    print("  own probe schedule %s the oracle's" % ("equals" if same else "differs from"), flush=True)
     for lev, c in o["peel_cols"].items():
         assert abs(info.peel_rank[lev] - o["peel_ranks"][lev]) <= 2
-        same_cols = same_cols and info.peel_cols[lev] == c
     np.testing.assert_allclose(list(info.q), o["q"], rtol=1e-9)
-    np.testing.assert_allclose(list(info.t), o["t"], rtol=1e-8 if same_cols else 10 * eps_peel)
+    # rounding-level parity on the oracle's probe schedule (no tolerance fallback)
+    monkeypatch.setenv("RSFGP_TEST_PEEL_COLS", ",".join(str(o["peel_cols"][lev]) for lev in sorted(o["peel_cols"])))
+    gs, infs = F.grad(_t(z), eps_peel, 33)
+    monkeypatch.delenv("RSFGP_TEST_PEEL_COLS")
+    for lev, c in o["peel_cols"].items():
+        assert infs.peel_cols[lev] == c
+    np.testing.assert_allclose(list(infs.t), o["t"], rtol=1e-8)
     oscale = np.abs(o["q"]) + 0.5 * np.abs(o["t"])
-    assert np.all(np.abs(np.array(g) - o["g"]) <= (1e-8 if same_cols else 10 * eps_peel) * oscale)
+    assert np.all(np.abs(np.array(gs) - o["g"]) <= 1e-8 * oscale)
     d = dense.loglik_and_grad(P, z, theta, kernel, want_terms=True)
     np.testing.assert_allclose(list(info.t), d["t"], rtol=20 * eps_peel)
     scale = np.abs(d["q"]) + 0.5 * np.abs(d["t"])

@@ -17,6 +17,14 @@ def _t(x):
     return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
 
 
+def _entrywise(got, ref, rtol, what):
+    """Every entry within rtol of the reference's largest entry (a few wrong
+    rows cannot hide under the norm of the whole block)."""
+    err = float(np.max(np.abs(got - ref))) / float(np.max(np.abs(ref)))
+    print("  %s: max entry error %.2e of max |ref| (bar %.0e)" % (what, err, rtol), flush=True)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=rtol * float(np.max(np.abs(ref))))
+
+
 def test_conditional_mean_and_sample_match_oracle():
     n1, n2 = 300, 4000
     print("conditional n1=%d n2=%d" % (n1, n2), flush=True)
@@ -30,11 +38,11 @@ def test_conditional_mean_and_sample_match_oracle():
     z = W.gaussian((n2, 3), 42)
     mu = R.cond_mean(F, F22, _t(z)).cpu().numpy()
     mu_o = rsf.conditional_mean(O, O22, z)
-    assert np.linalg.norm(mu - mu_o) <= 1e-9 * np.linalg.norm(mu_o)
+    _entrywise(mu, mu_o, 1e-9, "conditional mean")
     xi = W.gaussian((n1 + n2, 2), 43)
     dv = R.cond_sample(F, F22, _t(xi)).cpu().numpy()
     dv_o = rsf.conditional_deviation(O, O22, xi)
-    assert np.linalg.norm(dv - dv_o) <= 1e-6 * np.linalg.norm(dv_o)
+    _entrywise(dv, dv_o, 1e-6, "conditional deviation")
     # single vectors give the columns of the block calls
     m1 = R.cond_mean(F, F22, _t(z[:, 1])).cpu().numpy()
     assert np.allclose(m1, mu[:, 1], rtol=0, atol=1e-12 * np.abs(mu).max())
@@ -52,11 +60,11 @@ def test_conditional_covariance_against_dense():
     z = W.gaussian(n2, 33)
     mu = R.cond_mean(F, F22, _t(z)).cpu().numpy()
     mu_d = S12 @ np.linalg.solve(S22, z)
-    assert np.linalg.norm(mu - mu_d) <= 1e-6 * np.linalg.norm(mu_d)
+    _entrywise(mu, mu_d, 1e-6, "conditional mean vs dense")
     Sq = R.cond_sample(F, F22, _t(np.eye(n1 + n2))).cpu().numpy()
     C = Sq @ Sq.T
     C_d = S11 - S12 @ np.linalg.solve(S22, S12.T)
-    assert np.linalg.norm(C - C_d) <= 1e-6 * np.linalg.norm(C_d)
+    _entrywise(C, C_d, 1e-6, "conditional covariance vs dense")
 
 
 def test_conditional_errors():

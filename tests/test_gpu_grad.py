@@ -24,12 +24,17 @@ def _t(x):
     return torch.tensor(np.asarray(x), dtype=torch.float64, device="cuda")
 
 
+def _schedule(o):
+    """The oracle run's probe columns per level as the test-only override."""
+    return ",".join(str(o["peel_cols"][lev]) for lev in sorted(o["peel_cols"]))
+
+
 @pytest.mark.parametrize("n,eps,n_prox,rings,kernel,theta", [
     (1024, 1e-9, 64, 1, K.MATERN32, (0.1, 1.0, 1e-4)),
     (2500, 1e-7, 256, 4, K.MATERN52, (0.06, 1.2, 1e-3)),
     (4096, 1e-6, 256, 4, K.MATERN32, (0.05, 1.0, 1e-4)),
 ])
-def test_grad_matches_oracle_and_dense(n, eps, n_prox, rings, kernel, theta):
+def test_grad_matches_oracle_and_dense(n, eps, n_prox, rings, kernel, theta, monkeypatch):
     print("grad case n=%d eps=%g" % (n, eps), flush=True)
     P = W.uniform_points(n, 11)
     z = dense.sample(P, W.gaussian(n, 12), theta, kernel)
@@ -39,23 +44,43 @@ def test_grad_matches_oracle_and_dense(n, eps, n_prox, rings, kernel, theta):
     o = rsf.loglik_grad(P, z, theta, kernel, eps, 64, eps_peel=eps_peel, seed=33, n_prox=n_prox,
                         prox_rings=rings)
     # the rank of a sample block is a threshold decision on a decaying
-    # spectrum taken by different (equivalent) factorizations on each side:
-    # a +-1 difference at the threshold is rounding, not a bug
-    same_cols = True
+    # spectrum taken by different (equivalent) factorizations on each side
+    # (pivoted Cholesky of the Gram matrix here, pivoted QR in the oracle): a
+    # difference of 1 or 2 at the threshold is rounding, and it can move the
+    # next level's probe count
+    same = all(info.peel_cols[lev] == c for lev, c in o["peel_cols"].items())
+    print("  own probe schedule %s, oracle's %s (%s)" % ([info.peel_cols[lev] for lev in sorted(o["peel_cols"])],
+          [o["peel_cols"][lev] for lev in sorted(o["peel_cols"])], "same" if same else "different"), flush=True)
     for lev, c in o["peel_cols"].items():
         assert abs(info.peel_rank[lev] - o["peel_ranks"][lev]) <= 2
-        same_cols = same_cols and info.peel_cols[lev] == c
     np.testing.assert_allclose(list(info.q), o["q"], rtol=1e-9)
-    np.testing.assert_allclose(list(info.t), o["t"], rtol=1e-8 if same_cols else 10 * eps_peel)
+    # parity at rounding level: the same probes, run with the oracle's probe
+    # schedule (no tolerance fallback)
+    monkeypatch.setenv("RSFGP_TEST_PEEL_COLS", _schedule(o))
+    gs, infs = F.grad(_t(z), eps_peel, 33)
+    monkeypatch.delenv("RSFGP_TEST_PEEL_COLS")
+    for lev, c in o["peel_cols"].items():
+        assert infs.peel_cols[lev] == c
+    terr = np.abs(np.array(list(infs.t)) - o["t"]) / np.abs(o["t"])
+    print("  traces vs oracle on its schedule: %s" % ["%.1e" % v for v in terr], flush=True)
+    np.testing.assert_allclose(list(infs.t), o["t"], rtol=1e-8)
+    np.testing.assert_allclose(list(infs.q), o["q"], rtol=1e-9)
     # g = q - t/2 cancels to O(sqrt n) at the generating theta: compare on the
     # scale of its halves
     oscale = np.abs(o["q"]) + 0.5 * np.abs(o["t"])
-    assert np.all(np.abs(np.array(g) - o["g"]) <= (1e-8 if same_cols else 10 * eps_peel) * oscale)
+    assert np.all(np.abs(np.array(gs) - o["g"]) <= 1e-8 * oscale)
     d = dense.loglik_and_grad(P, z, theta, kernel, want_terms=True)
     np.testing.assert_allclose(list(info.t), d["t"], rtol=20 * eps_peel)
     # the score itself: relative to the scale of its two halves (they cancel)
     scale = np.abs(d["q"]) + 0.5 * np.abs(d["t"])
-    assert np.all(np.abs(np.array(g) - d["g"]) <= 1e3 * eps * scale + 50 * eps_peel * scale)
+    gerr = np.abs(np.array(g) - d["g"]) / scale
+    print("  vs dense: traces %s, score over |q| + |t|/2 %s, |g - g_dense| / |g_dense| %.1e"
+          % (["%.1e" % v for v in np.abs(np.array(list(info.t)) - d["t"]) / np.abs(d["t"])],
+             ["%.1e" % v for v in gerr], np.linalg.norm(np.array(g) - d["g"]) / np.linalg.norm(d["g"])), flush=True)
+    # q_nugget = a^T a / 2 carries the forward error of a = F^-1 z, about
+    # kappa(Sigma) times the factorization's backward error: 100 eps_fact
+    # beside the traces' 10 eps_peel
+    assert np.all(gerr <= 100 * eps + 10 * eps_peel)
     # repeatable: same seed, same answer
     g2, _ = F.grad(_t(z), eps_peel, 33)
     assert g2 == g

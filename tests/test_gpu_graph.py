@@ -1,5 +1,6 @@
-"""The recorded log-likelihood graph: after the first (eager) call, rsf_loglik
-replays a HIP graph of the solve sweep and the dot products.  Every replay,
+"""The recorded log-likelihood graph: the first call on a handle runs eagerly,
+the second records a HIP graph of the solve sweep and the dot products and
+replays it, and later calls replay it.  Every replay,
 with eager work and synchronisations in between, must give what the eager
 path gives: alpha bitwise equal to rsf_solve (the same kernels), l equal to
 the value assembled from it."""
@@ -34,9 +35,13 @@ def test_loglik_graph_replays_match_eager(n, leaf):
         ell = -0.5 * float(z @ a) - 0.5 * F.logdet - 0.5 * n * math.log(2 * math.pi)
         refs.append((ell, a.clone()))
     assert F.graph_state == 0
-    ell0 = F.loglik(zs[0])  # eager, then recorded
+    ell0 = F.loglik(zs[0])  # eager: a handle used once records nothing
     assert ell0 == pytest.approx(refs[0][0], rel=1e-12)
+    assert F.graph_state == 0
+    ell1, a1 = F.loglik(zs[1], want_alpha=True)  # recorded, then replayed
     assert F.graph_state == 1
+    assert torch.equal(a1, refs[1][1])
+    assert ell1 == pytest.approx(refs[1][0], rel=1e-12)
     other = _t(W.gaussian(n, 999))
     for rep in range(3):
         for z, (ell_ref, a_ref) in zip(zs, refs):
