@@ -121,6 +121,27 @@ rsf_status rsf_logdet(rsf_factor f, double* out);
 rsf_status rsf_solve(rsf_factor f, const double* d_b, double* d_x, int64_t nrhs, int64_t ld,
                      void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): d_x =
+ * F^-1 d_b exactly as rsf_solve (same arguments, layout and errors), but every
+ * device work buffer (the tree-order panel, the sweep's level temporaries, the
+ * launch descriptors) is carved from one fixed 64 MiB device array per GPU
+ * that the library holds until the process ends.  The call makes no hipMalloc,
+ * hipFree or other allocating call: launch descriptors travel through the
+ * pinned staging ring that creating the handle already set up, and a level
+ * shape that no earlier call has autotuned takes the fused per-box kernel
+ * without timing trials.
+ * Limit: 8 (n nrhs + r nrhs) bytes + 8 MiB of descriptors must fit in 64 MiB
+ * (r: the largest number of redundant DOFs of one level, or the root size);
+ * larger calls return RSF_E_INVALID before any device work, and a call whose
+ * descriptors overrun the array returns RSF_E_INVALID with d_x untouched.
+ * Every call on one GPU uses the same array, which keeps the previous call's
+ * contents (nothing in it has to start at zero): calls on one stream are
+ * ordered by the stream, but calls that overlap on one GPU (other streams, or
+ * other host threads) race on it. */
+rsf_status rsf_solve_noalloc(rsf_factor f, const double* d_b, double* d_x, int64_t nrhs, int64_t ld,
+                             void* stream);
+
 /* d_y = F d_x (Section 2.4).  Same layout rules as rsf_solve. */
 rsf_status rsf_apply(rsf_factor f, const double* d_x, double* d_y, int64_t nrhs, int64_t ld,
                      void* stream);

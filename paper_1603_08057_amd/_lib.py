@@ -60,6 +60,7 @@ def load():
         "rsf_factor_destroy": ([vp], None),
         "rsf_logdet": ([vp, dp], C.c_int),
         "rsf_solve": ([vp, vp, vp, i64, i64, vp], C.c_int),
+        "rsf_solve_noalloc": ([vp, vp, vp, i64, i64, vp], C.c_int),
         "rsf_apply": ([vp, vp, vp, i64, i64, vp], C.c_int),
         "rsf_apply_sqrt": ([vp, vp, vp, i64, i64, vp], C.c_int),
         "rsf_loglik": ([vp, vp, dp, vp, vp], C.c_int),
@@ -240,6 +241,11 @@ class Factor:
 
     def solve(self, b):
         return self._block(load().rsf_solve, b)
+
+    def solve_noalloc(self, b):
+        """F^-1 b with the library's fixed work space (no device allocation
+        inside the library; the result tensor is allocated here)."""
+        return self._block(load().rsf_solve_noalloc, b)
 
     def apply(self, x):
         return self._block(load().rsf_apply, x)

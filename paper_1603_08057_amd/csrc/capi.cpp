@@ -274,6 +274,68 @@ rsf_status rsf_solve(rsf_factor f, const double* d_b, double* d_x, int64_t nrhs,
   });
 }
 
+}  // extern "C"
+
+// ---- the solve without device allocation
+// Work space of rsf_solve_noalloc: one fixed array per GPU, held until the
+// process ends.  Host code never uses the array's name as an address: the
+// device address of each GPU's copy is looked up once per device with
+// hipGetSymbolAddress (with that device current) and kept in g_noalloc_ptr.
+namespace {
+constexpr size_t NOALLOC_BYTES = size_t(64) << 20;
+// bytes kept free for launch descriptors and tile tables beside the panel and
+// the level temporaries
+constexpr size_t NOALLOC_DESC_RESERVE = size_t(8) << 20;
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+std::mutex g_noalloc_mu;
+std::map<int, char*> g_noalloc_ptr;  // device ordinal -> its copy of scratch
+
+char* noalloc_scratch() {
+  int dev = 0;
+  RSF_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  auto it = g_noalloc_ptr.find(dev);
+  if (it != g_noalloc_ptr.end()) return it->second;
+  void* ptr = nullptr;
+  RSF_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  RSF_CHECK(ptr != nullptr, RSF_E_HIP, "no device address for the no-allocation work space");
+  g_noalloc_ptr[dev] = static_cast<char*>(ptr);
+  return static_cast<char*>(ptr);
+}
+
+size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+}  // namespace
+
+extern "C" {
+
+rsf_status rsf_solve_noalloc(rsf_factor f, const double* d_b, double* d_x, int64_t nrhs, int64_t ld, void* stream) {
+  return guarded([&] {
+    check_block(f, d_b, d_x, nrhs, ld);
+    if (nrhs == 0) return;
+    const int nc = (int)nrhs;
+    const long long n = f->tree.n;
+    long long maxr = 1;
+    for (size_t d = 1; d < f->F.levels.size(); ++d) maxr = std::max(maxr, f->F.levels[d].total_r);
+    maxr = std::max<long long>(maxr, f->F.nroot);
+    // the tree-order panel and the sweep's level temporaries, plus room for
+    // the launch descriptors
+    const size_t need = align256((size_t)n * nc * sizeof(double)) + align256((size_t)maxr * nc * sizeof(double)) +
+                        NOALLOC_DESC_RESERVE;
+    RSF_CHECK(need <= NOALLOC_BYTES, RSF_E_INVALID,
+              "rsf_solve_noalloc: n = " + std::to_string(n) + " with nrhs = " + std::to_string(nc) + " needs " +
+                  std::to_string(need) + " bytes of work space, more than its fixed " +
+                  std::to_string(NOALLOC_BYTES) + " (use rsf_solve, or fewer columns per call)");
+    char* ptr = noalloc_scratch();
+    hipStream_t s = as_stream(stream);
+    NoAllocScope na;
+    Scratch scr(s, ptr, NOALLOC_BYTES);
+    double* P = scr.make<double>((size_t)n * nc);
+    to_panel(f, d_b, ld, P, nc, nc, s);
+    sweep_solve(f, f->F, P, nc, nc, scr, s);
+    from_panel(f, P, nc, nc, d_x, ld, s);
+  });
+}
+
 rsf_status rsf_apply(rsf_factor f, const double* d_x, double* d_y, int64_t nrhs, int64_t ld, void* stream) {
   return guarded([&] {
     check_block(f, d_x, d_y, nrhs, ld);

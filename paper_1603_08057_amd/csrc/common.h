@@ -59,8 +59,20 @@ struct Arena {
   ~Arena() { release(); }
 };
 
+// While alive on a thread, that thread may not take device memory from the
+// pool (pool_alloc throws RSF_E_INVALID) and the level-step autotuner runs no
+// timing trials: the calls behind the no-allocation entry points.
+struct NoAllocScope {
+  bool was;
+  NoAllocScope();
+  ~NoAllocScope();
+};
+bool no_alloc_active();
+
 // Scratch allocations for one call, returned to the stream-ordered pool when
-// the object goes out of scope.
+// the object goes out of scope.  A Scratch made over a fixed device buffer
+// instead carves every request from that buffer (256-byte aligned, in order)
+// and never touches the pool; a request beyond its end throws RSF_E_INVALID.
 struct Scratch {
   std::vector<void*> blocks;
   std::vector<size_t> sizes;
@@ -72,7 +84,10 @@ struct Scratch {
   std::vector<void*> slabs;
   char* slab = nullptr;
   size_t slab_left = 0;
+  char* fixed = nullptr;  // fixed-buffer mode: base, size and bytes handed out
+  size_t fixed_cap = 0, fixed_used = 0;
   explicit Scratch(hipStream_t s) : stream(s) {}
+  Scratch(hipStream_t s, void* buf, size_t nbytes) : stream(s), fixed(static_cast<char*>(buf)), fixed_cap(nbytes) {}
   void* alloc(size_t nbytes);
   template <class T>
   T* make(size_t count) {

@@ -87,7 +87,13 @@ size_t pool_release_empty() {
 static thread_local bool g_pool_no_sync = false;
 void pool_sync_free(bool on) { g_pool_no_sync = on; }
 
+static thread_local bool g_no_alloc = false;
+NoAllocScope::NoAllocScope() : was(g_no_alloc) { g_no_alloc = true; }
+NoAllocScope::~NoAllocScope() { g_no_alloc = was; }
+bool no_alloc_active() { return g_no_alloc; }
+
 void* pool_alloc(size_t nbytes, hipStream_t s) {
+  RSF_CHECK(!g_no_alloc, RSF_E_INVALID, "device allocation requested inside a no-allocation call");
   const size_t n = (std::max<size_t>(nbytes, 1) + POOL_ALIGN - 1) / POOL_ALIGN * POOL_ALIGN;
   std::lock_guard<std::mutex> lk(g_pool.mu);
   int ri = -1;
@@ -202,7 +208,7 @@ void upload_bytes(void* dst, const void* src, size_t nbytes, hipStream_t s) {
     return;
   }
   std::lock_guard<std::mutex> lk(g_ring.mu);
-  if (!g_ring.buf) {
+  if (!g_ring.buf && !g_no_alloc) {
     void* p = nullptr;
     if (hipHostMalloc(&p, RING_BYTES, hipHostMallocDefault) == hipSuccess) {
       g_ring.buf = static_cast<char*>(p);
@@ -284,6 +290,15 @@ void Arena::release() {
 
 void* Scratch::alloc(size_t nbytes) {
   if (nbytes == 0) nbytes = 8;
+  if (fixed) {
+    const size_t n = (nbytes + 255) & ~size_t(255);
+    RSF_CHECK(n <= fixed_cap - fixed_used, RSF_E_INVALID,
+              "work space of a no-allocation call exhausted (" + std::to_string(fixed_used + n) + " > " +
+                  std::to_string(fixed_cap) + " bytes)");
+    void* p = fixed + fixed_used;
+    fixed_used += n;
+    return p;
+  }
   if (nbytes <= SMALL_MAX) {
     const size_t n = (nbytes + 255) & ~size_t(255);
     if (n > slab_left) {
@@ -304,6 +319,7 @@ void* Scratch::alloc(size_t nbytes) {
 }
 
 void Scratch::release(const void* p) {
+  if (fixed) return;
   for (size_t i = 0; i < blocks.size(); ++i)
     if (blocks[i] == p) {
       pool_free(blocks[i], sizes[i], stream);

@@ -499,7 +499,11 @@ static void level_step(const rsf_factor_s* h, const LevelFactor& L, const std::v
     auto it = g_tune.find(key);
     if (it != g_tune.end()) path = it->second;
   }
-  if (path < 0) {
+  if (path < 0 && no_alloc_active()) {
+    // a no-allocation call runs no timing trials (they need panel copies):
+    // an untuned shape takes the fused kernel and is not recorded
+    path = 1;
+  } else if (path < 0) {
     TracePause tp;
     const long long sz = h->tree.n * ld;
     Scratch ts(s);
