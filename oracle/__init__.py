@@ -18,6 +18,9 @@ rsf       the recursive skeletonization factorization written out step by step
           the derivative operator.
 peel      matrix peeling for weakly admissible matrices (Section 3.2) and the
           trace extraction at the leaves.
+peel_strong  matrix peeling in the strongly admissible format (the form the
+          remark after Theorem 2 points to): interaction blocks of separated
+          boxes, coloured probes, near field never compressed.
 philox    the Philox4x32-10 counter-based generator (Salmon et al., SC'11) and
           the Box-Muller transform, used to draw the Gaussian peeling probes.
 """

@@ -520,7 +520,7 @@ def hutchinson_traces(F, Fr, nprobe, seed):
 
 
 def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0,
-                n_prox=256, prox_rings=4, want_grad=True, hutch_probes=0):
+                n_prox=256, prox_rings=4, want_grad=True, hutch_probes=0, strong=False):
     """The paper's Algorithm 1 with the readings used throughout this package.
 
     l_hat = -1/2 z^T F^-1 z - 1/2 log|F| - (n/2) log 2 pi; for theta =
@@ -539,6 +539,8 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
     Sigma_theta1, Sigma_theta2; the three operators B B^T, B F_1 B^T and
     B F_2 B^T are peeled jointly from one set of probes (as the two are for
     rho above); q_nug = 1/2 a^T a, t_nug = Tr F^-1.
+    strong: the traces peeled in the strongly admissible format
+    (oracle.peel_strong) instead of the weakly admissible one (oracle.peel).
     Returns a dict (user order for vectors)."""
     from . import peel
     eps_peel = eps if eps_peel is None else eps_peel
@@ -556,6 +558,9 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
         return _loglik_grad_aniso(out, F, P, a, theta, kernel, eps, leaf, eps_peel, seed, alpha,
                                   n_prox, prox_rings, hutch_probes)
     rho, s2, nug = (float(v) for v in theta)
+    Peeler = peel.Peeler
+    if strong:
+        from .peel_strong import StrongPeeler as Peeler
     Fr = Factor(P, theta, kernel, eps, leaf, alpha=alpha, n_prox=n_prox, prox_rings=prox_rings,
                 mode="mult", tree=F.tree)
     aa = float(a @ a)
@@ -571,7 +576,7 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
         H = F.half_down(Wm)
         return [F.half_up(H), F.half_up(Fr.apply(H))]
 
-    pl = peel.Peeler(F.tree, applies, 2, eps_peel, seed)
+    pl = Peeler(F.tree, applies, 2, eps_peel, seed)
     t_inv, t_rho = pl.run()
     t = np.array([t_rho, (n - nug * t_inv) / s2, t_inv])
     out.update(q=q, t=t, g=q - 0.5 * t, factor_rho=Fr, peel_cols=pl.cols, peel_ranks=pl.ranks)
