@@ -189,6 +189,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--hutch", type=int, default=0,
                     help="score traces by Hutchinson's estimator with this many probes instead of peeling")
+    ap.add_argument("--peeling", choices=["weak", "strong"], default="weak",
+                    help="the format the score's traces are peeled in (weakly or strongly admissible)")
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64",
                     help="arithmetic of the timed factorizations (mixed: FP32 kernel entries and Schur products; "
                          "the data z is drawn in FP64 either way)")
@@ -244,7 +246,7 @@ def main():
 
     def step(precision=args.precision):
         # Sigma_rho is factored beside Sigma (second stream), as the score needs it
-        F = R.Factor(P, theta, with_score=True, precision=precision, **kw)
+        F = R.Factor(P, theta, with_score=True, precision=precision, peeling=args.peeling, **kw)
         ell = F.loglik(z)
         if args.hutch > 0:
             g, info = F.grad_hutch(z, args.hutch, spec.get("peel_seed", 0))
@@ -301,7 +303,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"precision": args.precision,
+        "config": {"precision": args.precision, "peeling": args.peeling,
                    "workload": name if not (args.n or args.eps or args.eps_peel) else
                    "%s_recipe_n%d_eps%g_peel%g" % (name, n, spec["eps"], eps_peel), "n": n,
                    "kernel": KERNEL_NAMES.get(spec["kernel"], spec["kernel"]), "theta": list(theta),

@@ -85,12 +85,26 @@ typedef struct {
                            kernels), on a second stream while Sigma is factored;
                            rsf_grad then reuses them.  0 (default): rsf_grad
                            factors them itself */
+  int peeling;          /* how the score's traces are peeled (Section 3):
+                           RSF_PEEL_WEAK (default): the weakly admissible format of
+                           Section 3.2, every sibling block compressed (four probe
+                           blocks per level, one per quadrant);
+                           RSF_PEEL_STRONG: the strongly admissible format the remark
+                           after Theorem 2 points to: only blocks of boxes that do not
+                           touch (while their parents do) are compressed, their probes
+                           coloured so that each sampled box sees one source box per
+                           colour (36 colours on a complete quadtree, counter stream 2 of
+                           the same Gaussian probes), the near field of touching leaves
+                           never compressed and the leaves' diagonal blocks extracted with
+                           colours that separate touching leaves */
 } rsf_opts;
 
 enum { RSF_FP64 = 0, RSF_MIXED = 1 };
+enum { RSF_PEEL_WEAK = 0, RSF_PEEL_STRONG = 1 };
 
 /* Fills *opts with the defaults above (n_prox 256, 4 rings, 1.8, 1.75, 2.45,
- * alpha 1, no cap, FP64, with_score 0).  Errors: RSF_E_INVALID if opts is NULL. */
+ * alpha 1, no cap, FP64, with_score 0, weak peeling).  Errors: RSF_E_INVALID if
+ * opts is NULL. */
 rsf_status rsf_opts_default(rsf_opts* opts);
 
 /* Builds F ~= Sigma(theta) (Section 2, eq. rskelf; Algorithm 1, step "factor").

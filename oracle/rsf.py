@@ -556,7 +556,7 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
         return out
     if K.is_aniso(kernel):
         return _loglik_grad_aniso(out, F, P, a, theta, kernel, eps, leaf, eps_peel, seed, alpha,
-                                  n_prox, prox_rings, hutch_probes)
+                                  n_prox, prox_rings, hutch_probes, strong)
     rho, s2, nug = (float(v) for v in theta)
     Peeler = peel.Peeler
     if strong:
@@ -584,8 +584,11 @@ def loglik_grad(P, z, theta, kernel, eps, leaf, eps_peel=None, seed=0, alpha=1.0
 
 
 def _loglik_grad_aniso(out, F, P, a, theta, kernel, eps, leaf, eps_peel, seed, alpha,
-                       n_prox, prox_rings, hutch_probes):
+                       n_prox, prox_rings, hutch_probes, strong=False):
     from . import peel
+    Peeler = peel.Peeler
+    if strong:
+        from .peel_strong import StrongPeeler as Peeler
     Fs = [Factor(P, theta, kernel, eps, leaf, alpha=alpha, n_prox=n_prox, prox_rings=prox_rings,
                  mode="mult", tree=F.tree, deriv=w) for w in (0, 1)]
     aa = float(a @ a)
@@ -598,7 +601,7 @@ def _loglik_grad_aniso(out, F, P, a, theta, kernel, eps, leaf, eps_peel, seed, a
             H = F.half_down(Wm)
             return [F.half_up(H), F.half_up(Fs[0].apply(H)), F.half_up(Fs[1].apply(H))]
 
-        pl = peel.Peeler(F.tree, applies, 3, eps_peel, seed)
+        pl = Peeler(F.tree, applies, 3, eps_peel, seed)
         t_inv, t1, t2 = pl.run()
         out.update(peel_cols=pl.cols, peel_ranks=pl.ranks)
     t = np.array([t1, t2, t_inv])

@@ -17,12 +17,14 @@ class RsfError(RuntimeError):
 
 
 PRECISIONS = {"fp64": 0, "mixed": 1}
+PEELINGS = {"weak": 0, "strong": 1}
 
 
 class Options(C.Structure):
     _fields_ = [("n_prox", C.c_int), ("prox_rings", C.c_int), ("r_near", C.c_double),
                 ("prox_r_in", C.c_double), ("prox_r_out", C.c_double), ("rq_alpha", C.c_double),
-                ("mem_cap_bytes", C.c_size_t), ("precision", C.c_int), ("with_score", C.c_int)]
+                ("mem_cap_bytes", C.c_size_t), ("precision", C.c_int), ("with_score", C.c_int),
+                ("peeling", C.c_int)]
 
 
 class GradInfo(C.Structure):
@@ -188,7 +190,7 @@ class Factor:
 
     def __init__(self, points, theta, kernel=MATERN32, eps=1e-6, leaf=64, n_prox=256, prox_rings=4,
                  r_near=1.8, prox_r_in=1.75, prox_r_out=2.45, rq_alpha=1.0, mem_cap_bytes=0,
-                 precision="fp64", with_score=False):
+                 precision="fp64", with_score=False, peeling="weak"):
         lib = load()
         torch = _torch()
         if not torch.cuda.is_available():
@@ -207,6 +209,9 @@ class Factor:
             raise ValueError("precision must be one of %s" % sorted(PRECISIONS))
         opts.precision = PRECISIONS[precision]
         opts.with_score = 1 if with_score else 0
+        if peeling not in PEELINGS:
+            raise ValueError("peeling must be one of %s" % sorted(PEELINGS))
+        opts.peeling = PEELINGS[peeling]
         self.precision = precision
         th = (C.c_double * 3)(*[float(v) for v in theta])
         h = C.c_void_p()
@@ -326,7 +331,7 @@ class BatchedFactor:
 
     def __init__(self, points_list, thetas, kernel=MATERN32, eps=1e-6, leaf=64, n_prox=256, prox_rings=4,
                  r_near=1.8, prox_r_in=1.75, prox_r_out=2.45, rq_alpha=1.0, mem_cap_bytes=0,
-                 precision="fp64", with_score=False):
+                 precision="fp64", with_score=False, peeling="weak"):
         lib = load()
         torch = _torch()
         if not torch.cuda.is_available():
@@ -348,6 +353,9 @@ class BatchedFactor:
         opts.mem_cap_bytes = mem_cap_bytes
         opts.precision = PRECISIONS[precision]
         opts.with_score = 1 if with_score else 0
+        if peeling not in PEELINGS:
+            raise ValueError("peeling must be one of %s" % sorted(PEELINGS))
+        opts.peeling = PEELINGS[peeling]
         ptrs = (C.c_void_p * self.nb)(*[p.data_ptr() for p in pts])
         ns = (C.c_int64 * self.nb)(*self.ns)
         tharr = (C.c_double * len(th))(*th)

@@ -74,6 +74,7 @@ rsf_status rsf_opts_default(rsf_opts* o) {
   o->mem_cap_bytes = 0;
   o->precision = RSF_FP64;
   o->with_score = 0;
+  o->peeling = RSF_PEEL_WEAK;
   return RSF_OK;
 }
 
@@ -110,6 +111,7 @@ static rsf_factor_s* create_handle(const std::vector<std::vector<double>>& xy, c
             "bad proxy geometry or rq_alpha");
   RSF_CHECK(o.precision == RSF_FP64 || o.precision == RSF_MIXED, RSF_E_INVALID, "unknown precision");
   RSF_CHECK(o.with_score == 0 || o.with_score == 1, RSF_E_INVALID, "with_score must be 0 or 1");
+  RSF_CHECK(o.peeling == RSF_PEEL_WEAK || o.peeling == RSF_PEEL_STRONG, RSF_E_INVALID, "unknown peeling form");
   RSF_CHECK(!(o.precision == RSF_MIXED && kernel >= RSF_MATERN32_ANISO), RSF_E_INVALID,
             "mixed precision takes the isotropic kernels only");
   std::unique_ptr<rsf_factor_s> h(new rsf_factor_s());
@@ -121,6 +123,7 @@ static rsf_factor_s* create_handle(const std::vector<std::vector<double>>& xy, c
   h->opt.rq_alpha = o.rq_alpha;
   h->opt.mem_cap = o.mem_cap_bytes;
   h->opt.mixed = o.precision == RSF_MIXED;
+  h->opt.strong_peeling = o.peeling == RSF_PEEL_STRONG;
   h->arena.cap = o.mem_cap_bytes;
   h->kernel = kernel;
   h->eps = eps;

@@ -11,6 +11,7 @@
 // B F_rho B^T (trace Tr F^-1 F_rho) are peeled together from the same probes
 // and share the product B^T W, so one probe block costs one and a half solve
 // sweeps and one multiply sweep.
+#include <algorithm>
 #include <chrono>
 #include <exception>
 #include <thread>
@@ -54,14 +55,16 @@ __device__ __forceinline__ double probe_normal(uint32_t d, uint32_t j, uint32_t 
   return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
 }
 
-// Probe columns of one chunk for the DOFs of the depth-`level` boxes (qd[d] =
-// quadrant of d's box, -1 elsewhere): for t < act[i] (i = instance of d),
-//   W[d, 4 t + q(d)] = Om[d, j0[i] + t] = N(d, j0[i] + t, level),
-// W is zero elsewhere.  W interleaves the quadrant blocks (column 4 t + q), so
-// every instance's active columns form a prefix of the panel.
+// Probe columns of one chunk for the DOFs of the nodes peeled at `level`
+// (qd[d] = the column block of d's node: its quadrant in the weak form, its
+// colour in the strong form; -1 for rows without one): for t < act[i] (i =
+// instance of d),
+//   W[d, ncol t + q(d)] = Om[d, j0[i] + t] = N(d, j0[i] + t, level, stream),
+// W is zero elsewhere.  W interleaves the ncol column blocks (column
+// ncol t + q), so every instance's active columns form a prefix of the panel.
 __global__ void probe_kernel(const int* __restrict__ qd, const int* __restrict__ rinst, const int* __restrict__ act,
-                             const int* __restrict__ j0, long long n, int ncw, int level, uint64_t seed,
-                             double* __restrict__ W, double* __restrict__ Om, long long ldo) {
+                             const int* __restrict__ j0, long long n, int ncw, int ncol, int level, uint32_t stream,
+                             uint64_t seed, double* __restrict__ W, double* __restrict__ Om, long long ldo) {
   const long long tot = n * ncw;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
     const long long d = e / ncw;
@@ -70,25 +73,26 @@ __global__ void probe_kernel(const int* __restrict__ qd, const int* __restrict__
     if (q < 0) continue;
     const int i = rinst[d];
     if (t >= act[i]) continue;
-    const double v = probe_normal((uint32_t)d, (uint32_t)(j0[i] + t), (uint32_t)level, 0u, seed);
-    W[d * 4LL * ncw + 4LL * t + q] = v;
+    const double v = probe_normal((uint32_t)d, (uint32_t)(j0[i] + t), (uint32_t)level, stream, seed);
+    W[d * (long long)ncol * ncw + (long long)ncol * t + q] = v;
     Om[d * ldo + j0[i] + t] = v;
   }
 }
 
-// Y[d, q * C + j0[i] + t] = B[d, 4 t + q] for the rows of the depth-`level`
-// boxes and t < act[i] (i = instance of d).
+// Y[d, q * C + j0[i] + t] = B[d, ncol t + q] for the rows of the nodes peeled
+// at this level and t < act[i] (i = instance of d).
 __global__ void store_samples_kernel(const int* __restrict__ qd, const int* __restrict__ rinst,
                                      const int* __restrict__ act, const int* __restrict__ j0, long long n, int ncw,
-                                     int C, const double* __restrict__ B, double* __restrict__ Y) {
-  const long long tot = n * 4LL * ncw;
+                                     int ncol, int C, const double* __restrict__ B, double* __restrict__ Y) {
+  const long long w = (long long)ncol * ncw;
+  const long long tot = n * w;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
-    const long long d = e / (4LL * ncw);
-    const int c = (int)(e - d * 4LL * ncw);
+    const long long d = e / w;
+    const int c = (int)(e - d * w);
     if (qd[d] < 0) continue;
-    const int i = rinst[d], t = c >> 2, q = c & 3;
+    const int i = rinst[d], t = c / ncol, q = c - t * ncol;
     if (t >= act[i]) continue;
-    Y[d * 4LL * C + (long long)q * C + j0[i] + t] = B[e];
+    Y[d * (long long)ncol * C + (long long)q * C + j0[i] + t] = B[e];
   }
 }
 
@@ -104,22 +108,26 @@ __global__ void regrid_kernel(long long n, int nq, int cols, const double* __res
   }
 }
 
-__global__ void eye_blocks_kernel(const int* __restrict__ lbeg, const int* __restrict__ lcnt, int nleaf,
-                                  double* __restrict__ E, int nL) {
+// E[begin_b + t, col0_b + t] = 1 for every leaf b and t < count_b (E: ld
+// columns; col0 null: every leaf's block starts at column 0)
+__global__ void eye_blocks_kernel(const int* __restrict__ lbeg, const int* __restrict__ lcnt,
+                                  const int* __restrict__ lcol0, int nleaf, double* __restrict__ E, int ld) {
   const int b = blockIdx.x;
   if (b >= nleaf) return;
-  for (int t = threadIdx.x; t < lcnt[b]; t += blockDim.x) E[(long long)(lbeg[b] + t) * nL + t] = 1.0;
+  const int c0 = lcol0 ? lcol0[b] : 0;
+  for (int t = threadIdx.x; t < lcnt[b]; t += blockDim.x) E[(long long)(lbeg[b] + t) * ld + c0 + t] = 1.0;
 }
 
-// sum over leaves b and t < count_b of H[begin_b + t, t], in a fixed order
+// sum over leaves b and t < count_b of H[begin_b + t, col0_b + t], in a fixed order
 __global__ __launch_bounds__(256) void leaf_trace_kernel(const int* __restrict__ lbeg, const int* __restrict__ lcnt,
-                                                          int nleaf, const double* __restrict__ H, int nL,
-                                                          double* out) {
+                                                          const int* __restrict__ lcol0, int nleaf,
+                                                          const double* __restrict__ H, int ld, double* out) {
   __shared__ double part[256];
   double acc = 0.0;
   for (int b = threadIdx.x; b < nleaf; b += 256) {
     double s = 0.0;
-    for (int t = 0; t < lcnt[b]; ++t) s += H[(long long)(lbeg[b] + t) * nL + t];
+    const int c0 = lcol0 ? lcol0[b] : 0;
+    for (int t = 0; t < lcnt[b]; ++t) s += H[(long long)(lbeg[b] + t) * ld + c0 + t];
     acc += s;
   }
   part[threadIdx.x] = acc;
@@ -391,6 +399,142 @@ struct LevelLR {
   std::vector<int> off_i, off_j, pos_i, pos_j;
 };
 
+// ---- geometry of the strongly admissible format
+// Integer cell coordinates of every box at its own depth (each instance's
+// root at (0, 0); a child at quadrant q of (X, Y) is (2X + [q east],
+// 2Y + [q north])), so that touching squares are decided exactly.
+struct Cells {
+  std::vector<long long> X, Y;
+};
+
+Cells cell_coords(const Tree& t) {
+  Cells c;
+  c.X.assign(t.nbox(), 0);
+  c.Y.assign(t.nbox(), 0);
+  for (int b = 0; b < t.nbox(); ++b) {  // parents precede children in box order
+    const int p = t.parent[b], q = t.quad[b];
+    if (p < 0) continue;
+    c.X[b] = 2 * c.X[p] + ((q == 1 || q == 3) ? 1 : 0);
+    c.Y[b] = 2 * c.Y[p] + ((q == 0 || q == 1) ? 1 : 0);
+  }
+  return c;
+}
+
+// the closed squares of boxes a and b intersect (boxes of one instance)
+bool touch(const Tree& t, const Cells& c, int a, int b) {
+  if (t.inst[a] != t.inst[b]) return false;
+  const int D = std::max(t.depth[a], t.depth[b]);
+  const long long sa = 1LL << (D - t.depth[a]), sb = 1LL << (D - t.depth[b]);
+  return c.X[a] * sa <= (c.X[b] + 1) * sb && c.X[b] * sb <= (c.X[a] + 1) * sa && c.Y[a] * sa <= (c.Y[b] + 1) * sb &&
+         c.Y[b] * sb <= (c.Y[a] + 1) * sa;
+}
+
+// Smallest colour not taken by an already coloured conflicting node, in node order.
+std::vector<int> greedy_colors(const std::vector<int>& nodes, const std::vector<std::vector<int>>& conflicts,
+                               const std::vector<int>& pos) {
+  std::vector<int> col(nodes.size(), -1);
+  std::vector<char> used;
+  for (size_t a = 0; a < nodes.size(); ++a) {
+    used.assign(conflicts[a].size() + 1, 0);
+    for (int b : conflicts[a]) {
+      const int k = col[pos[b]];
+      if (k >= 0 && k < (int)used.size()) used[k] = 1;
+    }
+    int k = 0;
+    while (used[k]) ++k;
+    col[a] = k;
+  }
+  return col;
+}
+
+// The strongly admissible structure of one level: nodes (boxes of depth lev
+// and leaves of smaller depth, in box order), their colours for the probes
+// (nodes whose parent nodes both touch the parent node of some node get
+// different colours) and the admissible pairs (nodes that do not touch while
+// their parent nodes touch).  A depth-lev box's parent node is its parent; a
+// leaf carried down is its own parent node.
+struct StrongLevel {
+  std::vector<int> nodes, color;  // color: per box id (-1: not a node)
+  int ncol = 0;
+  std::vector<std::pair<int, int>> pairs;
+};
+
+StrongLevel strong_level(const Tree& t, const Cells& cells, int lev) {
+  StrongLevel L;
+  const int nbx = t.nbox();
+  std::vector<int> pos(nbx, -1), par;
+  for (int b = 0; b < nbx; ++b)
+    if (t.depth[b] == lev || (t.leaf[b] && t.depth[b] < lev)) {
+      pos[b] = (int)L.nodes.size();
+      L.nodes.push_back(b);
+      par.push_back(t.depth[b] == lev ? t.parent[b] : b);
+    }
+  L.color.assign(nbx, -1);
+  const int nn = (int)L.nodes.size();
+  if (nn == 0) return L;
+  // distinct parent nodes, the nodes under each, and which parents touch
+  std::vector<int> plist(par);
+  std::sort(plist.begin(), plist.end());
+  plist.erase(std::unique(plist.begin(), plist.end()), plist.end());
+  std::vector<int> ppos(nbx, -1);
+  for (size_t a = 0; a < plist.size(); ++a) ppos[plist[a]] = (int)a;
+  std::vector<std::vector<int>> under(plist.size());
+  for (int a = 0; a < nn; ++a) under[ppos[par[a]]].push_back(L.nodes[a]);
+  std::vector<std::vector<int>> near(plist.size());
+  for (size_t a = 0; a < plist.size(); ++a)
+    for (size_t c = 0; c < plist.size(); ++c)
+      if (touch(t, cells, plist[a], plist[c])) near[a].push_back((int)c);
+  // conflicts: the nodes of one window (every node under a parent touching p)
+  std::vector<std::vector<int>> conf(nn);
+  for (size_t a = 0; a < plist.size(); ++a) {
+    std::vector<int> win;
+    for (int c : near[a]) win.insert(win.end(), under[c].begin(), under[c].end());
+    for (int b : win)
+      for (int b2 : win)
+        if (b2 != b) conf[pos[b]].push_back(b2);
+  }
+  const std::vector<int> col = greedy_colors(L.nodes, conf, pos);
+  for (int a = 0; a < nn; ++a) {
+    L.color[L.nodes[a]] = col[a];
+    L.ncol = std::max(L.ncol, col[a] + 1);
+  }
+  // admissible pairs (i before j in node order)
+  for (int a = 0; a < nn; ++a) {
+    const int i = L.nodes[a];
+    for (int c : near[ppos[par[a]]])
+      for (int j : under[c])
+        if (pos[j] > a && !touch(t, cells, i, j)) L.pairs.emplace_back(i, j);
+  }
+  std::sort(L.pairs.begin(), L.pairs.end(), [&](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+    return std::make_pair(pos[x.first], pos[x.second]) < std::make_pair(pos[y.first], pos[y.second]);
+  });
+  return L;
+}
+
+// Colours of the leaves with no two touching leaves alike (the extraction of
+// the diagonal blocks in the strong form); returns the number of colours.
+int leaf_colors(const Tree& t, const Cells& cells, const std::vector<int>& leaves, std::vector<int>& col) {
+  std::vector<int> pos(t.nbox(), -1);
+  for (size_t a = 0; a < leaves.size(); ++a) pos[leaves[a]] = (int)a;
+  std::vector<std::vector<int>> conf(leaves.size());
+  for (size_t a = 0; a < leaves.size(); ++a)
+    for (size_t c = a + 1; c < leaves.size(); ++c)
+      if (touch(t, cells, leaves[a], leaves[c])) {
+        conf[a].push_back(leaves[c]);
+        conf[c].push_back(leaves[a]);
+      }
+  col = greedy_colors(leaves, conf, pos);
+  int nc = 0;
+  for (int k : col) nc = std::max(nc, k + 1);
+  return nc;
+}
+
+// Probe counts of the strong form: 64 at the first level with admissible
+// blocks; then the largest rank found at the level above plus the
+// oversampling (the ranks of separated blocks change little between levels).
+constexpr int FIRST_COLS_STRONG = 64;
+int next_cols_strong(int prev_rank) { return round8(std::max(MIN_COLS, prev_rank + OVERSAMPLE)); }
+
 struct Peeler {
   // per-phase wall times (host clock around the enqueue and its waits), for
   // RSFGP_PEEL_TIMES diagnostics
@@ -404,8 +548,9 @@ struct Peeler {
   std::vector<LevelLR> lr[MAXOP];
   const FactorData* Fd[MAXOP - 1];  // the derivative factorizations
   int nop;
-  Peeler(const rsf_factor_s* hh, const FactorData* const* fd, int nd, hipStream_t ss)
-      : h(hh), t(hh->tree), s(ss), nop(1 + nd) {
+  bool strong = false;  // strongly admissible format (else weakly admissible)
+  Peeler(const rsf_factor_s* hh, const FactorData* const* fd, int nd, hipStream_t ss, bool strong_form = false)
+      : h(hh), t(hh->tree), s(ss), nop(1 + nd), strong(strong_form) {
     RSF_CHECK(nd >= 1 && nd <= MAXOP - 1, RSF_E_INVALID, "peeling takes one or two derivative factorizations");
     for (int k = 0; k < nd; ++k) Fd[k] = fd[k];
   }
@@ -484,19 +629,21 @@ struct Peeler {
 
   int cols_of(const int* cols, int box, int nc) const { return cols ? std::min(nc, cols[t.inst[box]]) : nc; }
 
-  // Probes of one chunk in compact form: row d holds its own quadrant's
-  // columns, Om[d * ldo + j0[instance] + t] = X[d, 4 t + qd[d]] (qd: the
-  // quadrant of d's box at the level being peeled, -1 for rows without one).
+  // Probes of one chunk in compact form: row d holds its own column block's
+  // columns, Om[d * ldo + j0[instance] + t] = X[d, ncol t + qd[d]] (qd: the
+  // column block of d's node at the level being peeled, -1 for rows without
+  // one; ncol blocks).
   struct CompactProbes {
     const double* Om;
     long long ldo;
     const std::vector<int>* j0;
     const std::vector<int>* qd;
+    int ncol;
   };
 
   // out -= sum_{m < upto} G^(m) X  for operator op (same column rule as apply_ops).
-  // With cp, X is a probe chunk and U_b^T X[I_b] is formed per quadrant from
-  // the rows of that quadrant only (the other rows are zero in its columns).
+  // With cp, X is a probe chunk and U_b^T X[I_b] is formed per column block
+  // from the rows of that block only (the other rows are zero in its columns).
   void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr, const int* cols,
                         const CompactProbes* cp = nullptr, hipStream_t st = nullptr) {
     if (!st) st = s;
@@ -519,29 +666,36 @@ struct Peeler {
                                  panel(X + (long long)t.begin[box] * nc, nc), 0.0, panel(P + poff[b], nc)));
         }
       } else {
-        // rows of each box by quadrant (box-relative); a quadrant whose rows
+        // rows of each box by column block (box-relative); a block whose rows
         // form one run is passed as a contiguous block
         const std::vector<int>& qd = *cp->qd;
+        const int ncol = cp->ncol;
+        // column blocks without rows in a box leave their columns of P zero
+        fill_zero(P, poff[nbx], st);
         std::vector<int> rows;
-        std::vector<long long> lo(4 * nbx + 1, 0);
+        std::vector<long long> lo((long long)ncol * nbx + 1, 0);
+        std::vector<std::vector<int>> byq(ncol);
         for (int b = 0; b < nbx; ++b) {
           const int box = L.boxes[b], b0 = t.begin[box], cnt = t.count[box];
-          for (int q = 0; q < 4; ++q) {
-            for (int u = 0; u < cnt; ++u)
-              if (qd[b0 + u] == q) rows.push_back(u);
-            lo[4 * b + q + 1] = (long long)rows.size();
+          for (auto& v : byq) v.clear();
+          for (int u = 0; u < cnt; ++u)
+            if (qd[b0 + u] >= 0) byq[qd[b0 + u]].push_back(u);
+          for (int q = 0; q < ncol; ++q) {
+            rows.insert(rows.end(), byq[q].begin(), byq[q].end());
+            lo[(long long)ncol * b + q + 1] = (long long)rows.size();
           }
         }
         int* drows = scr.make<int>(std::max<size_t>(rows.size(), 1));
         upload(drows, rows, st);
         for (int b = 0; b < nbx; ++b) {
           const int box = L.boxes[b], cnt = t.count[box];
-          const int N = cols_of(cols, box, nc) / 4;
+          const int N = cols_of(cols, box, nc) / ncol;
           const double* Ob = cp->Om + (long long)t.begin[box] * cp->ldo + (*cp->j0)[t.inst[box]];
-          for (int q = 0; q < 4; ++q) {
-            const long long a = lo[4 * b + q], e = lo[4 * b + q + 1];
+          for (int q = 0; q < ncol; ++q) {
+            const long long a = lo[(long long)ncol * b + q], e = lo[(long long)ncol * b + q + 1];
             const int K = (int)(e - a);
-            const Mat C{P + poff[b] + q, nc, 4, nullptr};
+            if (K == 0) continue;
+            const Mat C{P + poff[b] + q, nc, ncol, nullptr};
             if (K > 0 && rows[e - 1] - rows[a] == K - 1) {
               const int r0 = rows[a];
               g1.push_back(gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b] + r0, cnt), panel(Ob + (long long)r0 * cp->ldo, cp->ldo),
@@ -661,8 +815,9 @@ struct Peeler {
   // probes (ld C); pivots of block e at dpiv + poff[e].
   // Every sibling pair of one level and operator, in chunks that bound the
   // work memory.
-  void lowrank_level(LevelLR& L, const std::vector<int>& tot, int C, const double* Yop, const double* Om,
-                     const int* dpiv, const std::vector<long long>& poff, int blk0, hipStream_t st) {
+  void lowrank_level(LevelLR& L, const std::vector<int>& tot, int C, int ncol, const std::vector<int>& qbox,
+                     const double* Yop, const double* Om, const int* dpiv, const std::vector<long long>& poff,
+                     int blk0, hipStream_t st) {
     TraceTag tg("peel_lowrank");
     const int np = (int)L.pairs.size();
     int p0 = 0;
@@ -679,16 +834,16 @@ struct Peeler {
         bytes += est;
         ++p1;
       }
-      lowrank_chunk(L, p0, p1, tot, C, Yop, Om, dpiv, poff, blk0, st);
+      lowrank_chunk(L, p0, p1, tot, C, ncol, qbox, Yop, Om, dpiv, poff, blk0, st);
       p0 = p1;
     }
   }
 
-  void lowrank_chunk(LevelLR& L, int p0, int p1, const std::vector<int>& tot, int C, const double* Yop,
-                     const double* Om, const int* dpiv, const std::vector<long long>& poff, int blk0,
-                     hipStream_t st) {
+  void lowrank_chunk(LevelLR& L, int p0, int p1, const std::vector<int>& tot, int C, int ncol,
+                     const std::vector<int>& qbox, const double* Yop, const double* Om, const int* dpiv,
+                     const std::vector<long long>& poff, int blk0, hipStream_t st) {
     Scratch ms(st);
-    const long long ld = 4LL * C;
+    const long long ld = (long long)ncol * C;
     // every per-pair buffer is carved from one block (one allocation per chunk)
     long long need = 0;
     for (int p = p0; p < p1; ++p) {
@@ -722,7 +877,7 @@ struct Peeler {
         b.e = blk0 + 2 * p + side;
         b.k = k;
         b.cnt = t.count[rb];
-        b.Yb = Yop + (long long)t.begin[rb] * ld + (long long)t.quad[cb] * C;
+        b.Yb = Yop + (long long)t.begin[rb] * ld + (long long)qbox[cb] * C;
         b.Yg = carve((long long)b.cnt * k);
         b.G = carve((long long)k * k);
         b.Li = carve((long long)k * k);
@@ -764,7 +919,7 @@ struct Peeler {
       const Mat OmiT{Om + (long long)t.begin[bi] * C, 1, (long long)C, nullptr};
       const Mat Omi = panel(Om + (long long)t.begin[bi] * C, C);
       const Mat Omj = panel(Om + (long long)t.begin[bj] * C, C);
-      const double* Yij = Yop + (long long)t.begin[bi] * ld + (long long)t.quad[bj] * C;
+      const double* Yij = Yop + (long long)t.begin[bi] * ld + (long long)qbox[bj] * C;
       double* A1 = carve((long long)total * k1);
       double* A2 = carve((long long)k2 * total);
       double* W1 = carve((long long)ci * k1);
@@ -838,10 +993,14 @@ struct Peeler {
     Scratch keep(s);
     int* drinst = keep.make<int>(n);
     upload(drinst, rinst, s);
-    // probe and sample stores, kept across levels (capacity Ccap columns per quadrant block)
+    // probe and sample stores, kept across levels (capacity: Ccap probe columns
+    // per row, Ycap sample columns per row)
     double* Om = nullptr;
     double* Y[MAXOP] = {nullptr, nullptr, nullptr};
     int Ccap = 0;
+    long long Ycap = 0;
+    const Cells cells = strong ? cell_coords(t) : Cells();
+    const uint32_t stream_id = strong ? 2u : 0u;
     for (int lev = 1; lev <= D; ++lev) {
       const auto cl0 = std::chrono::steady_clock::now();
       struct LevelClock {
@@ -850,22 +1009,35 @@ struct Peeler {
         ~LevelClock() { acc += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
       } level_clock{tm[7], cl0};
       Scratch scr(s);
-      const int b0 = t.lev[lev], b1 = t.lev[lev + 1];
+      // the blocks peeled at this level and the column block of every node's
+      // probes: sibling pairs by quadrant (weak form), or the admissible pairs
+      // by colour (strong form)
       std::vector<std::pair<int, int>> pairs;
-      for (int p = t.lev[lev - 1]; p < t.lev[lev]; ++p) {
-        std::vector<int> ks;
-        for (int c : t.child[p])
-          if (c >= 0) ks.push_back(c);
-        for (size_t a = 0; a < ks.size(); ++a)
-          for (size_t b = a + 1; b < ks.size(); ++b) pairs.emplace_back(ks[a], ks[b]);
+      std::vector<int> qbox(t.nbox(), -1);
+      int ncol = 4;
+      if (strong) {
+        StrongLevel sl = strong_level(t, cells, lev);
+        pairs.swap(sl.pairs);
+        qbox.swap(sl.color);
+        ncol = std::max(1, sl.ncol);
+      } else {
+        for (int p = t.lev[lev - 1]; p < t.lev[lev]; ++p) {
+          std::vector<int> ks;
+          for (int c : t.child[p])
+            if (c >= 0) ks.push_back(c);
+          for (size_t a = 0; a < ks.size(); ++a)
+            for (size_t b = a + 1; b < ks.size(); ++b) pairs.emplace_back(ks[a], ks[b]);
+        }
+        for (int b = t.lev[lev]; b < t.lev[lev + 1]; ++b) qbox[b] = t.quad[b];
       }
       if (pairs.empty()) continue;
       std::fill(qd.begin(), qd.end(), -1);
-      for (int b = b0; b < b1; ++b)
-        for (int u = 0; u < t.count[b]; ++u) qd[t.begin[b] + u] = t.quad[b];
+      for (int b = 0; b < t.nbox(); ++b)
+        if (qbox[b] >= 0)
+          for (int u = 0; u < t.count[b]; ++u) qd[t.begin[b] + u] = qbox[b];
       int* dqd = scr.make<int>(n);
       upload(dqd, qd, s);
-      // per ordered sample block: (row box, column quadrant box)
+      // per ordered sample block: (row box, column-block box)
       std::vector<std::pair<int, int>> blocks;
       for (auto& pr : pairs) {
         blocks.emplace_back(pr.first, pr.second);
@@ -877,7 +1049,10 @@ struct Peeler {
       for (auto& pr : pairs) has[t.inst[pr.first]] = 1;
       for (int i = 0; i < ni; ++i)
         if (has[i]) {
-          cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i], peeled[i]);
+          if (strong)
+            cc[i] = prev[i] < 0 ? FIRST_COLS_STRONG : next_cols_strong(prev[i]);
+          else
+            cc[i] = prev[i] < 0 ? first_cols(t.ioff[i + 1] - t.ioff[i]) : next_cols(prev[i], peeled[i]);
           if (lev <= (int)forced.size()) cc[i] = forced[lev - 1];
         }
       int C = 0;  // layout of the probe and sample stores (columns per quadrant block)
@@ -888,19 +1063,20 @@ struct Peeler {
       while (true) {
         const int cnew = *std::max_element(cc.begin(), cc.end());
         auto cg0 = std::chrono::steady_clock::now();
-        if (C == 0 && cnew <= Ccap) {
+        if (C == 0 && cnew <= Ccap && (long long)ncol * cnew <= Ycap) {
           C = cnew;  // a new level reuses the stores of the previous ones
         } else if (cnew > C) {
           // grow the probe and sample stores: a new layout, the samples taken so far copied over
           const int cap = std::max(cnew, Ccap);
+          const long long ycap = std::max<long long>((long long)ncol * cnew, Ycap);
           double* Om2 = keep.make<double>((size_t)n * cap);
           double* Y2[MAXOP] = {nullptr, nullptr, nullptr};
-          for (int op = 0; op < nop; ++op) Y2[op] = keep.make<double>((size_t)n * 4 * cap);
+          for (int op = 0; op < nop; ++op) Y2[op] = keep.make<double>((size_t)n * ycap);
           if (C > 0) {
             hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * C)), dim3(256), 0, s, n, 1, C, Om, C, Om2, cnew);
             for (int op = 0; op < nop; ++op)
-              hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * 4 * C)), dim3(256), 0, s, n, 4, C, Y[op], C, Y2[op],
-                                 cnew);
+              hipLaunchKernelGGL(regrid_kernel, dim3(grid_of(n * ncol * C)), dim3(256), 0, s, n, ncol, C, Y[op], C,
+                                 Y2[op], cnew);
             RSF_HIP(hipGetLastError());
           }
           keep.release(Om);
@@ -910,6 +1086,7 @@ struct Peeler {
           }
           Om = Om2;
           Ccap = cap;
+          Ycap = ycap;
           C = cnew;
         }
         tm[6] += std::chrono::duration<double>(std::chrono::steady_clock::now() - cg0).count();
@@ -918,7 +1095,7 @@ struct Peeler {
         // PEEL_CHUNK_BYTES
         int newmax = 0;
         for (int i = 0; i < ni; ++i) newmax = std::max(newmax, cc[i] - tot[i]);
-        const long long per_col = 2LL * nop * n * 4 * (long long)sizeof(double);
+        const long long per_col = 2LL * nop * n * ncol * (long long)sizeof(double);
         const int cw = std::min(newmax, (int)std::max<long long>(8, PEEL_CHUNK_BYTES / per_col / 8 * 8));
         int* dact = scr.make<int>(ni);
         int* dj0 = scr.make<int>(ni);
@@ -928,28 +1105,28 @@ struct Peeler {
           for (int i = 0; i < ni; ++i) {
             act[i] = std::max(0, std::min(ncw, cc[i] - tot[i] - t0));
             j0[i] = tot[i] + t0;
-            pcols[i] = 4 * act[i];
+            pcols[i] = ncol * act[i];
           }
           upload(dact, act, s);
           upload(dj0, j0, s);
           Scratch rs(s);
-          const long long sz = n * 4LL * ncw;
-          double* Wm = rs.make<double>(n * 4LL * cw);  // full-chunk sizes: reused by every chunk
+          const long long sz = n * (long long)ncol * ncw;
+          double* Wm = rs.make<double>(n * (long long)ncol * cw);  // full-chunk sizes: reused by every chunk
           fill_zero(Wm, sz, s);
-          hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * ncw)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw, lev,
-                             seed, Wm, Om, (long long)C);
+          hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * ncw)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw,
+                             ncol, lev, stream_id, seed, Wm, Om, (long long)C);
           RSF_HIP(hipGetLastError());
           double* Bo[MAXOP] = {nullptr, nullptr, nullptr};
-          for (int op = 0; op < nop; ++op) Bo[op] = rs.make<double>(n * 4LL * cw);
+          for (int op = 0; op < nop; ++op) Bo[op] = rs.make<double>(n * (long long)ncol * cw);
           const int* pc = ni > 1 ? pcols.data() : nullptr;
           auto c0 = std::chrono::steady_clock::now();
-          apply_ops(Wm, 4 * ncw, Bo, rs, pc);
+          apply_ops(Wm, ncol * ncw, Bo, rs, pc);
           auto c1 = std::chrono::steady_clock::now();
-          const CompactProbes cpr{Om, (long long)C, &j0, &qd};
+          const CompactProbes cpr{Om, (long long)C, &j0, &qd, ncol};
           auto sub_store = [&](int op, Scratch& r, hipStream_t st) {
-            subtract_lowrank(op, lev, Wm, 4 * ncw, Bo[op], r, pc, &cpr, st);
+            subtract_lowrank(op, lev, Wm, ncol * ncw, Bo[op], r, pc, &cpr, st);
             hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, st, dqd, drinst, dact, dj0, n,
-                               ncw, C, Bo[op], Y[op]);
+                               ncw, ncol, C, Bo[op], Y[op]);
             RSF_HIP(hipGetLastError());
           };
           // the operators' subtractions and sample stores side by side
@@ -997,8 +1174,9 @@ struct Peeler {
             for (int idx = e0; idx < e1; ++idx) {
               const int op = idx / nblk, e = idx % nblk;
               const int rb = blocks[e].first, cbx = blocks[e].second, c = bc[idx];
-              const double* Yb = Y[op] + (long long)t.begin[rb] * 4 * C + (long long)t.quad[cbx] * C;
-              g.push_back(gemm_desc(c, c, t.count[rb], 1.0, Mat{Yb, 1, 4LL * C, nullptr}, panel(Yb, 4LL * C), 0.0,
+              const long long ldy = (long long)ncol * C;
+              const double* Yb = Y[op] + (long long)t.begin[rb] * ldy + (long long)qbox[cbx] * C;
+              g.push_back(gemm_desc(c, c, t.count[rb], 1.0, Mat{Yb, 1, ldy, nullptr}, panel(Yb, ldy), 0.0,
                                     colmaj(Gram + goff[idx - e0], c)));
             }
             {
@@ -1109,47 +1287,62 @@ struct Peeler {
       }
       // bases and core matrices: operator 1 on the side stream beside operator 0
       auto c0 = std::chrono::steady_clock::now();
-      beside([&](hipStream_t s2) { lowrank_level(lr[1][lev], tot, C, Y[1], Om, dpiv, poff, nblk, s2); },
+      beside([&](hipStream_t s2) { lowrank_level(lr[1][lev], tot, C, ncol, qbox, Y[1], Om, dpiv, poff, nblk, s2); },
              [&] {
                for (int op = 0; op < nop; ++op)
-                 if (op != 1) lowrank_level(lr[op][lev], tot, C, Y[op], Om, dpiv, poff, op * nblk, s);
+                 if (op != 1) lowrank_level(lr[op][lev], tot, C, ncol, qbox, Y[op], Om, dpiv, poff, op * nblk, s);
              });
       tm[3] += std::chrono::duration<double>(std::chrono::steady_clock::now() - c0).count();
     }
-    // extraction at the leaves: traces of every instance over its own leaves
+    // extraction at the leaves: traces of every instance over its own leaves.
+    // Weak form: every leaf's identity block in the same n_L columns (only the
+    // leaves' own diagonal blocks remain after the subtraction).  Strong form:
+    // the near field remains, so touching leaves get different column blocks.
     const auto cx0 = std::chrono::steady_clock::now();
     Scratch scr(s);
-    std::vector<int> lbeg, lcnt, lfirst(ni + 1, 0);
+    std::vector<int> lbeg, lcnt, lbox, lfirst(ni + 1, 0);
     int nL = 1;
     for (int i = 0; i < ni; ++i) {
       for (int b = 0; b < t.nbox(); ++b)
         if (t.leaf[b] && t.inst[b] == i) {
           lbeg.push_back(t.begin[b]);
           lcnt.push_back(t.count[b]);
+          lbox.push_back(b);
           nL = std::max(nL, t.count[b]);
         }
       lfirst[i + 1] = (int)lbeg.size();
     }
     const int nleaf = (int)lbeg.size();
+    int ncl = 1;
+    std::vector<int> lcol0;
+    if (strong) {
+      std::vector<int> lc;
+      ncl = std::max(1, leaf_colors(t, cells, lbox, lc));
+      lcol0.resize(nleaf);
+      for (int a = 0; a < nleaf; ++a) lcol0[a] = lc[a] * nL;
+    }
+    const int ncE = ncl * nL;
     int* dlb = scr.make<int>(nleaf);
     int* dlc = scr.make<int>(nleaf);
+    int* dl0 = strong ? scr.make<int>(nleaf) : nullptr;
     upload(dlb, lbeg, s);
     upload(dlc, lcnt, s);
-    const long long sz = n * nL;
+    if (strong) upload(dl0, lcol0, s);
+    const long long sz = n * ncE;
     double* E = scr.make<double>(sz);
     fill_zero(E, sz, s);
-    hipLaunchKernelGGL(eye_blocks_kernel, dim3(nleaf), dim3(256), 0, s, dlb, dlc, nleaf, E, nL);
+    hipLaunchKernelGGL(eye_blocks_kernel, dim3(nleaf), dim3(256), 0, s, dlb, dlc, dl0, nleaf, E, ncE);
     RSF_HIP(hipGetLastError());
     double* Ho[MAXOP] = {nullptr, nullptr, nullptr};
     for (int op = 0; op < nop; ++op) Ho[op] = scr.make<double>(sz);
-    apply_ops(E, nL, Ho, scr, nullptr);
-    for (int op = 0; op < nop; ++op) subtract_lowrank(op, D + 1, E, nL, Ho[op], scr, nullptr);
+    apply_ops(E, ncE, Ho, scr, nullptr);
+    for (int op = 0; op < nop; ++op) subtract_lowrank(op, D + 1, E, ncE, Ho[op], scr, nullptr);
     double* tr = scr.make<double>(nop * ni);
     for (int i = 0; i < ni; ++i) {
       const int l0 = lfirst[i], nl = lfirst[i + 1] - lfirst[i];
       for (int op = 0; op < nop; ++op)
-        hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb + l0, dlc + l0, nl, Ho[op], nL,
-                           tr + op * ni + i);
+        hipLaunchKernelGGL(leaf_trace_kernel, dim3(1), dim3(256), 0, s, dlb + l0, dlc + l0, dl0 ? dl0 + l0 : nullptr,
+                           nl, Ho[op], ncE, tr + op * ni + i);
     }
     RSF_HIP(hipGetLastError());
     std::vector<double> th(nop * ni);
@@ -1159,7 +1352,7 @@ struct Peeler {
       for (int i = 0; i < ni; ++i) traces[op][i] = th[op * ni + i];
     if (st) {
       st->levels = D;
-      st->leaf_cols = nL;
+      st->leaf_cols = ncE;
     }
     tm[5] = std::chrono::duration<double>(std::chrono::steady_clock::now() - cx0).count();
     if (std::getenv("RSFGP_PEEL_TIMES"))
@@ -1175,7 +1368,7 @@ void peel_traces(const rsf_factor_s* h, double eps_peel, uint64_t seed, double* 
                  PeelStats* st, hipStream_t s, const FactorData* Fd2, double* tr_rho2) {
   const FactorData* fd[2] = {h->Frho.get(), Fd2};
   double* traces[3] = {tr_inv, tr_rho, tr_rho2};
-  Peeler p(h, fd, Fd2 ? 2 : 1, s);
+  Peeler p(h, fd, Fd2 ? 2 : 1, s, h->opt.strong_peeling);
   p.run(eps_peel, seed, traces, st);
 }
 

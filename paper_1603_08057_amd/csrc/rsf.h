@@ -87,6 +87,7 @@ struct Options {
   double r_near = 1.8, r_in = 1.75, r_out = 2.45, rq_alpha = 1.0;
   size_t mem_cap = 0;
   bool mixed = false;  // FP32 kernel entries and Schur-complement products
+  bool strong_peeling = false;  // traces peeled in the strongly admissible format
 };
 
 }  // namespace rsf
