@@ -338,9 +338,10 @@ constexpr int OVERSAMPLE = 10;
 // device memory for the work panels of one chunk of probe columns, for the
 // Gram matrices of one chunk of sample blocks and for the bases and core
 // matrices of one chunk of sibling pairs
-constexpr long long PEEL_CHUNK_BYTES = 48LL << 30;
+constexpr long long PEEL_CHUNK_BYTES = 24LL << 30;
 constexpr long long GRAM_CHUNK_BYTES = 8LL << 30;
 constexpr long long LOWRANK_CHUNK_BYTES = 8LL << 30;
+constexpr long long SUB_CHUNK_BYTES = 4LL << 30;
 constexpr int FIRST_COLS = 64;
 constexpr int MIN_COLS = 24;
 
@@ -644,36 +645,30 @@ struct Peeler {
   // out -= sum_{m < upto} G^(m) X  for operator op (same column rule as apply_ops).
   // With cp, X is a probe chunk and U_b^T X[I_b] is formed per column block
   // from the rows of that block only (the other rows are zero in its columns).
+  // The coarser levels' products U_b^T X and M (U^T X) are kept for a slice of
+  // the columns at a time, sized so that both stay within SUB_CHUNK_BYTES (the
+  // strong form's boxes carry bases for up to 27 partners).
   void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr, const int* cols,
                         const CompactProbes* cp = nullptr, hipStream_t st = nullptr) {
     if (!st) st = s;
     TraceTag tag("peel_subtract");
+    const int unit = cp ? cp->ncol : 1;
     for (int m = 1; m < upto && m < (int)lr[op].size(); ++m) {
       const LevelLR& L = lr[op][m];
       if (!L.any) continue;
       const int nbx = (int)L.boxes.size();
-      std::vector<long long> poff(nbx + 1, 0);
-      for (int b = 0; b < nbx; ++b) poff[b + 1] = poff[b] + (long long)L.K[b] * nc;
-      double* P = scr.make<double>(std::max<long long>(poff[nbx], 1));
-      double* Q = scr.make<double>(std::max<long long>(poff[nbx], 1));
-      // a pair with one empty basis contributes nothing: its Q segment stays zero
-      fill_zero(Q, poff[nbx], st);
-      std::vector<GemmDesc> g1;
-      if (!cp) {
-        for (int b = 0; b < nbx; ++b) {
-          const int box = L.boxes[b];
-          g1.push_back(gemm_desc(L.K[b], cols_of(cols, box, nc), t.count[box], 1.0, colmajT(L.U[b], t.count[box]),
-                                 panel(X + (long long)t.begin[box] * nc, nc), 0.0, panel(P + poff[b], nc)));
-        }
-      } else {
-        // rows of each box by column block (box-relative); a block whose rows
-        // form one run is passed as a contiguous block
+      long long ksum = 0;
+      for (int b = 0; b < nbx; ++b) ksum += L.K[b];
+      if (ksum == 0) continue;
+      int w = (int)std::min<long long>(nc, std::max<long long>(unit, SUB_CHUNK_BYTES / (16 * ksum) / unit * unit));
+      // rows of each box by column block (box-relative), for the compact probes
+      std::vector<int> rows;
+      std::vector<long long> lo;
+      int* drows = nullptr;
+      if (cp) {
         const std::vector<int>& qd = *cp->qd;
         const int ncol = cp->ncol;
-        // column blocks without rows in a box leave their columns of P zero
-        fill_zero(P, poff[nbx], st);
-        std::vector<int> rows;
-        std::vector<long long> lo((long long)ncol * nbx + 1, 0);
+        lo.assign((long long)ncol * nbx + 1, 0);
         std::vector<std::vector<int>> byq(ncol);
         for (int b = 0; b < nbx; ++b) {
           const int box = L.boxes[b], b0 = t.begin[box], cnt = t.count[box];
@@ -685,51 +680,78 @@ struct Peeler {
             lo[(long long)ncol * b + q + 1] = (long long)rows.size();
           }
         }
-        int* drows = scr.make<int>(std::max<size_t>(rows.size(), 1));
+        drows = scr.make<int>(std::max<size_t>(rows.size(), 1));
         upload(drows, rows, st);
-        for (int b = 0; b < nbx; ++b) {
-          const int box = L.boxes[b], cnt = t.count[box];
-          const int N = cols_of(cols, box, nc) / ncol;
-          const double* Ob = cp->Om + (long long)t.begin[box] * cp->ldo + (*cp->j0)[t.inst[box]];
-          for (int q = 0; q < ncol; ++q) {
-            const long long a = lo[(long long)ncol * b + q], e = lo[(long long)ncol * b + q + 1];
-            const int K = (int)(e - a);
-            if (K == 0) continue;
-            const Mat C{P + poff[b] + q, nc, ncol, nullptr};
-            if (K > 0 && rows[e - 1] - rows[a] == K - 1) {
-              const int r0 = rows[a];
-              g1.push_back(gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b] + r0, cnt), panel(Ob + (long long)r0 * cp->ldo, cp->ldo),
-                                     0.0, C));
-            } else {
-              GemmDesc d = gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b], cnt), Mat{Ob, cp->ldo, 1, drows + a}, 0.0, C);
-              d.kidx = drows + a;
-              g1.push_back(d);
+      }
+      std::vector<long long> poff(nbx + 1, 0);
+      for (int b = 0; b < nbx; ++b) poff[b + 1] = poff[b] + (long long)L.K[b] * w;
+      double* P = scr.make<double>(std::max<long long>(poff[nbx], 1));
+      double* Q = scr.make<double>(std::max<long long>(poff[nbx], 1));
+      for (int c0 = 0; c0 < nc; c0 += w) {
+        const int wc = std::min(w, nc - c0);
+        // columns of this slice each box takes part in
+        auto cols_in = [&](int box) { return std::max(0, std::min(wc, cols_of(cols, box, nc) - c0)); };
+        // a pair with one empty basis contributes nothing: its Q segment stays zero
+        fill_zero(Q, poff[nbx], st);
+        std::vector<GemmDesc> g1;
+        if (!cp) {
+          for (int b = 0; b < nbx; ++b) {
+            const int box = L.boxes[b];
+            g1.push_back(gemm_desc(L.K[b], cols_in(box), t.count[box], 1.0, colmajT(L.U[b], t.count[box]),
+                                   panel(X + (long long)t.begin[box] * nc + c0, nc), 0.0, panel(P + poff[b], w)));
+          }
+        } else {
+          // a block whose rows form one run is passed as a contiguous block;
+          // column blocks without rows in a box leave their columns of P zero
+          const int ncol = cp->ncol;
+          fill_zero(P, poff[nbx], st);
+          for (int b = 0; b < nbx; ++b) {
+            const int box = L.boxes[b], cnt = t.count[box];
+            const int N = cols_in(box) / ncol;
+            if (N == 0) continue;
+            const double* Ob = cp->Om + (long long)t.begin[box] * cp->ldo + (*cp->j0)[t.inst[box]] + c0 / ncol;
+            for (int q = 0; q < ncol; ++q) {
+              const long long a = lo[(long long)ncol * b + q], e = lo[(long long)ncol * b + q + 1];
+              const int K = (int)(e - a);
+              if (K == 0) continue;
+              const Mat C{P + poff[b] + q, w, ncol, nullptr};
+              if (rows[e - 1] - rows[a] == K - 1) {
+                const int r0 = rows[a];
+                g1.push_back(gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b] + r0, cnt),
+                                       panel(Ob + (long long)r0 * cp->ldo, cp->ldo), 0.0, C));
+              } else {
+                GemmDesc d = gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b], cnt), Mat{Ob, cp->ldo, 1, drows + a}, 0.0, C);
+                d.kidx = drows + a;
+                g1.push_back(d);
+              }
             }
           }
         }
+        gemm_batched(g1, scr, st);
+        std::vector<GemmDesc> g2;
+        for (size_t p = 0; p < L.pairs.size(); ++p) {
+          const PairLR& pr = L.pairs[p];
+          if (pr.k1 == 0 || pr.k2 == 0) continue;
+          const int N = cols_in(pr.i);
+          // Q_i[seg(i, j)] = M P_j[seg(j, i)],  Q_j[seg(j, i)] = M^T P_i[seg(i, j)]
+          g2.push_back(gemm_desc(pr.k1, N, pr.k2, 1.0, colmaj(pr.M, pr.k1),
+                                 panel(P + poff[L.pos_j[p]] + (long long)L.off_j[p] * w, w), 0.0,
+                                 panel(Q + poff[L.pos_i[p]] + (long long)L.off_i[p] * w, w)));
+          g2.push_back(gemm_desc(pr.k2, N, pr.k1, 1.0, colmajT(pr.M, pr.k1),
+                                 panel(P + poff[L.pos_i[p]] + (long long)L.off_i[p] * w, w), 0.0,
+                                 panel(Q + poff[L.pos_j[p]] + (long long)L.off_j[p] * w, w)));
+        }
+        gemm_batched(g2, scr, st);
+        std::vector<GemmDesc> g3;
+        for (int b = 0; b < nbx; ++b) {
+          const int box = L.boxes[b];
+          g3.push_back(gemm_desc(t.count[box], cols_in(box), L.K[b], -1.0, colmaj(L.U[b], t.count[box]),
+                                 panel(Q + poff[b], w), 1.0, panel(out + (long long)t.begin[box] * nc + c0, nc)));
+        }
+        gemm_batched(g3, scr, st);
       }
-      gemm_batched(g1, scr, st);
-      std::vector<GemmDesc> g2;
-      for (size_t p = 0; p < L.pairs.size(); ++p) {
-        const PairLR& pr = L.pairs[p];
-        if (pr.k1 == 0 || pr.k2 == 0) continue;
-        const int N = cols_of(cols, pr.i, nc);
-        // Q_i[seg(i, j)] = M P_j[seg(j, i)],  Q_j[seg(j, i)] = M^T P_i[seg(i, j)]
-        g2.push_back(gemm_desc(pr.k1, N, pr.k2, 1.0, colmaj(pr.M, pr.k1),
-                               panel(P + poff[L.pos_j[p]] + (long long)L.off_j[p] * nc, nc), 0.0,
-                               panel(Q + poff[L.pos_i[p]] + (long long)L.off_i[p] * nc, nc)));
-        g2.push_back(gemm_desc(pr.k2, N, pr.k1, 1.0, colmajT(pr.M, pr.k1),
-                               panel(P + poff[L.pos_i[p]] + (long long)L.off_i[p] * nc, nc), 0.0,
-                               panel(Q + poff[L.pos_j[p]] + (long long)L.off_j[p] * nc, nc)));
-      }
-      gemm_batched(g2, scr, st);
-      std::vector<GemmDesc> g3;
-      for (int b = 0; b < nbx; ++b) {
-        const int box = L.boxes[b];
-        g3.push_back(gemm_desc(t.count[box], cols_of(cols, box, nc), L.K[b], -1.0, colmaj(L.U[b], t.count[box]),
-                               panel(Q + poff[b], nc), 1.0, panel(out + (long long)t.begin[box] * nc, nc)));
-      }
-      gemm_batched(g3, scr, st);
+      scr.release(P);
+      scr.release(Q);
     }
   }
 
