@@ -10,7 +10,12 @@ resident on the device before the timed region.
 
 Workload (default): n = 65536 sites uniform in [0,1]^2 (seed 31), Matern 3/2,
 theta = (0.05, 1.0, 1e-4), eps = 1e-6, leaf 64, 256 proxies on 4 rings,
-eps_peel = eps; z = F^(1/2) w with w ~ N(0, I) (seed 32), drawn once before timing.
+eps_peel = eps; z = L w, the draw from the model by the dense Cholesky factor
+(w ~ N(0, I), seed 32; committed with the dense oracle's l, log-det and score
+for it, so the line carries the errors against the dense definitions); other
+sizes draw z = F^(1/2) w once before timing.  The default run also times the
+64-instance batch (one warm-up batch, one timed) against its instances one by
+one.
 
 Prints one JSON line (see the repository's design notes for the fields).
 """
@@ -27,8 +32,9 @@ sys.path.insert(0, HERE)
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 DEFAULT = "c3_matern32_n65536"
 TRAFFIC = os.path.join(HERE, "profiles", "gemm_family_c3_matern32_n65536_traffic.json")
-FAMILY_SOURCES = ["paper_1603_08057_amd/csrc/gemm.hip", "paper_1603_08057_amd/csrc/sweep.hip",
-                  "paper_1603_08057_amd/csrc/common.h"]
+# every library source: the kernels and the host code that sets the launch mix
+FAMILY_SOURCES = ["paper_1603_08057_amd/csrc/" + f for f in
+                  ("capi.cpp", "common.h", "factor.hip", "gemm.hip", "grad.hip", "rsf.h", "sweep.hip", "tree.cpp")]
 
 
 def measured_traffic(launches_per_step):
@@ -107,17 +113,67 @@ def cpu_baseline(spec, name, budget_s=35.0):
     scale = (spec["n"] / m) ** 3
     return {"value": 1.0 / (t * scale), "unit": "evals/s", "cores": cores, "kind": "oracle",
             "sample": "dense FP64 oracle l+grad at n=%d (same recipe), %.2f s, scaled by (%d/%d)^3"
-                      % (m, t, spec["n"], m)}
+                      % (m, t, spec["n"], m),
+            "host": host_description()}
 
 
-def bench_batch(args):
+def host_description():
+    """CPU model and memory of the host (for the CPU baseline record)."""
+    out = {}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                out["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        for line in open("/proc/meminfo"):
+            if line.startswith("MemTotal"):
+                out["ram_gib"] = round(int(line.split()[1]) / 2 ** 20, 1)
+                break
+    except OSError:
+        pass
+    out["logical_cpus"] = os.cpu_count()
+    return out
+
+
+def dense_errors(spec, P, theta, kw, z, gold, eps_fact, eps_peel, seed):
+    """Errors of l, log|F|, the sampled F^-1 z and the score against the dense
+    oracle's reference for the same model draw z (committed golden values)."""
+    import numpy as np
+    import torch
+    import paper_1603_08057_amd as R
+    kw = dict(kw)
+    kw["eps"] = eps_fact
+    F = R.Factor(P, theta, with_score=True, **kw)
+    ell, alpha = F.loglik(z, want_alpha=True)
+    g, info = F.grad(z, eps_peel, seed)
+    logdet = F.logdet
+    F.close()
+    a = alpha.cpu().numpy()
+    idx = np.array(gold["alpha_index"])
+    ref = np.array(gold["alpha_value"])
+    gd, qd, td = np.array(gold["g"]), np.array(gold["q"]), np.array(gold["t"])
+    scale = np.abs(qd) + 0.5 * np.abs(td)
+    return {"eps_fact": eps_fact, "eps_peel": eps_peel,
+            "loglik": abs(ell - gold["ell"]) / abs(gold["ell"]),
+            "logdet": abs(logdet - gold["logdet"]) / abs(gold["logdet"]),
+            "solve_sampled_max": float(np.max(np.abs(a[idx] - ref)) / np.max(np.abs(ref))),
+            "grad_l2": float(np.linalg.norm(np.array(g) - gd) / np.linalg.norm(gd)),
+            "grad_over_q_plus_half_t": (np.abs(np.array(g) - gd) / scale).tolist(),
+            "traces": (np.abs(np.array(list(info.t)) - td) / np.abs(td)).tolist()}
+
+
+def measure_batch(args, name, steps, warmup):
     """Independent instances: one batched handle per step (every level of all
-    instances in one launch set) against the same instances one by one."""
+    instances in one launch set) against the same instances one by one.
+    Returns (seconds per batch, one-by-one seconds, record)."""
     import numpy as np
     import torch
     import paper_1603_08057_amd as R
     import workloads as W
-    spec = W.BATCHES[args.workload]
+    spec = W.BATCHES[name]
     inst = W.batch_instances(spec["count"], spec["master_seed"])
     dev = torch.device("cuda:0")
     pts = [torch.tensor(p, dtype=torch.float64, device=dev) for p, _ in inst]
@@ -149,30 +205,39 @@ def bench_batch(args):
             out.append((ell, g))
         return out
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         step_batched()
     torch.cuda.synchronize()
     t0 = time.time()
-    for i in range(args.steps):
+    for i in range(steps):
         ls, gs = step_batched()
         print("batched step %d done" % i, file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    tb = (time.time() - t0) / args.steps
+    tb = (time.time() - t0) / steps
     t0 = time.time()
     single = step_single()
     torch.cuda.synchronize()
     ts = time.time() - t0
     print("one by one: %.3f s" % ts, file=sys.stderr, flush=True)
     rel_l = max(abs(a - b[0]) / abs(b[0]) for a, b in zip(ls, single))
+    rec = {"workload": name, "instances": len(pts), "points": ntot,
+           "n_range": [min(len(p) for p in pts), max(len(p) for p in pts)], "eps": spec["eps"], "leaf": spec["leaf"],
+           "seconds_per_batch": tb, "batch_evals_per_s": 1.0 / tb, "steps": steps, "warmup": warmup,
+           "one_by_one": {"seconds": ts, "speedup_of_batching": ts / tb, "max_rel_diff_loglik": rel_l}}
+    return tb, ts, rec
+
+
+def bench_batch(args):
+    tb, ts, rec = measure_batch(args, args.workload, args.steps, args.warmup)
     out = {
-        "metric": "loglik+grad evals/sec of a %d-instance batch (eps=%g)" % (len(pts), spec["eps"]),
+        "metric": "loglik+grad evals/sec of a %d-instance batch (eps=%g)" % (rec["instances"], rec["eps"]),
         "value": 1.0 / tb, "unit": "batch evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": 1000.0 * tb, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64", "data": "synthetic",
-        "config": {"precision": args.precision, "workload": args.workload, "instances": len(pts), "points": ntot,
-                   "n_range": [min(len(p) for p in pts), max(len(p) for p in pts)], "eps": spec["eps"],
-                   "leaf": spec["leaf"], "parallelism": "single GPU"},
-        "one_by_one": {"seconds": ts, "speedup_of_batching": ts / tb, "max_rel_diff_loglik": rel_l},
+        "config": {"precision": args.precision, "workload": args.workload, "instances": rec["instances"],
+                   "points": rec["points"], "n_range": rec["n_range"], "eps": rec["eps"], "leaf": rec["leaf"],
+                   "parallelism": "single GPU"},
+        "one_by_one": rec["one_by_one"],
     }
     print(json.dumps(out))
 
@@ -187,6 +252,8 @@ def main():
     ap.add_argument("--eps", type=float, default=None, help="override the factorization tolerance")
     ap.add_argument("--eps-peel", type=float, default=None, help="override the peeling tolerance")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-instance batch measurement that the default run appends")
     ap.add_argument("--hutch", type=int, default=0,
                     help="score traces by Hutchinson's estimator with this many probes instead of peeling")
     ap.add_argument("--peeling", choices=["weak", "strong"], default="weak",
@@ -236,9 +303,18 @@ def main():
     eps_peel = spec.get("eps_peel", spec["eps"])
     kw = dict(kernel=spec["kernel"], eps=spec["eps"], leaf=spec["leaf"], n_prox=spec["n_prox"],
               prox_rings=spec["prox_rings"], rq_alpha=spec["alpha"])
-    F0 = R.Factor(P, theta, **kw)
-    z = F0.apply_sqrt(w)
-    F0.close()
+    gold = None
+    gpath = os.path.join(HERE, "tests", "golden", "%s_model_dense.json" % name)
+    zpath = os.path.join(HERE, "tests", "golden", "%s_model_z.npy" % name)
+    if not (args.n or args.eps) and os.path.exists(gpath) and os.path.exists(zpath):
+        # the draw from the model by the dense Cholesky factor whose l, log-det
+        # and score the dense oracle wrote: the errors below are against it
+        gold = json.load(open(gpath))
+        z = torch.tensor(np.load(zpath), dtype=torch.float64, device=dev)
+    else:
+        F0 = R.Factor(P, theta, **kw)
+        z = F0.apply_sqrt(w)
+        F0.close()
     torch.cuda.synchronize()
     print("setup done: n=%d" % n, file=sys.stderr, flush=True)
     if args.mle:
@@ -331,6 +407,19 @@ def main():
         "result": {"loglik": ell, "grad": g, "peel_cols": list(info.peel_cols)[:12],
                    "peel_rank": list(info.peel_rank)[:12]},
     }
+    if gold is not None and gold.get("g") is not None and args.precision == "fp64" and args.hutch <= 0:
+        # untimed: errors against the dense oracle at the benchmark's eps_fact
+        # and at eps_fact = eps / 1000 (the paper pairs eps_fact = eps_peel / 1000)
+        out["rel_err"] = {
+            "reference": "dense FP64 oracle on the model draw z = L w (tests/golden/%s_model_dense.json)" % name,
+            "at_benchmark_eps": dense_errors(spec, P, theta, kw, z, gold, spec["eps"], eps_peel,
+                                             spec.get("peel_seed", 0)),
+            "at_eps_over_1000": dense_errors(spec, P, theta, kw, z, gold, spec["eps"] / 1000, eps_peel,
+                                             spec.get("peel_seed", 0))}
+    if not args.no_batch and name == DEFAULT and not (args.n or args.eps or args.eps_peel) and args.hutch <= 0:
+        print("timing the 64-instance batch", file=sys.stderr, flush=True)
+        tb, ts, rec = measure_batch(args, "c4_batch64_matern32", 1, 1)
+        out["batch"] = rec
     if args.precision != "fp64":
         # the same evaluation in FP64, untimed: the mixed form's error against it
         ell64, g64, info64 = step("fp64")

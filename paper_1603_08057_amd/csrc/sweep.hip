@@ -3,6 +3,7 @@
 // operator.  Vectors are row-major panels in tree order (row = DOF), so each
 // box's S and R rows are gathered / scattered through index maps inside one
 // batched matrix-core GEMM per step and level.
+#include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <functional>
@@ -444,12 +445,15 @@ static void gemm_step(const LevelFactor& L, const std::vector<int>& bc, int op, 
 
 // ---- autotuning of the level steps
 // Where both forms apply (every box of the level has at most BS_AMAX active
-// DOFs), the first step of a given shape (operation, boxes, largest box,
-// redundant DOFs, panel width rounded up to a power of two) runs both forms
-// on copies of the panels (once untimed, then twice timed with HIP events),
-// and the faster one is kept
-// for every later step of that shape in the process.  The real step always
-// runs the chosen form, so repeated calls give bitwise equal results.
+// DOFs), the first step of a given shape class runs both forms on copies of
+// the panels (once untimed, then twice timed with HIP events), and the faster
+// one is kept for every later step of that class in the process.  The class
+// buckets the shape so that a factorization at another theta (the same sites,
+// slightly different ranks) reuses the choice: operation, the fused kernel's
+// size class of the largest box (64, 128, 256 DOFs), the panel width rounded
+// up to a power of two, and the number of boxes and of redundant DOFs in
+// quarter-octave buckets (steps of 2^(1/4)).  The real step always runs the
+// chosen form, so repeated calls give bitwise equal results.
 namespace {
 struct TuneKey {
   int op, nb, amax, ncb;
@@ -492,7 +496,9 @@ static void level_step(const rsf_factor_s* h, const LevelFactor& L, const std::v
   }
   int ncb = 1;
   while (ncb < nc) ncb <<= 1;
-  const TuneKey key{op, L.nb, amax, ncb, sr};
+  auto quarter_octave = [](long long x) { return (long long)std::floor(4.0 * std::log2((double)std::max(1LL, x))); };
+  const int aclass = amax <= 64 ? 64 : amax <= 128 ? 128 : 256;
+  const TuneKey key{op, (int)quarter_octave(L.nb), aclass, ncb, quarter_octave(sr)};
   int path = -1;
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
