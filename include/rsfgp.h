@@ -241,9 +241,11 @@ rsf_status rsf_logdet_batched(rsf_factor f, double* out_nb);
 rsf_status rsf_loglik_batched(rsf_factor f, const double* const* d_z, double* out_nb, void* stream);
 
 /* g_nb_p (host, nb x 3 values) = the score of every instance, as rsf_grad.
- * The peeling of all instances shares its probe counts per level (the largest
- * rank over all instances' sibling blocks decides); info_or_null receives
- * instance 0's split terms and the shared peeling statistics. */
+ * Every level of every instance's peeling runs in one set of launches, each
+ * instance with its own probe counts (its own ranks decide them, so a small
+ * instance does not pay for the largest one's ranks); info_or_null receives
+ * instance 0's split terms and, per level, the largest probe count and rank
+ * over the instances. */
 rsf_status rsf_grad_batched(rsf_factor f, const double* const* d_z, double eps_peel, uint64_t seed,
                             double* g_nb_p, rsf_grad_info* info_or_null, void* stream);
 
