@@ -565,6 +565,8 @@ namespace {
 struct TraceEv {
   hipEvent_t a, b;
   std::string tag;
+  double flops;
+  const void* stream;
 };
 // One record for the process; launches may come from several host threads
 // (the two factorizations built side by side), so the record is locked and
@@ -581,9 +583,10 @@ struct GemmTrace {
 thread_local std::string t_tag = "other";
 thread_local bool t_paused = false;
 bool tracing() { return g_trace.on.load() && !t_paused; }
-void trace_push(hipEvent_t e0, hipEvent_t e1, const std::string& tag, double flops, double bytes) {
+void trace_push(hipEvent_t e0, hipEvent_t e1, const std::string& tag, double flops, double bytes,
+                const void* stream) {
   std::lock_guard<std::mutex> lk(g_trace.mu);
-  g_trace.ev.push_back(TraceEv{e0, e1, tag});
+  g_trace.ev.push_back(TraceEv{e0, e1, tag, flops, stream});
   g_trace.flops += flops;
   g_trace.bytes += bytes;
   g_trace.launches += 1;
@@ -606,7 +609,7 @@ TraceLaunch::TraceLaunch(hipStream_t st, double fl, double by) : s(st), flops(fl
 TraceLaunch::~TraceLaunch() {
   if (!e0) return;
   (void)hipEventRecord(e1, s);
-  trace_push(e0, e1, t_tag, flops, bytes);
+  trace_push(e0, e1, t_tag, flops, bytes, s);
 }
 TraceTag::TraceTag(const char* t) : prev(t_tag) { t_tag = t; }
 TraceTag::~TraceTag() { t_tag = prev; }
@@ -617,6 +620,10 @@ void trace_read(double* ms, double* flops, double* bytes, long long* launches, b
   // the length of the union of the intervals (timestamps relative to the
   // first launch's start event)
   std::vector<std::pair<double, double>> iv;
+  // RSFGP_TRACE_DUMP=<file>: one line per traced launch (start and duration
+  // in ms from the first traced launch, flops, stream, tag), appended
+  static const char* dump_path = std::getenv("RSFGP_TRACE_DUMP");
+  FILE* dump = dump_path ? fopen(dump_path, "a") : nullptr;
   for (auto& e : g_trace.ev) {
     float t = 0.f, a = 0.f;
     RSF_HIP(hipEventSynchronize(e.b));
@@ -625,7 +632,9 @@ void trace_read(double* ms, double* flops, double* bytes, long long* launches, b
     iv.emplace_back((double)a, (double)a + t);
     g_trace.ms += t;
     g_trace.tag_ms[e.tag] += t;
+    if (dump) fprintf(dump, "%.4f %.4f %.6e %p %s\n", a, t, e.flops, e.stream, e.tag.c_str());
   }
+  if (dump) fclose(dump);
   std::sort(iv.begin(), iv.end());
   double cur0 = 0.0, cur1 = 0.0;
   bool open = false;
@@ -1006,7 +1015,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   if (traced) {
     RSF_HIP(hipEventRecord(e1, s));
     // launches with FP32 products are booked under "<phase>/f32"
-    trace_push(e0, e1, probs[9].empty() ? t_tag : t_tag + "/f32", flops, bytes);
+    trace_push(e0, e1, probs[9].empty() ? t_tag : t_tag + "/f32", flops, bytes, s);
   }
 }
 
