@@ -61,10 +61,16 @@ __device__ __forceinline__ double probe_normal(uint32_t d, uint32_t j, uint32_t 
 // instance of d),
 //   W[d, ncol t + q(d)] = Om[d, j0[i] + t] = N(d, j0[i] + t, level, stream),
 // W is zero elsewhere.  W interleaves the ncol column blocks (column
-// ncol t + q), so every instance's active columns form a prefix of the panel.
+// ncol t + q), so every instance's active columns form a prefix of the panel;
+// with qmajor (one instance) the blocks are contiguous instead (column
+// q ncw + t).
+__device__ __forceinline__ long long probe_col(int t, int q, int ncol, int ncw, int qmajor) {
+  return qmajor ? (long long)q * ncw + t : (long long)ncol * t + q;
+}
 __global__ void probe_kernel(const int* __restrict__ qd, const int* __restrict__ rinst, const int* __restrict__ act,
-                             const int* __restrict__ j0, long long n, int ncw, int ncol, int level, uint32_t stream,
-                             uint64_t seed, double* __restrict__ W, double* __restrict__ Om, long long ldo) {
+                             const int* __restrict__ j0, long long n, int ncw, int ncol, int qmajor, int level,
+                             uint32_t stream, uint64_t seed, double* __restrict__ W, double* __restrict__ Om,
+                             long long ldo) {
   const long long tot = n * ncw;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
     const long long d = e / ncw;
@@ -74,23 +80,24 @@ __global__ void probe_kernel(const int* __restrict__ qd, const int* __restrict__
     const int i = rinst[d];
     if (t >= act[i]) continue;
     const double v = probe_normal((uint32_t)d, (uint32_t)(j0[i] + t), (uint32_t)level, stream, seed);
-    W[d * (long long)ncol * ncw + (long long)ncol * t + q] = v;
+    W[d * (long long)ncol * ncw + probe_col(t, q, ncol, ncw, qmajor)] = v;
     Om[d * ldo + j0[i] + t] = v;
   }
 }
 
-// Y[d, q * C + j0[i] + t] = B[d, ncol t + q] for the rows of the nodes peeled
-// at this level and t < act[i] (i = instance of d).
+// Y[d, q * C + j0[i] + t] = B[d, column of (t, q)] for the rows of the nodes
+// peeled at this level and t < act[i] (i = instance of d).
 __global__ void store_samples_kernel(const int* __restrict__ qd, const int* __restrict__ rinst,
                                      const int* __restrict__ act, const int* __restrict__ j0, long long n, int ncw,
-                                     int ncol, int C, const double* __restrict__ B, double* __restrict__ Y) {
+                                     int ncol, int qmajor, int C, const double* __restrict__ B, double* __restrict__ Y) {
   const long long w = (long long)ncol * ncw;
   const long long tot = n * w;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
     const long long d = e / w;
     const int c = (int)(e - d * w);
     if (qd[d] < 0) continue;
-    const int i = rinst[d], t = c / ncol, q = c - t * ncol;
+    const int i = rinst[d];
+    const int t = qmajor ? c % ncw : c / ncol, q = qmajor ? c / ncw : c - (c / ncol) * ncol;
     if (t >= act[i]) continue;
     Y[d * (long long)ncol * C + (long long)q * C + j0[i] + t] = B[e];
   }
@@ -342,6 +349,9 @@ constexpr long long PEEL_CHUNK_BYTES = 24LL << 30;
 constexpr long long GRAM_CHUNK_BYTES = 8LL << 30;
 constexpr long long LOWRANK_CHUNK_BYTES = 8LL << 30;
 constexpr long long SUB_CHUNK_BYTES = 4LL << 30;
+// nodes of at least this many rows on average take the per-node subtraction
+// that skips their own quadrant's columns
+constexpr int SPLIT_MIN_ROWS = 128;
 constexpr int FIRST_COLS = 64;
 constexpr int MIN_COLS = 24;
 
@@ -640,6 +650,9 @@ struct Peeler {
     const std::vector<int>* j0;
     const std::vector<int>* qd;
     int ncol;
+    int qmajor;                      // column blocks contiguous (q ncw + t) rather than interleaved
+    int lev;                         // the level being peeled
+    const std::vector<int>* qbox;    // column block of every node peeled at lev (-1 elsewhere)
   };
 
   // out -= sum_{m < upto} G^(m) X  for operator op (same column rule as apply_ops).
@@ -653,6 +666,31 @@ struct Peeler {
     if (!st) st = s;
     TraceTag tag("peel_subtract");
     const int unit = cp ? cp->ncol : 1;
+    // the level's nodes in tree order (their rows are contiguous): with
+    // contiguous quadrant blocks and nodes of at least SPLIT_MIN_ROWS rows on
+    // average, the last product is split per node (see below)
+    std::vector<int> lbeg, lnode;
+    bool split = false;
+    if (cp && cp->qmajor) {
+      long long rows = 0;
+      for (int b = 0; b < t.nbox(); ++b)
+        if ((*cp->qbox)[b] >= 0) {
+          lbeg.push_back(t.begin[b]);
+          lnode.push_back(b);
+          rows += t.count[b];
+        }
+      std::vector<int> ord(lbeg.size());
+      for (size_t u = 0; u < ord.size(); ++u) ord[u] = (int)u;
+      std::sort(ord.begin(), ord.end(), [&](int x, int y) { return lbeg[x] < lbeg[y]; });
+      std::vector<int> b2(ord.size()), n2(ord.size());
+      for (size_t u = 0; u < ord.size(); ++u) {
+        b2[u] = lbeg[ord[u]];
+        n2[u] = lnode[ord[u]];
+      }
+      lbeg.swap(b2);
+      lnode.swap(n2);
+      split = !lnode.empty() && rows >= (long long)SPLIT_MIN_ROWS * (long long)lnode.size();
+    }
     for (int m = 1; m < upto && m < (int)lr[op].size(); ++m) {
       const LevelLR& L = lr[op][m];
       if (!L.any) continue;
@@ -661,6 +699,8 @@ struct Peeler {
       for (int b = 0; b < nbx; ++b) ksum += L.K[b];
       if (ksum == 0) continue;
       int w = (int)std::min<long long>(nc, std::max<long long>(unit, SUB_CHUNK_BYTES / (16 * ksum) / unit * unit));
+      // contiguous quadrant blocks are kept whole (one slice)
+      if (cp && cp->qmajor) w = nc;
       // rows of each box by column block (box-relative), for the compact probes
       std::vector<int> rows;
       std::vector<long long> lo;
@@ -714,7 +754,8 @@ struct Peeler {
               const long long a = lo[(long long)ncol * b + q], e = lo[(long long)ncol * b + q + 1];
               const int K = (int)(e - a);
               if (K == 0) continue;
-              const Mat C{P + poff[b] + q, w, ncol, nullptr};
+              const Mat C = cp->qmajor ? Mat{P + poff[b] + (long long)q * (wc / ncol), w, 1, nullptr}
+                                     : Mat{P + poff[b] + q, w, ncol, nullptr};
               if (rows[e - 1] - rows[a] == K - 1) {
                 const int r0 = rows[a];
                 g1.push_back(gemm_desc(L.K[b], N, K, 1.0, colmajT(L.U[b] + r0, cnt),
@@ -743,10 +784,34 @@ struct Peeler {
         }
         gemm_batched(g2, scr, st);
         std::vector<GemmDesc> g3;
-        for (int b = 0; b < nbx; ++b) {
-          const int box = L.boxes[b];
-          g3.push_back(gemm_desc(t.count[box], cols_in(box), L.K[b], -1.0, colmaj(L.U[b], t.count[box]),
-                                 panel(Q + poff[b], w), 1.0, panel(out + (long long)t.begin[box] * nc + c0, nc)));
+        if (split) {
+          // rows of the level's nodes only (the samples are taken there), and
+          // of each node only the column blocks of the other quadrants (the
+          // node's own block is never used as a sample)
+          const int qw = wc / cp->ncol;
+          for (int b = 0; b < nbx; ++b) {
+            const int box = L.boxes[b], bb = t.begin[box], be = bb + t.count[box];
+            auto it = std::lower_bound(lbeg.begin(), lbeg.end(), bb);
+            for (size_t u = it - lbeg.begin(); u < lbeg.size() && lbeg[u] < be; ++u) {
+              const int node = lnode[u], q = (*cp->qbox)[node];
+              const int r0 = t.begin[node], rc = t.count[node];
+              const Mat A = colmaj(L.U[b] + (r0 - bb), t.count[box]);
+              // columns [0, q qw) and [(q + 1) qw, ncol qw)
+              if (q > 0)
+                g3.push_back(gemm_desc(rc, q * qw, L.K[b], -1.0, A, panel(Q + poff[b], w), 1.0,
+                                       panel(out + (long long)r0 * nc, nc)));
+              if (q + 1 < cp->ncol)
+                g3.push_back(gemm_desc(rc, (cp->ncol - q - 1) * qw, L.K[b], -1.0, A,
+                                       panel(Q + poff[b] + (long long)(q + 1) * qw, w), 1.0,
+                                       panel(out + (long long)r0 * nc + (long long)(q + 1) * qw, nc)));
+            }
+          }
+        } else {
+          for (int b = 0; b < nbx; ++b) {
+            const int box = L.boxes[b];
+            g3.push_back(gemm_desc(t.count[box], cols_in(box), L.K[b], -1.0, colmaj(L.U[b], t.count[box]),
+                                   panel(Q + poff[b], w), 1.0, panel(out + (long long)t.begin[box] * nc + c0, nc)));
+          }
         }
         gemm_batched(g3, scr, st);
       }
@@ -1121,6 +1186,9 @@ struct Peeler {
         const int cw = std::min(newmax, (int)std::max<long long>(8, PEEL_CHUNK_BYTES / per_col / 8 * 8));
         int* dact = scr.make<int>(ni);
         int* dj0 = scr.make<int>(ni);
+        // one instance in the weak form: contiguous quadrant blocks, so that the
+        // coarser levels' subtraction can skip each row's own quadrant
+        const bool qmajor = !strong && ni == 1;
         for (int t0 = 0; t0 < newmax; t0 += cw) {
           const int ncw = std::min(cw, newmax - t0);
           std::vector<int> act(ni), j0(ni), pcols(ni);
@@ -1136,7 +1204,7 @@ struct Peeler {
           double* Wm = rs.make<double>(n * (long long)ncol * cw);  // full-chunk sizes: reused by every chunk
           fill_zero(Wm, sz, s);
           hipLaunchKernelGGL(probe_kernel, dim3(grid_of(n * ncw)), dim3(256), 0, s, dqd, drinst, dact, dj0, n, ncw,
-                             ncol, lev, stream_id, seed, Wm, Om, (long long)C);
+                             ncol, qmajor ? 1 : 0, lev, stream_id, seed, Wm, Om, (long long)C);
           RSF_HIP(hipGetLastError());
           double* Bo[MAXOP] = {nullptr, nullptr, nullptr};
           for (int op = 0; op < nop; ++op) Bo[op] = rs.make<double>(n * (long long)ncol * cw);
@@ -1144,11 +1212,11 @@ struct Peeler {
           auto c0 = std::chrono::steady_clock::now();
           apply_ops(Wm, ncol * ncw, Bo, rs, pc);
           auto c1 = std::chrono::steady_clock::now();
-          const CompactProbes cpr{Om, (long long)C, &j0, &qd, ncol};
+          const CompactProbes cpr{Om, (long long)C, &j0, &qd, ncol, qmajor ? 1 : 0, lev, &qbox};
           auto sub_store = [&](int op, Scratch& r, hipStream_t st) {
             subtract_lowrank(op, lev, Wm, ncol * ncw, Bo[op], r, pc, &cpr, st);
             hipLaunchKernelGGL(store_samples_kernel, dim3(grid_of(sz)), dim3(256), 0, st, dqd, drinst, dact, dj0, n,
-                               ncw, ncol, C, Bo[op], Y[op]);
+                               ncw, ncol, qmajor ? 1 : 0, C, Bo[op], Y[op]);
             RSF_HIP(hipGetLastError());
           };
           // the operators' subtractions and sample stores side by side
