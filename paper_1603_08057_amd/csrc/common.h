@@ -133,6 +133,9 @@ struct GemmDesc {
   int M, N, K;
   double alpha, beta;
   int lower;  // 1: only tiles touching the lower triangle of C (i >= j) are computed
+  int tri;    // A triangular with zeros stored in its other half: 1 lower (A(i, p) = 0
+              // for p > i), 2 upper (A(i, p) = 0 for p < i); each tile then multiplies
+              // only the K chunks its rows can reach (plain A only: no row or K map)
   int f32;    // 1: operands rounded to FP32, FP32 matrix-core products with FP32
               //    accumulation; alpha * acc + beta * C is formed in FP64
 };
@@ -172,6 +175,7 @@ inline GemmDesc gemm_desc(int M, int N, int K, double alpha, Mat A, Mat B, doubl
   d.alpha = alpha;
   d.beta = beta;
   d.lower = 0;
+  d.tri = 0;
   d.f32 = 0;
   return d;
 }

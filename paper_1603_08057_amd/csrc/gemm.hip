@@ -440,8 +440,10 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
       rbv[r] = v;
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < d.K; k0 += 16) {
+  // a triangular A reaches only the K chunks of the tile's rows
+  const int kbeg = d.tri == 2 ? i0 : 0, kend = d.tri == 1 ? min(d.K, i0 + 64) : d.K;
+  fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
@@ -449,7 +451,7 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
       Bs[kb[r]][jb[r]] = rbv[r];
     }
     __syncthreads();
-    if (k0 + 16 < d.K) fetch(k0 + 16);
+    if (k0 + 16 < kend) fetch(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
@@ -757,10 +759,12 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
       }
     }
   };
-  fetch(0);
+  // a triangular A reaches only the K chunks of the tile's rows
+  const int kbeg = dg.tri == 2 ? i0 : 0, kend = dg.tri == 1 ? min(K, i0 + BT) : K;
+  fetch(kbeg);
   const int lane = tid & 63, wave = tid >> 6;
   const int rb0 = (wave >> 1) * 64, cb0 = (wave & 1) * 64;
-  for (int k0 = 0; k0 < K; k0 += 16) {
+  for (int k0 = kbeg; k0 < kend; k0 += 16) {
     __syncthreads();
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
@@ -774,7 +778,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
         Bs[b_k][b_j + 16 * r] = rbv[r];
     }
     __syncthreads();
-    if (k0 + 16 < K) fetch(k0 + 16);
+    if (k0 + 16 < kend) fetch(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
@@ -862,7 +866,9 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     if (d.M <= 0 || d.N <= 0) continue;
     RSF_CHECK(!d.lower || d.M == d.N, RSF_E_INVALID, "lower-triangle GEMM needs a square C");
     RSF_CHECK(!(d.kidx && d.f32), RSF_E_INVALID, "column-mapped A needs the FP64 tile kernel");
-    flops += (d.lower ? 1.0 : 2.0) * d.M * d.N * d.K;
+    RSF_CHECK(!d.tri || (!d.aidx && !d.kidx && !d.f32), RSF_E_INVALID, "triangular A must be a plain matrix");
+    // a triangular A (K = M) holds about half the products
+    flops += (d.lower || d.tri ? 1.0 : 2.0) * d.M * d.N * d.K;
     bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
     const int p = (int)live.size();
     live.push_back(d);
@@ -901,7 +907,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
       const int p = probs[g][u];
       const GemmDesc d = live[p];
       const int sp = std::min(want, d.K / SPLIT_MIN_K);
-      if (d.lower || sp < 2) continue;
+      if (d.lower || d.tri || sp < 2) continue;
       const int kpart = (d.K + sp - 1) / sp / 16 * 16 + 16;
       const int nparts = (d.K + kpart - 1) / kpart;
       if (nparts < 2) continue;

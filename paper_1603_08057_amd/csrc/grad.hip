@@ -664,7 +664,9 @@ struct Peeler {
   void subtract_lowrank(int op, int upto, const double* X, int nc, double* out, Scratch& scr, const int* cols,
                         const CompactProbes* cp = nullptr, hipStream_t st = nullptr) {
     if (!st) st = s;
-    TraceTag tag("peel_subtract");
+    // phase "peel_subtract/<level being peeled>" (L = the leaf extraction)
+    const std::string tname = std::string("peel_subtract/") + (cp ? std::to_string(cp->lev) : std::string("L"));
+    TraceTag tag(tname.c_str());
     const int unit = cp ? cp->ncol : 1;
     // the level's nodes in tree order (their rows are contiguous): with
     // contiguous quadrant blocks and nodes of at least SPLIT_MIN_ROWS rows on
@@ -1031,7 +1033,9 @@ struct Peeler {
       gd.push_back(gemm_desc(k1, k2, total, 1.0, colmaj(T1, k1), colmajT(A2, k2), 0.0, colmaj(T2, k1)));
       // M = N1^-1 T2 N2^-1 with N^-1 = Linv^T Linv
       ge.push_back(gemm_desc(k1, k2, k1, 1.0, colmaj(N1i, k1), colmaj(T2, k1), 0.0, colmaj(X, k1)));
+      ge.back().tri = 1;  // the inverse Cholesky factors are lower triangular
       gf.push_back(gemm_desc(k1, k2, k1, 1.0, colmajT(N1i, k1), colmaj(X, k1), 0.0, colmaj(T2, k1)));
+      gf.back().tri = 2;
       gg.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(T2, k1), colmajT(N2i, k2), 0.0, colmaj(X, k1)));
       gh.push_back(gemm_desc(k1, k2, k2, 1.0, colmaj(X, k1), colmaj(N2i, k2), 0.0, colmaj(pr.M, k1)));
     }

@@ -373,10 +373,11 @@ static std::vector<int> box_cols(const rsf_factor_s* h, const LevelFactor& L, co
 
 static int root_cols(const int* inst_cols, int i, int nc) { return inst_cols ? std::min(nc, inst_cols[i]) : nc; }
 
+// tri: the per-box A is triangular (1 lower, 2 upper; GemmDesc::tri)
 template <class AFn>
 static void level_gemm(const LevelFactor& L, const std::vector<int>& bc, int nc, double alpha, AFn afn, Rows brows,
                        const double* Bp, long long ldb, double beta, Rows crows, double* Cp, long long ldc,
-                       Scratch& scr, hipStream_t s) {
+                       Scratch& scr, hipStream_t s, int tri = 0) {
   std::vector<GemmDesc> g;
   g.reserve(L.nb);
   for (int i = 0; i < L.nb; ++i) {
@@ -393,7 +394,9 @@ static void level_gemm(const LevelFactor& L, const std::vector<int>& bc, int nc,
       if (w == RR) return panel(P, ld, L.R + L.r_off[i]);
       return panel(P + L.r_off[i] * nc, nc);
     };
-    g.push_back(gemm_desc(M, N, K, alpha, A, rowsel(brows, Bp, ldb), beta, rowsel(crows, Cp, ldc)));
+    GemmDesc d = gemm_desc(M, N, K, alpha, A, rowsel(brows, Bp, ldb), beta, rowsel(crows, Cp, ldc));
+    d.tri = tri;
+    g.push_back(d);
   }
   gemm_batched(g, scr, s);
 }
@@ -406,9 +409,9 @@ static void gemm_step(const LevelFactor& L, const std::vector<int>& bc, int op, 
     // X_R -= T^T X_S
     level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.T + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, X, ld, scr, s);
-    // tmp = L^-1 X_R
+    // tmp = L^-1 X_R (L^-1 lower triangular)
     level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lm + L.l_off[i], r); },
-               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
+               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s, 1);
     // X_S -= W tmp
     level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.W + L.t_off[i], k); },
                RTMP, tmp, nc, 1.0, RS, X, ld, scr, s);
@@ -417,9 +420,9 @@ static void gemm_step(const LevelFactor& L, const std::vector<int>& bc, int op, 
     // X_R -= W^T X_S
     level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, X, ld, scr, s);
-    // tmp = L^-T X_R
+    // tmp = L^-T X_R (L^-T upper triangular)
     level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lm + L.l_off[i], r); },
-               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s);
+               RR, X, ld, 0.0, RTMP, tmp, nc, scr, s, 2);
     scatter_rows(L.R, L.total_r, tmp, nc, X, ld, s);
     // X_S -= T tmp
     level_gemm(L, bc, nc, -1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
@@ -571,7 +574,9 @@ void sweep_solve(const rsf_factor_s* h, const FactorData& F, double* X, int nc, 
       const int* ri = F.root_idx + rb.off;
       double* tr = tmp + (long long)rb.off * nc;
       g1.push_back(gemm_desc(N, cols, N, 1.0, colmaj(rb.Linv, N), panel(X, ld, ri), 0.0, panel(tr, nc)));
+      g1.back().tri = 1;
       g2.push_back(gemm_desc(N, cols, N, 1.0, colmajT(rb.Linv, N), panel(tr, nc), 0.0, panel(X, ld, ri)));
+      g2.back().tri = 2;
     }
     gemm_batched(g1, scr, s);
     gemm_batched(g2, scr, s);
@@ -606,6 +611,7 @@ static void root_half(const FactorData& F, bool trans, double* X, int nc, long l
     if (N == 0 || cols == 0) continue;
     g.push_back(gemm_desc(N, cols, N, 1.0, trans ? colmajT(rb.Linv, N) : colmaj(rb.Linv, N),
                           panel(X, ld, F.root_idx + rb.off), 0.0, panel(tmp + (long long)rb.off * nc, nc)));
+    g.back().tri = trans ? 2 : 1;
   }
   gemm_batched(g, scr, s);
   scatter_rows(F.root_idx, F.nroot, tmp, nc, X, ld, s);
@@ -651,9 +657,9 @@ void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double*
     // X_S += T X_R
     level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = k; K = r; return colmaj(L.T + L.t_off[i], k); },
                RR, X, ld, 1.0, RS, X, ld, scr, s);
-    // Out_R = L^T X_R + W^T X_S
+    // Out_R = L^T X_R + W^T X_S (L^T upper triangular)
     level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmajT(L.Lf + L.l_off[i], r); },
-               RR, X, ld, 0.0, RR, Out, ld, scr, s);
+               RR, X, ld, 0.0, RR, Out, ld, scr, s, 2);
     level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = k; return colmajT(L.W + L.t_off[i], k); },
                RS, X, ld, 1.0, RR, Out, ld, scr, s);
   }
@@ -663,6 +669,7 @@ void sweep_sqrt_t(const rsf_factor_s* h, const FactorData& F, double* X, double*
       if (rb.N > 0)
         g.push_back(gemm_desc(rb.N, nc, rb.N, 1.0, colmajT(rb.L, rb.N), panel(X, ld, F.root_idx + rb.off), 0.0,
                               panel(Out, ld, F.root_idx + rb.off)));
+    for (GemmDesc& d : g) d.tri = 2;
     gemm_batched(g, scr, s);
   }
 }
@@ -677,7 +684,7 @@ void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, dou
     LevelTag lt(d, "up");
     const std::vector<int> bc = box_cols(h, L, inst_cols, nc);
     level_gemm(L, bc, nc, 1.0, [&](int i, int k, int r, int& M, int& K) { M = r; K = r; return colmaj(L.Lf + L.l_off[i], r); },
-               RR, Y, ld, 0.0, RR, V, ld, scr, s);
+               RR, Y, ld, 0.0, RR, V, ld, scr, s, 1);
   }
   if (F.nroot > 0) {
     std::vector<GemmDesc> g;
@@ -685,6 +692,7 @@ void sweep_sqrt(const rsf_factor_s* h, const FactorData& F, const double* Y, dou
       if (rb.N > 0)
         g.push_back(gemm_desc(rb.N, nc, rb.N, 1.0, colmaj(rb.L, rb.N), panel(Y, ld, F.root_idx + rb.off), 0.0,
                               panel(V, ld, F.root_idx + rb.off)));
+    for (GemmDesc& d : g) d.tri = 1;
     gemm_batched(g, scr, s);
   }
   for (int d = 1; d <= D; ++d) {
