@@ -717,7 +717,10 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
   const int b_k = BJ ? (tid >> 7) : (tid & 15);
   const long long astr = AI ? dg.acs : dg.ars;  // AI: step along k; else: step between the 8 rows (x16)
   const long long bstr = BJ ? dg.brs : dg.bcs;
-  const double* __restrict__ pa = dg.A + (long long)(i0 + a_i) * (AI ? 1 : dg.ars);
+  // AI: this thread's row of A, through the row map when there is one
+  const long long arow0 = AI ? (dg.aidx ? (i0 + a_i < M ? (long long)dg.aidx[i0 + a_i] : 0LL) : (long long)(i0 + a_i))
+                             : (long long)(i0 + a_i) * dg.ars;
+  const double* __restrict__ pa = dg.A + arow0;
   const double* __restrict__ pb = dg.B + (long long)(j0 + b_j) * (BJ ? 1 : dg.bcs);
   const int* __restrict__ bidx = dg.bidx;
   unsigned amask = 0, bmask = 0;  // bit r: row / column r of this thread is inside the problem
@@ -847,7 +850,8 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const SplitRed* __re
 
 static int big_class(const GemmDesc& d) {
   if (d.kidx) return -1;
-  const bool ai = (d.ars == 1 && d.aidx == nullptr), ak = (d.acs == 1 && d.aidx == nullptr);
+  // rows-contiguous A may take a row map (one row pointer per thread)
+  const bool ai = d.ars == 1, ak = (d.acs == 1 && d.aidx == nullptr);
   const bool bj = (d.bcs == 1), bk = (d.brs == 1 && d.bidx == nullptr);
   if (!(ai || ak) || !(bj || bk)) return -1;
   return (ai ? 4 : 0) | (bj ? 2 : 0) | ((bj && d.bidx) ? 1 : 0);
