@@ -32,25 +32,226 @@ sys.path.insert(0, HERE)
 FP64_MFMA_PEAK_TFLOPS = 78.6  # MI355X dense FP64 matrix peak
 DEFAULT = "c3_matern32_n65536"
 TRAFFIC = os.path.join(HERE, "profiles", "gemm_family_c3_matern32_n65536_traffic.json")
-# every library source: the kernels and the host code that sets the launch mix
+# every library source (the kernels and the host code that sets the launch mix
+# and the probe rule) and the workload recipe: the counters are void once any
+# of them changes
 FAMILY_SOURCES = ["paper_1603_08057_amd/csrc/" + f for f in
                   ("capi.cpp", "common.h", "factor.hip", "gemm.hip", "grad.hip", "rsf.h", "sweep.hip", "tree.cpp")]
+FAMILY_SOURCES.append("workloads/__init__.py")
+# the kernels whose launches the library's own trace counts (the roofline's family)
+FAMILY_KERNELS = ("gemm_big_kernel", "gemm_tiles_kernel", "box_sweep_kernel")
+PMC_COMMAND = ("cd /tmp && export TMPDIR=/tmp && timeout -s KILL 400 rocprofv3 --pmc {ctr} --output-format csv "
+               "-d <out>/{run} -o run -- python3 <repo>/bench.py {args}")
+PMC_BENCH_ARGS = "--steps {s} --warmup 0 --no-cpu-baseline --no-batch --no-rel-err"
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in FAMILY_SOURCES:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _pmc_rows(d):
+    """(kernel name, counter value) per dispatch from a rocprofv3 --pmc csv run
+    directory (one counter per run)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit("%s: expected one counter_collection.csv, found %d" % (d, len(files)))
+    per = {}
+    with open(files[0]) as fh:
+        for row in csv.DictReader(fh):
+            key = row["Dispatch_Id"]
+            name = row["Kernel_Name"]
+            per[key] = (name, per.get(key, (name, 0.0))[1] + float(row["Counter_Value"]))
+    return list(per.values())
+
+
+def traffic_record(root):
+    """Write the family's HBM traffic record and the per-kernel FETCH_SIZE /
+    WRITE_SIZE summaries from the counter runs under root: fetch_1, fetch_2,
+    write_1, write_2 (the benchmark at one and at two steps) and cal_fetch,
+    cal_write (the 1 GiB copy)."""
+    def fam(name):
+        return any(k in name for k in FAMILY_KERNELS)
+
+    def per_kernel(rows):
+        out = {}
+        for name, v in rows:
+            a = out.setdefault(name, [0, 0.0])
+            a[0] += 1
+            a[1] += v
+        return out
+
+    runs = {k: per_kernel(_pmc_rows(os.path.join(root, k)))
+            for k in ("fetch_1", "fetch_2", "write_1", "write_2", "cal_fetch", "cal_write")}
+
+    def copy_kib(r):
+        return sum(v for name, (c, v) in runs[r].items() if "copyBuffer" in name)
+
+    copy_bytes = 1 << 30
+    cal = {"copy_bytes": copy_bytes, "FETCH_SIZE_KiB": copy_kib("cal_fetch"), "WRITE_SIZE_KiB": copy_kib("cal_write")}
+    cal["fetch_scale"] = copy_bytes / 1024.0 / cal["FETCH_SIZE_KiB"]
+    cal["write_scale"] = copy_bytes / 1024.0 / cal["WRITE_SIZE_KiB"]
+    rec = {"kernel_family": "batched FP64 matrix-core products: " + ", ".join(k + "<...>" for k in FAMILY_KERNELS),
+           "workload": "%s, one steady-state step (difference of a two-step and a one-step run)" % DEFAULT,
+           "commands": [PMC_COMMAND.format(ctr=c, run=c.split("_")[0].lower() + "_S",
+                                           args=PMC_BENCH_ARGS.format(s="S")) + "   (S = 1 and S = 2)"
+                        for c in ("FETCH_SIZE", "WRITE_SIZE")] + [
+               "one steady-state step = the S = 2 run minus the S = 1 run (the setup and the first step's "
+               "autotuning cancel)",
+               "calibration: " + PMC_COMMAND.format(ctr="FETCH_SIZE (then WRITE_SIZE)", run="cal_fetch",
+                                                    args="--copy-calibration") + " (a 1 GiB device-to-device copy)",
+               "record: python3 bench.py --traffic-record <out>"],
+           "calibration": cal, "runs": {}}
+    step = {}
+    for ctr in ("fetch", "write"):
+        a, b = runs[ctr + "_1"], runs[ctr + "_2"]
+        rec["runs"][ctr + "_1"] = [sum(c for n, (c, v) in a.items() if fam(n)), sum(v for n, (c, v) in a.items() if fam(n))]
+        rec["runs"][ctr + "_2"] = [sum(c for n, (c, v) in b.items() if fam(n)), sum(v for n, (c, v) in b.items() if fam(n))]
+        diff = {n: (b[n][0] - a.get(n, (0, 0.0))[0], b[n][1] - a.get(n, (0, 0.0))[1]) for n in b}
+        step[ctr] = diff
+        label = "FETCH_SIZE" if ctr == "fetch" else "WRITE_SIZE"
+        lines = ["%s (KiB) per kernel for one steady-state step: dispatches, KiB, kernel, as the difference of two "
+                 "runs: %s, with S = 2 minus S = 1; ×%.4f gives bytes of HBM traffic by the copy calibration"
+                 % (label, PMC_COMMAND.format(ctr=label, run=ctr + "_S", args=PMC_BENCH_ARGS.format(s="S")),
+                    1024.0 * cal[ctr + "_scale"])]
+        for n, (c, v) in sorted(diff.items(), key=lambda kv: -kv[1][1]):
+            if c > 0 and v > 0:
+                lines.append("%10d %16.1f %s" % (c, v, n[:140]))
+        with open(os.path.join(HERE, "profiles", "gemm_family_%s_%s.txt" % (DEFAULT, label.lower())), "w") as fh:
+            fh.write("\n".join(lines[:40]) + "\n")
+    rec["family_dispatches_per_step"] = sum(c for n, (c, v) in step["fetch"].items() if fam(n))
+    rec["family_dispatches_per_step_write_runs"] = sum(c for n, (c, v) in step["write"].items() if fam(n))
+    rec["family_FETCH_SIZE_KiB_per_step"] = sum(v for n, (c, v) in step["fetch"].items() if fam(n))
+    rec["family_WRITE_SIZE_KiB_per_step"] = sum(v for n, (c, v) in step["write"].items() if fam(n))
+    rec["sources_sha256"] = sources_sha256()
+    rec["family_hbm_bytes_per_step"] = 1024.0 * (rec["family_FETCH_SIZE_KiB_per_step"] * cal["fetch_scale"] +
+                                                 rec["family_WRITE_SIZE_KiB_per_step"] * cal["write_scale"])
+    with open(TRAFFIC, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps({k: rec[k] for k in ("family_dispatches_per_step", "family_hbm_bytes_per_step")}))
+
+
+def _pmc_by_kernel(d):
+    """{kernel: {"n": dispatches, "ns": summed durations, counter: summed value}}
+    from a rocprofv3 --pmc csv run directory."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    if len(files) != 1:
+        raise SystemExit("%s: expected one counter_collection.csv, found %d" % (d, len(files)))
+    disp = {}
+    with open(files[0]) as fh:
+        for row in csv.DictReader(fh):
+            e = disp.setdefault(row["Dispatch_Id"], {"name": row["Kernel_Name"],
+                                                     "ns": float(row["End_Timestamp"]) - float(row["Start_Timestamp"])})
+            e[row["Counter_Name"]] = e.get(row["Counter_Name"], 0.0) + float(row["Counter_Value"])
+    out = {}
+    for e in disp.values():
+        if "MfmaUtil" in e:
+            e["MfmaUtil_ns"] = e["MfmaUtil"] * e["ns"]  # the busy share, weighted by duration
+        a = out.setdefault(e["name"], {"n": 0})
+        a["n"] += 1
+        for k, v in e.items():
+            if k != "name":
+                a[k] = a.get(k, 0.0) + v
+    return out
+
+
+def _step_diff(a, b):
+    """Per-kernel difference of the two-step and the one-step run."""
+    out = {}
+    for name, eb in b.items():
+        ea = a.get(name, {})
+        out[name] = {k: v - ea.get(k, 0.0) for k, v in eb.items()}
+    return out
+
+
+def _short(name):
+    base = name.split("(")[0].replace("void ", "").replace("rsf::", "")
+    return base
+
+
+def frac_record(root):
+    """Per-kernel fraction of peak for one steady-state step, from the counter
+    runs under root: mfma_1, mfma_2 (MfmaFlopsF64, MfmaUtil and
+    SQ_INSTS_VALU_FLOPS_FP64 at one and two steps), the FETCH_SIZE / WRITE_SIZE
+    runs and their copy calibration (as for the traffic record)."""
+    mf = _step_diff(_pmc_by_kernel(os.path.join(root, "mfma_1")), _pmc_by_kernel(os.path.join(root, "mfma_2")))
+    fe = _step_diff(_pmc_by_kernel(os.path.join(root, "fetch_1")), _pmc_by_kernel(os.path.join(root, "fetch_2")))
+    wr = _step_diff(_pmc_by_kernel(os.path.join(root, "write_1")), _pmc_by_kernel(os.path.join(root, "write_2")))
+    cal_f = sum(e.get("FETCH_SIZE", 0.0) for n, e in _pmc_by_kernel(os.path.join(root, "cal_fetch")).items()
+                if "copyBuffer" in n)
+    cal_w = sum(e.get("WRITE_SIZE", 0.0) for n, e in _pmc_by_kernel(os.path.join(root, "cal_write")).items()
+                if "copyBuffer" in n)
+    fscale, wscale = (1 << 30) / cal_f, (1 << 30) / cal_w  # bytes per counted KiB
+    cmd = PMC_COMMAND.format(ctr="MfmaFlopsF64 MfmaUtil SQ_INSTS_VALU_FLOPS_FP64", run="mfma_S",
+                             args=PMC_BENCH_ARGS.format(s="S"))
+    lines = ["# Per-kernel fraction of peak: %s, one steady-state step" % DEFAULT, "",
+             "Commands (S = 1 and S = 2; one step = the S = 2 run minus the S = 1 run):", "", "```", cmd,
+             PMC_COMMAND.format(ctr="FETCH_SIZE", run="fetch_S", args=PMC_BENCH_ARGS.format(s="S")),
+             PMC_COMMAND.format(ctr="WRITE_SIZE", run="write_S", args=PMC_BENCH_ARGS.format(s="S")),
+             PMC_COMMAND.format(ctr="FETCH_SIZE", run="cal_fetch", args="--copy-calibration") +
+             "   (and WRITE_SIZE into cal_write)",
+             "python3 bench.py --frac-record <out>", "```", "",
+             "Durations are the counter runs' dispatch timestamps: under --pmc every dispatch runs alone, so "
+             "they are the kernels' own times without the second stream beside them.  MFMA flops are the "
+             "hardware's count (MfmaFlopsF64 = 512 x SQ_INSTS_VALU_MFMA_MOPS_F64), padding and skipped "
+             "triangles included; MFMA util is the busy share of the matrix cores over the dispatch "
+             "(MfmaUtil, weighted by duration).  HBM bytes are FETCH_SIZE and WRITE_SIZE scaled by what "
+             "they read for a 1 GiB copy (x%.3f and x%.3f).  Peaks: FP64 matrix 78.6 TFLOP/s, HBM 8 TB/s, "
+             "FP64 vector 78.6 TFLOP/s." % (fscale / 1024, wscale / 1024), "",
+             "| kernel | dispatches | ms | MFMA TFLOP/s | frac of 78.6 | MFMA util % | VALU FP64 TFLOP/s | "
+             "HBM GB | HBM TB/s | frac of 8 TB/s |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    rows = []
+    for name, e in mf.items():
+        if e["n"] <= 0 or e["ns"] <= 0:
+            continue
+        hb = fe.get(name, {}).get("FETCH_SIZE", 0.0) * fscale + wr.get(name, {}).get("WRITE_SIZE", 0.0) * wscale
+        rows.append((e["ns"], name, e, hb))
+    rows.sort(key=lambda r: -r[0])
+    tot = {"ns": 0.0, "fl": 0.0, "hb": 0.0}
+    fam = {"ns": 0.0, "fl": 0.0, "hb": 0.0, "util": 0.0, "n": 0}
+    for ns, name, e, hb in rows[:28]:
+        s = ns * 1e-9
+        util = e.get("MfmaUtil_ns", 0.0) / ns
+        lines.append("| `%s` | %d | %.2f | %.2f | %.3f | %.1f | %.3f | %.2f | %.2f | %.3f |" % (
+            _short(name), int(e["n"]), ns * 1e-6, e.get("MfmaFlopsF64", 0.0) / s / 1e12,
+            e.get("MfmaFlopsF64", 0.0) / s / 1e12 / FP64_MFMA_PEAK_TFLOPS, util,
+            e.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) / s / 1e12, hb / 1e9, hb / s / 1e12, hb / s / 8e12))
+    for ns, name, e, hb in rows:
+        tot["ns"] += ns
+        tot["fl"] += e.get("MfmaFlopsF64", 0.0)
+        tot["hb"] += hb
+        if any(k in name for k in FAMILY_KERNELS):
+            fam["ns"] += ns
+            fam["fl"] += e.get("MfmaFlopsF64", 0.0)
+            fam["hb"] += hb
+    lines += ["", "Matrix-core family (%s): %.1f ms of dispatch time per step, %.3e MFMA flops, %.2f TFLOP/s "
+              "(frac %.3f of the FP64 matrix peak), %.1f GB of HBM traffic (%.2f TB/s).  All kernels: %.1f ms."
+              % (", ".join(FAMILY_KERNELS), fam["ns"] * 1e-6, fam["fl"], fam["fl"] / (fam["ns"] * 1e-9) / 1e12,
+                 fam["fl"] / (fam["ns"] * 1e-9) / 1e12 / FP64_MFMA_PEAK_TFLOPS, fam["hb"] / 1e9,
+                 fam["hb"] / (fam["ns"] * 1e-9) / 1e12, tot["ns"] * 1e-6)]
+    path = os.path.join(HERE, "profiles", "kernel_frac_%s.md" % DEFAULT)
+    with open(path, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("wrote", path)
 
 
 def measured_traffic(launches_per_step):
     """HBM bytes per launch of the kernel family from the committed FETCH_SIZE /
     WRITE_SIZE counter runs (scaled by the copy-kernel calibration), or None
     when the kernel sources changed since the counters were taken."""
-    import hashlib
     try:
         rec = json.load(open(TRAFFIC))
     except (OSError, ValueError):
         return None
-    h = hashlib.sha256()
-    for f in FAMILY_SOURCES:
-        with open(os.path.join(HERE, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != rec.get("sources_sha256") or "family_hbm_bytes_per_step" not in rec:
+    if sources_sha256() != rec.get("sources_sha256") or "family_hbm_bytes_per_step" not in rec:
         return None
     # two counted runs of one and of two steps: their difference is one
     # steady-state step (the setup and the first step's autotuning cancel)
@@ -254,6 +455,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-instance batch measurement that the default run appends")
+    ap.add_argument("--no-rel-err", action="store_true",
+                    help="skip the untimed evaluations that measure the error against the dense oracle")
+    ap.add_argument("--traffic-record", metavar="DIR", default=None,
+                    help="(no GPU) write the family's HBM traffic record from the FETCH_SIZE / WRITE_SIZE counter "
+                         "runs under DIR (fetch_1, fetch_2, write_1, write_2, cal_fetch, cal_write)")
+    ap.add_argument("--frac-record", metavar="DIR", default=None,
+                    help="(no GPU) write the per-kernel fraction-of-peak table from the counter runs under DIR "
+                         "(mfma_1, mfma_2 and the traffic runs)")
     ap.add_argument("--hutch", type=int, default=0,
                     help="score traces by Hutchinson's estimator with this many probes instead of peeling")
     ap.add_argument("--peeling", choices=["weak", "strong"], default="weak",
@@ -267,6 +476,10 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device (the known-size run that scales the HBM counters)")
     args = ap.parse_args()
+    if args.traffic_record:
+        return traffic_record(args.traffic_record)
+    if args.frac_record:
+        return frac_record(args.frac_record)
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (--gpus %d refused)" % args.gpus,
               file=sys.stderr)
@@ -407,7 +620,8 @@ def main():
         "result": {"loglik": ell, "grad": g, "peel_cols": list(info.peel_cols)[:12],
                    "peel_rank": list(info.peel_rank)[:12]},
     }
-    if gold is not None and gold.get("g") is not None and args.precision == "fp64" and args.hutch <= 0:
+    if (gold is not None and gold.get("g") is not None and args.precision == "fp64" and args.hutch <= 0
+            and not args.no_rel_err):
         # untimed: errors against the dense oracle at the benchmark's eps_fact
         # and at eps_fact = eps / 1000 (the paper pairs eps_fact = eps_peel / 1000)
         out["rel_err"] = {
