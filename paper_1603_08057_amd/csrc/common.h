@@ -128,7 +128,7 @@ struct GemmDesc {
   const int* aidx;
   const int* bidx;
   const int* cidx;
-  const int* kidx;  // A(i, k) reads column kidx[k] of A (64 x 64 tile kernel only)
+  const int* kidx;  // A(i, k) reads column kidx[k] of A (the 128 x 128 kernels: k-contiguous A only)
   long long ars, acs, brs, bcs, crs, ccs;
   int M, N, K;
   double alpha, beta;

@@ -735,11 +735,15 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
 #pragma unroll
     for (int q = 0; q < 4; ++q) acc[m][q] = v4d{0, 0, 0, 0};
   double ra[8], rbv[8];
+  // k-contiguous A may read its columns through a map (A(i, kidx[k])); one
+  // index per thread and chunk
+  const int* __restrict__ kidx = AI ? nullptr : dg.kidx;
   auto fetch = [&](int k0) {
     if (full && k0 + 16 <= K) {
+      const int kA = AI ? 0 : (kidx ? kidx[k0 + a_k] : k0 + a_k);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        ra[r] = AI ? pa[(long long)(k0 + a_k + 2 * r) * astr] : pa[(long long)(16 * r) * astr + k0 + a_k];
+        ra[r] = AI ? pa[(long long)(k0 + a_k + 2 * r) * astr] : pa[(long long)(16 * r) * astr + kA];
         if (BJ) {
           const int kb = k0 + b_k + 2 * r;
           rbv[r] = pb[(long long)(BIDX ? bidx[kb] : kb) * bstr];
@@ -748,11 +752,13 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
         }
       }
     } else {
+      const int kc = k0 + a_k;
+      const int kA = AI ? 0 : (kc < K ? (kidx ? kidx[kc] : kc) : 0);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int ka = k0 + a_k + (AI ? 2 * r : 0);
         ra[r] = ((amask >> r) & 1u) && ka < K
-                    ? (AI ? pa[(long long)ka * astr] : pa[(long long)(16 * r) * astr + ka])
+                    ? (AI ? pa[(long long)ka * astr] : pa[(long long)(16 * r) * astr + kA])
                     : 0.0;
         const int kb = k0 + b_k + (BJ ? 2 * r : 0);
         double v = 0.0;
@@ -849,8 +855,14 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(const SplitRed* __re
 }
 
 static int big_class(const GemmDesc& d) {
-  if (d.kidx) return -1;
-  // rows-contiguous A may take a row map (one row pointer per thread)
+  // rows-contiguous A may take a row map (one row pointer per thread),
+  // k-contiguous A a column map
+  if (d.kidx) {
+    if (d.acs != 1 || d.aidx) return -1;
+    const bool bj = (d.bcs == 1), bk = (d.brs == 1 && d.bidx == nullptr);
+    if (!(bj || bk)) return -1;
+    return (bj ? 2 : 0) | ((bj && d.bidx) ? 1 : 0);
+  }
   const bool ai = d.ars == 1, ak = (d.acs == 1 && d.aidx == nullptr);
   const bool bj = (d.bcs == 1), bk = (d.brs == 1 && d.bidx == nullptr);
   if (!(ai || ak) || !(bj || bk)) return -1;
