@@ -190,6 +190,15 @@ def frac_record(root):
     cal_w = sum(e.get("WRITE_SIZE", 0.0) for n, e in _pmc_by_kernel(os.path.join(root, "cal_write")).items()
                 if "copyBuffer" in n)
     fscale, wscale = (1 << 30) / cal_f, (1 << 30) / cal_w  # bytes per counted KiB
+    # algorithmic work per kernel and step, booked by the library during the
+    # two-step counter run
+    work = {}
+    try:
+        with open(os.path.join(root, "mfma_2.json")) as fh:
+            line = [l for l in fh.read().splitlines() if l.startswith("{")][-1]
+        work = json.loads(line)["roofline"].get("kernel_work_per_step", {})
+    except (OSError, IndexError, ValueError, KeyError):
+        pass
     cmd = PMC_COMMAND.format(ctr="MfmaFlopsF64 MfmaUtil SQ_INSTS_VALU_FLOPS_FP64", run="mfma_S",
                              args=PMC_BENCH_ARGS.format(s="S"))
     lines = ["# Per-kernel fraction of peak: %s, one steady-state step" % DEFAULT, "",
@@ -206,8 +215,15 @@ def frac_record(root):
              "(MfmaUtil, weighted by duration).  HBM bytes are FETCH_SIZE and WRITE_SIZE scaled by what "
              "they read for a 1 GiB copy (x%.3f and x%.3f).  Peaks: FP64 matrix 78.6 TFLOP/s, HBM 8 TB/s, "
              "FP64 vector 78.6 TFLOP/s." % (fscale / 1024, wscale / 1024), "",
-             "| kernel | dispatches | ms | MFMA TFLOP/s | frac of 78.6 | MFMA util % | VALU FP64 TFLOP/s | "
-             "HBM GB | HBM TB/s | frac of 8 TB/s |", "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+             "Algorithmic columns: the work the library books per kernel (2 M N K flops per product, M N K "
+             "for a lower-triangle or triangular-operand product, so no zero triangle and no unused quadrant "
+             "counts; 2 c r (2 k + r) per box and column for the fused level steps; for the pivoting steps of "
+             "the interpolative decompositions 16 bytes per entry of the trailing block each step reads and "
+             "writes) over the kernel's own time; the same rate against the peak of the kernel's bound "
+             "(FP64 matrix for the products, HBM for the pivoting steps) is the frac.", "",
+             "| kernel | dispatches | ms | alg. TFLOP/s | alg. GB/s | frac (alg.) | MFMA TFLOP/s (hw) | "
+             "MFMA util % | VALU FP64 TFLOP/s | HBM GB | HBM TB/s |",
+             "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
     rows = []
     for name, e in mf.items():
         if e["n"] <= 0 or e["ns"] <= 0:
@@ -217,13 +233,23 @@ def frac_record(root):
     rows.sort(key=lambda r: -r[0])
     tot = {"ns": 0.0, "fl": 0.0, "hb": 0.0}
     fam = {"ns": 0.0, "fl": 0.0, "hb": 0.0, "util": 0.0, "n": 0}
+    alg = {"fl": 0.0}
     for ns, name, e, hb in rows[:28]:
         s = ns * 1e-9
         util = e.get("MfmaUtil_ns", 0.0) / ns
-        lines.append("| `%s` | %d | %.2f | %.2f | %.3f | %.1f | %.3f | %.2f | %.2f | %.3f |" % (
-            _short(name), int(e["n"]), ns * 1e-6, e.get("MfmaFlopsF64", 0.0) / s / 1e12,
-            e.get("MfmaFlopsF64", 0.0) / s / 1e12 / FP64_MFMA_PEAK_TFLOPS, util,
-            e.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) / s / 1e12, hb / 1e9, hb / s / 1e12, hb / s / 8e12))
+        w = work.get(_short(name))
+        afl = w["gflop"] * 1e9 / s / 1e12 if w else None
+        aby = w["gbyte"] * 1e9 / s / 1e9 if w else None
+        if w is None:
+            frac = "-"
+        elif "cpqr" in name:
+            frac = "%.3f" % (aby / 8000.0)
+        else:
+            frac = "%.3f" % (afl / FP64_MFMA_PEAK_TFLOPS)
+        lines.append("| `%s` | %d | %.2f | %s | %s | %s | %.2f | %.1f | %.3f | %.2f | %.2f |" % (
+            _short(name), int(e["n"]), ns * 1e-6, "%.2f" % afl if w else "-", "%.0f" % aby if w else "-", frac,
+            e.get("MfmaFlopsF64", 0.0) / s / 1e12, util, e.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) / s / 1e12,
+            hb / 1e9, hb / s / 1e12))
     for ns, name, e, hb in rows:
         tot["ns"] += ns
         tot["fl"] += e.get("MfmaFlopsF64", 0.0)
@@ -232,11 +258,16 @@ def frac_record(root):
             fam["ns"] += ns
             fam["fl"] += e.get("MfmaFlopsF64", 0.0)
             fam["hb"] += hb
-    lines += ["", "Matrix-core family (%s): %.1f ms of dispatch time per step, %.3e MFMA flops, %.2f TFLOP/s "
-              "(frac %.3f of the FP64 matrix peak), %.1f GB of HBM traffic (%.2f TB/s).  All kernels: %.1f ms."
-              % (", ".join(FAMILY_KERNELS), fam["ns"] * 1e-6, fam["fl"], fam["fl"] / (fam["ns"] * 1e-9) / 1e12,
-                 fam["fl"] / (fam["ns"] * 1e-9) / 1e12 / FP64_MFMA_PEAK_TFLOPS, fam["hb"] / 1e9,
-                 fam["hb"] / (fam["ns"] * 1e-9) / 1e12, tot["ns"] * 1e-6)]
+            w = work.get(_short(name))
+            alg["fl"] += w["gflop"] * 1e9 if w else 0.0
+    fs = fam["ns"] * 1e-9
+    lines += ["", "Matrix-core family (%s): %.1f ms of dispatch time per step; algorithmic %.3e flops, %.2f TFLOP/s "
+              "(frac %.3f of the FP64 matrix peak); the hardware's MFMA count %.3e flops, %.2f TFLOP/s (%.3f); "
+              "%.1f GB of HBM traffic (%.2f TB/s).  All kernels: %.1f ms."
+              % (", ".join(FAMILY_KERNELS), fam["ns"] * 1e-6, alg["fl"], alg["fl"] / fs / 1e12,
+                 alg["fl"] / fs / 1e12 / FP64_MFMA_PEAK_TFLOPS, fam["fl"], fam["fl"] / fs / 1e12,
+                 fam["fl"] / fs / 1e12 / FP64_MFMA_PEAK_TFLOPS, fam["hb"] / 1e9, fam["hb"] / fs / 1e12,
+                 tot["ns"] * 1e-6)]
     path = os.path.join(HERE, "profiles", "kernel_frac_%s.md" % DEFAULT)
     with open(path, "w") as fh:
         fh.write("\n".join(lines) + "\n")
@@ -563,6 +594,7 @@ def main():
     R.trace_enable(False)
     ms, flops, nbytes, launches, phases = R.trace_read(reset=False, phases=True)
     busy = R.trace_busy_ms()
+    kern = R.trace_kernels()
     R.trace_read(reset=True)
     ms_per_step = 1000.0 * elapsed / args.steps
     # phases are "<phase>" or "<phase>/<sweep direction><depth>": the JSON line
@@ -614,6 +646,11 @@ def main():
                      # (union of the launch intervals) and the rate over it
                      "busy_ms_per_step": busy / args.steps,
                      "achieved_over_busy_time": (flops / (busy * 1e-3) / 1e12) if busy > 0 else 0.0,
+                     # algorithmic work per kernel (host counts; the counter runs
+                     # divide it by each kernel's own time)
+                     "kernel_work_per_step": {k: {"gflop": v[0] / args.steps / 1e9, "gbyte": v[1] / args.steps / 1e9,
+                                                  "dispatches": v[2] / args.steps}
+                                              for k, v in sorted(kern.items())},
                      "phases": {k: {"ms_per_step": v[0] / args.steps,
                                     "tflops": (v[1] / (v[0] * 1e-3) / 1e12) if v[0] > 0 else 0.0}
                                 for k, v in sorted(phases.items())}},

@@ -336,6 +336,15 @@ rsf_status rsf_trace_busy(double* busy_ms);
  * Phases: factor, factor_rho, chol, sweep_solve, sweep_mult, sweep_sqrt,
  * peel_subtract, peel_gram, peel_lowrank. */
 rsf_status rsf_trace_phases(char* buf, size_t len);
+/* Algorithmic work booked per kernel while tracing was on, from host counts
+ * (no events): "kernel:flops:bytes:dispatches;..." (NUL-terminated, truncated
+ * to len - 1 characters).  The matrix-core kernels count as in rsf_trace_read
+ * (a lower-triangle or triangular-operand product M N K flops); the fused
+ * level steps 2 c r (2 k + r) flops per box of k skeleton and r redundant
+ * DOFs and c columns (2 c k r to multiply down); the pivoting steps of the
+ * interpolative decompositions 6 flops and 16 bytes per entry of the trailing
+ * block they read and write.  Cleared by rsf_trace_read with reset. */
+rsf_status rsf_trace_kernels(char* buf, size_t len);
 
 /* Message describing the last error on this thread ("" if none). */
 const char* rsf_last_error(void);

@@ -11,7 +11,7 @@ built library, or without a HIP device, the calls raise.
 """
 from ._lib import (  # noqa: F401
     MATERN12, MATERN32, MATERN52, RQ, MATERN32_ANISO, RQ_ANISO, PRECISIONS, RsfError, Factor, BatchedFactor, Options, GradInfo, library_path, load,
-    trace_enable, trace_read, trace_busy_ms, cond_mean, cond_sample,
+    trace_enable, trace_read, trace_busy_ms, trace_kernels, cond_mean, cond_sample,
 )
 from .autograd import loglik_fn  # noqa: F401
 from .mle import fit, FitResult  # noqa: F401

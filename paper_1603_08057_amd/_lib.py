@@ -87,6 +87,7 @@ def load():
         "rsf_trace_read": ([dp, dp, dp, C.POINTER(C.c_int64), C.c_int], C.c_int),
         "rsf_trace_phases": ([C.c_char_p, C.c_size_t], C.c_int),
         "rsf_trace_busy": ([dp], C.c_int),
+        "rsf_trace_kernels": ([C.c_char_p, C.c_size_t], C.c_int),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(lib, name)
@@ -164,6 +165,19 @@ def trace_busy_ms():
     out = C.c_double()
     _check(load().rsf_trace_busy(C.byref(out)))
     return out.value
+
+
+def trace_kernels():
+    """Algorithmic work per kernel while tracing was on: dict kernel ->
+    (flops, bytes, dispatches); read before trace_read(reset=True)."""
+    buf = C.create_string_buffer(1 << 16)
+    _check(load().rsf_trace_kernels(buf, 1 << 16))
+    out = {}
+    for item in buf.value.decode().split(";"):
+        if item:
+            name, f, b, n = item.rsplit(":", 3)
+            out[name] = (float(f), float(b), float(n))
+    return out
 
 
 def trace_read(reset=False, phases=False):

@@ -645,6 +645,15 @@ rsf_status rsf_trace_phases(char* buf, size_t len) {
   });
 }
 
+rsf_status rsf_trace_kernels(char* buf, size_t len) {
+  return guarded([&] {
+    RSF_CHECK(buf != nullptr && len > 0, RSF_E_INVALID, "null buffer");
+    const std::string t = trace_kernels();
+    std::strncpy(buf, t.c_str(), len - 1);
+    buf[len - 1] = 0;
+  });
+}
+
 rsf_status rsf_grad(rsf_factor f, const double* d_z, double eps_peel, uint64_t seed, double* g,
                     rsf_grad_info* info, void* stream) {
   return guarded([&] {

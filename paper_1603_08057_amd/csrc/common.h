@@ -219,6 +219,10 @@ void trace_read(double* ms, double* flops, double* bytes, long long* launches, b
 double trace_busy();
 // "tag:ms:flops;..." per call-site tag (read after trace_read)
 std::string trace_tags();
+// algorithmic work booked per kernel name while tracing is on (host counts,
+// no events): flops, bytes and dispatches; "name:flops:bytes:dispatches;..."
+void trace_kernel_work(const std::string& kernel, double flops, double bytes, double dispatches = 1.0);
+std::string trace_kernels();
 // The current phase name.
 std::string trace_current();
 // Times the launches issued on stream s while it is alive (HIP events) and

@@ -926,7 +926,9 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
     }
     int* piv = scr.make<int>(std::max<long long>(aoff[nb], 1));
     int* kout = scr.make<int>(nb);
-    bool id_big = false;
+    bool id_big = false, id_tall = false;
+    long long n_pivot = 0, n_update = 0;  // pivoting-step launches
+    std::vector<int> nh(nb);              // exact row counts (big form)
     {
       int maxa = 0;
       long long maxm = 0;
@@ -957,7 +959,6 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         int* ndone = done + nb;
         RSF_HIP(hipMemsetAsync(ndone, 0, sizeof(int), s));
         // exact row counts (the near field is compacted on the device)
-        std::vector<int> nh(nb);
         RSF_HIP(hipMemcpyAsync(nh.data(), ncnt, nb * sizeof(int), hipMemcpyDeviceToHost, s));
         RSF_HIP(hipStreamSynchronize(s));
         maxm = 0;
@@ -984,7 +985,10 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         for (int st = 0; st <= steps; ++st) {
           hipLaunchKernelGGL(cpqr_big_pivot_kernel, dim3(nb), dim3(256), 0, s, dj, st, h->eps, nprox, ndone);
           RSF_HIP(hipGetLastError());
+          ++n_pivot;
           if (st == steps) break;
+          ++n_update;
+          id_tall = maxm > big_maxm;
           if (maxm <= big_maxm)
             hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, ucols), dim3(256), (size_t)maxm * sizeof(double), s,
                                dj, st, nprox, cw);
@@ -1006,6 +1010,26 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
     RSF_HIP(hipMemcpyAsync(&fh, fail, sizeof(int), hipMemcpyDeviceToHost, s));
     RSF_HIP(hipStreamSynchronize(s));
     RSF_CHECK(fh == 0, RSF_E_NOT_SPD, "redundant block not positive definite at depth " + std::to_string(d + 1));
+    {
+      // algorithmic work of the pivoting steps: step s of a box with m rows
+      // and a columns reads and writes the trailing (m - s) x (a - s - 1)
+      // block once (a dot product, an update and the recomputed norm: 6 flops
+      // and 16 bytes per entry)
+      double fl = 0.0, by = 0.0;
+      for (int i = 0; i < nb; ++i) {
+        // sum over s < k of (m - s)(a - 1 - s), k <= min(m, a)
+        const double m = id_big ? (double)nh[i] + nprox : (double)mub[i], v = L.a[i] - 1.0, k = kh[i];
+        const double e = k * m * v - (m + v) * k * (k - 1.0) / 2.0 + (k - 1.0) * k * (2.0 * k - 1.0) / 6.0;
+        fl += 6.0 * e;
+        by += 16.0 * e;
+      }
+      if (!id_big) {
+        trace_kernel_work("cpqr_box_kernel", fl, by);
+      } else {
+        trace_kernel_work(id_tall ? "cpqr_big_update_tall_kernel" : "cpqr_big_update_kernel", fl, by, (double)n_update);
+        trace_kernel_work("cpqr_big_pivot_kernel", 0.0, 0.0, (double)n_pivot);
+      }
+    }
     if (id_big) {
       // T = R_11^-1 R_12 with the ranks now on the host
       std::vector<double*> Ab(nb);

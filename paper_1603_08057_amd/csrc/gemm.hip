@@ -1,5 +1,6 @@
 // Batched FP64 GEMM on the gfx950 matrix cores, device memory helpers and
 // fixed-order reductions.
+#include <array>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
@@ -581,6 +582,7 @@ struct GemmTrace {
   double busy = 0.0, last_busy = 0.0;  // union of the launch intervals (ms)
   long long launches = 0;
   std::map<std::string, double> tag_ms, tag_flops;
+  std::map<std::string, std::array<double, 3>> kern;  // flops, bytes, dispatches per kernel
 } g_trace;
 thread_local std::string t_tag = "other";
 thread_local bool t_paused = false;
@@ -597,6 +599,27 @@ void trace_push(hipEvent_t e0, hipEvent_t e1, const std::string& tag, double flo
 }  // namespace
 
 void trace_enable(bool on) { g_trace.on = on; }
+
+void trace_kernel_work(const std::string& kernel, double flops, double bytes, double dispatches) {
+  if (!tracing()) return;
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  auto& a = g_trace.kern[kernel];
+  a[0] += flops;
+  a[1] += bytes;
+  a[2] += dispatches;
+}
+
+std::string trace_kernels() {
+  std::lock_guard<std::mutex> lk(g_trace.mu);
+  std::string out;
+  for (auto& kv : g_trace.kern) {
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s%s:%.6g:%.6g:%.0f", out.empty() ? "" : ";", kv.first.c_str(), kv.second[0],
+             kv.second[1], kv.second[2]);
+    out += buf;
+  }
+  return out;
+}
 
 std::string trace_current() { return t_tag; }
 TracePause::TracePause() : was(t_paused) { t_paused = true; }
@@ -666,6 +689,7 @@ void trace_read(double* ms, double* flops, double* bytes, long long* launches, b
     g_trace.launches = 0;
     g_trace.tag_ms.clear();
     g_trace.tag_flops.clear();
+    g_trace.kern.clear();
   }
 }
 
@@ -839,15 +863,17 @@ struct SplitRed {
   double* C;
   const int* cidx;
   long long crs, ccs;
+  int lower;  // only the lower triangle (i >= j) is formed
 };
 
 __global__ __launch_bounds__(256) void splitk_reduce_kernel(const SplitRed* __restrict__ jobs) {
   const SplitRed J = jobs[blockIdx.y];
   const long long tot = J.M * J.N, blk = tot;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.x) {
+    const long long i = e % J.M, j = e / J.M;
+    if (J.lower && i < j) continue;
     double v = 0.0;
     for (int p = 0; p < J.s; ++p) v += J.W[p * blk + e];
-    const long long i = e % J.M, j = e / J.M;
     const long long row = J.cidx ? (long long)J.cidx[i] : i;
     double* c = J.C + row * J.crs + j * J.ccs;
     *c = (J.beta == 0.0) ? J.alpha * v : J.alpha * v + J.beta * *c;
@@ -877,15 +903,17 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   std::vector<int> probs[NG], toff[NG];
   for (auto& v : toff) v.push_back(0);
   std::vector<GemmDesc> live;
-  double flops = 0.0, bytes = 0.0;
+  double flops = 0.0, bytes = 0.0, gfl[NG] = {}, gby[NG] = {};
   for (const GemmDesc& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
     RSF_CHECK(!d.lower || d.M == d.N, RSF_E_INVALID, "lower-triangle GEMM needs a square C");
     RSF_CHECK(!(d.kidx && d.f32), RSF_E_INVALID, "column-mapped A needs the FP64 tile kernel");
     RSF_CHECK(!d.tri || (!d.aidx && !d.kidx && !d.f32), RSF_E_INVALID, "triangular A must be a plain matrix");
     // a triangular A (K = M) holds about half the products
-    flops += (d.lower || d.tri ? 1.0 : 2.0) * d.M * d.N * d.K;
-    bytes += 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
+    const double pf = (d.lower || d.tri ? 1.0 : 2.0) * d.M * d.N * d.K;
+    const double pb = 8.0 * ((double)d.M * d.K + (double)d.K * d.N + (d.beta != 0.0 ? 2.0 : 1.0) * d.M * d.N);
+    flops += pf;
+    bytes += pb;
     const int p = (int)live.size();
     live.push_back(d);
     const int cls = big_class(d);
@@ -905,6 +933,8 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     RSF_CHECK(toff[g].back() + nt < (1LL << 31), RSF_E_INVALID, "too many GEMM tiles in one launch");
     probs[g].push_back(p);
     toff[g].push_back(toff[g].back() + (int)nt);
+    gfl[g] += pf;
+    gby[g] += pb;
   }
   if (live.empty()) return;
   // Split-K for launch groups with fewer tiles than two per CU: problems with
@@ -923,12 +953,12 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
       const int p = probs[g][u];
       const GemmDesc d = live[p];
       const int sp = std::min(want, d.K / SPLIT_MIN_K);
-      if (d.lower || d.tri || sp < 2) continue;
+      if (d.tri || sp < 2) continue;
       const int kpart = (d.K + sp - 1) / sp / 16 * 16 + 16;
       const int nparts = (d.K + kpart - 1) / kpart;
       if (nparts < 2) continue;
       double* W = scr.make<double>((size_t)nparts * d.M * d.N);
-      reds.push_back(SplitRed{W, d.M, d.N, nparts, d.alpha, d.beta, d.C, d.cidx, d.crs, d.ccs});
+      reds.push_back(SplitRed{W, d.M, d.N, nparts, d.alpha, d.beta, d.C, d.cidx, d.crs, d.ccs, d.lower ? 1 : 0});
       for (int q = 0; q < nparts; ++q) {
         const int k0 = q * kpart;
         GemmDesc e = d;
@@ -1038,6 +1068,17 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     RSF_HIP(hipEventRecord(e1, s));
     // launches with FP32 products are booked under "<phase>/f32"
     trace_push(e0, e1, probs[9].empty() ? t_tag : t_tag + "/f32", flops, bytes, s);
+    for (int g = 0; g < NG; ++g) {
+      if (probs[g].empty()) continue;
+      const char* tf[2] = {"false", "true"};
+      const int c = g - 1;
+      const std::string name = g == 0 ? std::string("gemm_tiles_kernel")
+                               : g == 9 ? std::string("gemm_tiles_f32_kernel")
+                                        : std::string("gemm_big_kernel<") + tf[(c >> 2) & 1] + ", " +
+                                              tf[(c >> 1) & 1] + ", " + tf[c & 1] + ">";
+      trace_kernel_work(name, gfl[g], gby[g]);
+    }
+    for (const SplitRed& r : reds) trace_kernel_work("splitk_reduce_kernel", 0.0, 8.0 * (r.s + 2.0) * r.M * r.N);
   }
 }
 

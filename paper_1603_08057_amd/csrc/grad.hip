@@ -159,7 +159,7 @@ __global__ __launch_bounds__(256) void leaf_trace_kernel(const int* __restrict__
 // panel and the residual diagonal stay indexed by the original column, and a
 // row that has been chosen as pivot is marked in the residual diagonal.
 struct PpanelJob {
-  const double* Gw;  // c x c (ld c), the Gram matrix minus the previous panels' products
+  const double* Gw;  // c x c (ld c), the Gram matrix minus the previous panels' products (lower triangle)
   double* d;         // c residual diagonal; PIV_DONE marks chosen rows
   double* Lp;        // c x NB panel (ld c): this launch's columns of the factor
   int* piv;          // c pivots in order
@@ -262,6 +262,8 @@ __global__ __launch_bounds__(WGS) void ppanel_kernel(const PpanelJob* __restrict
     }
     __syncthreads();
     const double lss = sqrt(dp);
+    // column p of the symmetric matrix from its lower triangle: rows below p
+    // down the column, rows above p along row p
     const double* Gp = J.Gw + (long long)p * c;
 #pragma unroll
     for (int r = 0; r < RPT; ++r) {
@@ -271,7 +273,7 @@ __global__ __launch_bounds__(WGS) void ppanel_kernel(const PpanelJob* __restrict
         x = lss;
         dl[r] = PIV_DONE;
       } else if (dl[r] != PIV_DONE) {
-        double a0 = Gp[i], a1 = 0.0;
+        double a0 = i > p ? Gp[i] : J.Gw[(long long)i * c + p], a1 = 0.0;
 #pragma unroll
         for (int t = 0; t < NB; t += 2) {
           a0 -= lr[r][t] * lp[t];
@@ -883,9 +885,12 @@ struct Peeler {
         if (active.empty()) break;
       }
       std::vector<GemmDesc> tg;
-      for (int e : active)
-        tg.push_back(gemm_desc(c[e], c[e], NB, -1.0, colmaj(all[e].Lp, c[e]), colmajT(all[e].Lp, c[e]), 1.0,
-                               colmaj(Gw + goff[e], c[e])));
+      for (int e : active) {
+        GemmDesc gd = gemm_desc(c[e], c[e], NB, -1.0, colmaj(all[e].Lp, c[e]), colmajT(all[e].Lp, c[e]), 1.0,
+                                colmaj(Gw + goff[e], c[e]));
+        gd.lower = true;
+        tg.push_back(gd);
+      }
       gemm_batched(tg, ws, st);
     }
     RSF_CHECK(active.empty(), RSF_E_INVALID, "pivoted Cholesky did not terminate");
@@ -1270,8 +1275,11 @@ struct Peeler {
               const int rb = blocks[e].first, cbx = blocks[e].second, c = bc[idx];
               const long long ldy = (long long)ncol * C;
               const double* Yb = Y[op] + (long long)t.begin[rb] * ldy + (long long)qbox[cbx] * C;
-              g.push_back(gemm_desc(c, c, t.count[rb], 1.0, Mat{Yb, 1, ldy, nullptr}, panel(Yb, ldy), 0.0,
-                                    colmaj(Gram + goff[idx - e0], c)));
+              // the lower triangle only (the pivoted Cholesky reads no other entry)
+              GemmDesc gd = gemm_desc(c, c, t.count[rb], 1.0, Mat{Yb, 1, ldy, nullptr}, panel(Yb, ldy), 0.0,
+                                      colmaj(Gram + goff[idx - e0], c));
+              gd.lower = true;
+              g.push_back(gd);
             }
             {
               TraceTag tg("peel_gram");

@@ -306,6 +306,9 @@ static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int o
   const long long grid = ((long long)toff[L.nb] + 7) / 8 * 8;
   const dim3 g((unsigned)grid), blk(256);
   TraceLaunch tl(s, fl, by);
+  trace_kernel_work("box_sweep_kernel<" + std::to_string((int)op) + ", " +
+                        std::to_string(amax <= 64 ? 1 : amax <= 128 ? 2 : 4) + ">",
+                    fl, by);
   // the largest boxes need more than the default dynamic LDS limit of 64 KiB
   static bool lds_set[4][3] = {};
   const int max_lds = (BS_AMAX + 4) * BS_NCT * (int)sizeof(double);
