@@ -988,9 +988,14 @@ struct Peeler {
       for (const Blk& b : bl) {
         gj.push_back(GatherColsJob{b.Yb, ld, dpiv + poff[b.e], b.k, b.cnt, b.Yg});
         maxe = std::max(maxe, (long long)b.cnt * b.k);
+        // G = Yg^T Yg: the lower triangle (all the Cholesky reads)
         g1.push_back(gemm_desc(b.k, b.k, b.cnt, 1.0, colmajT(b.Yg, b.cnt), colmaj(b.Yg, b.cnt), 0.0, colmaj(b.G, b.k)));
+        g1.back().lower = true;
         cp.push_back(CholProblem{b.G, b.k, b.k, b.Li, b.k, nullptr});
-        g2.push_back(gemm_desc(b.cnt, b.k, b.k, 1.0, colmaj(b.Yg, b.cnt), colmajT(b.Li, b.k), 0.0, colmaj(b.U, b.cnt)));
+        // U = Yg Li^T, formed as U^T = Li Yg^T so that the triangular factor is
+        // the A operand (its zero upper triangle skipped)
+        g2.push_back(gemm_desc(b.k, b.cnt, b.k, 1.0, colmaj(b.Li, b.k), colmajT(b.Yg, b.cnt), 0.0, colmajT(b.U, b.cnt)));
+        g2.back().tri = 1;
       }
       GatherColsJob* dg = ms.make<GatherColsJob>(gj.size());
       upload(dg, gj, st);
@@ -1030,7 +1035,9 @@ struct Peeler {
       // W1 = Om_i A1, N1 = A1^T A1, N2 = A2 A2^T
       gb.push_back(gemm_desc(ci, k1, total, 1.0, Omi, colmaj(A1, total), 0.0, colmaj(W1, ci)));
       gb.push_back(gemm_desc(k1, k1, total, 1.0, colmajT(A1, total), colmaj(A1, total), 0.0, colmaj(N1, k1)));
+      gb.back().lower = true;
       gb.push_back(gemm_desc(k2, k2, total, 1.0, colmaj(A2, k2), colmajT(A2, k2), 0.0, colmaj(N2, k2)));
+      gb.back().lower = true;
       cn.push_back(CholProblem{N1, k1, k1, N1i, k1, nullptr});
       cn.push_back(CholProblem{N2, k2, k2, N2i, k2, nullptr});
       // T1 = W1^T Y_ij, T2 = T1 A2^T
