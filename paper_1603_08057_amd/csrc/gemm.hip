@@ -342,18 +342,42 @@ Scratch::~Scratch() {
 //
 // Operand layout of v_mfma_f64_16x16x4f64 (lane l, register r):
 //   A(row l % 16, k l / 16),  B(k l / 16, col l % 16),  D(row 4 r + l / 16, col l % 16).
-__device__ __forceinline__ void store_block(const GemmDesc& d, const v4d& acc, int ib, int jb,
-                                            int lane) {
+// A wave's 32 x 32 quarter (2 x 2 MFMA blocks) to C: the row map and every C
+// entry the update reads are loaded before any store, so the loads overlap.
+__device__ __forceinline__ void store_tile32(const GemmDesc& d, const v4d& a00, const v4d& a01, const v4d& a10,
+                                             const v4d& a11, int ib, int jb, int lane) {
+  double* cp[2][4][2];
+  bool ok[2][4][2];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int gi = ib + 4 * r + (lane >> 4);
-    const int gj = jb + (lane & 15);
-    if (gi < d.M && gj < d.N) {
-      const long long row = d.cidx ? (long long)d.cidx[gi] : (long long)gi;
-      double* c = d.C + row * d.crs + (long long)gj * d.ccs;
-      *c = (d.beta == 0.0) ? d.alpha * acc[r] : d.alpha * acc[r] + d.beta * *c;
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int gi = ib + 16 * h + 4 * r + (lane >> 4);
+      const bool rin = gi < d.M;
+      const long long row = d.cidx ? (rin ? (long long)d.cidx[gi] : 0LL) : (long long)gi;
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const int gj = jb + 16 * w + (lane & 15);
+        ok[h][r][w] = rin && gj < d.N;
+        cp[h][r][w] = d.C + row * d.crs + (long long)gj * d.ccs;
+      }
     }
-  }
+  double cv[2][4][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int w = 0; w < 2; ++w) cv[h][r][w] = (d.beta != 0.0 && ok[h][r][w]) ? *cp[h][r][w] : 0.0;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const double a = h == 0 ? (w == 0 ? a00[r] : a01[r]) : (w == 0 ? a10[r] : a11[r]);
+        if (ok[h][r][w]) *cp[h][r][w] = (d.beta == 0.0) ? d.alpha * a : d.alpha * a + d.beta * cv[h][r][w];
+      }
 }
 
 // The tile of workgroup `bid` in a launch over problems probs[0 .. np) whose
@@ -423,26 +447,35 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
     }
   }
   double ra[4], rbv[4];
+  // mapped K indices are loaded one chunk ahead of the operands they address
+  int aix[4], bix[4];
+  auto load_idx = [&](int k0) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ga = k0 + ka[r], gb = k0 + kb[r];
+      aix[r] = d.kidx ? (ga < d.K ? d.kidx[ga] : 0) : ga;
+      bix[r] = d.bidx ? (gb < d.K ? d.bidx[gb] : 0) : gb;
+    }
+  };
   // the next chunk is fetched into registers while the current one is multiplied
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gk = k0 + ka[r];
-      ra[r] = (arow[r] >= 0 && gk < d.K) ? d.A[arow[r] + (long long)(d.kidx ? d.kidx[gk] : gk) * d.acs] : 0.0;
+      ra[r] = (arow[r] >= 0 && gk < d.K) ? d.A[arow[r] + (long long)aix[r] * d.acs] : 0.0;
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gj = j0 + jb[r], gk = k0 + kb[r];
       double v = 0.0;
-      if (gj < d.N && gk < d.K) {
-        const long long row = d.bidx ? (long long)d.bidx[gk] : (long long)gk;
-        v = d.B[row * d.brs + (long long)gj * d.bcs];
-      }
+      if (gj < d.N && gk < d.K) v = d.B[(long long)bix[r] * d.brs + (long long)gj * d.bcs];
       rbv[r] = v;
     }
+    load_idx(k0 + 16);
   };
   // a triangular A reaches only the K chunks of the tile's rows
   const int kbeg = d.tri == 2 ? i0 : 0, kend = d.tri == 1 ? min(d.K, i0 + 64) : d.K;
+  load_idx(kbeg);
   fetch(kbeg);
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
     __syncthreads();
@@ -466,10 +499,7 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
       acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc11, 0, 0, 0);
     }
   }
-  store_block(d, acc00, i0 + rb, j0 + cb, lane);
-  store_block(d, acc01, i0 + rb, j0 + cb + 16, lane);
-  store_block(d, acc10, i0 + rb + 16, j0 + cb, lane);
-  store_block(d, acc11, i0 + rb + 16, j0 + cb + 16, lane);
+  store_tile32(d, acc00, acc01, acc10, acc11, i0 + rb, j0 + cb, lane);
 }
 
 // The 64 x 64 tile kernel in mixed precision: operands are rounded to FP32 as
@@ -760,24 +790,33 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
     for (int q = 0; q < 4; ++q) acc[m][q] = v4d{0, 0, 0, 0};
   double ra[8], rbv[8];
   // k-contiguous A may read its columns through a map (A(i, kidx[k])); one
-  // index per thread and chunk
+  // index per thread and chunk.  Mapped indices are loaded one chunk ahead of
+  // the operands they address, so that the operand loads do not wait for them.
   const int* __restrict__ kidx = AI ? nullptr : dg.kidx;
+  int kix = 0, bix[8];
+  auto load_idx = [&](int k0) {
+    if (!AI && kidx) kix = k0 + a_k < K ? kidx[k0 + a_k] : 0;
+    if (BJ && BIDX) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) bix[r] = k0 + b_k + 2 * r < K ? bidx[k0 + b_k + 2 * r] : 0;
+    }
+  };
   auto fetch = [&](int k0) {
     if (full && k0 + 16 <= K) {
-      const int kA = AI ? 0 : (kidx ? kidx[k0 + a_k] : k0 + a_k);
+      const int kA = AI ? 0 : (kidx ? kix : k0 + a_k);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         ra[r] = AI ? pa[(long long)(k0 + a_k + 2 * r) * astr] : pa[(long long)(16 * r) * astr + kA];
         if (BJ) {
           const int kb = k0 + b_k + 2 * r;
-          rbv[r] = pb[(long long)(BIDX ? bidx[kb] : kb) * bstr];
+          rbv[r] = pb[(long long)(BIDX ? bix[r] : kb) * bstr];
         } else {
           rbv[r] = pb[(long long)(16 * r) * bstr + k0 + b_k];
         }
       }
     } else {
       const int kc = k0 + a_k;
-      const int kA = AI ? 0 : (kc < K ? (kidx ? kidx[kc] : kc) : 0);
+      const int kA = AI ? 0 : (kc < K ? (kidx ? kix : kc) : 0);
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
         const int ka = k0 + a_k + (AI ? 2 * r : 0);
@@ -787,13 +826,15 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
         const int kb = k0 + b_k + (BJ ? 2 * r : 0);
         double v = 0.0;
         if (((bmask >> r) & 1u) && kb < K)
-          v = BJ ? pb[(long long)(BIDX ? bidx[kb] : kb) * bstr] : pb[(long long)(16 * r) * bstr + kb];
+          v = BJ ? pb[(long long)(BIDX ? bix[r] : kb) * bstr] : pb[(long long)(16 * r) * bstr + kb];
         rbv[r] = v;
       }
     }
+    load_idx(k0 + 16);
   };
   // a triangular A reaches only the K chunks of the tile's rows
   const int kbeg = dg.tri == 2 ? i0 : 0, kend = dg.tri == 1 ? min(K, i0 + BT) : K;
+  load_idx(kbeg);
   fetch(kbeg);
   const int lane = tid & 63, wave = tid >> 6;
   const int rb0 = (wave >> 1) * 64, cb0 = (wave & 1) * 64;
@@ -830,23 +871,36 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
   const int* __restrict__ cidx = dg.cidx;
   double* __restrict__ Cb = dg.C;
   const long long crs = dg.crs, ccs = dg.ccs;
+  // per 16-row block: the row map, then every C entry the update reads, are
+  // loaded together before any store (a load after a store to C would wait
+  // for the memory round trip of each entry in turn)
 #pragma unroll
-  for (int m = 0; m < 4; ++m)
+  for (int m = 0; m < 4; ++m) {
+    double* cp[4][4];
+    bool ok[4][4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gi = i0 + rb0 + m * 16 + 4 * r + (lane >> 4);
-      if (!full && gi >= M) continue;
-      const long long row = cidx ? (long long)cidx[gi] : (long long)gi;
-      double* crow = Cb + row * crs;
+      const bool rin = full || gi < M;
+      const long long row = cidx ? (rin ? (long long)cidx[gi] : 0LL) : (long long)gi;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int gj = j0 + cb0 + q * 16 + (lane & 15);
-        if (!full && gj >= N) continue;
-        double* c = crow + (long long)gj * ccs;
-        const double v = acc[m][q][r];
-        *c = (beta == 0.0) ? alpha * v : alpha * v + beta * *c;
+        ok[r][q] = rin && (full || gj < N);
+        cp[r][q] = Cb + row * crs + (long long)gj * ccs;
       }
     }
+    double cv[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cv[r][q] = (beta != 0.0 && ok[r][q]) ? *cp[r][q] : 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (ok[r][q]) *cp[r][q] = (beta == 0.0) ? alpha * acc[m][q][r] : alpha * acc[m][q][r] + beta * cv[r][q];
+  }
 }
 
 // layout class of a problem for the 128 x 128 kernels: bit 2 = A rows
@@ -1116,58 +1170,120 @@ struct DiagJob {
   double* logd;  // one value or null
 };
 
-// Cholesky of one diagonal block (nb <= 64) in LDS, written back in place
-// (zero above the diagonal), its log-diagonal sum and its inverse.
+// Cholesky of one diagonal block (nb <= 64), written back in place (zero
+// above the diagonal), its log-diagonal sum and its inverse.  Thread (row
+// i = tid mod 64, group g = tid / 64) keeps row i's entries in columns g,
+// g + 4, ..., g + 60 in registers: each elimination step takes two barriers
+// (the pivot, then the scaled column through LDS) and every thread updates
+// its own entries in the order of the steps.  The inverse X = L^-1 is formed
+// by forward substitution over the rows, column c of X on threads (c, g),
+// row l in the registers of group l mod 4; the dot products are split over
+// the four groups and summed in group order.
 __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* __restrict__ jobs, int* fail) {
-  __shared__ double B[64][65];
-  __shared__ double I[64][65];
+  __shared__ double col[64];      // column j of L during step j
+  __shared__ double Ls[64][65];   // L, for the inverse
+  __shared__ double part[2][4][64];
   __shared__ double dg[64];
+  __shared__ int bad;
   const DiagJob J = jobs[blockIdx.x];
-  const int nb = J.nb, tid = threadIdx.x;
-  // thread (row ti, column group tg): rows are lanes, the four waves split the columns
-  const int ti = tid & 63, tg = tid >> 6;
-  for (int c = tg; c < nb; c += 4)
-    if (ti < nb) B[ti][c] = J.A[(long long)c * J.lda + ti];
+  const int nb = J.nb, tid = threadIdx.x, i = tid & 63, g = tid >> 6;
+  double r[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int l = g + 4 * u;
+    r[u] = (i < nb && l <= i) ? J.A[(long long)l * J.lda + i] : 0.0;
+  }
+  if (tid == 0) bad = 0;
   __syncthreads();
   for (int j = 0; j < nb; ++j) {
-    const double d = B[j][j];
-    if (!(d > 0.0)) {
+    const int gj = j & 3, uj = j >> 2;
+    // the pivot's owner checks it and publishes its square root
+    if (g == gj && i == j) {
+      double d = 0.0;
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u == uj) d = r[u];
+      if (!(d > 0.0)) {
+        bad = 1;
+      } else {
+        const double sq = sqrt(d);
+        dg[j] = sq;
+        col[j] = sq;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+          if (u == uj) r[u] = sq;
+      }
+    }
+    __syncthreads();
+    if (bad) {
       if (tid == 0) *fail = 1;
       return;
     }
-    const double sq = sqrt(d);
-    // column j below the diagonal (the diagonal itself is written at the end)
-    if (tg == 0 && ti > j && ti < nb) B[ti][j] /= sq;
-    if (tid == 0) dg[j] = sq;
+    // column j below the diagonal
+    if (g == gj && i > j && i < nb) {
+      const double sq = dg[j];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u == uj) {
+          r[u] /= sq;
+          col[i] = r[u];
+        }
+    }
     __syncthreads();
-    if (ti > j && ti < nb) {
-      const double bij = B[ti][j];
-      for (int l = j + 1 + tg; l <= ti; l += 4) B[ti][l] -= bij * B[l][j];
+    // trailing entries (l, i) with j < l <= i
+    if (i > j && i < nb) {
+      const double lij = col[i];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        const int l = g + 4 * u;
+        if (l > j && l <= i) r[u] -= lij * col[l];
+      }
     }
     __syncthreads();
   }
-  if (tid < nb) B[tid][tid] = dg[tid];
-  __syncthreads();
+  // L to memory (zero above the diagonal) and to LDS
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int l = g + 4 * u;
+    if (i < nb && l < nb) {
+      const double v = l <= i ? r[u] : 0.0;
+      J.A[(long long)l * J.lda + i] = v;
+      Ls[i][l] = v;
+    }
+  }
   if (tid == 0 && J.logd) {
     double sm = 0.0;
-    for (int j = 0; j < nb; ++j) sm += log(B[j][j]);
+    for (int q = 0; q < nb; ++q) sm += log(dg[q]);
     *J.logd = 2.0 * sm;
   }
-  for (int c = tid; c < nb; c += 256) {
-    for (int i = 0; i < nb; ++i) I[i][c] = 0.0;
-    I[c][c] = 1.0 / B[c][c];
-    for (int i = c + 1; i < nb; ++i) {
-      double x = 0.0;
-      for (int l = c; l < i; ++l) x -= B[i][l] * I[l][c];
-      I[i][c] = x / B[i][i];
+  __syncthreads();
+  // X = L^-1: thread (c, g), rows g + 4 u of column c
+  const int c = i;
+  double x[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) x[u] = 0.0;
+  for (int row = 0; row < nb; ++row) {
+    double p = 0.0;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int l = g + 4 * u;
+      if (l < row) p += Ls[row][l] * x[u];
+    }
+    part[row & 1][g][c] = p;
+    __syncthreads();
+    if (g == (row & 3)) {
+      const double sm = ((part[row & 1][0][c] + part[row & 1][1][c]) + part[row & 1][2][c]) + part[row & 1][3][c];
+      const double v = ((row == c ? 1.0 : 0.0) - sm) / Ls[row][row];
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (u == (row >> 2)) x[u] = v;
     }
   }
-  __syncthreads();
-  for (int c = tg; c < nb; c += 4)
-    if (ti < nb) {
-      J.A[(long long)c * J.lda + ti] = (ti >= c) ? B[ti][c] : 0.0;
-      J.Dinv[(long long)c * 64 + ti] = I[ti][c];
-    }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int l = g + 4 * u;
+    if (c < nb && l < nb) J.Dinv[(long long)c * 64 + l] = x[u];
+  }
 }
 
 void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr, hipStream_t s) {
