@@ -271,14 +271,38 @@ __device__ double householder_step(double* A, long long ld, long long m, int s, 
 __device__ void reflect_columns(double* A, long long ld, long long m, int s, int j0, int j1,
                                 const double* v, double vtv, double* norms) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  // four rows per lane are loaded together (the stores of one group would
+  // otherwise hold back the loads of the next); the sums keep the row order
   for (int j = j0 + wave; j < j1; j += nw) {
     double* col = A + (long long)j * ld;
     double w = 0.0;
-    for (long long i = s + lane; i < m; i += 64) w += v[i - s] * col[i];
+    long long i = s + lane;
+    for (; i + 192 < m; i += 256) {
+      const double c0 = col[i], c1 = col[i + 64], c2 = col[i + 128], c3 = col[i + 192];
+      w += v[i - s] * c0;
+      w += v[i - s + 64] * c1;
+      w += v[i - s + 128] * c2;
+      w += v[i - s + 192] * c3;
+    }
+    for (; i < m; i += 64) w += v[i - s] * col[i];
     w = wave_sum(w);
     const double f = vtv > 0.0 ? 2.0 * w / vtv : 0.0;
     double sq = 0.0;
-    for (long long i = s + lane; i < m; i += 64) {
+    i = s + lane;
+    for (; i + 192 < m; i += 256) {
+      const double c0 = col[i], c1 = col[i + 64], c2 = col[i + 128], c3 = col[i + 192];
+      const double x0 = c0 - f * v[i - s], x1 = c1 - f * v[i - s + 64];
+      const double x2 = c2 - f * v[i - s + 128], x3 = c3 - f * v[i - s + 192];
+      col[i] = x0;
+      col[i + 64] = x1;
+      col[i + 128] = x2;
+      col[i + 192] = x3;
+      if (i > s) sq += x0 * x0;
+      sq += x1 * x1;
+      sq += x2 * x2;
+      sq += x3 * x3;
+    }
+    for (; i < m; i += 64) {
       const double x = col[i] - f * v[i - s];
       col[i] = x;
       if (i > s) sq += x * x;
