@@ -82,6 +82,8 @@ static void scatter_rows(const int* rows, long long nrows, const double* Tmp, in
 constexpr int BS_AMAX = 256;  // boxes up to 64 DOFs take 1 row block per wave, up to 128 take 2, up to 256 take 4
 constexpr int BS_NCT = 32;
 constexpr int BS_KC = 8;  // k-steps per batch of operand loads
+constexpr int BS_GB = 8;  // rows per batch of the gather and scatter loads
+constexpr int BS_RS = 256 / BS_NCT;  // rows a workgroup's gather covers per pass
 enum BoxOp { BS_SOLVE_UP = 0, BS_SOLVE_DOWN = 1, BS_MULT_UP = 2, BS_MULT_DOWN = 3 };
 
 // LDS position of (row, col) in a BS_NCT-wide buffer: odd rows swap their
@@ -151,6 +153,43 @@ __device__ __forceinline__ void box_epilogue(int M, const v4d (&acc)[RB][2], int
   }
 }
 
+// Y(rows[i], j0 + c) += acc entry (i, c) for i < M, c < ncol: per row block,
+// the row indices, then the eight Y entries a lane updates, are loaded before
+// any store.
+template <int RB>
+__device__ __forceinline__ void add_rows_epilogue(int M, const v4d (&acc)[RB][2], int wave, int lane,
+                                                  const int* __restrict__ rows, double* __restrict__ Y, long long ld,
+                                                  int j0, int ncol) {
+#pragma unroll
+  for (int p = 0; p < RB; ++p) {
+    const int rb = 16 * (wave + 4 * p);
+    if (rb >= M) continue;
+    double* yp[4][2];
+    bool ok[4][2];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = rb + 4 * v + (lane >> 4);
+      const long long g = i < M ? (long long)rows[i] : 0LL;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int c = 16 * q + (lane & 15);
+        ok[v][q] = i < M && c < ncol;
+        yp[v][q] = Y + g * ld + j0 + c;
+      }
+    }
+    double yv[4][2];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < 2; ++q) yv[v][q] = ok[v][q] ? *yp[v][q] : 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (ok[v][q]) *yp[v][q] = yv[v][q] + acc[p][q][v];
+  }
+}
+
 template <int OP, int RB>
 __global__ __launch_bounds__(256, RB == 1 ? 6 : RB == 2 ? 4 : 2) void box_sweep_kernel(const BoxRec* __restrict__ boxes, int nbox,
                                                         const int* __restrict__ tile_off,
@@ -192,15 +231,26 @@ __global__ __launch_bounds__(256, RB == 1 ? 6 : RB == 2 ? 4 : 2) void box_sweep_
   const double* W = Wm + b.t_off;  // k x r
   const double* L = Lm + b.l_off;  // r x r
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // gather [X_S; X_R] (Y_S in place of X_S for the multiply down-sweep), zero rows up to a + 4
-  for (int e = tid; e < (a + 4) * BS_NCT; e += 256) {
-    const int row = e / BS_NCT, col = e - row * BS_NCT;
-    double v = 0.0;
-    if (row < a && col < ncol) {
-      const long long g = row < k ? Sb[row] : Rb[row - k];
-      v = (OP == BS_MULT_DOWN && row < k) ? Y[g * ld + j0 + col] : X[g * ld + j0 + col];
+  // gather [X_S; X_R] (Y_S in place of X_S for the multiply down-sweep), zero
+  // rows up to a + 4.  Thread (row r0 + BS_RS u, column tid mod BS_NCT): the
+  // row indices, then the values of BS_GB rows are loaded together.
+  const int gcol = tid % BS_NCT, r0 = tid / BS_NCT;
+  for (int rb = r0; rb < a + 4; rb += BS_RS * BS_GB) {
+    long long g[BS_GB];
+    double v[BS_GB];
+#pragma unroll
+    for (int u = 0; u < BS_GB; ++u) {
+      const int row = rb + BS_RS * u;
+      g[u] = (row < a && gcol < ncol) ? (long long)(row < k ? Sb[row] : Rb[row - k]) : -1LL;
     }
-    Xl[bsi(row, col)] = v;
+#pragma unroll
+    for (int u = 0; u < BS_GB; ++u) {
+      const int row = rb + BS_RS * u;
+      v[u] = g[u] < 0 ? 0.0 : ((OP == BS_MULT_DOWN && row < k) ? Y : X)[g[u] * ld + j0 + gcol];
+    }
+#pragma unroll
+    for (int u = 0; u < BS_GB; ++u)
+      if (rb + BS_RS * u < a + 4) Xl[bsi(rb + BS_RS * u, gcol)] = v[u];
   }
   __syncthreads();
   v4d acc[RB][2];
@@ -240,9 +290,7 @@ __global__ __launch_bounds__(256, RB == 1 ? 6 : RB == 2 ? 4 : 2) void box_sweep_
     zero_acc(acc);
     box_mm(r, r, [&](int i, int q) { return L[i + (long long)q * r]; }, Xl, k, acc, wave, lane);
     box_mm(r, k, [&](int i, int q) { return W[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
-    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) {
-      if (c < ncol) Y[(long long)Rb[i] * ld + j0 + c] += v;
-    });
+    add_rows_epilogue(r, acc, wave, lane, Rb, Y, ld, j0, ncol);
   } else {
     // Y_S += X_sr X_R  (Y_S in the S rows)
     zero_acc(acc);
@@ -252,22 +300,22 @@ __global__ __launch_bounds__(256, RB == 1 ? 6 : RB == 2 ? 4 : 2) void box_sweep_
     // Y_R += T^T Y_S
     zero_acc(acc);
     box_mm(r, k, [&](int i, int q) { return T[q + (long long)i * k]; }, Xl, 0, acc, wave, lane);
-    box_epilogue(r, acc, wave, lane, [&](int i, int c, double v) {
-      if (c < ncol) Y[(long long)Rb[i] * ld + j0 + c] += v;
-    });
+    add_rows_epilogue(r, acc, wave, lane, Rb, Y, ld, j0, ncol);
   }
-  // scatter the changed rows back
-  if (OP == BS_SOLVE_UP || OP == BS_SOLVE_DOWN) {
-    for (int e = tid; e < a * BS_NCT; e += 256) {
-      const int row = e / BS_NCT, col = e - row * BS_NCT;
-      if (col >= ncol) continue;
-      X[(long long)(row < k ? Sb[row] : Rb[row - k]) * ld + j0 + col] = Xl[bsi(row, col)];
-    }
-  } else {
-    double* dst = OP == BS_MULT_UP ? X : Y;
-    for (int e = tid; e < k * BS_NCT; e += 256) {
-      const int row = e / BS_NCT, col = e - row * BS_NCT;
-      if (col < ncol) dst[(long long)Sb[row] * ld + j0 + col] = Xl[bsi(row, col)];
+  // scatter the changed rows back (the row indices of BS_GB rows loaded together)
+  {
+    const int nrow = (OP == BS_SOLVE_UP || OP == BS_SOLVE_DOWN) ? a : k;
+    double* dst = OP == BS_MULT_DOWN ? Y : X;
+    for (int rb = r0; rb < nrow; rb += BS_RS * BS_GB) {
+      long long g[BS_GB];
+#pragma unroll
+      for (int u = 0; u < BS_GB; ++u) {
+        const int row = rb + BS_RS * u;
+        g[u] = (row < nrow && gcol < ncol) ? (long long)(row < k ? Sb[row] : Rb[row - k]) : -1LL;
+      }
+#pragma unroll
+      for (int u = 0; u < BS_GB; ++u)
+        if (g[u] >= 0) dst[g[u] * ld + j0 + gcol] = Xl[bsi(rb + BS_RS * u, gcol)];
     }
   }
 }
