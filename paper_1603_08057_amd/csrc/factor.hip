@@ -229,11 +229,28 @@ __device__ double wg_sum(double v, double* red) {
 __device__ double householder_step(double* A, long long ld, long long m, int s, int p, int* piv,
                                    double* vbuf, double* red) {
   const int tid = threadIdx.x;
+  const long long bd = blockDim.x;
+  // every loop loads four entries per thread before it stores any (a store
+  // would otherwise hold back the next load's round trip); sums keep the order
   if (p != s) {
-    for (long long i = tid; i < m; i += blockDim.x) {
-      const double t = A[(long long)s * ld + i];
-      A[(long long)s * ld + i] = A[(long long)p * ld + i];
-      A[(long long)p * ld + i] = t;
+    double* cs = A + (long long)s * ld;
+    double* cq = A + (long long)p * ld;
+    for (long long i = tid; i < m; i += 4 * bd) {
+      double ts[4], tq[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long ii = i + u * bd;
+        ts[u] = ii < m ? cs[ii] : 0.0;
+        tq[u] = ii < m ? cq[ii] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const long long ii = i + u * bd;
+        if (ii < m) {
+          cs[ii] = tq[u];
+          cq[ii] = ts[u];
+        }
+      }
     }
     if (tid == 0) {
       const int t = piv[s];
@@ -244,10 +261,16 @@ __device__ double householder_step(double* A, long long ld, long long m, int s, 
   __syncthreads();
   double* col = A + (long long)s * ld;
   double ss = 0.0;
-  for (long long i = s + tid; i < m; i += blockDim.x) {
-    const double x = col[i];
-    vbuf[i - s] = x;
-    ss += x * x;
+  for (long long i = s + tid; i < m; i += 4 * bd) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = i + u * bd < m ? col[i + u * bd] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * bd < m) {
+        vbuf[i + u * bd - s] = x[u];
+        ss += x[u] * x[u];
+      }
   }
   const double sigma2 = wg_sum(ss, red);
   const double sigma = sqrt(sigma2);
@@ -256,7 +279,14 @@ __device__ double householder_step(double* A, long long ld, long long m, int s, 
   const double v0 = x0 - alpha;
   // v^T v = sigma^2 - x0^2 + v0^2 summed as in a direct dot product
   double vv = 0.0;
-  for (long long i = s + 1 + tid; i < m; i += blockDim.x) vv += vbuf[i - s] * vbuf[i - s];
+  for (long long i = s + 1 + tid; i < m; i += 4 * bd) {
+    double x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) x[u] = i + u * bd < m ? vbuf[i + u * bd - s] : 0.0;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * bd < m) vv += x[u] * x[u];
+  }
   const double vtv = wg_sum(vv, red) + v0 * v0;
   __syncthreads();
   if (tid == 0) vbuf[0] = v0;
