@@ -457,10 +457,52 @@ __global__ __launch_bounds__(256) void cpqr_big_pivot_kernel(const CpqrJob* __re
 
 constexpr int BIG_MAXM = 12288;
 
+// reflect_columns with each column held in registers between the dot product
+// and the update (rows s + lane + 64 u, u < R; every row below m - s <= 64 R):
+// one read and one write per entry, every load of a column in flight at once,
+// and the same operations in the same order.
+template <int R>
+__device__ void reflect_columns_reg(double* A, long long ld, long long m, int s, int j0, int j1,
+                                    const double* v, double vtv, double* norms) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int j = j0 + wave; j < j1; j += nw) {
+    double* col = A + (long long)j * ld;
+    double x[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const long long i = s + lane + 64LL * u;
+      x[u] = i < m ? col[i] : 0.0;
+    }
+    double w = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const long long i = s + lane + 64LL * u;
+      if (i < m) w += v[i - s] * x[u];
+    }
+    w = wave_sum(w);
+    const double f = vtv > 0.0 ? 2.0 * w / vtv : 0.0;
+    double sq = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const long long i = s + lane + 64LL * u;
+      if (i < m) {
+        const double y = x[u] - f * v[i - s];
+        col[i] = y;
+        if (i > s) sq += y * y;
+      }
+    }
+    sq = wave_sum(sq);
+    if (lane == 0) norms[j] = sqrt(sq);
+  }
+}
+
 // One workgroup per cw columns of a box (cw = 4, 8 or 16: levels with few
 // boxes take narrow chunks so that one step still spreads over the CUs).
 // The reflector is staged in dynamic LDS sized by the level's longest
 // compression matrix (so short ones leave room for many workgroups per CU).
+// R > 0: the columns' rows below the step stay in registers in boxes where
+// they are at most 64 R (taller boxes take the two-pass form).
+template <int R>
 __global__ __launch_bounds__(256) void cpqr_big_update_kernel(const CpqrJob* __restrict__ jobs,
                                                                int s, int nprox, int cw) {
   extern __shared__ double v[];
@@ -471,7 +513,10 @@ __global__ __launch_bounds__(256) void cpqr_big_update_kernel(const CpqrJob* __r
   const long long m = (long long)*J.ncnt + nprox;
   for (long long i = s + threadIdx.x; i < m; i += blockDim.x) v[i - s] = J.v[i - s];
   __syncthreads();
-  reflect_columns(J.A, J.ld, m, s, j0, j1, v, J.scal[0], J.norms);
+  if (R > 0 && m - s <= 64LL * R)
+    reflect_columns_reg<(R > 0 ? R : 1)>(J.A, J.ld, m, s, j0, j1, v, J.scal[0], J.norms);
+  else
+    reflect_columns(J.A, J.ld, m, s, j0, j1, v, J.scal[0], J.norms);
 }
 
 // The same for compression matrices taller than BIG_MAXM rows: the reflector
@@ -1019,8 +1064,11 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
         for (int i = 0; i < nb; ++i) maxm = std::max<long long>(maxm, (long long)nh[i] + nprox);
         static bool upd_lds = false;
         if (!upd_lds) {
-          RSF_HIP(hipFuncSetAttribute((const void*)cpqr_big_update_kernel,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, BIG_MAXM * (int)sizeof(double)));
+          for (const void* kf : {(const void*)cpqr_big_update_kernel<16>,
+                                 (const void*)cpqr_big_update_kernel<32>, (const void*)cpqr_big_update_kernel<48>,
+                                 (const void*)cpqr_big_update_kernel<64>, (const void*)cpqr_big_update_kernel<80>,
+                                 (const void*)cpqr_big_update_kernel<96>})
+            RSF_HIP(hipFuncSetAttribute(kf, hipFuncAttributeMaxDynamicSharedMemorySize, BIG_MAXM * (int)sizeof(double)));
           upd_lds = true;
         }
         if (stats) {
@@ -1043,10 +1091,27 @@ void build_factor(rsf_factor_s* h, FactorData& F, int mult, hipStream_t s) {
           if (st == steps) break;
           ++n_update;
           id_tall = maxm > big_maxm;
-          if (maxm <= big_maxm)
-            hipLaunchKernelGGL(cpqr_big_update_kernel, dim3(nb, ucols), dim3(256), (size_t)maxm * sizeof(double), s,
-                               dj, st, nprox, cw);
-          else
+          if (maxm <= big_maxm) {
+            // the register form for the shortest bucket that holds the rows below
+            // the step (the largest bucket when none does: taller boxes fall back)
+            const long long below = maxm - st;
+            const dim3 ug(nb, ucols);
+            const size_t lds = (size_t)maxm * sizeof(double);
+#define RSF_UPD(RV) hipLaunchKernelGGL(cpqr_big_update_kernel<RV>, ug, dim3(256), lds, s, dj, st, nprox, cw)
+            if (below <= 64 * 16)
+              RSF_UPD(16);
+            else if (below <= 64 * 32)
+              RSF_UPD(32);
+            else if (below <= 64 * 48)
+              RSF_UPD(48);
+            else if (below <= 64 * 64)
+              RSF_UPD(64);
+            else if (below <= 64 * 80)
+              RSF_UPD(80);
+            else
+              RSF_UPD(96);
+#undef RSF_UPD
+          } else
             hipLaunchKernelGGL(cpqr_big_update_tall_kernel, dim3(nb, ucols), dim3(256), 0, s, dj, st, nprox, cw);
           RSF_HIP(hipGetLastError());
           if ((st & 15) == 15) {
