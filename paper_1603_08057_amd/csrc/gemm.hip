@@ -384,18 +384,9 @@ __device__ __forceinline__ void store_tile32(const GemmDesc& d, const v4d& a00, 
 // tiles are numbered consecutively (toff: prefix counts): row-major over the
 // tile grid, or over its lower triangle (b <= a) for lower problems.
 // Returns (problem, tile row, tile column).
-__device__ __forceinline__ int3 find_tile(const GemmDesc* __restrict__ descs, const int* __restrict__ probs,
-                                          const int* __restrict__ toff, int np, int ts, int bid) {
-  int lo = 0, hi = np;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (toff[mid] <= bid)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const int p = probs[lo], l = bid - toff[lo];
-  const GemmDesc& d = descs[p];
+// (tile row, tile column) of tile l of a problem: row-major over its tile grid,
+// or over the grid's lower triangle (b <= a) for lower problems.
+__device__ __forceinline__ int2 tile_of(const GemmDesc& d, int l, int ts) {
   int a, b;
   if (d.lower) {
     a = (int)((sqrt(8.0 * l + 1.0) - 1.0) * 0.5);
@@ -407,17 +398,52 @@ __device__ __forceinline__ int3 find_tile(const GemmDesc* __restrict__ descs, co
     a = l / tn;
     b = l - a * tn;
   }
-  return make_int3(p, a, b);
+  return make_int2(a, b);
 }
 
-__global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restrict__ descs,
-                                                          const int* __restrict__ probs,
-                                                          const int* __restrict__ toff, int np) {
+__device__ __forceinline__ int3 find_tile(const GemmDesc* __restrict__ descs, const int* __restrict__ probs,
+                                          const int* __restrict__ toff, int np, int ts, int bid) {
+  int lo = 0, hi = np;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (toff[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int p = probs[lo];
+  const int2 ab = tile_of(descs[p], bid - toff[lo], ts);
+  return make_int3(p, ab.x, ab.y);
+}
+
+// Launch groups of at most PACK_NP problems pass their descriptors and tile
+// prefix counts in the kernel arguments (read in place from the argument
+// segment), so that the launch needs no upload.
+constexpr int PACK_NP = 20;
+struct GemmPack {
+  GemmDesc d[PACK_NP];
+  int toff[PACK_NP + 1];
+  int np;
+};
+
+__device__ __forceinline__ int3 find_tile_pack(const GemmPack& pk, int ts, int bid) {
+  int lo = 0, hi = pk.np;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (pk.toff[mid] <= bid)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const int2 ab = tile_of(pk.d[lo], bid - pk.toff[lo], ts);
+  return make_int3(lo, ab.x, ab.y);
+}
+
+__device__ __forceinline__ void tile64(const GemmDesc& dref, int ti, int tj) {
+  const GemmDesc d = dref;
   __shared__ double As[16][66];  // As[k][i]
   __shared__ double Bs[16][66];  // Bs[k][j]
-  const int3 t = find_tile(descs, probs, toff, np, 64, blockIdx.x);
-  const GemmDesc d = descs[t.x];
-  const int i0 = t.y * 64, j0 = t.z * 64;
+  const int i0 = ti * 64, j0 = tj * 64;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int rb = (wave >> 1) * 32, cb = (wave & 1) * 32;
   v4d acc00 = {0, 0, 0, 0}, acc01 = acc00, acc10 = acc00, acc11 = acc00;
@@ -500,6 +526,18 @@ __global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restr
     }
   }
   store_tile32(d, acc00, acc01, acc10, acc11, i0 + rb, j0 + cb, lane);
+}
+
+__global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restrict__ descs,
+                                                          const int* __restrict__ probs,
+                                                          const int* __restrict__ toff, int np) {
+  const int3 t = find_tile(descs, probs, toff, np, 64, blockIdx.x);
+  tile64(descs[t.x], t.y, t.z);
+}
+
+__global__ __launch_bounds__(256) void gemm_tiles_kernel_p(const GemmPack pk) {
+  const int3 t = find_tile_pack(pk, 64, blockIdx.x);
+  tile64(pk.d[t.x], t.y, t.z);
 }
 
 // The 64 x 64 tile kernel in mixed precision: operands are rounded to FP32 as
@@ -751,15 +789,11 @@ std::string trace_tags() {
 constexpr int BT = 128;
 
 template <bool AI, bool BJ, bool BIDX>
-__global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
-                                                           const int* __restrict__ probs,
-                                                           const int* __restrict__ toff, int np) {
-  __shared__ double As[16][BT + 4];
-  __shared__ double Bs[16][BT + 4];
-  const int3 t = find_tile(descs, probs, toff, np, BT, blockIdx.x);
-  const GemmDesc& dg = descs[t.x];
+__device__ __forceinline__ void big_tile(const GemmDesc& dg, int ti, int tj) {
+  __shared__ double As[16][BT + 5];  // odd row stride: conflict-free column writes
+  __shared__ double Bs[16][BT + 5];
   const int M = dg.M, N = dg.N, K = dg.K;
-  const int i0 = t.y * BT, j0 = t.z * BT;
+  const int i0 = ti * BT, j0 = tj * BT;
   const int tid = threadIdx.x;
   const bool full = (i0 + BT <= M) && (j0 + BT <= N);
   // fetch geometry (see the layout note above):
@@ -901,6 +935,20 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
       for (int q = 0; q < 4; ++q)
         if (ok[r][q]) *cp[r][q] = (beta == 0.0) ? alpha * acc[m][q][r] : alpha * acc[m][q][r] + beta * cv[r][q];
   }
+}
+
+template <bool AI, bool BJ, bool BIDX>
+__global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
+                                                           const int* __restrict__ probs,
+                                                           const int* __restrict__ toff, int np) {
+  const int3 t = find_tile(descs, probs, toff, np, BT, blockIdx.x);
+  big_tile<AI, BJ, BIDX>(descs[t.x], t.y, t.z);
+}
+
+template <bool AI, bool BJ, bool BIDX>
+__global__ __launch_bounds__(256, 2) void gemm_big_kernel_p(const GemmPack pk) {
+  const int3 t = find_tile_pack(pk, BT, blockIdx.x);
+  big_tile<AI, BJ, BIDX>(pk.d[t.x], t.y, t.z);
 }
 
 // layout class of a problem for the 128 x 128 kernels: bit 2 = A rows
@@ -1066,26 +1114,39 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
               probs[g].size(), toff[g].back(), fl * 1e-9, sm / np, sn / np, sk / np);
     }
   }
-  std::vector<int> cat;
-  size_t po[NG], to[NG];
-  for (int g = 0; g < NG; ++g) {
-    po[g] = cat.size();
-    cat.insert(cat.end(), probs[g].begin(), probs[g].end());
-    to[g] = cat.size();
-    cat.insert(cat.end(), toff[g].begin(), toff[g].end());
+  // launch groups of at most PACK_NP problems pass them in the kernel
+  // arguments when no group needs more (and no split-K sums are queued);
+  // otherwise every table goes up in one copy
+  bool packed = reds.empty();
+  for (int g = 0; g < NG; ++g)
+    if (!probs[g].empty() && (g == 9 || probs[g].size() > (size_t)PACK_NP)) packed = false;
+  size_t po[NG] = {}, to[NG] = {};
+  size_t b_desc = 0, b_cat = 0;
+  char* dblk = nullptr;
+  GemmDesc* dd = nullptr;
+  int* dc = nullptr;
+  if (!packed) {
+    std::vector<int> cat;
+    for (int g = 0; g < NG; ++g) {
+      po[g] = cat.size();
+      cat.insert(cat.end(), probs[g].begin(), probs[g].end());
+      to[g] = cat.size();
+      cat.insert(cat.end(), toff[g].begin(), toff[g].end());
+    }
+    // descriptors, problem / tile tables and split-K jobs go up in one copy
+    auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+    b_desc = al(live.size() * sizeof(GemmDesc));
+    b_cat = al(cat.size() * sizeof(int));
+    const size_t b_red = reds.size() * sizeof(SplitRed);
+    std::vector<char> stage(b_desc + b_cat + b_red);
+    std::memcpy(stage.data(), live.data(), live.size() * sizeof(GemmDesc));
+    std::memcpy(stage.data() + b_desc, cat.data(), cat.size() * sizeof(int));
+    if (b_red) std::memcpy(stage.data() + b_desc + b_cat, reds.data(), b_red);
+    dblk = scr.make<char>(stage.size());
+    upload_bytes(dblk, stage.data(), stage.size(), s);
+    dd = reinterpret_cast<GemmDesc*>(dblk);
+    dc = reinterpret_cast<int*>(dblk + b_desc);
   }
-  // descriptors, problem / tile tables and split-K jobs go up in one copy
-  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t b_desc = al(live.size() * sizeof(GemmDesc)), b_cat = al(cat.size() * sizeof(int));
-  const size_t b_red = reds.size() * sizeof(SplitRed);
-  std::vector<char> stage(b_desc + b_cat + b_red);
-  std::memcpy(stage.data(), live.data(), live.size() * sizeof(GemmDesc));
-  std::memcpy(stage.data() + b_desc, cat.data(), cat.size() * sizeof(int));
-  if (b_red) std::memcpy(stage.data() + b_desc + b_cat, reds.data(), b_red);
-  char* dblk = scr.make<char>(stage.size());
-  upload_bytes(dblk, stage.data(), stage.size(), s);
-  GemmDesc* dd = reinterpret_cast<GemmDesc*>(dblk);
-  int* dc = reinterpret_cast<int*>(dblk + b_desc);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   const bool traced = tracing();
   if (traced) {
@@ -1094,21 +1155,47 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     RSF_HIP(hipEventRecord(e0, s));
   }
   auto grid = [&](int g) { return dim3((unsigned)toff[g].back()); };
-  auto args = [&](int g) { return std::make_tuple(dc + po[g], dc + to[g], (int)probs[g].size()); };
+  if (packed) {
+    auto pack = [&](int g) {
+      GemmPack pk;
+      pk.np = (int)probs[g].size();
+      for (int u = 0; u < pk.np; ++u) {
+        pk.d[u] = live[probs[g][u]];
+        pk.toff[u] = toff[g][u];
+      }
+      pk.toff[pk.np] = toff[g][pk.np];
+      return pk;
+    };
+#define RSF_PLAUNCH(KERNEL, g)                                        \
+  if (!probs[g].empty()) {                                            \
+    const GemmPack pk_ = pack(g);                                     \
+    hipLaunchKernelGGL(KERNEL, grid(g), dim3(256), 0, s, pk_);        \
+  }
+    RSF_PLAUNCH((gemm_big_kernel_p<true, true, true>), 1 + 7)
+    RSF_PLAUNCH((gemm_big_kernel_p<true, true, false>), 1 + 6)
+    RSF_PLAUNCH((gemm_big_kernel_p<true, false, false>), 1 + 4)
+    RSF_PLAUNCH((gemm_big_kernel_p<false, true, true>), 1 + 3)
+    RSF_PLAUNCH((gemm_big_kernel_p<false, true, false>), 1 + 2)
+    RSF_PLAUNCH((gemm_big_kernel_p<false, false, false>), 1 + 0)
+    RSF_PLAUNCH(gemm_tiles_kernel_p, 0)
+#undef RSF_PLAUNCH
+  } else {
+    auto args = [&](int g) { return std::make_tuple(dc + po[g], dc + to[g], (int)probs[g].size()); };
 #define RSF_LAUNCH(KERNEL, g)                                                                        \
   if (!probs[g].empty()) {                                                                           \
     auto a_ = args(g);                                                                               \
     hipLaunchKernelGGL(KERNEL, grid(g), dim3(256), 0, s, dd, std::get<0>(a_), std::get<1>(a_), std::get<2>(a_)); \
   }
-  RSF_LAUNCH((gemm_big_kernel<true, true, true>), 1 + 7)
-  RSF_LAUNCH((gemm_big_kernel<true, true, false>), 1 + 6)
-  RSF_LAUNCH((gemm_big_kernel<true, false, false>), 1 + 4)
-  RSF_LAUNCH((gemm_big_kernel<false, true, true>), 1 + 3)
-  RSF_LAUNCH((gemm_big_kernel<false, true, false>), 1 + 2)
-  RSF_LAUNCH((gemm_big_kernel<false, false, false>), 1 + 0)
-  RSF_LAUNCH(gemm_tiles_kernel, 0)
-  RSF_LAUNCH(gemm_tiles_f32_kernel, 9)
+    RSF_LAUNCH((gemm_big_kernel<true, true, true>), 1 + 7)
+    RSF_LAUNCH((gemm_big_kernel<true, true, false>), 1 + 6)
+    RSF_LAUNCH((gemm_big_kernel<true, false, false>), 1 + 4)
+    RSF_LAUNCH((gemm_big_kernel<false, true, true>), 1 + 3)
+    RSF_LAUNCH((gemm_big_kernel<false, true, false>), 1 + 2)
+    RSF_LAUNCH((gemm_big_kernel<false, false, false>), 1 + 0)
+    RSF_LAUNCH(gemm_tiles_kernel, 0)
+    RSF_LAUNCH(gemm_tiles_f32_kernel, 9)
 #undef RSF_LAUNCH
+  }
   RSF_HIP(hipGetLastError());
   if (!reds.empty()) {
     SplitRed* dr = reinterpret_cast<SplitRed*>(dblk + b_desc + b_cat);
@@ -1126,9 +1213,10 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
       if (probs[g].empty()) continue;
       const char* tf[2] = {"false", "true"};
       const int c = g - 1;
-      const std::string name = g == 0 ? std::string("gemm_tiles_kernel")
+      const std::string sfx = packed ? "_p" : "";
+      const std::string name = g == 0 ? "gemm_tiles_kernel" + sfx
                                : g == 9 ? std::string("gemm_tiles_f32_kernel")
-                                        : std::string("gemm_big_kernel<") + tf[(c >> 2) & 1] + ", " +
+                                        : "gemm_big_kernel" + sfx + "<" + tf[(c >> 2) & 1] + ", " +
                                               tf[(c >> 1) & 1] + ", " + tf[c & 1] + ">";
       trace_kernel_work(name, gfl[g], gby[g]);
     }
