@@ -778,10 +778,13 @@ std::string trace_tags() {
   return out;
 }
 
-// 128 x 128 tiles for the large products: each wave owns a 64 x 64 quarter as
-// 4 x 4 blocks of v_mfma_f64_16x16x4 (16 accumulators), eight LDS reads feed
-// sixteen MFMAs per k-step, and the next 16-wide K chunk is fetched into
-// registers while the current one is multiplied.  One kernel per operand
+// 128 x 128 tiles for the large products, eight waves per workgroup: each
+// wave owns a 64 x 32 block as 4 x 2 blocks of v_mfma_f64_16x16x4 (8
+// accumulators), six LDS reads feed eight MFMAs per k-step, and the next
+// 16-wide K chunk is fetched into registers while the current one is
+// multiplied.  Small accumulators leave room for four waves per SIMD (two
+// workgroups per CU), which hide the chunk loads better than two waves with
+// 64 x 64 blocks.  One kernel per operand
 // layout (A: rows contiguous or k contiguous; B: columns contiguous, with or
 // without a row map, or k contiguous), chosen on the host.  Interior tiles
 // and full K chunks take unchecked loads through per-thread pointers that
@@ -795,11 +798,12 @@ __device__ __forceinline__ void big_tile(const GemmDesc& dg, int ti, int tj) {
   const int M = dg.M, N = dg.N, K = dg.K;
   const int i0 = ti * BT, j0 = tj * BT;
   const int tid = threadIdx.x;
+  constexpr int NT = 512, LPT = 2048 / NT, KST = NT / 128, RST = NT / 16;
   const bool full = (i0 + BT <= M) && (j0 + BT <= N);
   // fetch geometry (see the layout note above):
   //   AI: A(i0 + (tid & 127), k0 + (tid >> 7) + 2 r)   else A(i0 + (tid >> 4) + 16 r, k0 + (tid & 15))
   //   BJ: B(k0 + (tid >> 7) + 2 r, j0 + (tid & 127))   else B(k0 + (tid & 15), j0 + (tid >> 4) + 16 r)
-  const int a_i = AI ? (tid & 127) : (tid >> 4);
+  const int a_i = AI ? (tid & 127) : (tid >> 4);  // NT / 16 rows per pass
   const int a_k = AI ? (tid >> 7) : (tid & 15);
   const int b_j = BJ ? (tid & 127) : (tid >> 4);
   const int b_k = BJ ? (tid >> 7) : (tid & 15);
@@ -813,54 +817,54 @@ __device__ __forceinline__ void big_tile(const GemmDesc& dg, int ti, int tj) {
   const int* __restrict__ bidx = dg.bidx;
   unsigned amask = 0, bmask = 0;  // bit r: row / column r of this thread is inside the problem
 #pragma unroll
-  for (int r = 0; r < 8; ++r) {
-    if (i0 + (AI ? a_i : a_i + 16 * r) < M) amask |= 1u << r;
-    if (j0 + (BJ ? b_j : b_j + 16 * r) < N) bmask |= 1u << r;
+  for (int r = 0; r < LPT; ++r) {
+    if (i0 + (AI ? a_i : a_i + RST * r) < M) amask |= 1u << r;
+    if (j0 + (BJ ? b_j : b_j + RST * r) < N) bmask |= 1u << r;
   }
-  v4d acc[4][4];
+  v4d acc[4][2];
 #pragma unroll
   for (int m = 0; m < 4; ++m)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) acc[m][q] = v4d{0, 0, 0, 0};
-  double ra[8], rbv[8];
+    for (int q = 0; q < 2; ++q) acc[m][q] = v4d{0, 0, 0, 0};
+  double ra[LPT], rbv[LPT];
   // k-contiguous A may read its columns through a map (A(i, kidx[k])); one
   // index per thread and chunk.  Mapped indices are loaded one chunk ahead of
   // the operands they address, so that the operand loads do not wait for them.
   const int* __restrict__ kidx = AI ? nullptr : dg.kidx;
-  int kix = 0, bix[8];
+  int kix = 0, bix[LPT];
   auto load_idx = [&](int k0) {
     if (!AI && kidx) kix = k0 + a_k < K ? kidx[k0 + a_k] : 0;
     if (BJ && BIDX) {
 #pragma unroll
-      for (int r = 0; r < 8; ++r) bix[r] = k0 + b_k + 2 * r < K ? bidx[k0 + b_k + 2 * r] : 0;
+      for (int r = 0; r < LPT; ++r) bix[r] = k0 + b_k + KST * r < K ? bidx[k0 + b_k + KST * r] : 0;
     }
   };
   auto fetch = [&](int k0) {
     if (full && k0 + 16 <= K) {
       const int kA = AI ? 0 : (kidx ? kix : k0 + a_k);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        ra[r] = AI ? pa[(long long)(k0 + a_k + 2 * r) * astr] : pa[(long long)(16 * r) * astr + kA];
+      for (int r = 0; r < LPT; ++r) {
+        ra[r] = AI ? pa[(long long)(k0 + a_k + KST * r) * astr] : pa[(long long)(RST * r) * astr + kA];
         if (BJ) {
-          const int kb = k0 + b_k + 2 * r;
+          const int kb = k0 + b_k + KST * r;
           rbv[r] = pb[(long long)(BIDX ? bix[r] : kb) * bstr];
         } else {
-          rbv[r] = pb[(long long)(16 * r) * bstr + k0 + b_k];
+          rbv[r] = pb[(long long)(RST * r) * bstr + k0 + b_k];
         }
       }
     } else {
       const int kc = k0 + a_k;
       const int kA = AI ? 0 : (kc < K ? (kidx ? kix : kc) : 0);
 #pragma unroll
-      for (int r = 0; r < 8; ++r) {
-        const int ka = k0 + a_k + (AI ? 2 * r : 0);
+      for (int r = 0; r < LPT; ++r) {
+        const int ka = k0 + a_k + (AI ? KST * r : 0);
         ra[r] = ((amask >> r) & 1u) && ka < K
-                    ? (AI ? pa[(long long)ka * astr] : pa[(long long)(16 * r) * astr + kA])
+                    ? (AI ? pa[(long long)ka * astr] : pa[(long long)(RST * r) * astr + kA])
                     : 0.0;
-        const int kb = k0 + b_k + (BJ ? 2 * r : 0);
+        const int kb = k0 + b_k + (BJ ? KST * r : 0);
         double v = 0.0;
         if (((bmask >> r) & 1u) && kb < K)
-          v = BJ ? pb[(long long)(BIDX ? bix[r] : kb) * bstr] : pb[(long long)(16 * r) * bstr + kb];
+          v = BJ ? pb[(long long)(BIDX ? bix[r] : kb) * bstr] : pb[(long long)(RST * r) * bstr + kb];
         rbv[r] = v;
       }
     }
@@ -871,34 +875,34 @@ __device__ __forceinline__ void big_tile(const GemmDesc& dg, int ti, int tj) {
   load_idx(kbeg);
   fetch(kbeg);
   const int lane = tid & 63, wave = tid >> 6;
-  const int rb0 = (wave >> 1) * 64, cb0 = (wave & 1) * 64;
+  const int rb0 = (wave >> 2) * 64, cb0 = (wave & 3) * 32;
   for (int k0 = kbeg; k0 < kend; k0 += 16) {
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
+    for (int r = 0; r < LPT; ++r) {
       if (AI)
-        As[a_k + 2 * r][a_i] = ra[r];
+        As[a_k + KST * r][a_i] = ra[r];
       else
-        As[a_k][a_i + 16 * r] = ra[r];
+        As[a_k][a_i + RST * r] = ra[r];
       if (BJ)
-        Bs[b_k + 2 * r][b_j] = rbv[r];
+        Bs[b_k + KST * r][b_j] = rbv[r];
       else
-        Bs[b_k][b_j + 16 * r] = rbv[r];
+        Bs[b_k][b_j + RST * r] = rbv[r];
     }
     __syncthreads();
     if (k0 + 16 < kend) fetch(k0 + 16);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
-      double a[4], b[4];
+      double a[4], b[2];
 #pragma unroll
       for (int m = 0; m < 4; ++m) a[m] = As[kk][rb0 + m * 16 + (lane & 15)];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) b[q] = Bs[kk][cb0 + q * 16 + (lane & 15)];
+      for (int q = 0; q < 2; ++q) b[q] = Bs[kk][cb0 + q * 16 + (lane & 15)];
 #pragma unroll
       for (int m = 0; m < 4; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
+        for (int q = 0; q < 2; ++q) acc[m][q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[m], b[q], acc[m][q], 0, 0, 0);
     }
   }
   const double alpha = dg.alpha, beta = dg.beta;
@@ -910,35 +914,35 @@ __device__ __forceinline__ void big_tile(const GemmDesc& dg, int ti, int tj) {
   // for the memory round trip of each entry in turn)
 #pragma unroll
   for (int m = 0; m < 4; ++m) {
-    double* cp[4][4];
-    bool ok[4][4];
+    double* cp[4][2];
+    bool ok[4][2];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gi = i0 + rb0 + m * 16 + 4 * r + (lane >> 4);
       const bool rin = full || gi < M;
       const long long row = cidx ? (rin ? (long long)cidx[gi] : 0LL) : (long long)gi;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 2; ++q) {
         const int gj = j0 + cb0 + q * 16 + (lane & 15);
         ok[r][q] = rin && (full || gj < N);
         cp[r][q] = Cb + row * crs + (long long)gj * ccs;
       }
     }
-    double cv[4][4];
+    double cv[4][2];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) cv[r][q] = (beta != 0.0 && ok[r][q]) ? *cp[r][q] : 0.0;
+      for (int q = 0; q < 2; ++q) cv[r][q] = (beta != 0.0 && ok[r][q]) ? *cp[r][q] : 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
+      for (int q = 0; q < 2; ++q)
         if (ok[r][q]) *cp[r][q] = (beta == 0.0) ? alpha * acc[m][q][r] : alpha * acc[m][q][r] + beta * cv[r][q];
   }
 }
 
 template <bool AI, bool BJ, bool BIDX>
-__global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
+__global__ __launch_bounds__(512, 2) void gemm_big_kernel(const GemmDesc* __restrict__ descs,
                                                            const int* __restrict__ probs,
                                                            const int* __restrict__ toff, int np) {
   const int3 t = find_tile(descs, probs, toff, np, BT, blockIdx.x);
@@ -946,7 +950,7 @@ __global__ __launch_bounds__(256, 2) void gemm_big_kernel(const GemmDesc* __rest
 }
 
 template <bool AI, bool BJ, bool BIDX>
-__global__ __launch_bounds__(256, 2) void gemm_big_kernel_p(const GemmPack pk) {
+__global__ __launch_bounds__(512, 2) void gemm_big_kernel_p(const GemmPack pk) {
   const int3 t = find_tile_pack(pk, BT, blockIdx.x);
   big_tile<AI, BJ, BIDX>(pk.d[t.x], t.y, t.z);
 }
@@ -1169,7 +1173,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
 #define RSF_PLAUNCH(KERNEL, g)                                        \
   if (!probs[g].empty()) {                                            \
     const GemmPack pk_ = pack(g);                                     \
-    hipLaunchKernelGGL(KERNEL, grid(g), dim3(256), 0, s, pk_);        \
+    hipLaunchKernelGGL(KERNEL, grid(g), dim3(g == 0 ? 256 : 512), 0, s, pk_); \
   }
     RSF_PLAUNCH((gemm_big_kernel_p<true, true, true>), 1 + 7)
     RSF_PLAUNCH((gemm_big_kernel_p<true, true, false>), 1 + 6)
@@ -1184,7 +1188,7 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
 #define RSF_LAUNCH(KERNEL, g)                                                                        \
   if (!probs[g].empty()) {                                                                           \
     auto a_ = args(g);                                                                               \
-    hipLaunchKernelGGL(KERNEL, grid(g), dim3(256), 0, s, dd, std::get<0>(a_), std::get<1>(a_), std::get<2>(a_)); \
+    hipLaunchKernelGGL(KERNEL, grid(g), dim3(g == 0 || g == 9 ? 256 : 512), 0, s, dd, std::get<0>(a_), std::get<1>(a_), std::get<2>(a_)); \
   }
     RSF_LAUNCH((gemm_big_kernel<true, true, true>), 1 + 7)
     RSF_LAUNCH((gemm_big_kernel<true, true, false>), 1 + 6)
