@@ -1265,14 +1265,19 @@ struct DiagJob {
 // Cholesky of one diagonal block (nb <= 64), written back in place (zero
 // above the diagonal), its log-diagonal sum and its inverse.  Thread (row
 // i = tid mod 64, group g = tid / 64) keeps row i's entries in columns g,
-// g + 4, ..., g + 60 in registers: each elimination step takes two barriers
-// (the pivot, then the scaled column through LDS) and every thread updates
-// its own entries in the order of the steps.  The inverse X = L^-1 is formed
-// by forward substitution over the rows, column c of X on threads (c, g),
-// row l in the registers of group l mod 4; the dot products are split over
-// the four groups and summed in group order.
+// g + 4, ..., g + 60 in registers, as a shift register: after the four
+// steps of column block jj (columns 4 jj .. 4 jj + 3) each thread's slot 0,
+// now final, goes to LDS and the slots move down by one, so that every
+// register index is a constant while the loop over jj stays a loop (the
+// code fits the instruction cache).  Column j lives in the wave of group
+// j mod 4: that wave reads the pivot from lane j, scales the column and puts
+// it in LDS; after one barrier every thread updates its own entries, and the
+// wave owning column j + 1 forms it at once (two LDS column buffers).  The
+// inverse X = L^-1 is formed by forward substitution over the rows, column c
+// of X on threads (c, g), row l in the registers of group l mod 4; the dot
+// products are split over the four groups and summed in group order.
 __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* __restrict__ jobs, int* fail) {
-  __shared__ double col[64];      // column j of L during step j
+  __shared__ double colb[2][64];  // the scaled column of the current step
   __shared__ double Ls[64][65];   // L, for the inverse
   __shared__ double part[2][4][64];
   __shared__ double dg[64];
@@ -1286,62 +1291,65 @@ __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* _
     r[u] = (i < nb && l <= i) ? J.A[(long long)l * J.lda + i] : 0.0;
   }
   if (tid == 0) bad = 0;
+  // L's LDS copy starts at zero (the forward substitution below reads whole rows)
+  for (int e = tid; e < 64 * 65; e += 256) (&Ls[0][0])[e] = 0.0;
   __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    const int gj = j & 3, uj = j >> 2;
-    // the pivot's owner checks it and publishes its square root
-    if (g == gj && i == j) {
-      double d = 0.0;
-#pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u == uj) d = r[u];
-      if (!(d > 0.0)) {
-        bad = 1;
-      } else {
-        const double sq = sqrt(d);
-        dg[j] = sq;
-        col[j] = sq;
-#pragma unroll
-        for (int u = 0; u < 16; ++u)
-          if (u == uj) r[u] = sq;
-      }
+  // the owner wave of column j forms it (rv: this lane's entry of column j)
+  auto form = [&](int j, double& rv) {
+    // the pivot from lane j through scalar registers (j is the same in every lane)
+    const unsigned long long bits = __double_as_longlong(rv);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)bits, j);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(bits >> 32), j);
+    const double d = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+    // a failed pivot is only recorded: the steps run on (their values are
+    // discarded) and the flag is read once, after the loop
+    if (!(d > 0.0) && i == 0) bad = 1;
+    const double sq = sqrt(d);
+    if (i == j) {
+      rv = sq;
+      dg[j] = sq;
+    } else if (i > j && i < nb) {
+      rv /= sq;
     }
-    __syncthreads();
-    if (bad) {
-      if (tid == 0) *fail = 1;
-      return;
-    }
-    // column j below the diagonal
-    if (g == gj && i > j && i < nb) {
-      const double sq = dg[j];
+    colb[j & 1][i] = (i >= j && i < nb) ? rv : 0.0;
+  };
+  if (g == 0) form(0, r[0]);
+  __syncthreads();
+  const int nblk = (nb + 3) >> 2;
+  for (int jj = 0; jj < nblk; ++jj) {
+    // slot u holds column g + 4 (u + jj)
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u == uj) {
-          r[u] /= sq;
-          col[i] = r[u];
+    for (int gg = 0; gg < 4; ++gg) {
+      const int j = 4 * jj + gg;
+      if (j < nb) {
+        // branch-free (a multiplier of zero leaves an entry unchanged), so the
+        // sixteen column reads go out together
+        const double lij = (i > j && i < nb) ? colb[j & 1][i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+          const int l = g + 4 * (u + jj);
+          const double cl = colb[j & 1][l & 63];
+          const double f = (l > j && l <= i) ? lij : 0.0;
+          r[u] = r[u] - f * cl;
         }
-    }
-    __syncthreads();
-    // trailing entries (l, i) with j < l <= i
-    if (i > j && i < nb) {
-      const double lij = col[i];
-#pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int l = g + 4 * u;
-        if (l > j && l <= i) r[u] -= lij * col[l];
+        if (j + 1 < nb && g == ((gg + 1) & 3)) form(j + 1, r[gg == 3 ? 1 : 0]);
+        __syncthreads();
       }
     }
-    __syncthreads();
-  }
-  // L to memory (zero above the diagonal) and to LDS
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int l = g + 4 * u;
-    if (i < nb && l < nb) {
-      const double v = l <= i ? r[u] : 0.0;
-      J.A[(long long)l * J.lda + i] = v;
-      Ls[i][l] = v;
+    // slot 0 (column g + 4 jj) is final: to LDS and memory; shift down
+    const int l0 = g + 4 * jj;
+    if (i < nb && l0 < nb) {
+      const double v = l0 <= i ? r[0] : 0.0;
+      J.A[(long long)l0 * J.lda + i] = v;
+      Ls[i][l0] = v;
     }
+#pragma unroll
+    for (int u = 0; u < 15; ++u) r[u] = r[u + 1];
+    r[15] = 0.0;
+  }
+  if (bad) {
+    if (tid == 0) *fail = 1;
+    return;
   }
   if (tid == 0 && J.logd) {
     double sm = 0.0;
@@ -1354,23 +1362,27 @@ __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* _
   double x[16];
 #pragma unroll
   for (int u = 0; u < 16; ++u) x[u] = 0.0;
-  for (int row = 0; row < nb; ++row) {
-    double p = 0.0;
+  for (int uu = 0; uu < nblk; ++uu)
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
-      const int l = g + 4 * u;
-      if (l < row) p += Ls[row][l] * x[u];
-    }
-    part[row & 1][g][c] = p;
-    __syncthreads();
-    if (g == (row & 3)) {
-      const double sm = ((part[row & 1][0][c] + part[row & 1][1][c]) + part[row & 1][2][c]) + part[row & 1][3][c];
-      const double v = ((row == c ? 1.0 : 0.0) - sm) / Ls[row][row];
+    for (int gg = 0; gg < 4; ++gg) {
+      const int row = 4 * uu + gg;
+      if (row < nb) {
+        // whole row: L is zero above the diagonal and x is still zero at
+        // row and below, so the added terms are exact zeros
+        double p = 0.0;
 #pragma unroll
-      for (int u = 0; u < 16; ++u)
-        if (u == (row >> 2)) x[u] = v;
+        for (int u = 0; u < 16; ++u) p += Ls[row][g + 4 * u] * x[u];
+        part[row & 1][g][c] = p;
+        __syncthreads();
+        if (g == gg) {
+          const double sm = ((part[row & 1][0][c] + part[row & 1][1][c]) + part[row & 1][2][c]) + part[row & 1][3][c];
+          const double v = ((row == c ? 1.0 : 0.0) - sm) / Ls[row][row];
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            if (u == uu) x[u] = v;
+        }
+      }
     }
-  }
 #pragma unroll
   for (int u = 0; u < 16; ++u) {
     const int l = g + 4 * u;
