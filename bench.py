@@ -224,6 +224,21 @@ def frac_record(root):
              "| kernel | dispatches | ms | alg. TFLOP/s | alg. GB/s | frac (alg.) | MFMA TFLOP/s (hw) | "
              "MFMA util % | VALU FP64 TFLOP/s | HBM GB | HBM TB/s |",
              "|---|---:|---:|---:|---:|---:|---:|---:|---:|---:|---:|"]
+    # kernels booked under their name without template arguments (the ID's
+    # update kernel, one instantiation per register bucket) are summed over
+    # their instantiations
+    def merge(d):
+        out = {}
+        for name, e in d.items():
+            short = _short(name)
+            base = short.split("<")[0]
+            key = base if (short not in work and base in work) else name
+            a = out.setdefault(key, {})
+            for k, v in e.items():
+                a[k] = a.get(k, 0.0) + v
+        return out
+
+    mf, fe, wr = merge(mf), merge(fe), merge(wr)
     rows = []
     for name, e in mf.items():
         if e["n"] <= 0 or e["ns"] <= 0:

@@ -848,22 +848,18 @@ struct Peeler {
     std::vector<PpanelJob> all(nj);
     for (int e = 0; e < nj; ++e)
       all[e] = PpanelJob{Gw + goff[e], d + doff[e], Lp + doff[e] * NB, dpiv + poff[e], state + 2 * e, d1 + e, c[e]};
-    {
-      PpanelJob* dj = ws.make<PpanelJob>(nj);
-      upload(dj, all, st);
-      hipLaunchKernelGGL(ppanel_init_kernel, dim3(nj), dim3(256), 0, st, dj);
-      RSF_HIP(hipGetLastError());
-    }
+    // the job table goes up once: every panel launch covers all matrices,
+    // and a finished one's workgroup returns at once (its state says so)
+    PpanelJob* dj = ws.make<PpanelJob>(nj);
+    upload(dj, all, st);
+    hipLaunchKernelGGL(ppanel_init_kernel, dim3(nj), dim3(256), 0, st, dj);
+    RSF_HIP(hipGetLastError());
     std::vector<int> active(nj);
     for (int e = 0; e < nj; ++e) active[e] = e;
     std::vector<int> hs(2 * nj, 0);
     const int npanel = (cmax + NB - 1) / NB;
     for (int pnl = 0; pnl <= npanel && !active.empty(); ++pnl) {
-      std::vector<PpanelJob> jobs;
-      for (int e : active) jobs.push_back(all[e]);
-      PpanelJob* dj = ws.make<PpanelJob>(jobs.size());
-      upload(dj, jobs, st);
-      const dim3 grid((unsigned)jobs.size()), blk(PCHOL_WG);
+      const dim3 grid((unsigned)nj), blk(PCHOL_WG);
       // one row per thread and panel column: small Gram matrices take small workgroups
       if (cmax <= 256)
         hipLaunchKernelGGL((ppanel_kernel<1, 32, 256>), grid, dim3(256), 0, st, dj, tol2);
