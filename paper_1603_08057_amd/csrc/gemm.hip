@@ -1229,14 +1229,25 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
 }
 
 // ---- batched blocked Cholesky with inverse
-__global__ __launch_bounds__(256) void copy_blocks_kernel(const CopyBlock* __restrict__ jobs) {
-  const CopyBlock J = jobs[blockIdx.x];
+__device__ __forceinline__ void copy_block(const CopyBlock& J) {
   const long long tot = (long long)J.m * J.n;
   for (long long e = blockIdx.y * 256LL + threadIdx.x; e < tot; e += 256LL * gridDim.y) {
     const int i = (int)(e % J.m), j = (int)(e / J.m);
     J.dst[(long long)j * J.ldd + i] = (J.src == nullptr || (J.lower && i < j)) ? 0.0 : J.src[(long long)j * J.lds + i];
   }
 }
+
+__global__ __launch_bounds__(256) void copy_blocks_kernel(const CopyBlock* __restrict__ jobs) {
+  const CopyBlock J = jobs[blockIdx.x];
+  copy_block(J);
+}
+
+// up to JOB_PACK jobs travel in the kernel arguments (no upload before the launch)
+constexpr int JOB_PACK = 32;
+struct CopyPack {
+  CopyBlock j[JOB_PACK];
+};
+__global__ __launch_bounds__(256) void copy_blocks_kernel_p(const CopyPack pk) { copy_block(pk.j[blockIdx.x]); }
 
 void copy_blocks(const std::vector<CopyBlock>& jobs, Scratch& scr, hipStream_t s) {
   std::vector<CopyBlock> live;
@@ -1247,10 +1258,16 @@ void copy_blocks(const std::vector<CopyBlock>& jobs, Scratch& scr, hipStream_t s
       mx = std::max(mx, (long long)j.m * j.n);
     }
   if (live.empty()) return;
-  CopyBlock* d = scr.make<CopyBlock>(live.size());
-  upload(d, live, s);
   const unsigned gy = (unsigned)std::max<long long>(1, std::min<long long>(64, (mx + 2047) / 2048));
-  hipLaunchKernelGGL(copy_blocks_kernel, dim3((unsigned)live.size(), gy), dim3(256), 0, s, d);
+  if (live.size() <= (size_t)JOB_PACK) {
+    CopyPack pk;
+    for (size_t u = 0; u < live.size(); ++u) pk.j[u] = live[u];
+    hipLaunchKernelGGL(copy_blocks_kernel_p, dim3((unsigned)live.size(), gy), dim3(256), 0, s, pk);
+  } else {
+    CopyBlock* d = scr.make<CopyBlock>(live.size());
+    upload(d, live, s);
+    hipLaunchKernelGGL(copy_blocks_kernel, dim3((unsigned)live.size(), gy), dim3(256), 0, s, d);
+  }
   RSF_HIP(hipGetLastError());
 }
 
@@ -1276,13 +1293,12 @@ struct DiagJob {
 // inverse X = L^-1 is formed by forward substitution over the rows, column c
 // of X on threads (c, g), row l in the registers of group l mod 4; the dot
 // products are split over the four groups and summed in group order.
-__global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* __restrict__ jobs, int* fail) {
+__device__ __forceinline__ void diag_chol_block(const DiagJob& J, int* fail) {
   __shared__ double colb[2][64];  // the scaled column of the current step
   __shared__ double Ls[64][65];   // L, for the inverse
   __shared__ double part[2][4][64];
   __shared__ double dg[64];
   __shared__ int bad;
-  const DiagJob J = jobs[blockIdx.x];
   const int nb = J.nb, tid = threadIdx.x, i = tid & 63, g = tid >> 6;
   double r[16];
 #pragma unroll
@@ -1390,6 +1406,19 @@ __global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* _
   }
 }
 
+__global__ __launch_bounds__(256) void diag_chol_batched_kernel(const DiagJob* __restrict__ jobs, int* fail) {
+  const DiagJob J = jobs[blockIdx.x];
+  diag_chol_block(J, fail);
+}
+
+struct DiagPack {
+  DiagJob j[JOB_PACK];
+};
+__global__ __launch_bounds__(256) void diag_chol_batched_kernel_p(const DiagPack pk, int* fail) {
+  const DiagJob J = pk.j[blockIdx.x];
+  diag_chol_block(J, fail);
+}
+
 void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr, hipStream_t s) {
   TraceTag tag("chol");
   int maxn = 0;
@@ -1426,9 +1455,15 @@ void batched_chol_inv(const std::vector<CholProblem>& P, int* fail, Scratch& scr
       }
     }
     if (!dj.empty()) {
-      DiagJob* d = scr.make<DiagJob>(dj.size());
-      upload(d, dj, s);
-      hipLaunchKernelGGL(diag_chol_batched_kernel, dim3((unsigned)dj.size()), dim3(256), 0, s, d, fail);
+      if (dj.size() <= (size_t)JOB_PACK) {
+        DiagPack pk;
+        for (size_t u = 0; u < dj.size(); ++u) pk.j[u] = dj[u];
+        hipLaunchKernelGGL(diag_chol_batched_kernel_p, dim3((unsigned)dj.size()), dim3(256), 0, s, pk, fail);
+      } else {
+        DiagJob* d = scr.make<DiagJob>(dj.size());
+        upload(d, dj, s);
+        hipLaunchKernelGGL(diag_chol_batched_kernel, dim3((unsigned)dj.size()), dim3(256), 0, s, d, fail);
+      }
       RSF_HIP(hipGetLastError());
     }
     gemm_batched(pan, scr, s);
