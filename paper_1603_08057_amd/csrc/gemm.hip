@@ -346,10 +346,11 @@ Scratch::~Scratch() {
 // entry the update reads are loaded before any store, so the loads overlap.
 __device__ __forceinline__ void store_tile32(const GemmDesc& d, const v4d& a00, const v4d& a01, const v4d& a10,
                                              const v4d& a11, int ib, int jb, int lane) {
-  double* cp[2][4][2];
-  bool ok[2][4][2];
+  // per 16-row half, so that the batch's pointers and values stay few
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < 2; ++h) {
+    double* cp[4][2];
+    bool ok[4][2];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int gi = ib + 16 * h + 4 * r + (lane >> 4);
@@ -358,26 +359,23 @@ __device__ __forceinline__ void store_tile32(const GemmDesc& d, const v4d& a00, 
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
         const int gj = jb + 16 * w + (lane & 15);
-        ok[h][r][w] = rin && gj < d.N;
-        cp[h][r][w] = d.C + row * d.crs + (long long)gj * d.ccs;
+        ok[r][w] = rin && gj < d.N;
+        cp[r][w] = d.C + row * d.crs + (long long)gj * d.ccs;
       }
     }
-  double cv[2][4][2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
+    double cv[4][2];
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
-      for (int w = 0; w < 2; ++w) cv[h][r][w] = (d.beta != 0.0 && ok[h][r][w]) ? *cp[h][r][w] : 0.0;
-#pragma unroll
-  for (int h = 0; h < 2; ++h)
+      for (int w = 0; w < 2; ++w) cv[r][w] = (d.beta != 0.0 && ok[r][w]) ? *cp[r][w] : 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r)
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
         const double a = h == 0 ? (w == 0 ? a00[r] : a01[r]) : (w == 0 ? a10[r] : a11[r]);
-        if (ok[h][r][w]) *cp[h][r][w] = (d.beta == 0.0) ? d.alpha * a : d.alpha * a + d.beta * cv[h][r][w];
+        if (ok[r][w]) *cp[r][w] = (d.beta == 0.0) ? d.alpha * a : d.alpha * a + d.beta * cv[r][w];
       }
+  }
 }
 
 // The tile of workgroup `bid` in a launch over problems probs[0 .. np) whose
@@ -528,14 +526,14 @@ __device__ __forceinline__ void tile64(const GemmDesc& dref, int ti, int tj) {
   store_tile32(d, acc00, acc01, acc10, acc11, i0 + rb, j0 + cb, lane);
 }
 
-__global__ __launch_bounds__(256) void gemm_tiles_kernel(const GemmDesc* __restrict__ descs,
+__global__ __launch_bounds__(256, 4) void gemm_tiles_kernel(const GemmDesc* __restrict__ descs,
                                                           const int* __restrict__ probs,
                                                           const int* __restrict__ toff, int np) {
   const int3 t = find_tile(descs, probs, toff, np, 64, blockIdx.x);
   tile64(descs[t.x], t.y, t.z);
 }
 
-__global__ __launch_bounds__(256) void gemm_tiles_kernel_p(const GemmPack pk) {
+__global__ __launch_bounds__(256, 4) void gemm_tiles_kernel_p(const GemmPack pk) {
   const int3 t = find_tile_pack(pk, 64, blockIdx.x);
   tile64(pk.d[t.x], t.y, t.z);
 }
