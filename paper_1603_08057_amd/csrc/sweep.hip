@@ -199,7 +199,7 @@ __global__ __launch_bounds__(256, RB == 1 ? 6 : RB == 2 ? 4 : 2) void box_sweep_
                                                         const double* __restrict__ Wm,
                                                         const double* __restrict__ Lm, double* __restrict__ X,
                                                         double* __restrict__ Y, int nc, long long ld,
-                                                        int amax) {
+                                                        int amax, int ucols) {
   // LDS: one (amax + 4)-row buffer of BS_NCT columns (amax = the level's
   // largest box): rows [0, k) hold the S rows, [k, a) the R rows.  Every step
   // works in place: a product that overwrites its own operand rows keeps its
@@ -207,24 +207,36 @@ __global__ __launch_bounds__(256, RB == 1 ? 6 : RB == 2 ? 4 : 2) void box_sweep_
   extern __shared__ double bs_smem[];
   double* Xl = bs_smem;
   // tiles of one box stay on one XCD (consecutive workgroup ids alternate XCDs);
-  // box bx owns the tiles [tile_off[bx], tile_off[bx + 1]) of its box_cols[bx] columns
-  const int total = tile_off[nbox];
+  // box bx owns the tiles [tile_off[bx], tile_off[bx + 1]) of its box_cols[bx]
+  // columns, or (tile_off null: every box takes the same ucols columns) the
+  // tiles [bx T, bx T + T), T = ceil(ucols / BS_NCT)
+  const int ut = (ucols + BS_NCT - 1) / BS_NCT;
+  const int total = tile_off ? tile_off[nbox] : nbox * ut;
   const int per = (int)(gridDim.x / 8);
   const int item = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   if (item >= total) return;
-  int lo = 0, hi = nbox;  // last box with tile_off[box] <= item
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (tile_off[mid] <= item)
-      lo = mid;
-    else
-      hi = mid;
+  int bx, tile, bcol;
+  if (tile_off) {
+    int lo = 0, hi = nbox;  // last box with tile_off[box] <= item
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tile_off[mid] <= item)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    bx = lo;
+    tile = item - tile_off[bx];
+    bcol = box_cols[bx];
+  } else {
+    bx = item / ut;
+    tile = item - bx * ut;
+    bcol = ucols;
   }
-  const int bx = lo, tile = item - tile_off[bx];
   const BoxRec b = boxes[bx];
   const int k = b.k, r = b.r, a = k + r;
   if (r == 0) return;
-  const int j0 = tile * BS_NCT, ncol = min(BS_NCT, box_cols[bx] - j0);
+  const int j0 = tile * BS_NCT, ncol = min(BS_NCT, bcol - j0);
   const int* Sb = S + b.s_off;
   const int* Rb = R + b.r_off;
   const double* T = Tm + b.t_off;  // k x r
@@ -345,13 +357,26 @@ static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int o
     if (r > 0) by += 8.0 * c * (op == BS_SOLVE_UP || op == BS_SOLVE_DOWN ? 2.0 * (k + r) : 2.0 * k + 3.0 * r);
   }
   if (toff[L.nb] == 0) return true;
-  // tile offsets and column counts in one upload
-  std::vector<int> tc(toff);
-  tc.insert(tc.end(), cols.begin(), cols.end());
-  int* dtoff = scr.make<int>(tc.size());
-  upload(dtoff, tc, s);
-  int* dcols = dtoff + (L.nb + 1);
-  const long long grid = ((long long)toff[L.nb] + 7) / 8 * 8;
+  // when every box takes the same columns the kernel derives its tile from
+  // the workgroup index (boxes without redundant rows return at once);
+  // otherwise tile offsets and column counts go up in one copy
+  bool uniform = true;
+  for (int i = 1; i < L.nb; ++i) uniform = uniform && cols[i] == cols[0];
+  int* dtoff = nullptr;
+  int* dcols = nullptr;
+  long long tiles = toff[L.nb];
+  const int ucols = cols[0];
+  if (uniform) {
+    tiles = (long long)L.nb * ((ucols + BS_NCT - 1) / BS_NCT);
+    RSF_CHECK(tiles < (1LL << 30), RSF_E_INVALID, "panel too wide for the fused sweep");
+  } else {
+    std::vector<int> tc(toff);
+    tc.insert(tc.end(), cols.begin(), cols.end());
+    dtoff = scr.make<int>(tc.size());
+    upload(dtoff, tc, s);
+    dcols = dtoff + (L.nb + 1);
+  }
+  const long long grid = (tiles + 7) / 8 * 8;
   const dim3 g((unsigned)grid), blk(256);
   TraceLaunch tl(s, fl, by);
   trace_kernel_work("box_sweep_kernel<" + std::to_string((int)op) + ", " +
@@ -368,7 +393,7 @@ static bool box_sweep(const LevelFactor& L, const std::vector<int>& bcols, int o
       lds_set[OPV][RBV / 2] = true;                                                                           \
     }                                                                                                         \
     hipLaunchKernelGGL((box_sweep_kernel<OPV, RBV>), g, blk, lds, s, L.box, L.nb, dtoff, dcols, L.S, L.R, L.T, \
-                       L.W, L.Lm, X, Y, nc, ld, amax);                                                        \
+                       L.W, L.Lm, X, Y, nc, ld, amax, ucols);                                                 \
   }
   if (amax <= 64) {
     // small boxes: one row block per wave, fewer registers, more resident
