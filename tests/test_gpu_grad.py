@@ -113,6 +113,26 @@ def test_autograd_function_backward():
     assert np.all(np.abs(th.grad.numpy() - d["g"]) <= 1e-4 * gscale)
 
 
+def test_autograd_recomputed_factor_gives_the_same_score():
+    # backward with the forward factorization released and made again (the
+    # memory-short path) against backward on the kept factorization
+    P = W.uniform_points(1500, 17)
+    theta = (0.07, 1.2, 1e-3)
+    z = dense.sample(P, W.gaussian(1500, 18), theta, K.MATERN32)
+    grads, ells = [], []
+    # the first call also settles the level-step autotuner's choices
+    for keep in (True, True, False, "auto"):
+        th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+        ell = R.loglik_fn(th, _t(P), _t(z), kernel=K.MATERN32, eps=1e-8, leaf=64, eps_peel=1e-7, seed=3,
+                          keep_factor=keep)
+        ell.backward()
+        ells.append(float(ell.detach()))
+        grads.append(th.grad.numpy().copy())
+    for e, g in zip(ells[2:], grads[2:]):
+        assert e == pytest.approx(ells[1], rel=1e-13)
+        np.testing.assert_allclose(g, grads[1], rtol=1e-12, atol=0)
+
+
 def test_grad_matches_central_difference_of_frozen_loglik():
     # the score of the approximate log-likelihood, with every ID tolerance tight,
     # against a central difference of the dense log-likelihood (relative step 1e-5)
