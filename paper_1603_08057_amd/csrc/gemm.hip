@@ -1,10 +1,12 @@
 // Batched FP64 GEMM on the gfx950 matrix cores, device memory helpers and
 // fixed-order reductions.
 #include <array>
+#include <cmath>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <atomic>
 #include <mutex>
@@ -999,7 +1001,135 @@ static int big_class(const GemmDesc& d) {
   return (ai ? 4 : 0) | (bj ? 2 : 0) | ((bj && d.bidx) ? 1 : 0);
 }
 
+// ---- tile-shape autotuning of the batched products
+// Problems that fit the 128 x 128 kernels can run on the 64 x 64 one as well.
+// Both accumulate every output entry over K in the same order with the same
+// instruction, so the choice changes no result, only the time.  The first
+// call of a launch shape (the layout classes present, the number of such
+// problems and their mean M, N and K in quarter-octave buckets, lower and
+// triangular problems) times both forms on scratch outputs and keeps the
+// faster; later calls of that shape reuse the choice.  No-allocation calls
+// and calls under stream capture run no trials (the 128 x 128 form, not
+// recorded).
+namespace {
+struct TileKey {
+  unsigned classes;
+  int count, m, n, k, lower, tri;
+  bool operator<(const TileKey& o) const {
+    return std::tie(classes, count, m, n, k, lower, tri) < std::tie(o.classes, o.count, o.m, o.n, o.k, o.lower, o.tri);
+  }
+};
+std::mutex g_tile_mu;
+std::map<TileKey, int> g_tile;  // 1: 128 x 128 tiles, 0: 64 x 64 tiles
+thread_local int g_tile_force = -1;
+
+int quarter_octave_of(double x) { return (int)std::floor(4.0 * std::log2(std::max(1.0, x))); }
+
+bool fits_big(const GemmDesc& d) {
+  return !d.f32 && big_class(d) >= 0 && d.M >= 96 && d.N >= 96 && d.K >= 32;
+}
+
+float time_launch(hipStream_t s, const std::function<void()>& fn) {
+  hipEvent_t e0, e1;
+  RSF_HIP(hipEventCreate(&e0));
+  RSF_HIP(hipEventCreate(&e1));
+  RSF_HIP(hipEventRecord(e0, s));
+  fn();
+  RSF_HIP(hipEventRecord(e1, s));
+  RSF_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  RSF_HIP(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return ms;
+}
+}  // namespace
+
+// 1 when the problems that fit the 128 x 128 kernels take them, 0 when they
+// take the 64 x 64 kernel (timed at the first call of the launch shape).
+static int tile_choice(const std::vector<GemmDesc>& descs, hipStream_t s) {
+  if (g_tile_force >= 0) return g_tile_force;
+  // tests may fix the form for every call (read at each call)
+  if (const char* e = std::getenv("RSFGP_TEST_TILES")) {
+    if (!std::strcmp(e, "64")) return 0;
+    if (!std::strcmp(e, "128")) return 1;
+  }
+  unsigned classes = 0;
+  long long cnt = 0;
+  double sm = 0.0, sn = 0.0, sk = 0.0;
+  int lower = 0, tri = 0;
+  for (const GemmDesc& d : descs) {
+    if (d.M <= 0 || d.N <= 0 || !fits_big(d)) continue;
+    classes |= 1u << big_class(d);
+    ++cnt;
+    sm += d.M;
+    sn += d.N;
+    sk += d.K;
+    lower |= d.lower ? 1 : 0;
+    tri |= d.tri ? 1 : 0;
+  }
+  if (cnt == 0) return 1;
+  const TileKey key{classes, quarter_octave_of((double)cnt), quarter_octave_of(sm / cnt),
+                    quarter_octave_of(sn / cnt), quarter_octave_of(sk / cnt), lower, tri};
+  {
+    std::lock_guard<std::mutex> lk(g_tile_mu);
+    auto it = g_tile.find(key);
+    if (it != g_tile.end()) return it->second;
+  }
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  RSF_HIP(hipStreamIsCapturing(s, &cap));
+  if (no_alloc_active() || cap != hipStreamCaptureStatusNone) return 1;
+  // trial problems: the same operands, each C a fresh column-major block
+  // written with beta = 0 (the caller's C is not touched)
+  TracePause tp;
+  Scratch ts(s);
+  long long tot = 0;
+  for (const GemmDesc& d : descs)
+    if (d.M > 0 && d.N > 0 && fits_big(d)) tot += (long long)d.M * d.N;
+  double* W = ts.make<double>(tot);
+  std::vector<GemmDesc> trial;
+  long long off = 0;
+  for (const GemmDesc& d : descs) {
+    if (d.M <= 0 || d.N <= 0 || !fits_big(d)) continue;
+    GemmDesc e = d;
+    e.C = W + off;
+    e.cidx = nullptr;
+    e.crs = 1;
+    e.ccs = d.M;
+    e.beta = 0.0;
+    off += (long long)d.M * d.N;
+    trial.push_back(e);
+  }
+  auto run = [&](int force) {
+    const int was = g_tile_force;
+    g_tile_force = force;
+    gemm_batched(trial, ts, s);
+    g_tile_force = was;
+  };
+  // each form runs once untimed, then three timed runs of each alternate and
+  // the fastest of each counts (work that the other stream runs at the same
+  // time stretches single timings); the 64 x 64 form must win by 15 %, since
+  // the trials time each launch alone and the 128 x 128 tiles read less
+  // beside a second stream's work
+  run(1);
+  run(0);
+  float tb = 1e30f, tt = 1e30f;
+  for (int rep = 0; rep < 3; ++rep) {
+    tb = std::min(tb, time_launch(s, [&] { run(1); }));
+    tt = std::min(tt, time_launch(s, [&] { run(0); }));
+  }
+  const int choice = tt < 0.85f * tb ? 0 : 1;
+  static const bool dbg = std::getenv("RSFGP_TUNE_DEBUG") != nullptr;
+  if (dbg)
+    fprintf(stderr, "[tune] gemm %s classes %x probs %lld M %.0f N %.0f K %.0f: 128x128 %.3f ms 64x64 %.3f ms -> %s\n",
+            t_tag.c_str(), classes, cnt, sm / cnt, sn / cnt, sk / cnt, tb, tt, choice ? "128x128" : "64x64");
+  std::lock_guard<std::mutex> lk(g_tile_mu);
+  g_tile[key] = choice;
+  return choice;
+}
+
 void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t s) {
+  const int use_big = tile_choice(descs, s);
   // launch groups: 0 = 64 x 64 FP64 tiles, 1 + c = 128 x 128 tiles of layout
   // class c, 9 = 64 x 64 FP32 tiles; per group the problems and their tile
   // prefix counts (the kernels find their tile from these)
@@ -1008,6 +1138,11 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   for (auto& v : toff) v.push_back(0);
   std::vector<GemmDesc> live;
   double flops = 0.0, bytes = 0.0, gfl[NG] = {}, gby[NG] = {};
+  // the launch group each problem takes without the tile choice, and those
+  // groups' tile counts: split-K decides from these, so that the tile choice
+  // changes no result
+  std::vector<int> gnat;
+  long long tnat[NG] = {};
   for (const GemmDesc& d : descs) {
     if (d.M <= 0 || d.N <= 0) continue;
     RSF_CHECK(!d.lower || d.M == d.N, RSF_E_INVALID, "lower-triangle GEMM needs a square C");
@@ -1021,11 +1156,18 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
     const int p = (int)live.size();
     live.push_back(d);
     const int cls = big_class(d);
+    const int gn = d.f32 ? 9 : fits_big(d) ? 1 + cls : 0;
+    {
+      const int tsn = gn >= 1 && gn <= 8 ? BT : 64;
+      const long long tmn = (d.M + tsn - 1) / tsn, tnn = (d.N + tsn - 1) / tsn;
+      tnat[gn] += d.lower ? tmn * (tmn + 1) / 2 : tmn * tnn;
+      gnat.push_back(gn);
+    }
     int g, ts;
     if (d.f32) {
       g = 9;
       ts = 64;
-    } else if (cls >= 0 && d.M >= 96 && d.N >= 96 && d.K >= 32) {
+    } else if (use_big && fits_big(d)) {
       g = 1 + cls;
       ts = BT;
     } else {
@@ -1047,14 +1189,15 @@ void gemm_batched(const std::vector<GemmDesc>& descs, Scratch& scr, hipStream_t 
   constexpr int SPLIT_TILES = 512, SPLIT_MIN_K = 512, SPLIT_MAX = 8;
   std::vector<SplitRed> reds;
   for (int g = 0; g < 9; ++g) {
-    const int T = toff[g].back();
-    if (T == 0 || T >= SPLIT_TILES) continue;
-    const int want = std::min(SPLIT_MAX, SPLIT_TILES / T);
-    if (want < 2) continue;
+    if (toff[g].back() == 0) continue;
     const int ts = g == 0 ? 64 : BT;
     const size_t np0 = probs[g].size();
     for (size_t u = 0; u < np0; ++u) {
       const int p = probs[g][u];
+      const long long T = tnat[gnat[p]];
+      if (T == 0 || T >= SPLIT_TILES) continue;
+      const int want = std::min<long long>(SPLIT_MAX, SPLIT_TILES / T);
+      if (want < 2) continue;
       const GemmDesc d = live[p];
       const int sp = std::min(want, d.K / SPLIT_MIN_K);
       if (d.tri || sp < 2) continue;

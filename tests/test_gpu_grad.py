@@ -133,6 +133,31 @@ def test_autograd_recomputed_factor_gives_the_same_score():
         np.testing.assert_allclose(g, grads[1], rtol=1e-12, atol=0)
 
 
+def test_tile_choice_changes_no_result(monkeypatch):
+    # the batched products run on 128 x 128 or 64 x 64 tiles (the tile-shape
+    # autotuner's choice); both accumulate every entry in the same order with
+    # the same instruction, and split-K does not depend on the choice, so l,
+    # log|Sigma| and the score agree bit for bit under either form and the tuned one
+    P = W.uniform_points(4000, 21)
+    theta = (0.06, 1.0, 1e-3)
+    z = W.gaussian(4000, 22)
+    out = []
+    for tiles in ("128", "64", None):
+        if tiles:
+            monkeypatch.setenv("RSFGP_TEST_TILES", tiles)
+        else:
+            monkeypatch.delenv("RSFGP_TEST_TILES", raising=False)
+        F = R.Factor(_t(P), theta, kernel=K.MATERN32, eps=1e-8, leaf=64)
+        ell = F.loglik(_t(z))
+        ld = F.logdet
+        g, _ = F.grad(_t(z), 1e-7, 4)
+        F.close()
+        out.append((ell, ld, np.array(g)))
+    for ell, ld, g in out[1:]:
+        assert ell == out[0][0] and ld == out[0][1]
+        np.testing.assert_array_equal(g, out[0][2])
+
+
 def test_grad_matches_central_difference_of_frozen_loglik():
     # the score of the approximate log-likelihood, with every ID tolerance tight,
     # against a central difference of the dense log-likelihood (relative step 1e-5)
