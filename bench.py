@@ -452,8 +452,13 @@ def measure_batch(args, name, steps, warmup):
             out.append((ell, g))
         return out
 
+    # both forms are warmed up: their first calls time the autotuners' trials
+    # for launch shapes not seen before (the instances alone have shapes of
+    # their own)
     for i in range(warmup):
         step_batched()
+    if warmup > 0:
+        step_single()
     torch.cuda.synchronize()
     t0 = time.time()
     for i in range(steps):
